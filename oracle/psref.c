@@ -1,0 +1,772 @@
+/*
+ * psref.c -- FP64 CPU oracle for the pseudospectral Navier-Stokes / MHD step.
+ *
+ * TEST INFRASTRUCTURE: see psref.h.  Written for a reader checking it against
+ * the paper by eye: no blocking, fusion or reordering beyond what each
+ * definition states.  Loops over pencils and planes are threaded with OpenMP
+ * one loop level at a time, the loop-level threading the paper describes in
+ * Sec. 3; the threading never changes a result.
+ *
+ * A compile-time switch PSREF_MUTANT=n (n > 0) plants one deliberate mistake
+ * per n.  It exists only so the test suite can show that its pins catch
+ * plausible mistakes; the default build (PSREF_MUTANT undefined or 0) has
+ * none of them.
+ */
+#include "psref.h"
+
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#ifndef PSREF_MUTANT
+#define PSREF_MUTANT 0
+#endif
+#define MUT(n) (PSREF_MUTANT == (n))
+
+typedef double complex cplx;
+
+static const double TWO_PI = 6.28318530717958647692528676655900577;
+
+/* ------------------------------------------------------------------------ */
+/* Index conventions (Sec. 2, Fig. 1: real N^3 cube, half spectrum           */
+/* (N/2+1) x N x N after the real-to-complex transform).                     */
+/* ------------------------------------------------------------------------ */
+
+/* signed wavenumber of storage index i along ky or kz */
+static long wav(long i, long N) { return (i < N / 2) ? i : i - N; }
+
+/* derivative wavenumber: odd derivatives of the Nyquist mode are zero */
+static long dwav(long i, long N) {
+  if (MUT(9)) return wav(i, N);
+  return (2 * i == N) ? 0 : wav(i, N);
+}
+
+/* kx storage index -> wavenumber (kx = 0..N/2) */
+static long wavx(long i) { return i; }
+static long dwavx(long i, long N) {
+  if (MUT(9)) return i;
+  return (2 * i == N) ? 0 : i;
+}
+
+/* 2/3-rule dealiasing, spherical truncation: keep 9 |k|^2 < N^2 */
+static int dealias_keep(long k2, long N) {
+  if (MUT(3)) return 9 * k2 <= N * N;
+  return 9 * k2 < N * N;
+}
+
+/* ------------------------------------------------------------------------ */
+/* One-dimensional DFT by recursive mixed-radix decimation in time.          */
+/*   X[k] = sum_j x[j] exp(-+ 2 pi i j k / n)                                */
+/* n = p m with p the smallest prime factor; x[r + p j] gives p sub-DFTs of  */
+/* length m, combined as X[k] = sum_r W_n^{r k} Y_r[k mod m].                */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+  int n;
+  cplx *w; /* w[e] = exp(-2 pi i e / n), computed in FP64 */
+} line_plan;
+
+static int line_plan_init(line_plan *p, int n) {
+  p->n = n;
+  p->w = (cplx *)malloc(sizeof(cplx) * (size_t)n);
+  if (!p->w) return -3;
+  for (int e = 0; e < n; ++e) {
+    double a = TWO_PI * (double)e / (double)n;
+    p->w[e] = cos(a) - I * sin(a);
+  }
+  return 0;
+}
+
+static void line_plan_free(line_plan *p) { free(p->w); p->w = NULL; }
+
+static int smallest_factor(int n) {
+  for (int p = 2; p * p <= n; ++p)
+    if (n % p == 0) return p;
+  return n;
+}
+
+/* t: scratch of at least n entries, shared by all recursion levels (each
+ * level combines only after its sub-transforms have returned) */
+static void fft_rec(const line_plan *pl, int n, const cplx *x, long stride,
+                    cplx *X, cplx *t, int inverse) {
+  if (n == 1) {
+    X[0] = x[0];
+    return;
+  }
+  int p = smallest_factor(n), m = n / p;
+  for (int r = 0; r < p; ++r)
+    fft_rec(pl, m, x + (long)r * stride, stride * p, X + (long)r * m, t, inverse);
+  int scale = pl->n / n;
+  for (int q = 0; q < p; ++q) {
+    for (int k = 0; k < m; ++k) {
+      int kk = k + q * m;
+      cplx s = 0;
+      for (int r = 0; r < p; ++r) {
+        long e = ((long)r * kk) % n;
+        cplx w = pl->w[e * scale];
+        if (inverse && !MUT(8)) w = conj(w);
+        s += w * X[(long)r * m + k];
+      }
+      t[kk] = s;
+    }
+  }
+  memcpy(X, t, sizeof(cplx) * (size_t)n);
+}
+
+/* in and out are separate buffers of length pl->n */
+static void line_fft(const line_plan *pl, const cplx *in, cplx *out, int inverse) {
+  cplx *t = (cplx *)malloc(sizeof(cplx) * (size_t)pl->n);
+  fft_rec(pl, pl->n, in, 1, out, t, inverse);
+  free(t);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Three-dimensional real transforms (Sec. 2, Fig. 1): transforms along x,   */
+/* then y, then z for the forward direction; the reverse for the inverse.    */
+/* ------------------------------------------------------------------------ */
+
+static int size_ok(int N) { return N >= 2 && N <= 4096 && (N % 2) == 0; }
+
+/* complex transforms along y then z (or z then y) of one half-spectrum field */
+static void pass_y(const line_plan *pl, int N, cplx *X, int inverse) {
+  const long H = N / 2 + 1;
+#pragma omp parallel
+  {
+    cplx *a = (cplx *)malloc(sizeof(cplx) * (size_t)N);
+    cplx *b = (cplx *)malloc(sizeof(cplx) * (size_t)N);
+#pragma omp for schedule(static)
+    for (long zk = 0; zk < (long)N * H; ++zk) {
+      long z = zk / H, kx = zk % H;
+      for (long y = 0; y < N; ++y) a[y] = X[(z * N + y) * H + kx];
+      line_fft(pl, a, b, inverse);
+      for (long y = 0; y < N; ++y) X[(z * N + y) * H + kx] = b[y];
+    }
+    free(a);
+    free(b);
+  }
+}
+
+static void pass_z(const line_plan *pl, int N, cplx *X, int inverse) {
+  const long H = N / 2 + 1;
+#pragma omp parallel
+  {
+    cplx *a = (cplx *)malloc(sizeof(cplx) * (size_t)N);
+    cplx *b = (cplx *)malloc(sizeof(cplx) * (size_t)N);
+#pragma omp for schedule(static)
+    for (long yk = 0; yk < (long)N * H; ++yk) {
+      long ky = yk / H, kx = yk % H;
+      for (long z = 0; z < N; ++z) a[z] = X[(z * N + ky) * H + kx];
+      line_fft(pl, a, b, inverse);
+      for (long z = 0; z < N; ++z) X[(z * N + ky) * H + kx] = b[z];
+    }
+    free(a);
+    free(b);
+  }
+}
+
+static void r2c_field(const line_plan *pl, int N, const double *u, cplx *X) {
+  const long H = N / 2 + 1;
+#pragma omp parallel
+  {
+    cplx *a = (cplx *)malloc(sizeof(cplx) * (size_t)N);
+    cplx *b = (cplx *)malloc(sizeof(cplx) * (size_t)N);
+#pragma omp for schedule(static)
+    for (long row = 0; row < (long)N * N; ++row) {
+      for (long x = 0; x < N; ++x) a[x] = u[row * N + x];
+      line_fft(pl, a, b, 0);
+      for (long kx = 0; kx < H; ++kx) X[row * H + kx] = b[kx];
+    }
+    free(a);
+    free(b);
+  }
+  pass_y(pl, N, X, 0);
+  pass_z(pl, N, X, 0);
+}
+
+/* Y is overwritten (used as the z/y-transformed intermediate) */
+static void c2r_field_inplace(const line_plan *pl, int N, cplx *Y, double *u) {
+  const long H = N / 2 + 1;
+  pass_z(pl, N, Y, 1);
+  pass_y(pl, N, Y, 1);
+#pragma omp parallel
+  {
+    cplx *a = (cplx *)malloc(sizeof(cplx) * (size_t)N);
+    cplx *b = (cplx *)malloc(sizeof(cplx) * (size_t)N);
+#pragma omp for schedule(static)
+    for (long row = 0; row < (long)N * N; ++row) {
+      const cplx *y = Y + row * H;
+      /* Hermitian extension of the kx line; the imaginary parts of the
+       * kx = 0 and kx = N/2 bins are dropped */
+      a[0] = creal(y[0]);
+      for (long k = 1; k < N / 2; ++k) {
+        a[k] = y[k];
+        a[N - k] = conj(y[k]);
+      }
+      a[N / 2] = creal(y[N / 2]);
+      line_fft(pl, a, b, 1);
+      for (long x = 0; x < N; ++x) u[row * N + x] = creal(b[x]);
+    }
+    free(a);
+    free(b);
+  }
+}
+
+int psref_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+  return omp_get_max_threads();
+#else
+  (void)n;
+  return 1;
+#endif
+}
+
+int psref_fft_r2c(int N, int nf, const double *in, double *out) {
+  if (!in || !out || nf < 1) return -1;
+  if (!size_ok(N)) return -2;
+  line_plan pl;
+  if (line_plan_init(&pl, N)) return -3;
+  const long n3 = (long)N * N * N, nc = (long)N * N * (N / 2 + 1);
+  for (int f = 0; f < nf; ++f)
+    r2c_field(&pl, N, in + f * n3, (cplx *)out + f * nc);
+  line_plan_free(&pl);
+  return 0;
+}
+
+int psref_fft_c2r(int N, int nf, const double *in, double *out) {
+  if (!in || !out || nf < 1) return -1;
+  if (!size_ok(N)) return -2;
+  const long n3 = (long)N * N * N, nc = (long)N * N * (N / 2 + 1);
+  cplx *Y = (cplx *)malloc(sizeof(cplx) * (size_t)nc);
+  if (!Y) return -3;
+  line_plan pl;
+  if (line_plan_init(&pl, N)) { free(Y); return -3; }
+  for (int f = 0; f < nf; ++f) {
+    memcpy(Y, (const cplx *)in + f * nc, sizeof(cplx) * (size_t)nc);
+    c2r_field_inplace(&pl, N, Y, out + f * n3);
+  }
+  line_plan_free(&pl);
+  free(Y);
+  return 0;
+}
+
+int psref_dft_at(int N, const double *in, int nk, const int *kx, const int *ky,
+                 const int *kz, double *out) {
+  if (!in || !out || nk < 0 || (nk > 0 && (!kx || !ky || !kz))) return -1;
+  if (!size_ok(N)) return -2;
+  for (int i = 0; i < nk; ++i)
+    if (kx[i] < 0 || kx[i] > N / 2 || ky[i] < 0 || ky[i] >= N || kz[i] < 0 || kz[i] >= N)
+      return -1;
+  line_plan pl;
+  if (line_plan_init(&pl, N)) return -3;
+  for (int i = 0; i < nk; ++i) {
+    cplx s = 0;
+    for (long z = 0; z < N; ++z)
+      for (long y = 0; y < N; ++y)
+        for (long x = 0; x < N; ++x) {
+          long e = ((long)kx[i] * x + (long)ky[i] * y + (long)kz[i] * z) % N;
+          s += in[(z * N + y) * N + x] * pl.w[e];
+        }
+    out[2 * i] = creal(s);
+    out[2 * i + 1] = cimag(s);
+  }
+  line_plan_free(&pl);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Spectral operators (Sec. 2: derivatives in Fourier space; projection onto */
+/* divergence-free fields; dealiasing of the quadratic term).                */
+/* ------------------------------------------------------------------------ */
+
+/* w = i k_d x u for one 3-vector field set of nc modes each */
+static void curl_fields(int N, const cplx *u, cplx *w) {
+  const long H = N / 2 + 1, nc = (long)N * N * H;
+#pragma omp parallel for schedule(static)
+  for (long kz = 0; kz < N; ++kz)
+    for (long ky = 0; ky < N; ++ky)
+      for (long kx = 0; kx < H; ++kx) {
+        long m = (kz * N + ky) * H + kx;
+        double ax = (double)dwavx(kx, N), ay = (double)dwav(ky, N), az = (double)dwav(kz, N);
+        cplx ux = u[m], uy = u[nc + m], uz = u[2 * nc + m];
+        w[m] = I * (ay * uz - az * uy);
+        w[nc + m] = I * (az * ux - ax * uz);
+        w[2 * nc + m] = I * (ax * uy - ay * ux);
+        if (MUT(1)) w[nc + m] = -w[nc + m];
+      }
+}
+
+int psref_curl(int N, const double *uhat, double *what) {
+  if (!uhat || !what) return -1;
+  if (!size_ok(N)) return -2;
+  curl_fields(N, (const cplx *)uhat, (cplx *)what);
+  return 0;
+}
+
+/* v <- D(k) P(k) v / N^3 for a 3-vector field set (P(0) v := 0) */
+static void dealias_project(int N, cplx *v) {
+  const long H = N / 2 + 1, nc = (long)N * N * H;
+  const double inv = 1.0 / ((double)N * N * N);
+#pragma omp parallel for schedule(static)
+  for (long kz = 0; kz < N; ++kz)
+    for (long ky = 0; ky < N; ++ky)
+      for (long kx = 0; kx < H; ++kx) {
+        long m = (kz * N + ky) * H + kx;
+        long ix = wavx(kx), iy = wav(ky, N), iz = wav(kz, N);
+        long k2 = ix * ix + iy * iy + iz * iz;
+        if (k2 == 0 || !dealias_keep(k2, N)) {
+          v[m] = v[nc + m] = v[2 * nc + m] = 0;
+          continue;
+        }
+        double ax = (double)ix, ay = (double)iy, az = (double)iz;
+        cplx vx = v[m], vy = v[nc + m], vz = v[2 * nc + m];
+        cplx kv = ax * vx + ay * vy + az * vz;
+        if (MUT(2)) kv = 0;
+        double s = MUT(6) ? 1.0 : inv;
+        v[m] = s * (vx - ax * kv / (double)k2);
+        v[nc + m] = s * (vy - ay * kv / (double)k2);
+        v[2 * nc + m] = s * (vz - az * kv / (double)k2);
+      }
+}
+
+/* n = a x b pointwise on real fields (3 components each) */
+static void cross_real(long n3, const double *a, const double *b, double *n) {
+#pragma omp parallel for schedule(static)
+  for (long i = 0; i < n3; ++i) {
+    double ax = a[i], ay = a[n3 + i], az = a[2 * n3 + i];
+    double bx = b[i], by = b[n3 + i], bz = b[2 * n3 + i];
+    n[i] = ay * bz - az * by;
+    n[n3 + i] = az * bx - ax * bz;
+    n[2 * n3 + i] = ax * by - ay * bx;
+  }
+}
+
+/* c2r of a 3-field spectral set (input preserved) */
+static int c2r3(const line_plan *pl, int N, const cplx *in, double *out, cplx *tmp) {
+  const long n3 = (long)N * N * N, nc = (long)N * N * (N / 2 + 1);
+  for (int f = 0; f < 3; ++f) {
+    memcpy(tmp, in + f * nc, sizeof(cplx) * (size_t)nc);
+    c2r_field_inplace(pl, N, tmp, out + f * n3);
+  }
+  return 0;
+}
+
+static void r2c3(const line_plan *pl, int N, const double *in, cplx *out) {
+  const long n3 = (long)N * N * N, nc = (long)N * N * (N / 2 + 1);
+  for (int f = 0; f < 3; ++f) r2c_field(pl, N, in + f * n3, out + f * nc);
+}
+
+int psref_nonlinear_ns(int N, const double *uhat_, double *nhat_) {
+  if (!uhat_ || !nhat_) return -1;
+  if (!size_ok(N)) return -2;
+  const long n3 = (long)N * N * N, nc = (long)N * N * (N / 2 + 1);
+  const cplx *uhat = (const cplx *)uhat_;
+  cplx *nhat = (cplx *)nhat_;
+  cplx *what = (cplx *)malloc(sizeof(cplx) * 3 * (size_t)nc);
+  cplx *tmp = (cplx *)malloc(sizeof(cplx) * (size_t)nc);
+  double *u = (double *)malloc(sizeof(double) * 3 * (size_t)n3);
+  double *w = (double *)malloc(sizeof(double) * 3 * (size_t)n3);
+  line_plan pl;
+  int rc = 0;
+  if (!what || !tmp || !u || !w || line_plan_init(&pl, N)) {
+    rc = -3;
+    goto done;
+  }
+  curl_fields(N, uhat, what);               /* w^ = i k x u^            */
+  c2r3(&pl, N, uhat, u, tmp);               /* u(x)                      */
+  c2r3(&pl, N, what, w, tmp);               /* w(x)                      */
+  if (MUT(10))
+    cross_real(n3, w, u, u);                /* planted: operands swapped */
+  else
+    cross_real(n3, u, w, u);                /* u x w, written over u     */
+  r2c3(&pl, N, u, nhat);                    /* F[u x w]                  */
+  dealias_project(N, nhat);                 /* D P (.) / N^3             */
+  line_plan_free(&pl);
+done:
+  free(what);
+  free(tmp);
+  free(u);
+  free(w);
+  return rc;
+}
+
+int psref_nonlinear_mhd(int N, const double *zhat_, double *nhat_) {
+  if (!zhat_ || !nhat_) return -1;
+  if (!size_ok(N)) return -2;
+  const long H = N / 2 + 1, n3 = (long)N * N * N, nc = (long)N * N * H;
+  const cplx *zp = (const cplx *)zhat_, *zm = zp + 3 * nc;
+  cplx *np_ = (cplx *)nhat_, *nm = np_ + 3 * nc;
+  cplx *uh = (cplx *)malloc(sizeof(cplx) * 3 * (size_t)nc);
+  cplx *bh = (cplx *)malloc(sizeof(cplx) * 3 * (size_t)nc);
+  cplx *sh = (cplx *)malloc(sizeof(cplx) * 3 * (size_t)nc);
+  cplx *tmp = (cplx *)malloc(sizeof(cplx) * (size_t)nc);
+  double *u = (double *)malloc(sizeof(double) * 3 * (size_t)n3);
+  double *b = (double *)malloc(sizeof(double) * 3 * (size_t)n3);
+  double *w = (double *)malloc(sizeof(double) * 3 * (size_t)n3);
+  double *j = (double *)malloc(sizeof(double) * 3 * (size_t)n3);
+  line_plan pl;
+  int rc = 0;
+  if (!uh || !bh || !sh || !tmp || !u || !b || !w || !j || line_plan_init(&pl, N)) {
+    rc = -3;
+    goto done;
+  }
+  /* primitive variables u = (z+ + z-)/2, b = (z+ - z-)/2 */
+  for (long m = 0; m < 3 * nc; ++m) {
+    uh[m] = 0.5 * (zp[m] + zm[m]);
+    bh[m] = 0.5 * (zp[m] - zm[m]);
+  }
+  c2r3(&pl, N, uh, u, tmp);
+  c2r3(&pl, N, bh, b, tmp);
+  curl_fields(N, uh, sh);                   /* w^ = i k x u^ */
+  c2r3(&pl, N, sh, w, tmp);
+  curl_fields(N, bh, sh);                   /* j^ = i k x b^ */
+  c2r3(&pl, N, sh, j, tmp);
+  /* Lorentz + advection part: u x w + j x b  (into w), induction e = u x b (into u) */
+  cross_real(n3, u, w, w);
+  cross_real(n3, j, b, j);
+  for (long i = 0; i < 3 * n3; ++i) w[i] += j[i];
+  cross_real(n3, u, b, u);
+  r2c3(&pl, N, w, uh);                      /* F[u x w + j x b] */
+  r2c3(&pl, N, u, bh);                      /* F[u x b]         */
+  dealias_project(N, uh);                   /* D P (.) / N^3    */
+  curl_fields(N, bh, sh);                   /* i k x F[u x b]   */
+  {
+    const double inv = 1.0 / ((double)N * N * N);
+#pragma omp parallel for schedule(static)
+    for (long kz = 0; kz < N; ++kz)
+      for (long ky = 0; ky < N; ++ky)
+        for (long kx = 0; kx < H; ++kx) {
+          long m = (kz * N + ky) * H + kx;
+          long ix = wavx(kx), iy = wav(ky, N), iz = wav(kz, N);
+          long k2 = ix * ix + iy * iy + iz * iz;
+          double d = dealias_keep(k2, N) ? inv : 0.0;
+          double sg = MUT(7) ? -1.0 : 1.0;
+          for (int c = 0; c < 3; ++c) {
+            cplx a = uh[c * nc + m], e = d * sh[c * nc + m];
+            np_[c * nc + m] = a + sg * e;
+            nm[c * nc + m] = a - sg * e;
+          }
+        }
+  }
+  line_plan_free(&pl);
+done:
+  free(uh);
+  free(bh);
+  free(sh);
+  free(tmp);
+  free(u);
+  free(b);
+  free(w);
+  free(j);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Galerkin triad sum: the dealiased quadratic term as the convolution of    */
+/* Fourier coefficients, N(k) = D P sum_{p+q=k} u(p) x (i q x u(q)).  For a  */
+/* dealiased input no alias reaches a kept mode, so this equals the          */
+/* pseudospectral value there.                                               */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+  long K;     /* cube half-width: |k_i| <= K */
+  long side;  /* 2K+1 */
+  cplx *v;    /* [f][kz][ky][kx] over the cube, full spectrum */
+} full_cube;
+
+/* effective full-spectrum coefficient seen by the inverse transform: the kx = 0
+ * and kx = N/2 planes are used through their Hermitian part */
+static cplx eff_coef(int N, const cplx *F, long ix, long iy, long iz) {
+  const long H = N / 2 + 1;
+  long sx = ix < 0 ? -ix : ix;
+  long syi, szi, myi, mzi;
+  if (ix < 0) { iy = -iy; iz = -iz; }
+  syi = (iy % N + N) % N;
+  szi = (iz % N + N) % N;
+  myi = ((-iy) % N + N) % N;
+  mzi = ((-iz) % N + N) % N;
+  cplx a = F[(szi * N + syi) * H + sx];
+  if (sx == 0 || 2 * sx == N) {
+    cplx b = F[(mzi * N + myi) * H + sx];
+    a = 0.5 * (a + conj(b));
+  }
+  return ix < 0 ? conj(a) : a;
+}
+
+static int cube_build(int N, int nf, const cplx *F, full_cube *c) {
+  const long H = N / 2 + 1, nc = (long)N * N * H;
+  long K = 0;
+  for (int f = 0; f < nf; ++f)
+    for (long kz = 0; kz < N; ++kz)
+      for (long ky = 0; ky < N; ++ky)
+        for (long kx = 0; kx < H; ++kx) {
+          cplx a = F[f * nc + (kz * N + ky) * H + kx];
+          if (a != 0) {
+            long m = labs(wav(kz, N));
+            if (labs(wav(ky, N)) > m) m = labs(wav(ky, N));
+            if (kx > m) m = kx;
+            if (m > K) K = m;
+          }
+        }
+  /* content at Nyquist indices is outside the Galerkin set and ignored */
+  if (K > N / 2 - 1) K = N / 2 - 1;
+  c->K = K;
+  c->side = 2 * K + 1;
+  size_t n = (size_t)nf * c->side * c->side * c->side;
+  c->v = (cplx *)calloc(n, sizeof(cplx));
+  if (!c->v) return -3;
+  for (int f = 0; f < nf; ++f)
+    for (long iz = -K; iz <= K; ++iz)
+      for (long iy = -K; iy <= K; ++iy)
+        for (long ix = -K; ix <= K; ++ix)
+          c->v[(((size_t)f * c->side + (iz + K)) * c->side + (iy + K)) * c->side + (ix + K)] =
+              eff_coef(N, F + f * nc, ix, iy, iz);
+  return 0;
+}
+
+static cplx cube_at(const full_cube *c, int f, long ix, long iy, long iz) {
+  if (ix < -c->K || ix > c->K || iy < -c->K || iy > c->K || iz < -c->K || iz > c->K) return 0;
+  return c->v[(((size_t)f * c->side + (iz + c->K)) * c->side + (iy + c->K)) * c->side + (ix + c->K)];
+}
+
+static void cross_c(const cplx a[3], const cplx b[3], cplx o[3]) {
+  o[0] = a[1] * b[2] - a[2] * b[1];
+  o[1] = a[2] * b[0] - a[0] * b[2];
+  o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+/* i q x v with the derivative wavenumber (Nyquist components zero) */
+static void icurl_c(int N, long qx, long qy, long qz, const cplx v[3], cplx o[3]) {
+  double ax = (2 * labs(qx) == N) ? 0.0 : (double)qx;
+  double ay = (2 * labs(qy) == N) ? 0.0 : (double)qy;
+  double az = (2 * labs(qz) == N) ? 0.0 : (double)qz;
+  o[0] = I * (ay * v[2] - az * v[1]);
+  o[1] = I * (az * v[0] - ax * v[2]);
+  o[2] = I * (ax * v[1] - ay * v[0]);
+}
+
+int psref_nonlinear_at(int N, int model, const double *fhat, int nk, const int *kx,
+                       const int *ky, const int *kz, double *out) {
+  if (!fhat || !out || nk < 0 || (nk > 0 && (!kx || !ky || !kz))) return -1;
+  if (model != 0 && model != 1) return -1;
+  if (!size_ok(N)) return -2;
+  for (int i = 0; i < nk; ++i)
+    if (kx[i] < 0 || kx[i] > N / 2 || ky[i] < 0 || ky[i] >= N || kz[i] < 0 || kz[i] >= N)
+      return -1;
+  const int nf = model == 0 ? 3 : 6;
+  full_cube c;
+  if (cube_build(N, nf, (const cplx *)fhat, &c)) return -3;
+  const long K = c.K;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int i = 0; i < nk; ++i) {
+    long ox = kx[i], oy = wav(ky[i], N), oz = wav(kz[i], N);
+    cplx accL[3] = {0, 0, 0}, accE[3] = {0, 0, 0};
+    for (long pz = -K; pz <= K; ++pz)
+      for (long py = -K; py <= K; ++py)
+        for (long px = -K; px <= K; ++px) {
+          long qx = ox - px, qy = oy - py, qz = oz - pz;
+          if (qx < -K || qx > K || qy < -K || qy > K || qz < -K || qz > K) continue;
+          if (model == 0) {
+            cplx up[3], uq[3], wq[3], t[3];
+            for (int f = 0; f < 3; ++f) {
+              up[f] = cube_at(&c, f, px, py, pz);
+              uq[f] = cube_at(&c, f, qx, qy, qz);
+            }
+            if (up[0] == 0 && up[1] == 0 && up[2] == 0) continue;
+            icurl_c(N, qx, qy, qz, uq, wq);
+            cross_c(up, wq, t);
+            for (int f = 0; f < 3; ++f) accL[f] += t[f];
+          } else {
+            cplx up[3], bp[3], uq[3], bq[3], wq[3], jp[3], t1[3], t2[3], t3[3];
+            for (int f = 0; f < 3; ++f) {
+              cplx zpp = cube_at(&c, f, px, py, pz), zmp = cube_at(&c, 3 + f, px, py, pz);
+              cplx zpq = cube_at(&c, f, qx, qy, qz), zmq = cube_at(&c, 3 + f, qx, qy, qz);
+              up[f] = 0.5 * (zpp + zmp);
+              bp[f] = 0.5 * (zpp - zmp);
+              uq[f] = 0.5 * (zpq + zmq);
+              bq[f] = 0.5 * (zpq - zmq);
+            }
+            icurl_c(N, qx, qy, qz, uq, wq);  /* w(q) */
+            icurl_c(N, px, py, pz, bp, jp);  /* j(p) */
+            cross_c(up, wq, t1);             /* u(p) x w(q) */
+            cross_c(jp, bq, t2);             /* j(p) x b(q) */
+            cross_c(up, bq, t3);             /* u(p) x b(q) */
+            for (int f = 0; f < 3; ++f) {
+              accL[f] += t1[f] + t2[f];
+              accE[f] += t3[f];
+            }
+          }
+        }
+    long k2 = ox * ox + oy * oy + oz * oz;
+    cplx res[6] = {0, 0, 0, 0, 0, 0};
+    if (k2 != 0 && dealias_keep(k2, N)) {
+      double ax = (double)ox, ay = (double)oy, az = (double)oz;
+      cplx kv = ax * accL[0] + ay * accL[1] + az * accL[2];
+      cplx pl_[3] = {accL[0] - ax * kv / (double)k2, accL[1] - ay * kv / (double)k2,
+                     accL[2] - az * kv / (double)k2};
+      if (model == 0) {
+        for (int f = 0; f < 3; ++f) res[f] = pl_[f];
+      } else {
+        cplx ce[3];
+        icurl_c(N, ox, oy, oz, accE, ce);
+        for (int f = 0; f < 3; ++f) {
+          res[f] = pl_[f] + ce[f];
+          res[3 + f] = pl_[f] - ce[f];
+        }
+      }
+    }
+    for (int f = 0; f < nf; ++f) {
+      out[2 * ((long)i * nf + f)] = creal(res[f]);
+      out[2 * ((long)i * nf + f) + 1] = cimag(res[f]);
+    }
+  }
+  free(c.v);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Time advance.  The paper's "main time-advance loop" does not name its     */
+/* integrator; the explicit midpoint second-order Runge-Kutta method is used:*/
+/*   z* = z^n + (dt/2) F(z^n),   z^{n+1} = z^n + dt F(z*)                    */
+/* F(u) = N(u) - nu |k|^2 u (NS);  for MHD in Elsasser variables             */
+/* F(z+-) = N+-(z) - (nu+eta)/2 |k|^2 z+- - (nu-eta)/2 |k|^2 z-+.            */
+/* ------------------------------------------------------------------------ */
+
+static int rhs(int N, int model, const cplx *z, cplx *F, double nu, double eta) {
+  const long H = N / 2 + 1, nc = (long)N * N * H;
+  int rc = model == 0 ? psref_nonlinear_ns(N, (const double *)z, (double *)F)
+                      : psref_nonlinear_mhd(N, (const double *)z, (double *)F);
+  if (rc) return rc;
+  const double a = model == 0 ? nu : 0.5 * (nu + eta);
+  const double b = model == 0 ? 0.0 : 0.5 * (nu - eta);
+#pragma omp parallel for schedule(static)
+  for (long kz = 0; kz < N; ++kz)
+    for (long ky = 0; ky < N; ++ky)
+      for (long kx = 0; kx < H; ++kx) {
+        long m = (kz * N + ky) * H + kx;
+        long ix = wavx(kx), iy = wav(ky, N), iz = wav(kz, N);
+        double k2 = (double)(ix * ix + iy * iy + iz * iz);
+        if (model == 0) {
+          for (int c = 0; c < 3; ++c) F[c * nc + m] -= a * k2 * z[c * nc + m];
+        } else {
+          for (int c = 0; c < 3; ++c) {
+            cplx zp = z[c * nc + m], zm = z[(3 + c) * nc + m];
+            F[c * nc + m] -= a * k2 * zp + b * k2 * zm;
+            F[(3 + c) * nc + m] -= a * k2 * zm + b * k2 * zp;
+          }
+        }
+      }
+  return 0;
+}
+
+int psref_rk2_step(int N, int model, double *state_, double nu, double eta, double dt,
+                   int nsteps) {
+  if (!state_ || nsteps < 0 || (model != 0 && model != 1)) return -1;
+  if (!size_ok(N)) return -2;
+  const long nf = model == 0 ? 3 : 6;
+  const long n = nf * (long)N * N * (N / 2 + 1);
+  cplx *z = (cplx *)state_;
+  cplx *zs = (cplx *)malloc(sizeof(cplx) * (size_t)n);
+  cplx *F = (cplx *)malloc(sizeof(cplx) * (size_t)n);
+  int rc = 0;
+  if (!zs || !F) {
+    rc = -3;
+    goto done;
+  }
+  for (int s = 0; s < nsteps; ++s) {
+    if ((rc = rhs(N, model, z, F, nu, eta))) goto done;
+#pragma omp parallel for schedule(static)
+    for (long m = 0; m < n; ++m) zs[m] = z[m] + (MUT(11) ? 1.0 : 0.5) * dt * F[m];
+    if ((rc = rhs(N, model, MUT(5) ? z : zs, F, nu, eta))) goto done;
+#pragma omp parallel for schedule(static)
+    for (long m = 0; m < n; ++m) z[m] = z[m] + dt * F[m];
+  }
+done:
+  free(zs);
+  free(F);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Global quantities and spectra (Sec. 3: reductions over the grid).         */
+/* FP64 with Neumaier-compensated summation, in a fixed order.               */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+  double s, c;
+} nsum;
+
+static void nadd(nsum *a, double x) {
+  double t = a->s + x;
+  if (fabs(a->s) >= fabs(x))
+    a->c += (a->s - t) + x;
+  else
+    a->c += (x - t) + a->s;
+  a->s = t;
+}
+
+static double nval(const nsum *a) { return a->s + a->c; }
+
+/* smallest s >= 0 with 4 k2 < (2s+1)^2, i.e. |k| rounded to nearest */
+static long shell_of(long k2) {
+  long s = (long)floor(sqrt((double)k2));
+  if (MUT(12)) return s;
+  while (s > 0 && 4 * k2 < (2 * s - 1) * (2 * s - 1)) --s;
+  while (4 * k2 >= (2 * s + 1) * (2 * s + 1)) ++s;
+  return s;
+}
+
+int psref_num_shells(int N) {
+  if (!size_ok(N)) return -2;
+  long h = N / 2;
+  return (int)shell_of(3 * h * h) + 1;
+}
+
+int psref_energy_spectrum(int N, int nf, const double *fhat_, double *spec, double *totals) {
+  if (!fhat_ || !spec || !totals || nf < 1) return -1;
+  if (!size_ok(N)) return -2;
+  const long H = N / 2 + 1, nc = (long)N * N * H;
+  const int ns = psref_num_shells(N);
+  const cplx *F = (const cplx *)fhat_;
+  nsum *es = (nsum *)calloc((size_t)ns, sizeof(nsum));
+  if (!es) return -3;
+  nsum Z = {0, 0};
+  double maxdiv = 0;
+  for (long kz = 0; kz < N; ++kz)
+    for (long ky = 0; ky < N; ++ky)
+      for (long kx = 0; kx < H; ++kx) {
+        long m = (kz * N + ky) * H + kx;
+        long ix = wavx(kx), iy = wav(ky, N), iz = wav(kz, N);
+        long k2 = ix * ix + iy * iy + iz * iz;
+        double w = (kx == 0 || 2 * kx == N) ? 1.0 : 2.0;
+        if (MUT(4) && 2 * kx == N) w = 2.0;
+        double e = 0;
+        for (int f = 0; f < nf; ++f) {
+          cplx a = F[f * nc + m];
+          e += creal(a) * creal(a) + cimag(a) * cimag(a);
+        }
+        long s = shell_of(k2);
+        nadd(&es[s], 0.5 * w * e);
+        nadd(&Z, 0.5 * w * (double)k2 * e);
+        for (int f = 0; f + 2 < nf; f += 3) {
+          double ax = (double)dwavx(kx, N), ay = (double)dwav(ky, N), az = (double)dwav(kz, N);
+          cplx d = ax * F[f * nc + m] + ay * F[(f + 1) * nc + m] + az * F[(f + 2) * nc + m];
+          if (cabs(d) > maxdiv) maxdiv = cabs(d);
+        }
+      }
+  nsum E = {0, 0};
+  for (int s = 0; s < ns; ++s) {
+    spec[s] = nval(&es[s]);
+    nadd(&E, spec[s]);
+  }
+  totals[0] = nval(&E);
+  totals[1] = nval(&Z);
+  totals[2] = maxdiv;
+  free(es);
+  return 0;
+}

@@ -1,0 +1,91 @@
+/*
+ * psref.h -- FP64 CPU oracle for the pseudospectral Navier-Stokes / MHD step.
+ *
+ * TEST INFRASTRUCTURE. Only the test suite, the package smoke check and the
+ * CPU-baseline leg of the benchmark may load or call this library. The GPU
+ * library never links, includes or calls it, and it shares no code with the
+ * GPU library (no headers, tables or helpers).
+ *
+ * Source of every definition: Mininni, Rosenberg, Reddy & Pouquet, "A hybrid
+ * MPI-OpenMP scheme for scalable parallel pseudospectral computations for
+ * fluid turbulence", Sec. 2 (Eq. 1-2, the Fourier-Galerkin method, the
+ * Hermitian half-spectrum storage of Fig. 1), Sec. 3 (loop-level threading
+ * and reductions for spectra).  Where the paper defers to its references
+ * (projection, dealiasing, the time integrator), the textbook reading is used
+ * and stated at each function.
+ *
+ * Conventions (all arrays dense, C order):
+ *   real fields      [f][z][y][x]            double,   x fastest, N^3 per field
+ *   spectral fields  [f][kz][ky][kx]         complex double (re,im interleaved),
+ *                                            kx = 0..N/2 fastest, N*N*(N/2+1) per field
+ *   ky, kz index i   -> wavenumber i for i < N/2, i - N otherwise (N/2 -> -N/2)
+ *   derivative wavenumber (odd derivatives): 0 at the Nyquist index N/2
+ *   grid points      x_j = 2*pi*j/N on [0, 2*pi)
+ *
+ * All functions return 0 on success and a negative code on bad arguments
+ * (-1 null pointer / bad enum, -2 unsupported size, -3 out of memory).
+ */
+#ifndef PSREF_H
+#define PSREF_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Number of OpenMP threads the oracle uses (<= 0: leave the runtime default).
+ * Returns the number of threads that will be used. */
+int psref_set_threads(int n);
+
+/* Unnormalised forward 3D transform X(k) = sum_x u(x) exp(-i k.x) of nf real
+ * fields, stored for kx = 0..N/2.  N even, 2 <= N <= 4096. */
+int psref_fft_r2c(int N, int nf, const double *in, double *out);
+
+/* Unnormalised inverse 3D transform of nf half spectra, in pass order:
+ * inverse complex transforms along z then y on every kx plane, then
+ * u(x) = Re Y_0 + 2 sum_{0<kx<N/2} Re(Y_kx e^{i kx x}) + Re Y_{N/2} (-1)^x.
+ * The imaginary parts of the kx = 0 and kx = N/2 bins are ignored. */
+int psref_fft_c2r(int N, int nf, const double *in, double *out);
+
+/* Direct O(N^3)-per-bin sum of the forward transform at nk selected bins
+ * (kx[i], ky[i], kz[i] are storage indices). out: nk complex values. */
+int psref_dft_at(int N, const double *in, int nk, const int *kx, const int *ky,
+                 const int *kz, double *out);
+
+/* Spectral curl  w = i k_d x u  of one 3-component spectral vector. */
+int psref_curl(int N, const double *uhat, double *what);
+
+/* Dealiased, projected nonlinear term of incompressible Navier-Stokes in
+ * rotational form, nhat = D P F[u x w] / N^3 (3 fields in, 3 out). */
+int psref_nonlinear_ns(int N, const double *uhat, double *nhat);
+
+/* MHD nonlinear terms for the Elsasser state (z+ = u + b, z- = u - b):
+ * N+- = D [ P F[u x w + j x b] +- i k_d x F[u x b] ] / N^3
+ * (6 fields in: z+ then z-; 6 out: N+ then N-). */
+int psref_nonlinear_mhd(int N, const double *zhat, double *nhat);
+
+/* Galerkin (direct triad sum) value of the same nonlinear terms at nk
+ * selected storage indices.  model 0 = NS (uhat: 3 fields), 1 = MHD (6).
+ * out: nk x (3 or 6) complex values, component-major per mode. */
+int psref_nonlinear_at(int N, int model, const double *fhat, int nk,
+                       const int *kx, const int *ky, const int *kz, double *out);
+
+/* Explicit midpoint RK2 steps, in place.  model 0 = NS (3 fields, viscosity
+ * nu), 1 = MHD Elsasser (6 fields, viscosity nu, resistivity eta). */
+int psref_rk2_step(int N, int model, double *state, double nu, double eta,
+                   double dt, int nsteps);
+
+/* Number of spectral shells: s(3 (N/2)^2) + 1. */
+int psref_num_shells(int N);
+
+/* Shell energy spectrum E(s) = 1/2 sum_{shell(k)=s} w |f(k)|^2 over nf
+ * fields, w = 1 on the kx = 0 and kx = N/2 planes, 2 elsewhere, and the
+ * totals [E, Z, maxdiv] with Z = 1/2 sum w |k|^2 |f|^2 and maxdiv the largest
+ * |k_d . f| over consecutive component triples (0 if nf is not a multiple of
+ * 3).  shell(k) = round(|k|) evaluated exactly in integers. */
+int psref_energy_spectrum(int N, int nf, const double *fhat, double *spec,
+                          double *totals);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

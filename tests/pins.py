@@ -1,0 +1,461 @@
+"""Pins for the FP64 oracle: checks against what the mathematics fixes.
+
+Every function here takes an oracle instance and raises AssertionError when
+the oracle disagrees with a definition written out directly (a literal DFT
+sum, a literal triad sum), a closed form (ABC and Taylor-Green flows, a single
+Fourier mode), an invariant (energy, helicity and Elsasser-energy
+conservation of the dealiased quadratic term, solenoidality), a library
+special case (numpy's real FFT) or a convergence order.  The same functions
+run against deliberately broken builds of the oracle in the mutation tests,
+which check that every planted mistake trips at least one pin.
+
+The paper prints no worked numerical example, so no pin quotes a number from
+it; each pin names the passage whose mathematics it checks.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from oracle.psref import MHD, NS
+from paper_1003_4322_amd import synth
+
+TWO_PI = 2.0 * math.pi
+
+
+def _rel(a, b) -> float:
+    a = np.asarray(a)
+    b = np.asarray(b)
+    den = max(np.linalg.norm(b.ravel()), 1e-300)
+    return float(np.linalg.norm((a - b).ravel()) / den)
+
+
+def _hweights(N: int) -> np.ndarray:
+    w = np.full(N // 2 + 1, 2.0)
+    w[0] = 1.0
+    w[-1] = 1.0
+    return w
+
+
+def _wavenumbers(N: int):
+    """Signed wavenumber grids (KZ, KY, KX) over the half-spectrum storage."""
+    k = np.where(np.arange(N) < N // 2, np.arange(N), np.arange(N) - N)
+    return np.meshgrid(k, k, np.arange(N // 2 + 1), indexing="ij")
+
+
+def _grid(N: int):
+    x = TWO_PI * np.arange(N) / N
+    return np.meshgrid(x, x, x, indexing="ij")  # Z, Y, X
+
+
+def _random_half(rng, nf, N):
+    s = (nf, N, N, N // 2 + 1)
+    return rng.standard_normal(s) + 1j * rng.standard_normal(s)
+
+
+# ---------------------------------------------------------------------------
+# Transforms (Sec. 2: FFT of real N^3 data into an (N/2+1) x N x N half
+# spectrum, Fig. 1).
+# ---------------------------------------------------------------------------
+
+def brute_r2c(u: np.ndarray) -> np.ndarray:
+    """X(k) = sum_x u(x) exp(-i k.x), literally: every k against every x."""
+    N = u.shape[-1]
+    H = N // 2 + 1
+    kz, ky, kx = np.meshgrid(np.arange(N), np.arange(N), np.arange(H), indexing="ij")
+    z, y, x = np.meshgrid(np.arange(N), np.arange(N), np.arange(N), indexing="ij")
+    e = (np.outer(kx.ravel(), x.ravel()) + np.outer(ky.ravel(), y.ravel())
+         + np.outer(kz.ravel(), z.ravel())) % N
+    ph = np.exp(-1j * TWO_PI * e / N)
+    return (ph @ u.ravel()).reshape(N, N, H)
+
+
+def brute_c2r(X: np.ndarray) -> np.ndarray:
+    """The inverse in pass order: inverse sums along z and y on every kx plane,
+    then u = Re Y_0 + 2 sum_{0<k<N/2} Re(Y_k e^{ikx}) + Re Y_{N/2} (-1)^x."""
+    N = X.shape[0]
+    j = np.arange(N)
+    Einv = np.exp(1j * TWO_PI * (np.outer(j, j) % N) / N)  # [x, k]
+    Y = np.einsum("zc,cbk->zbk", Einv, X)   # along kz
+    Y = np.einsum("yb,zbk->zyk", Einv, Y)   # along ky
+    u = np.real(Y[..., 0])[..., None] * np.ones(N)
+    for k in range(1, N // 2):
+        u = u + 2.0 * np.real(Y[..., k][..., None] * np.exp(1j * TWO_PI * k * j / N))
+    u = u + np.real(Y[..., N // 2])[..., None] * ((-1.0) ** j)
+    return u
+
+
+def pin_fft_brute(o):
+    rng = np.random.default_rng(11)
+    for N in (6, 8, 12):
+        u = rng.standard_normal((N, N, N))
+        got = o.fft_r2c(u)
+        ref = brute_r2c(u)
+        assert _rel(got, ref) < 1e-13, (N, _rel(got, ref))
+        X = _random_half(rng, 1, N)[0]  # not Hermitian on the kx=0, N/2 planes
+        got = o.fft_c2r(X)
+        ref = brute_c2r(X)
+        assert _rel(got, ref) < 1e-13, (N, _rel(got, ref))
+
+
+def pin_fft_numpy(o):
+    """numpy's rfftn/irfftn use the same sign, storage and pass conventions."""
+    rng = np.random.default_rng(12)
+    for N in (16, 24, 18):
+        u = rng.standard_normal((2, N, N, N))
+        assert _rel(o.fft_r2c(u), np.fft.rfftn(u, axes=(1, 2, 3))) < 1e-13
+        X = _random_half(rng, 2, N)
+        ref = np.fft.irfftn(X, s=(N, N, N), axes=(1, 2, 3)) * N ** 3
+        assert _rel(o.fft_c2r(X), ref) < 1e-13
+
+
+def pin_fft_parseval_roundtrip(o):
+    rng = np.random.default_rng(13)
+    N = 16
+    u = rng.standard_normal((N, N, N))
+    X = o.fft_r2c(u)
+    lhs = np.sum(u * u)
+    rhs = np.sum(_hweights(N) * np.abs(X) ** 2) / N ** 3
+    assert abs(lhs - rhs) / lhs < 1e-13
+    assert _rel(o.fft_c2r(X), N ** 3 * u) < 1e-13
+
+
+def pin_fft_single_mode(o):
+    N = 16
+    Z, Y, X = _grid(N)
+    k = (3, -5, 2)  # (kx, ky, kz)
+    u = np.cos(k[0] * X + k[1] * Y + k[2] * Z + 0.7)
+    F = o.fft_r2c(u)
+    expect = np.zeros_like(F)
+    expect[k[2] % N, k[1] % N, k[0]] = 0.5 * N ** 3 * np.exp(1j * 0.7)
+    assert np.abs(F - expect).max() < 1e-10 * N ** 3
+
+
+def pin_dft_at(o):
+    rng = np.random.default_rng(14)
+    N = 8
+    u = rng.standard_normal((N, N, N))
+    ref = brute_r2c(u)
+    kx = np.array([0, 1, 4, 3]); ky = np.array([0, 7, 4, 2]); kz = np.array([5, 0, 4, 6])
+    got = o.dft_at(u, kx, ky, kz)
+    assert np.abs(got - ref[kz, ky, kx]).max() < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Spectral curl (derivatives of the Fourier expansion, Sec. 2)
+# ---------------------------------------------------------------------------
+
+def pin_curl_abc(o):
+    """ABC flows are Beltrami fields: curl u = k u at wavenumber k."""
+    N = 16
+    for k in (1, 3):
+        u = synth.abc_flow(N, 1.0, 0.7, 0.4, k=k)
+        assert np.abs(o.curl(u) - k * u).max() < 1e-14
+
+
+def pin_curl_single_modes(o):
+    """u = a cos(k.x + phi) differentiates exactly; checked on the grid."""
+    N = 16
+    Z, Y, X = _grid(N)
+    rng = np.random.default_rng(15)
+    for _ in range(4):
+        k = rng.integers(-7, 8, size=3)
+        a = rng.standard_normal(3)
+        ph = rng.uniform(0, TWO_PI)
+        arg = k[0] * X + k[1] * Y + k[2] * Z + ph
+        u = np.stack([a[c] * np.cos(arg) for c in range(3)])
+        uhat = np.fft.rfftn(u, axes=(1, 2, 3)) / N ** 3
+        w = np.fft.irfftn(o.curl(uhat), s=(N, N, N), axes=(1, 2, 3)) * N ** 3
+        s = -np.sin(arg)  # d/dx_j cos(k.x+ph) = -k_j sin(.)
+        ex = np.stack([(k[1] * a[2] - k[2] * a[1]) * s, (k[2] * a[0] - k[0] * a[2]) * s,
+                       (k[0] * a[1] - k[1] * a[0]) * s])
+        assert np.abs(w - ex).max() < 1e-12, (k, np.abs(w - ex).max())
+
+
+def pin_curl_nyquist(o):
+    """cos(N y / 2) is (-1)^j on the grid, where its derivative vanishes:
+    the spectral derivative of the Nyquist mode must be zero there."""
+    N = 12
+    Z, Y, X = _grid(N)
+    u = np.stack([np.cos(N // 2 * Y) * np.cos(X), np.zeros_like(X), np.cos(N // 2 * Z) * np.sin(2 * X)])
+    uhat = np.fft.rfftn(u, axes=(1, 2, 3)) / N ** 3
+    w = np.fft.irfftn(o.curl(uhat), s=(N, N, N), axes=(1, 2, 3)) * N ** 3
+    ex = np.stack([np.zeros_like(X), -2 * np.cos(N // 2 * Z) * np.cos(2 * X),
+                   np.zeros_like(X)])  # only d/dx of the second term survives
+    assert np.abs(w - ex).max() < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Nonlinear term (Eq. 1-2 in rotational form, projected and dealiased)
+# ---------------------------------------------------------------------------
+
+def _effective_full(F: np.ndarray):
+    """All modes of the full spectrum with |k_i| < N/2 as seen by the inverse
+    transform (Hermitian part of the kx = 0 plane): returns (K [M,3], V [nf,M])."""
+    nf, N = F.shape[0], F.shape[1]
+    ks, vals = [], []
+    for kz in range(-(N // 2) + 1, N // 2):
+        for ky in range(-(N // 2) + 1, N // 2):
+            for kx in range(-(N // 2) + 1, N // 2):
+                sx, sy, sz = (kx, ky, kz) if kx >= 0 else (-kx, -ky, -kz)
+                a = F[:, sz % N, sy % N, sx]
+                if sx == 0:
+                    a = 0.5 * (a + np.conj(F[:, (-sz) % N, (-sy) % N, 0]))
+                if kx < 0:
+                    a = np.conj(a)
+                if np.any(a != 0):
+                    ks.append((kx, ky, kz))
+                    vals.append(a)
+    return np.array(ks, dtype=np.int64).reshape(-1, 3), np.array(vals).T.reshape(nf, -1)
+
+
+def _kept_outputs(N):
+    out = []
+    for kz in range(N):
+        for ky in range(N):
+            for kx in range(N // 2 + 1):
+                k = np.array([kx, ky if ky < N // 2 else ky - N, kz if kz < N // 2 else kz - N])
+                k2 = int(k @ k)
+                if k2 > 0 and 9 * k2 < N * N:
+                    out.append(((kz, ky, kx), k))
+    return out
+
+
+def brute_triads(F: np.ndarray, model: int) -> np.ndarray:
+    """Dealiased, projected quadratic term as a literal sum over triads
+    p + q = k of Fourier coefficients (Galerkin convolution)."""
+    N = F.shape[1]
+    K, V = _effective_full(F)
+    index = {tuple(k): i for i, k in enumerate(K)}
+    out = np.zeros(F.shape, np.complex128)
+    if model == NS:
+        U = V
+    else:
+        U = 0.5 * (V[:3] + V[3:])
+        B = 0.5 * (V[:3] - V[3:])
+
+    def icross(k, v):  # i k x v, k [M,3], v [3,M]
+        return 1j * np.stack([k[:, 1] * v[2] - k[:, 2] * v[1], k[:, 2] * v[0] - k[:, 0] * v[2],
+                              k[:, 0] * v[1] - k[:, 1] * v[0]])
+
+    def cross(a, b):
+        return np.stack([a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2],
+                         a[0] * b[1] - a[1] * b[0]])
+
+    for (sz, sy, sx), k in _kept_outputs(N):
+        q = k[None, :] - K
+        qi = np.array([index.get(tuple(x), -1) for x in q])
+        m = qi >= 0
+        if not np.any(m):
+            continue
+        p_idx = np.nonzero(m)[0]
+        qq = q[m]
+        q_idx = qi[m]
+        if model == NS:
+            aL = cross(U[:, p_idx], icross(qq, U[:, q_idx])).sum(axis=1)
+        else:
+            aL = (cross(U[:, p_idx], icross(qq, U[:, q_idx]))
+                  + cross(icross(K[p_idx], B[:, p_idx]), B[:, q_idx])).sum(axis=1)
+            aE = cross(U[:, p_idx], B[:, q_idx]).sum(axis=1)
+        k2 = float(k @ k)
+        proj = aL - k * (k @ aL) / k2
+        if model == NS:
+            out[:, sz, sy, sx] = proj
+        else:
+            ce = icross(k[None, :], aE[:, None])[:, 0]
+            out[:3, sz, sy, sx] = proj + ce
+            out[3:, sz, sy, sx] = proj - ce
+    return out
+
+
+def pin_ns_abc_zero(o):
+    N = 16
+    u = synth.abc_flow(N, 1.0, 0.8, 0.6)
+    assert np.abs(o.nonlinear_ns(u)).max() < 1e-14
+
+
+def pin_ns_taylor_green(o):
+    """For u = (sin x cos y cos z, -cos x sin y cos z, 0):
+    P(u x w) = -1/8 (sin 2x cos 2z, sin 2y cos 2z, -(cos 2x + cos 2y) sin 2z)."""
+    for N in (16, 32):
+        n = o.nonlinear_ns(synth.taylor_green(N))
+        Z, Y, X = _grid(N)
+        ex = -0.125 * np.stack([np.sin(2 * X) * np.cos(2 * Z), np.sin(2 * Y) * np.cos(2 * Z),
+                                -(np.cos(2 * X) + np.cos(2 * Y)) * np.sin(2 * Z)])
+        got = np.fft.irfftn(n, s=(N, N, N), axes=(1, 2, 3)) * N ** 3
+        assert np.abs(got - ex).max() < 1e-14, np.abs(got - ex).max()
+
+
+def _inner(a, b, N):
+    return float(np.sum(_hweights(N) * np.real(np.conj(a) * b)))
+
+
+def pin_ns_invariants(o):
+    """Energy and helicity are conserved by the dealiased term; k.N = 0."""
+    N = 24
+    u = synth.random_ns(N, 7, 3.0)
+    n = o.nonlinear_ns(u)
+    w = o.curl(u)
+    nn = math.sqrt(_inner(n, n, N))
+    assert abs(_inner(u, n, N)) / (math.sqrt(_inner(u, u, N)) * nn) < 1e-14
+    assert abs(_inner(w, n, N)) / (math.sqrt(_inner(w, w, N)) * nn) < 1e-14
+    KZ, KY, KX = _wavenumbers(N)
+    div = KX * n[0] + KY * n[1] + KZ * n[2]
+    assert np.abs(div).max() < 1e-14 * np.abs(n).max() * N
+
+
+def pin_ns_triad_brute(o):
+    N = 12
+    u = synth.random_ns(N, 5, 2.0)
+    ref = brute_triads(u, NS)
+    assert _rel(o.nonlinear_ns(u), ref) < 1e-13
+
+
+def pin_mhd_equal_fields(o):
+    """u = b (z- = 0): u x w + j x b = 0 and u x b = 0 pointwise."""
+    N = 16
+    u = synth.random_ns(N, 21, 2.5)
+    z = np.concatenate([2 * u, np.zeros_like(u)])
+    assert np.abs(o.nonlinear_mhd(z)).max() < 1e-14 * np.abs(z).max()
+
+
+def pin_mhd_reduces_to_ns(o):
+    N = 16
+    u = synth.random_ns(N, 22, 2.5)
+    nm = o.nonlinear_mhd(np.concatenate([u, u]))
+    ns = o.nonlinear_ns(u)
+    assert _rel(nm[:3], ns) < 1e-14 and _rel(nm[3:], ns) < 1e-14
+
+
+def pin_mhd_invariants(o):
+    """Elsasser energies are conserved separately: sum Re(z+-* . N+-) = 0."""
+    N = 24
+    z = synth.random_mhd(N, 3, 4, 3.0)
+    n = o.nonlinear_mhd(z)
+    for s in (0, 3):
+        a, b = z[s:s + 3], n[s:s + 3]
+        assert abs(_inner(a, b, N)) / math.sqrt(_inner(a, a, N) * _inner(b, b, N)) < 1e-14
+
+
+def pin_mhd_triad_brute(o):
+    N = 12
+    z = synth.random_mhd(N, 31, 32, 2.0)
+    ref = brute_triads(z, MHD)
+    assert _rel(o.nonlinear_mhd(z), ref) < 1e-13
+
+
+def pin_nonlinear_at(o):
+    """The oracle's triad-sum entry agrees with the literal triad sum."""
+    N = 12
+    for model, f in ((NS, synth.random_ns(N, 41, 2.0)), (MHD, synth.random_mhd(N, 42, 43, 2.0))):
+        ref = brute_triads(f, model)
+        kz = np.array([1, 0, 11, 3]); ky = np.array([2, 1, 10, 0]); kx = np.array([0, 3, 1, 2])
+        got = o.nonlinear_at(f, model, kx, ky, kz)
+        assert np.abs(got.T - ref[:, kz, ky, kx]).max() < 1e-13 * np.abs(ref).max()
+
+
+# ---------------------------------------------------------------------------
+# Time advance (the main time-advance loop, Sec. 4; explicit midpoint RK2)
+# ---------------------------------------------------------------------------
+
+def pin_rk2_abc_decay(o):
+    """ABC has zero nonlinear term, so each step multiplies it by the RK2
+    stability polynomial R(-a) = 1 - a + a^2/2, a = nu |k|^2 dt."""
+    N = 16
+    nu, dt, k = 0.1, 0.1, 2
+    u = synth.abc_flow(N, 1.0, 0.9, 0.5, k=k)
+    got = o.rk2_step(u, NS, nu, 0.0, dt, 3)
+    a = nu * k * k * dt
+    assert _rel(got, (1 - a + 0.5 * a * a) ** 3 * u) < 1e-14
+
+
+def pin_rk2_taylor_green_energy(o):
+    """E(t) = 1/8 - (3/4) nu t + (9/4) nu^2 t^2 + O(t^3) for Taylor-Green:
+    E0 = 1/8, Z0 = 3/8, P0 = 9/8 and the t = 0 nonlinear term lives on modes
+    absent from u."""
+    N = 16
+    nu, dt, n = 0.05, 2e-4, 10
+    u = o.rk2_step(synth.taylor_green(N), NS, nu, 0.0, dt, n)
+    _, tot = o.energy_spectrum(u)
+    t = n * dt
+    second = (tot[0] - (0.125 - 0.75 * nu * t)) / (2.25 * nu * nu * t * t)
+    assert abs(second - 1.0) < 0.05, second
+
+
+def pin_rk2_second_order(o):
+    N = 16
+    nu, T = 0.02, 0.2
+    u0 = synth.random_ns(N, 3, 2.0)
+    ref = o.rk2_step(u0, NS, nu, 0.0, T / 64, 64)
+    errs = [_rel(o.rk2_step(u0, NS, nu, 0.0, T / m, m), ref) for m in (4, 8, 16)]
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 3.4 < r1 < 4.6 and 3.4 < r2 < 4.6, errs
+
+
+def pin_rk2_mhd_second_order(o):
+    N = 12
+    T = 0.2
+    z0 = synth.random_mhd(N, 5, 6, 2.0)
+    ref = o.rk2_step(z0, MHD, 0.02, 0.01, T / 64, 64)
+    errs = [_rel(o.rk2_step(z0, MHD, 0.02, 0.01, T / m, m), ref) for m in (4, 8, 16)]
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 3.4 < r1 < 4.6 and 3.4 < r2 < 4.6, errs
+
+
+def pin_rk2_divergence_free(o):
+    N = 16
+    u = o.rk2_step(synth.random_ns(N, 9, 2.0), NS, 0.01, 0.0, 0.01, 5)
+    KZ, KY, KX = _wavenumbers(N)
+    div = KX * u[0] + KY * u[1] + KZ * u[2]
+    kk = np.sqrt(KX ** 2 + KY ** 2 + KZ ** 2)
+    assert np.abs(div).max() < 1e-14 * np.max(kk * np.abs(u).max(axis=0))
+
+
+# ---------------------------------------------------------------------------
+# Spectra and global quantities (Sec. 3: reductions)
+# ---------------------------------------------------------------------------
+
+def pin_spectrum_brute(o):
+    """Shell energies by a plain loop: shell = round(|k|), weight 1 on the
+    kx = 0 and kx = N/2 planes, 2 elsewhere."""
+    N = 8
+    rng = np.random.default_rng(16)
+    F = _random_half(rng, 3, N)
+    ns = o.num_shells(N)
+    spec = np.zeros(ns)
+    Z = 0.0
+    maxdiv = 0.0
+    for kz in range(N):
+        for ky in range(N):
+            for kx in range(N // 2 + 1):
+                k = (kx, ky if ky < N // 2 else ky - N, kz if kz < N // 2 else kz - N)
+                k2 = k[0] ** 2 + k[1] ** 2 + k[2] ** 2
+                s = 0
+                while not (4 * k2 < (2 * s + 1) ** 2):
+                    s += 1
+                w = 1.0 if kx in (0, N // 2) else 2.0
+                e = sum(abs(F[c, kz, ky, kx]) ** 2 for c in range(3))
+                spec[s] += 0.5 * w * e
+                Z += 0.5 * w * k2 * e
+                kd = [0 if 2 * abs(v) == N else v for v in k]
+                maxdiv = max(maxdiv, abs(sum(kd[c] * F[c, kz, ky, kx] for c in range(3))))
+    got, tot = o.energy_spectrum(F)
+    assert ns == int(math.floor(math.sqrt(3 * (N // 2) ** 2) + 0.5)) + 1
+    assert _rel(got, spec) < 1e-14
+    assert abs(tot[0] - spec.sum()) < 1e-13 * spec.sum()
+    assert abs(tot[1] - Z) < 1e-13 * Z
+    assert abs(tot[2] - maxdiv) < 1e-13 * maxdiv
+
+
+def pin_spectrum_generator_shape(o):
+    """The generator's field has exactly its target shell energies."""
+    N = 32
+    u = synth.random_ns(N, 1, 2.0)
+    spec, tot = o.energy_spectrum(u)
+    tgt = synth.target_spectrum(N, 2.0)
+    assert np.abs(spec - tgt).max() < 1e-14
+    assert abs(tot[0] - 0.5) < 1e-14
+
+
+ALL_PINS = [v for k, v in sorted(globals().items()) if k.startswith("pin_")]
