@@ -1,0 +1,157 @@
+/*
+ * ps.h -- C ABI of libps.so, the gfx950 (MI355X) pseudospectral hot path.
+ *
+ * What it computes (Mininni, Rosenberg, Reddy & Pouquet, "A hybrid MPI-OpenMP
+ * scheme for scalable parallel pseudospectral computations for fluid
+ * turbulence"):
+ *   - Sec. 2, Eq. 1-2: incompressible Navier-Stokes  du/dt + u.grad u =
+ *     -grad p + nu lap u,  div u = 0, in a 2 pi-periodic box, discretised by
+ *     a truncated Fourier (Galerkin) expansion with the nonlinear term
+ *     evaluated in physical space through FFTs, projected onto
+ *     divergence-free fields and dealiased;
+ *   - Sec. 5: the same code with a magnetic field (MHD), here in Elsasser
+ *     variables z+- = u +- b;
+ *   - Sec. 2 / Fig. 1: real-to-complex 3D transforms stored as half spectra
+ *     of (N/2+1) x N x N complex values;
+ *   - Sec. 3: global quantities and spectra computed by reductions;
+ *   - Sec. 4: the main time-advance loop (its integrator is not named in the
+ *     paper; this library uses explicit midpoint RK2).
+ *
+ * Layouts (all dense, C order, element = float/double or its complex pair):
+ *   real field set     [box][f][z][y][x]        x fastest, N^3 reals per field
+ *   spectral field set [box][f][kz][ky][kx]     kx = 0..N/2 fastest, complex
+ *                      interleaved (re, im), N*N*(N/2+1) per field; identical
+ *                      to numpy/torch rfftn of a [z][y][x] array.
+ *   ky, kz index i <-> wavenumber i (i < N/2) or i - N (i >= N/2).
+ *   Spectral coefficients of the solver state are normalised:
+ *   u(x) = sum_k u_k exp(i k.x).  ps_fft_* are unnormalised.
+ *
+ * Ownership: every field pointer and the workspace are DEVICE memory owned by
+ * the caller.  The plan owns only its twiddle tables, schedule, private
+ * capture stream and cached graph, released by ps_plan_destroy.  After
+ * ps_plan_create no call allocates device memory.
+ *
+ * Execution: calls are asynchronous on the plan's stream (ps_plan_set_stream;
+ * default: the null stream).  Outputs are valid after the caller synchronises
+ * that stream.  A plan is not thread-safe; distinct plans are independent.
+ *
+ * Errors: every call validates its arguments before launching anything and
+ * returns a ps_status; nothing aborts, exits or throws across the ABI.
+ * ps_last_error() gives the detail text of the calling thread's last failure.
+ * Device pointers are checked to be device memory large enough for the
+ * shape (PS_ERR_ARG otherwise).
+ */
+#ifndef PS_H
+#define PS_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ps_plan_s *ps_plan;
+
+typedef enum { PS_F32 = 0, PS_F64 = 1 } ps_dtype;
+typedef enum { PS_NS = 0, PS_MHD = 1 } ps_model;
+typedef enum {
+  PS_OK = 0,
+  PS_ERR_ARG = -1,      /* null/invalid argument, host pointer, buffer too small */
+  PS_ERR_SIZE = -2,     /* unsupported grid size or field count */
+  PS_ERR_NOMEM = -3,    /* host or table allocation failed, workspace too small */
+  PS_ERR_HIP = -4,      /* a HIP runtime call failed (detail in ps_last_error) */
+  PS_ERR_STATE = -5,    /* call not valid in the plan's state (e.g. no workspace) */
+  PS_ERR_DIVERGED = -6  /* reserved: non-finite energy detected */
+} ps_status;
+
+/* Plan for one N^3 box of nfields fields (3: NS velocity; 6: MHD z+, z-).
+ * N must be one of 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512,
+ * 768, 1024 (even, 2^a 3^b).  Builds FP64-accurate twiddle tables on the
+ * device of the current HIP device.  *out is set to NULL on failure. */
+ps_status ps_plan_create(ps_plan *out, int N, int nfields, ps_dtype dtype);
+
+/* Plan for an ensemble of nbox independent boxes of sizes N[0..nbox), all
+ * with nfields fields; field sets are concatenated box after box. */
+ps_status ps_plan_create_batch(ps_plan *out, int nbox, const int *N, int nfields,
+                               ps_dtype dtype);
+
+/* Releases the plan (not the caller's buffers).  NULL is a no-op. */
+ps_status ps_plan_destroy(ps_plan p);
+
+/* Stream (a hipStream_t passed as void*) on which all later calls enqueue
+ * work.  NULL selects the null stream. */
+ps_status ps_plan_set_stream(ps_plan p, void *stream);
+
+/* Bytes of device workspace the plan needs (ensemble: all boxes). */
+size_t ps_plan_workspace_bytes(ps_plan p);
+
+/* Hands the plan a caller-owned device workspace of at least
+ * ps_plan_workspace_bytes(p) bytes, 256-byte aligned. */
+ps_status ps_plan_set_workspace(ps_plan p, void *dev, size_t bytes);
+
+/* Element offsets of box `box` inside the concatenated real (in reals) and
+ * spectral (in complex values) field sets. */
+ps_status ps_plan_box_offsets(ps_plan p, int box, size_t *real_off, size_t *cplx_off);
+
+/* Number of spectral shells of box `box`: s(3 (N/2)^2) + 1 with
+ * s(k2) = round(sqrt(k2)); 444 at N = 512, 888 at N = 1024; < 0 on error. */
+int ps_num_shells(ps_plan p, int box);
+
+/* Unnormalised forward transform X(k) = sum_x u(x) exp(-i k.x) of every
+ * field of every box (Sec. 2, Fig. 1).  real_in and cplx_out must not
+ * overlap. */
+ps_status ps_fft_r2c(ps_plan p, const void *real_in, void *cplx_out);
+
+/* Unnormalised inverse transform in pass order (inverse complex transforms
+ * along z, then y, then the real inverse along x, whose kx = 0 and kx = N/2
+ * bins contribute their real parts).  cplx_in is preserved. */
+ps_status ps_fft_c2r(ps_plan p, const void *cplx_in, void *real_out);
+
+/* Navier-Stokes nonlinear term (Sec. 2, Eq. 1-2, rotational form):
+ * nhat = D(k) P(k) F[u x w] / N^3 with u = c2r(uhat), w = c2r(i k x uhat),
+ * D the 2/3-rule spherical truncation (keep 9|k|^2 < N^2), P(k) = I - k k^T/|k|^2
+ * (P(0) = 0).  3 fields in, 3 out; the plan must have nfields = 3. */
+ps_status ps_nonlinear_ns(ps_plan p, const void *uhat, void *nhat);
+
+/* MHD nonlinear terms for the Elsasser state (z+ then z-; plan nfields = 6):
+ * N+- = D [ P F[u x w + j x b] +- i k x F[u x b] ] / N^3,
+ * u = (z+ + z-)/2, b = (z+ - z-)/2, w = curl u, j = curl b. */
+ps_status ps_nonlinear_mhd(ps_plan p, const void *zhat, void *nhat);
+
+/* nsteps explicit midpoint RK2 steps in place on the spectral state:
+ * z* = z + (dt/2) F(z), z <- z + dt F(z*), F = nonlinear term - viscous
+ * term (NS: nu |k|^2 u; MHD: |k|^2 ((nu+eta)/2 z+- + (nu-eta)/2 z-+)).
+ * One RK2 step is replayed from a captured HIP graph unless graphs are
+ * disabled or kernel timing is on.  Needs a workspace. */
+ps_status ps_rk2_step(ps_plan p, void *state, ps_model m, double nu, double eta, double dt,
+                      int nsteps);
+
+/* Shell spectrum of nfields fields per box (1 <= nfields <= plan nfields):
+ * spec_dev[s] = 1/2 sum_{round(|k|)=s} w |f(k)|^2 (w = 1 on the kx = 0 and
+ * kx = N/2 planes, 2 elsewhere) and totals_dev = [E, Z, maxdiv] with
+ * Z = 1/2 sum w |k|^2 |f|^2 and maxdiv = max |k . f| over consecutive
+ * component triples.  FP64, deterministic (fixed-order compensated sums).
+ * Ensembles: per-box spectra concatenated, 3 totals per box.  Device output. */
+ps_status ps_energy_spectrum(ps_plan p, const void *fhat, int nfields, double *spec_dev,
+                             double *totals_dev);
+
+/* Per-kernel timing with HIP events on the plan's stream (disables graph
+ * replay while on).  Statistics accumulate until ps_plan_timing_reset. */
+ps_status ps_plan_set_timing(ps_plan p, int enable);
+ps_status ps_plan_set_graphs(ps_plan p, int enable);
+ps_status ps_plan_timing_reset(ps_plan p);
+/* Number of kernel kinds with statistics (synchronises pending events). */
+int ps_plan_timing_count(ps_plan p);
+/* Statistics of kind idx: name (static storage), total milliseconds, launch
+ * count and algorithmic bytes moved per launch (reads + writes of the
+ * values the pass must touch). */
+ps_status ps_plan_timing_get(ps_plan p, int idx, const char **name, double *total_ms,
+                             long *launches, double *bytes_per_launch);
+
+const char *ps_status_string(ps_status s);
+const char *ps_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

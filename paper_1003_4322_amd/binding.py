@@ -1,0 +1,286 @@
+"""Thin ctypes binding of libps.so (C ABI in include/ps.h).
+
+Argument marshalling only: shapes, dtypes and devices are checked here, then
+the tensors' device pointers and torch's current HIP stream are handed to the
+library, where every step runs in hand-written gfx950 kernels.  PyTorch
+provides device memory and streams; nothing here computes.  If the library is
+missing the import raises -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, Optional, Sequence, Tuple, Union
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libps.so")
+
+PS_F32, PS_F64 = 0, 1
+PS_NS, PS_MHD = 0, 1
+_STATUS = {0: "PS_OK", -1: "PS_ERR_ARG", -2: "PS_ERR_SIZE", -3: "PS_ERR_NOMEM",
+           -4: "PS_ERR_HIP", -5: "PS_ERR_STATE", -6: "PS_ERR_DIVERGED"}
+
+# (name, restype, argtypes) of every exported function, in header order
+_vp, _sz, _i, _d = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_double
+_SIGS = [
+    ("ps_plan_create", _i, [ctypes.POINTER(_vp), _i, _i, _i]),
+    ("ps_plan_create_batch", _i, [ctypes.POINTER(_vp), _i, ctypes.POINTER(_i), _i, _i]),
+    ("ps_plan_destroy", _i, [_vp]),
+    ("ps_plan_set_stream", _i, [_vp, _vp]),
+    ("ps_plan_workspace_bytes", _sz, [_vp]),
+    ("ps_plan_set_workspace", _i, [_vp, _vp, _sz]),
+    ("ps_plan_box_offsets", _i, [_vp, _i, ctypes.POINTER(_sz), ctypes.POINTER(_sz)]),
+    ("ps_num_shells", _i, [_vp, _i]),
+    ("ps_fft_r2c", _i, [_vp, _vp, _vp]),
+    ("ps_fft_c2r", _i, [_vp, _vp, _vp]),
+    ("ps_nonlinear_ns", _i, [_vp, _vp, _vp]),
+    ("ps_nonlinear_mhd", _i, [_vp, _vp, _vp]),
+    ("ps_rk2_step", _i, [_vp, _vp, _i, _d, _d, _d, _i]),
+    ("ps_energy_spectrum", _i, [_vp, _vp, _i, _vp, _vp]),
+    ("ps_plan_set_timing", _i, [_vp, _i]),
+    ("ps_plan_set_graphs", _i, [_vp, _i]),
+    ("ps_plan_timing_reset", _i, [_vp]),
+    ("ps_plan_timing_count", _i, [_vp]),
+    ("ps_plan_timing_get", _i, [_vp, _i, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(_d),
+                                ctypes.POINTER(ctypes.c_long), ctypes.POINTER(_d)]),
+    ("ps_status_string", ctypes.c_char_p, [_i]),
+    ("ps_last_error", ctypes.c_char_p, []),
+]
+SYMBOLS = [s[0] for s in _SIGS]
+
+_lib: Optional[ctypes.CDLL] = None
+
+
+class PsError(RuntimeError):
+    def __init__(self, code: int, where: str, detail: str):
+        super().__init__(f"{where}: {_STATUS.get(code, code)} ({detail})")
+        self.code = code
+
+
+def lib() -> ctypes.CDLL:
+    """The in-tree libps.so (built by paper_1003_4322_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run paper_1003_4322_amd/build.py "
+                              "(there is no non-HIP fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, res, args in _SIGS:
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, where: str):
+    if rc != 0:
+        raise PsError(rc, where, lib().ps_last_error().decode(errors="replace"))
+
+
+def _ptr(t: torch.Tensor) -> int:
+    return t.data_ptr()
+
+
+_CDT = {PS_F32: torch.complex64, PS_F64: torch.complex128}
+_RDT = {PS_F32: torch.float32, PS_F64: torch.float64}
+
+
+def dtype_code(dtype: Union[str, torch.dtype, int]) -> int:
+    if dtype in (PS_F32, "f32", "float32", torch.float32, torch.complex64):
+        return PS_F32
+    if dtype in (PS_F64, "f64", "float64", torch.float64, torch.complex128):
+        return PS_F64
+    raise ValueError(f"unsupported dtype {dtype!r}")
+
+
+class Plan:
+    """A plan for one N^3 box (``N`` an int) or an ensemble (``N`` a list)."""
+
+    def __init__(self, N: Union[int, Sequence[int]], nfields: int = 3, dtype="f32",
+                 device: Union[int, str, torch.device, None] = None, workspace: bool = True):
+        self.dtype = dtype_code(dtype)
+        self.nfields = int(nfields)
+        self.sizes = [int(N)] if isinstance(N, int) else [int(n) for n in N]
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None \
+            else torch.device(device)
+        L = lib()
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            if len(self.sizes) == 1:
+                _check(L.ps_plan_create(ctypes.byref(h), self.sizes[0], self.nfields, self.dtype),
+                       "ps_plan_create")
+            else:
+                arr = (ctypes.c_int * len(self.sizes))(*self.sizes)
+                _check(L.ps_plan_create_batch(ctypes.byref(h), len(self.sizes), arr, self.nfields,
+                                              self.dtype), "ps_plan_create_batch")
+        self._h = h
+        self.ws: Optional[torch.Tensor] = None
+        self.real_off, self.cplx_off = [], []
+        for b in range(len(self.sizes)):
+            r, c = ctypes.c_size_t(), ctypes.c_size_t()
+            _check(L.ps_plan_box_offsets(h, b, ctypes.byref(r), ctypes.byref(c)), "box_offsets")
+            self.real_off.append(r.value)
+            self.cplx_off.append(c.value)
+        self.nshells = [L.ps_num_shells(h, b) for b in range(len(self.sizes))]
+        if workspace:
+            self.allocate_workspace()
+
+    # -- plumbing ------------------------------------------------------------
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        if self._h is None:
+            raise RuntimeError("plan is closed")
+        return self._h
+
+    def workspace_bytes(self) -> int:
+        return int(lib().ps_plan_workspace_bytes(self.handle))
+
+    def allocate_workspace(self):
+        n = self.workspace_bytes()
+        self.ws = torch.empty(max(n, 256), dtype=torch.uint8, device=self.device)
+        _check(lib().ps_plan_set_workspace(self.handle, _ptr(self.ws), self.ws.numel()),
+               "ps_plan_set_workspace")
+
+    def _stream(self):
+        s = torch.cuda.current_stream(self.device)
+        _check(lib().ps_plan_set_stream(self.handle, ctypes.c_void_p(s.cuda_stream)), "set_stream")
+
+    def close(self):
+        if self._h is not None:
+            lib().ps_plan_destroy(self._h)
+            self._h = None
+            self.ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def complex_dtype(self):
+        return _CDT[self.dtype]
+
+    @property
+    def real_dtype(self):
+        return _RDT[self.dtype]
+
+    def spectral_shape(self, nf: Optional[int] = None):
+        assert len(self.sizes) == 1, "ensembles use flat buffers"
+        N = self.sizes[0]
+        return (nf or self.nfields, N, N, N // 2 + 1)
+
+    def real_shape(self):
+        assert len(self.sizes) == 1, "ensembles use flat buffers"
+        N = self.sizes[0]
+        return (self.nfields, N, N, N)
+
+    def n_complex(self) -> int:
+        return sum(self.nfields * n * n * (n // 2 + 1) for n in self.sizes)
+
+    def n_real(self) -> int:
+        return sum(self.nfields * n ** 3 for n in self.sizes)
+
+    def _need(self, t: torch.Tensor, kind: str, name: str, numel: Optional[int] = None):
+        want = self.complex_dtype if kind == "c" else self.real_dtype
+        if not isinstance(t, torch.Tensor) or t.dtype != want:
+            raise TypeError(f"{name}: expected a {want} tensor")
+        if t.device != self.device:
+            raise ValueError(f"{name}: tensor on {t.device}, plan on {self.device}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name}: tensor must be contiguous")
+        n = numel if numel is not None else (self.n_complex() if kind == "c" else self.n_real())
+        if t.numel() != n:
+            raise ValueError(f"{name}: expected {n} elements, got {t.numel()}")
+
+    def _empty(self, kind: str, like_shape=None):
+        if len(self.sizes) == 1:
+            shape = self.spectral_shape() if kind == "c" else self.real_shape()
+        else:
+            shape = (self.n_complex() if kind == "c" else self.n_real(),)
+        dt = self.complex_dtype if kind == "c" else self.real_dtype
+        return torch.empty(shape, dtype=dt, device=self.device)
+
+    # -- API -------------------------------------------------------------------
+    def fft_r2c(self, real: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        self._need(real, "r", "real")
+        out = self._empty("c") if out is None else out
+        self._need(out, "c", "out")
+        self._stream()
+        _check(lib().ps_fft_r2c(self.handle, _ptr(real), _ptr(out)), "ps_fft_r2c")
+        return out
+
+    def fft_c2r(self, cplx: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        self._need(cplx, "c", "cplx")
+        out = self._empty("r") if out is None else out
+        self._need(out, "r", "out")
+        self._stream()
+        _check(lib().ps_fft_c2r(self.handle, _ptr(cplx), _ptr(out)), "ps_fft_c2r")
+        return out
+
+    def nonlinear_ns(self, uhat: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        self._need(uhat, "c", "uhat")
+        out = self._empty("c") if out is None else out
+        self._need(out, "c", "out")
+        self._stream()
+        _check(lib().ps_nonlinear_ns(self.handle, _ptr(uhat), _ptr(out)), "ps_nonlinear_ns")
+        return out
+
+    def nonlinear_mhd(self, zhat: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        self._need(zhat, "c", "zhat")
+        out = self._empty("c") if out is None else out
+        self._need(out, "c", "out")
+        self._stream()
+        _check(lib().ps_nonlinear_mhd(self.handle, _ptr(zhat), _ptr(out)), "ps_nonlinear_mhd")
+        return out
+
+    def rk2_step(self, state: torch.Tensor, model: int, nu: float, eta: float, dt: float,
+                 nsteps: int = 1) -> torch.Tensor:
+        """In place on ``state``; returns it."""
+        self._need(state, "c", "state")
+        self._stream()
+        _check(lib().ps_rk2_step(self.handle, _ptr(state), int(model), float(nu), float(eta),
+                                 float(dt), int(nsteps)), "ps_rk2_step")
+        return state
+
+    def energy_spectrum(self, fhat: torch.Tensor, nfields: Optional[int] = None
+                        ) -> Tuple[torch.Tensor, torch.Tensor]:
+        """Device FP64 (spectrum, totals[E, Z, maxdiv]); ensembles: concatenated."""
+        nf = nfields or self.nfields
+        if fhat.dtype != self.complex_dtype or fhat.device != self.device or not fhat.is_contiguous():
+            raise TypeError("fhat: contiguous complex tensor of the plan's dtype and device")
+        spec = torch.empty(sum(self.nshells), dtype=torch.float64, device=self.device)
+        tot = torch.empty(3 * len(self.sizes), dtype=torch.float64, device=self.device)
+        self._stream()
+        _check(lib().ps_energy_spectrum(self.handle, _ptr(fhat), nf, _ptr(spec), _ptr(tot)),
+               "ps_energy_spectrum")
+        return spec, tot
+
+    # -- timing ----------------------------------------------------------------
+    def set_timing(self, on: bool):
+        _check(lib().ps_plan_set_timing(self.handle, int(bool(on))), "set_timing")
+
+    def set_graphs(self, on: bool):
+        _check(lib().ps_plan_set_graphs(self.handle, int(bool(on))), "set_graphs")
+
+    def timing_reset(self):
+        _check(lib().ps_plan_timing_reset(self.handle), "timing_reset")
+
+    def timings(self) -> Dict[str, Dict[str, float]]:
+        L = lib()
+        n = L.ps_plan_timing_count(self.handle)
+        if n < 0:
+            _check(n, "timing_count")
+        out = {}
+        for i in range(n):
+            name = ctypes.c_char_p()
+            ms, bpl = ctypes.c_double(), ctypes.c_double()
+            cnt = ctypes.c_long()
+            _check(L.ps_plan_timing_get(self.handle, i, ctypes.byref(name), ctypes.byref(ms),
+                                        ctypes.byref(cnt), ctypes.byref(bpl)), "timing_get")
+            out[name.value.decode()] = {"total_ms": ms.value, "launches": cnt.value,
+                                        "bytes_per_launch": bpl.value}
+        return out

@@ -1,0 +1,697 @@
+// ps_api.cpp -- C ABI of libps.so: plans, workspace layout, pass sequencing,
+// graph capture of the RK2 step and per-kernel timing.
+//
+// One plan covers one box or an ensemble of independent boxes.  A box of
+// size N with F fields uses, inside the caller's workspace:
+//   zstar  F half spectra, dense pitch H = N/2+1       (RK2 midpoint state)
+//   work   2F half spectra, pitch P (H rounded up to 128 bytes)
+//          (physical-space passes: u, w [, b, j] and then the products)
+//   spec   N * nshell * 2 + N doubles                  (spectrum partials)
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/ps.h"
+#include "ps_launch.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+ps_status fail(ps_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+struct Box {
+  int N = 0;
+  long H = 0, P = 0;
+  long nc = 0;    // N*N*H   valid complex values per field
+  long ncp = 0;   // N*N*P   pitched complex values per field
+  long n3 = 0;    // N^3
+  size_t real_off = 0, cplx_off = 0;  // element offsets in user field sets
+  size_t ws_off = 0;                  // byte offset of this box's workspace
+  size_t zs_bytes = 0, work_bytes = 0, spec_bytes = 0;
+  int nshell = 0;
+  void* tw = nullptr;  // device twiddle table (length N), owned by the plan
+};
+
+struct TimingRec {
+  int kind;
+  hipEvent_t a, b;
+  double bytes;
+};
+
+struct KindStat {
+  std::string name;
+  double ms = 0;
+  long launches = 0;
+  double bytes = 0;
+};
+
+long shell_of(long k2) {
+  long s = (long)std::floor(std::sqrt((double)k2));
+  while (s > 0 && 4 * k2 < (2 * s - 1) * (2 * s - 1)) --s;
+  while (4 * k2 >= (2 * s + 1) * (2 * s + 1)) ++s;
+  return s;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+struct ps_plan_s {
+  int nfields = 0;
+  ps_dtype dtype = PS_F32;
+  int device = 0;
+  std::vector<Box> boxes;
+  std::map<int, void*> tables;
+  hipStream_t stream = nullptr;
+  hipStream_t cap = nullptr;  // private stream used only for graph capture
+  void* ws = nullptr;
+  size_t ws_bytes = 0, ws_need = 0;
+  size_t real_total = 0, cplx_total = 0;
+  // graph cache for one RK2 step
+  bool graphs = true;
+  hipGraphExec_t gexec = nullptr;
+  std::string gkey;
+  // timing
+  bool timing = false;
+  std::vector<TimingRec> pending;
+  std::vector<KindStat> stats;
+  std::map<std::string, int> kind_index;
+};
+
+namespace {
+
+size_t csize(const ps_plan_s* p) { return p->dtype == PS_F32 ? 8 : 16; }
+size_t rsize(const ps_plan_s* p) { return p->dtype == PS_F32 ? 4 : 8; }
+
+template <typename T>
+std::vector<ps::C2<T>> make_table(int N) {
+  std::vector<ps::C2<T>> t(N);
+  const long double tp = 6.283185307179586476925286766559005768L;
+  for (int e = 0; e < N; ++e) {
+    long double a = tp * (long double)e / (long double)N;
+    t[e].x = (T)cosl(a);
+    t[e].y = (T)(-sinl(a));
+  }
+  return t;
+}
+
+ps_status hip_fail(hipError_t e, const char* what) {
+  return fail(PS_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// device pointer with at least `bytes` accessible from it
+ps_status check_dev(const void* ptr, size_t bytes, const char* name) {
+  if (!ptr) return fail(PS_ERR_ARG, std::string(name) + " is NULL");
+  hipPointerAttribute_t at;
+  hipError_t e = hipPointerGetAttributes(&at, ptr);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(PS_ERR_ARG, std::string(name) + " is not a HIP device pointer");
+  }
+  if (at.type != hipMemoryTypeDevice && at.type != hipMemoryTypeManaged)
+    return fail(PS_ERR_ARG, std::string(name) + " is not device memory");
+  hipDeviceptr_t base = nullptr;
+  size_t size = 0;
+  e = hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)ptr);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(PS_ERR_ARG, std::string(name) + ": cannot query its allocation");
+  }
+  const size_t off = (const char*)ptr - (const char*)base;
+  if (off + bytes > size) {
+    char buf[256];
+    snprintf(buf, sizeof buf, "%s: %zu bytes needed but only %zu remain in its allocation", name, bytes,
+             size - off);
+    return fail(PS_ERR_ARG, buf);
+  }
+  return PS_OK;
+}
+
+int kind_of(ps_plan_s* p, const char* name) {
+  auto it = p->kind_index.find(name);
+  if (it != p->kind_index.end()) return it->second;
+  int k = (int)p->stats.size();
+  KindStat s;
+  s.name = name;
+  p->stats.push_back(s);
+  p->kind_index[name] = k;
+  return k;
+}
+
+// Enqueue one launch (a callable returning hipError_t) on stream s, with
+// optional timing events.
+template <class F>
+ps_status enqueue(ps_plan_s* p, hipStream_t s, const char* kind, double bytes, F&& launch) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (p->timing) {
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+      return fail(PS_ERR_HIP, "hipEventCreate failed");
+    hipEventRecord(a, s);
+  }
+  hipError_t e = launch(s);
+  if (e != hipSuccess) {
+    if (a) hipEventDestroy(a);
+    if (b) hipEventDestroy(b);
+    return hip_fail(e, kind);
+  }
+  if (p->timing) {
+    hipEventRecord(b, s);
+    p->pending.push_back({kind_of(p, kind), a, b, bytes});
+  }
+  return PS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Pass sequences for one box
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Seq {
+  ps_plan_s* p;
+  const Box& b;
+  hipStream_t s;
+  using C = ps::C2<T>;
+  const C* tw() const { return (const C*)b.tw; }
+  C* zstar() const { return (C*)((char*)p->ws + b.ws_off); }
+  C* work() const { return (C*)((char*)p->ws + b.ws_off + b.zs_bytes); }
+  double* spec_part() const { return (double*)((char*)p->ws + b.ws_off + b.zs_bytes + b.work_bytes); }
+  double cs() const { return (double)sizeof(C); }
+
+  // strided pass in place on nf fields, line = z (y pass) or ky (z pass)
+  ps_status ypass(C* x, long pitch, int nf, int dir) {
+    ps::StridedArgs<T> a{};
+    a.in = x; a.out = x; a.tw = tw();
+    a.in_fs = a.out_fs = (long)b.N * b.N * pitch;
+    a.in_ls = a.out_ls = (long)b.N * pitch;
+    a.in_es = a.out_es = pitch;
+    a.ncols = (int)b.H; a.nlines = b.N; a.nf = nf;
+    const double bytes = 2.0 * nf * b.nc * cs();
+    return enqueue(p, s, dir == ps::FWD ? "y_fwd" : "y_inv", bytes,
+                   [&](hipStream_t st) { return ps::launch_strided<T>(b.N, dir, a, st); });
+  }
+  ps_status zpass(const C* in, long in_pitch, C* out, long out_pitch, int nf, int dir) {
+    ps::StridedArgs<T> a{};
+    a.in = in; a.out = out; a.tw = tw();
+    a.in_fs = (long)b.N * b.N * in_pitch; a.out_fs = (long)b.N * b.N * out_pitch;
+    a.in_ls = in_pitch; a.out_ls = out_pitch;
+    a.in_es = (long)b.N * in_pitch; a.out_es = (long)b.N * out_pitch;
+    a.ncols = (int)b.H; a.nlines = b.N; a.nf = nf;
+    const double bytes = 2.0 * nf * b.nc * cs();
+    return enqueue(p, s, dir == ps::FWD ? "z_fwd" : "z_inv", bytes,
+                   [&](hipStream_t st) { return ps::launch_strided<T>(b.N, dir, a, st); });
+  }
+
+  ps_status r2c(const T* real_in, C* out) {
+    const int nf = p->nfields;
+    ps::XArgs<T> a{};
+    a.in = (const C*)real_in; a.out = out; a.tw = tw();
+    a.in_pitch = b.N / 2; a.in_fs = (long)b.N * b.N * (b.N / 2);
+    a.out_pitch = b.H; a.out_fs = b.nc;
+    a.rows = (long)b.N * b.N; a.nf = nf;
+    const double bytes = nf * (b.n3 * (double)sizeof(T) + b.nc * cs());
+    ps_status st = enqueue(p, s, "x_r2c", bytes, [&](hipStream_t q) { return ps::launch_x_r2c<T>(b.N, a, q); });
+    if (st) return st;
+    if ((st = ypass(out, b.H, nf, ps::FWD))) return st;
+    return zpass(out, b.H, out, b.H, nf, ps::FWD);
+  }
+
+  ps_status c2r(const C* in, T* real_out) {
+    const int nf = p->nfields;
+    C* w = work();
+    ps_status st = zpass(in, b.H, w, b.P, nf, ps::INV);
+    if (st) return st;
+    if ((st = ypass(w, b.P, nf, ps::INV))) return st;
+    ps::XArgs<T> a{};
+    a.in = w; a.out = (C*)real_out; a.tw = tw();
+    a.in_pitch = b.P; a.in_fs = b.ncp;
+    a.out_pitch = b.N / 2; a.out_fs = (long)b.N * b.N * (b.N / 2);
+    a.rows = (long)b.N * b.N; a.nf = nf;
+    const double bytes = nf * (b.n3 * (double)sizeof(T) + b.nc * cs());
+    return enqueue(p, s, "x_c2r", bytes, [&](hipStream_t q) { return ps::launch_x_c2r<T>(b.N, a, q); });
+  }
+
+  // nonlinear right-hand side, epilogue mode 0/1/2 (see k_z_epi)
+  ps_status rhs(const C* src, bool mhd, int mode, C* out, const C* st0, const C* st1, T h, T nua, T nub) {
+    const int nin = mhd ? 6 : 3, nphys = mhd ? 12 : 6, nprod = mhd ? 6 : 3;
+    C* w = work();
+    ps::ZCurlArgs<T> ca{};
+    ca.in = src; ca.out = w; ca.tw = tw();
+    ca.in_fs = b.nc; ca.in_pitch = b.H; ca.out_fs = b.ncp; ca.out_pitch = b.P; ca.N = b.N;
+    ps_status st = enqueue(p, s, "z_curl", (nin + nphys) * b.nc * cs(),
+                           [&](hipStream_t q) { return ps::launch_z_curl<T>(b.N, mhd, ca, q); });
+    if (st) return st;
+    if ((st = ypass(w, b.P, nphys, ps::INV))) return st;
+    ps::XArgs<T> xa{};
+    xa.in = w; xa.out = w; xa.tw = tw();
+    xa.in_pitch = xa.out_pitch = b.P; xa.in_fs = xa.out_fs = b.ncp;
+    xa.rows = (long)b.N * b.N; xa.nf = nphys;
+    st = enqueue(p, s, "x_prod", (nphys + nprod) * b.nc * cs(),
+                 [&](hipStream_t q) { return ps::launch_x_prod<T>(b.N, mhd, xa, q); });
+    if (st) return st;
+    if ((st = ypass(w, b.P, nprod, ps::FWD))) return st;
+    ps::ZEpiArgs<T> ea{};
+    ea.in = w; ea.out = out; ea.st0 = st0; ea.st1 = st1; ea.tw = tw();
+    ea.in_fs = b.ncp; ea.in_pitch = b.P; ea.out_fs = b.nc; ea.out_pitch = b.H;
+    ea.scale = (T)(1.0 / ((double)b.N * b.N * b.N));
+    ea.h = h; ea.nua = nua; ea.nub = nub; ea.N = b.N; ea.mode = mode;
+    const int nrw = mode == 0 ? 0 : (mode == 1 ? 1 : 2);
+    return enqueue(p, s, "z_epi", (nprod + nprod + nrw * nprod) * b.nc * cs(),
+                   [&](hipStream_t q) { return ps::launch_z_epi<T>(b.N, mhd, ea, q); });
+  }
+
+  ps_status rk2(C* state, bool mhd, double nu, double eta, double dt) {
+    const T nua = (T)(mhd ? 0.5 * (nu + eta) : nu), nub = (T)(mhd ? 0.5 * (nu - eta) : 0.0);
+    C* zs = zstar();
+    ps_status st = rhs(state, mhd, 1, zs, state, nullptr, (T)(0.5 * dt), nua, nub);
+    if (st) return st;
+    return rhs(zs, mhd, 2, nullptr, state, zs, (T)dt, nua, nub);
+  }
+
+  ps_status spectrum(const C* f, int nf, double* spec, double* totals) {
+    ps::SpecArgs<T> a{};
+    a.f = f; a.part = spec_part(); a.pmax = a.part + (long)b.N * b.nshell * 2;
+    a.fs = b.nc; a.pitch = b.H; a.N = b.N; a.nf = nf; a.nshell = b.nshell;
+    return enqueue(p, s, "spectrum", nf * b.nc * cs(),
+                   [&](hipStream_t q) { return ps::launch_spectrum<T>(a, spec, totals, q); });
+  }
+};
+
+ps_status validate_plan(ps_plan p) {
+  if (!p) return fail(PS_ERR_ARG, "plan is NULL");
+  return PS_OK;
+}
+
+ps_status need_ws(ps_plan p) {
+  if (!p->ws || p->ws_bytes < p->ws_need)
+    return fail(PS_ERR_STATE, "no (or too small) workspace: call ps_plan_set_workspace");
+  return PS_OK;
+}
+
+ps_status set_device(ps_plan p) {
+  hipError_t e = hipSetDevice(p->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  return PS_OK;
+}
+
+void free_plan(ps_plan p) {
+  if (!p) return;
+  for (auto& r : p->pending) {
+    hipEventDestroy(r.a);
+    hipEventDestroy(r.b);
+  }
+  if (p->gexec) hipGraphExecDestroy(p->gexec);
+  if (p->cap) hipStreamDestroy(p->cap);
+  for (auto& kv : p->tables) hipFree(kv.second);
+  delete p;
+}
+
+template <typename T>
+ps_status upload_table(ps_plan p, int N) {
+  if (p->tables.count(N)) return PS_OK;
+  auto t = make_table<T>(N);
+  void* d = nullptr;
+  hipError_t e = hipMalloc(&d, t.size() * sizeof(t[0]));
+  if (e != hipSuccess) return fail(PS_ERR_NOMEM, std::string("twiddle table: ") + hipGetErrorString(e));
+  e = hipMemcpy(d, t.data(), t.size() * sizeof(t[0]), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    hipFree(d);
+    return hip_fail(e, "twiddle upload");
+  }
+  p->tables[N] = d;
+  return PS_OK;
+}
+
+template <typename F>
+ps_status guarded(F&& f) {
+  try {
+    return f();
+  } catch (const std::bad_alloc&) {
+    return fail(PS_ERR_NOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(PS_ERR_HIP, "unexpected exception");
+  }
+}
+
+// dispatch on the plan's dtype
+template <class F>
+ps_status by_type(ps_plan p, F&& f) {
+  if (p->dtype == PS_F32) return f((float*)nullptr);
+  return f((double*)nullptr);
+}
+
+ps_status sync_timing(ps_plan p) {
+  for (auto& r : p->pending) {
+    float ms = 0;
+    hipError_t e = hipEventSynchronize(r.b);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
+    if (e != hipSuccess) return hip_fail(e, "timing event");
+    KindStat& k = p->stats[r.kind];
+    k.ms += ms;
+    k.launches += 1;
+    k.bytes = r.bytes;
+    hipEventDestroy(r.a);
+    hipEventDestroy(r.b);
+  }
+  p->pending.clear();
+  return PS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ps_status_string(ps_status s) {
+  switch (s) {
+    case PS_OK: return "ok";
+    case PS_ERR_ARG: return "invalid argument";
+    case PS_ERR_SIZE: return "unsupported size";
+    case PS_ERR_NOMEM: return "out of memory";
+    case PS_ERR_HIP: return "HIP runtime error";
+    case PS_ERR_STATE: return "invalid plan state";
+    case PS_ERR_DIVERGED: return "diverged";
+  }
+  return "unknown status";
+}
+
+const char* ps_last_error(void) { return g_last_error.c_str(); }
+
+ps_status ps_plan_create_batch(ps_plan* out, int nbox, const int* Ns, int nfields, ps_dtype dtype) {
+  return guarded([&]() -> ps_status {
+    if (!out) return fail(PS_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (nbox < 1 || !Ns) return fail(PS_ERR_ARG, "need nbox >= 1 and a size array");
+    if (nfields != 3 && nfields != 6) return fail(PS_ERR_SIZE, "nfields must be 3 (NS) or 6 (MHD)");
+    if (dtype != PS_F32 && dtype != PS_F64) return fail(PS_ERR_ARG, "dtype must be PS_F32 or PS_F64");
+    for (int i = 0; i < nbox; ++i)
+      if (!ps::size_supported(Ns[i])) {
+        char buf[128];
+        snprintf(buf, sizeof buf, "unsupported N = %d (box %d)", Ns[i], i);
+        return fail(PS_ERR_SIZE, buf);
+      }
+    ps_plan p = new ps_plan_s();
+    p->nfields = nfields;
+    p->dtype = dtype;
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) {
+      free_plan(p);
+      return hip_fail(e, "hipGetDevice");
+    }
+    const size_t cs = csize(p);
+    size_t ws = 0, roff = 0, coff = 0;
+    for (int i = 0; i < nbox; ++i) {
+      Box b;
+      b.N = Ns[i];
+      b.H = b.N / 2 + 1;
+      const long align = 128 / (long)cs;
+      b.P = (b.H + align - 1) / align * align;
+      b.nc = (long)b.N * b.N * b.H;
+      b.ncp = (long)b.N * b.N * b.P;
+      b.n3 = (long)b.N * b.N * b.N;
+      b.real_off = roff;
+      b.cplx_off = coff;
+      roff += (size_t)nfields * b.n3;
+      coff += (size_t)nfields * b.nc;
+      b.nshell = (int)shell_of(3L * (b.N / 2) * (b.N / 2)) + 1;
+      b.zs_bytes = align256((size_t)nfields * b.nc * cs);
+      b.work_bytes = align256((size_t)2 * nfields * b.ncp * cs);
+      b.spec_bytes = align256(((size_t)b.N * b.nshell * 2 + b.N) * sizeof(double));
+      b.ws_off = ws;
+      ws += b.zs_bytes + b.work_bytes + b.spec_bytes;
+      p->boxes.push_back(b);
+    }
+    p->ws_need = ws;
+    p->real_total = roff;
+    p->cplx_total = coff;
+    for (auto& b : p->boxes) {
+      ps_status st = dtype == PS_F32 ? upload_table<float>(p, b.N) : upload_table<double>(p, b.N);
+      if (st) {
+        free_plan(p);
+        return st;
+      }
+      b.tw = p->tables[b.N];
+    }
+    e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      free_plan(p);
+      return hip_fail(e, "hipStreamCreate");
+    }
+    *out = p;
+    return PS_OK;
+  });
+}
+
+ps_status ps_plan_create(ps_plan* out, int N, int nfields, ps_dtype dtype) {
+  return ps_plan_create_batch(out, 1, &N, nfields, dtype);
+}
+
+ps_status ps_plan_destroy(ps_plan p) {
+  if (!p) return PS_OK;
+  return guarded([&]() -> ps_status {
+    hipSetDevice(p->device);
+    free_plan(p);
+    return PS_OK;
+  });
+}
+
+ps_status ps_plan_set_stream(ps_plan p, void* stream) {
+  if (ps_status st = validate_plan(p)) return st;
+  p->stream = (hipStream_t)stream;
+  return PS_OK;
+}
+
+size_t ps_plan_workspace_bytes(ps_plan p) { return p ? p->ws_need : 0; }
+
+ps_status ps_plan_set_workspace(ps_plan p, void* dev, size_t bytes) {
+  if (ps_status st = validate_plan(p)) return st;
+  if (bytes < p->ws_need) return fail(PS_ERR_NOMEM, "workspace smaller than ps_plan_workspace_bytes");
+  if (((uintptr_t)dev & 255) != 0) return fail(PS_ERR_ARG, "workspace must be 256-byte aligned");
+  if (ps_status st = check_dev(dev, p->ws_need, "workspace")) return st;
+  p->ws = dev;
+  p->ws_bytes = bytes;
+  if (p->gexec) {
+    hipGraphExecDestroy(p->gexec);
+    p->gexec = nullptr;
+    p->gkey.clear();
+  }
+  return PS_OK;
+}
+
+ps_status ps_plan_box_offsets(ps_plan p, int box, size_t* real_off, size_t* cplx_off) {
+  if (ps_status st = validate_plan(p)) return st;
+  if (box < 0 || box >= (int)p->boxes.size()) return fail(PS_ERR_ARG, "box index out of range");
+  if (real_off) *real_off = p->boxes[box].real_off;
+  if (cplx_off) *cplx_off = p->boxes[box].cplx_off;
+  return PS_OK;
+}
+
+int ps_num_shells(ps_plan p, int box) {
+  if (!p || box < 0 || box >= (int)p->boxes.size()) return PS_ERR_ARG;
+  return p->boxes[box].nshell;
+}
+
+ps_status ps_fft_r2c(ps_plan p, const void* real_in, void* cplx_out) {
+  return guarded([&]() -> ps_status {
+    if (ps_status st = validate_plan(p)) return st;
+    if (ps_status st = check_dev(real_in, p->real_total * rsize(p), "real_in")) return st;
+    if (ps_status st = check_dev(cplx_out, p->cplx_total * csize(p), "cplx_out")) return st;
+    if (ps_status st = set_device(p)) return st;
+    return by_type(p, [&](auto* tag) -> ps_status {
+      using T = std::remove_pointer_t<decltype(tag)>;
+      for (auto& b : p->boxes) {
+        Seq<T> q{p, b, p->stream};
+        ps_status st = q.r2c((const T*)real_in + b.real_off, (ps::C2<T>*)cplx_out + b.cplx_off);
+        if (st) return st;
+      }
+      return PS_OK;
+    });
+  });
+}
+
+ps_status ps_fft_c2r(ps_plan p, const void* cplx_in, void* real_out) {
+  return guarded([&]() -> ps_status {
+    if (ps_status st = validate_plan(p)) return st;
+    if (ps_status st = need_ws(p)) return st;
+    if (ps_status st = check_dev(cplx_in, p->cplx_total * csize(p), "cplx_in")) return st;
+    if (ps_status st = check_dev(real_out, p->real_total * rsize(p), "real_out")) return st;
+    if (ps_status st = set_device(p)) return st;
+    return by_type(p, [&](auto* tag) -> ps_status {
+      using T = std::remove_pointer_t<decltype(tag)>;
+      for (auto& b : p->boxes) {
+        Seq<T> q{p, b, p->stream};
+        ps_status st = q.c2r((const ps::C2<T>*)cplx_in + b.cplx_off, (T*)real_out + b.real_off);
+        if (st) return st;
+      }
+      return PS_OK;
+    });
+  });
+}
+
+static ps_status nonlinear(ps_plan p, const void* in, void* out, bool mhd) {
+  return guarded([&]() -> ps_status {
+    if (ps_status st = validate_plan(p)) return st;
+    if (p->nfields != (mhd ? 6 : 3))
+      return fail(PS_ERR_ARG, mhd ? "MHD needs a plan with nfields = 6" : "NS needs a plan with nfields = 3");
+    if (ps_status st = need_ws(p)) return st;
+    if (ps_status st = check_dev(in, p->cplx_total * csize(p), "input")) return st;
+    if (ps_status st = check_dev(out, p->cplx_total * csize(p), "output")) return st;
+    if (ps_status st = set_device(p)) return st;
+    return by_type(p, [&](auto* tag) -> ps_status {
+      using T = std::remove_pointer_t<decltype(tag)>;
+      for (auto& b : p->boxes) {
+        if (mhd && !ps::mhd_supported<T>(b.N)) return fail(PS_ERR_SIZE, "MHD not supported at this N and dtype");
+        Seq<T> q{p, b, p->stream};
+        ps::C2<T>* o = (ps::C2<T>*)out + b.cplx_off;
+        ps_status st = q.rhs((const ps::C2<T>*)in + b.cplx_off, mhd, 0, o, nullptr, nullptr, T(0), T(0), T(0));
+        if (st) return st;
+      }
+      return PS_OK;
+    });
+  });
+}
+
+ps_status ps_nonlinear_ns(ps_plan p, const void* uhat, void* nhat) { return nonlinear(p, uhat, nhat, false); }
+ps_status ps_nonlinear_mhd(ps_plan p, const void* zhat, void* nhat) { return nonlinear(p, zhat, nhat, true); }
+
+ps_status ps_rk2_step(ps_plan p, void* state, ps_model m, double nu, double eta, double dt, int nsteps) {
+  return guarded([&]() -> ps_status {
+    if (ps_status st = validate_plan(p)) return st;
+    if (m != PS_NS && m != PS_MHD) return fail(PS_ERR_ARG, "model must be PS_NS or PS_MHD");
+    const bool mhd = m == PS_MHD;
+    if (p->nfields != (mhd ? 6 : 3)) return fail(PS_ERR_ARG, "model does not match the plan's nfields");
+    if (nsteps < 0) return fail(PS_ERR_ARG, "nsteps < 0");
+    if (!std::isfinite(nu) || !std::isfinite(eta) || !std::isfinite(dt))
+      return fail(PS_ERR_ARG, "nu, eta and dt must be finite");
+    if (ps_status st = need_ws(p)) return st;
+    if (ps_status st = check_dev(state, p->cplx_total * csize(p), "state")) return st;
+    if (ps_status st = set_device(p)) return st;
+    if (nsteps == 0) return PS_OK;
+    return by_type(p, [&](auto* tag) -> ps_status {
+      using T = std::remove_pointer_t<decltype(tag)>;
+      for (auto& b : p->boxes)
+        if (mhd && !ps::mhd_supported<T>(b.N)) return fail(PS_ERR_SIZE, "MHD not supported at this N and dtype");
+      auto one_step = [&](hipStream_t s) -> ps_status {
+        for (auto& b : p->boxes) {
+          Seq<T> q{p, b, s};
+          ps_status st = q.rk2((ps::C2<T>*)state + b.cplx_off, mhd, nu, eta, dt);
+          if (st) return st;
+        }
+        return PS_OK;
+      };
+      if (!p->graphs || p->timing) {
+        for (int i = 0; i < nsteps; ++i)
+          if (ps_status st = one_step(p->stream)) return st;
+        return PS_OK;
+      }
+      char key[256];
+      snprintf(key, sizeof key, "%p|%d|%.17g|%.17g|%.17g|%p", state, (int)m, nu, eta, dt, p->ws);
+      if (!p->gexec || p->gkey != key) {
+        if (p->gexec) {
+          hipGraphExecDestroy(p->gexec);
+          p->gexec = nullptr;
+        }
+        hipError_t e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+        ps_status st = one_step(p->cap);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(p->cap, &g);
+        if (st) {
+          if (g) hipGraphDestroy(g);
+          return st;
+        }
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        e = hipGraphInstantiate(&p->gexec, g, nullptr, nullptr, 0);
+        hipGraphDestroy(g);
+        if (e != hipSuccess) {
+          p->gexec = nullptr;
+          return hip_fail(e, "hipGraphInstantiate");
+        }
+        p->gkey = key;
+      }
+      for (int i = 0; i < nsteps; ++i) {
+        hipError_t e = hipGraphLaunch(p->gexec, p->stream);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+      }
+      return PS_OK;
+    });
+  });
+}
+
+ps_status ps_energy_spectrum(ps_plan p, const void* fhat, int nfields, double* spec_dev, double* totals_dev) {
+  return guarded([&]() -> ps_status {
+    if (ps_status st = validate_plan(p)) return st;
+    if (nfields < 1 || nfields > p->nfields) return fail(PS_ERR_ARG, "nfields out of range");
+    if (ps_status st = need_ws(p)) return st;
+    size_t nsh = 0;
+    for (auto& b : p->boxes) nsh += b.nshell;
+    // the input holds nfields fields per box at the plan's box offsets
+    if (ps_status st = check_dev(fhat, p->cplx_total * csize(p) - (size_t)(p->nfields - nfields) *
+                                           p->boxes.back().nc * csize(p), "fhat"))
+      return st;
+    if (ps_status st = check_dev(spec_dev, nsh * sizeof(double), "spec")) return st;
+    if (ps_status st = check_dev(totals_dev, 3 * p->boxes.size() * sizeof(double), "totals")) return st;
+    if (ps_status st = set_device(p)) return st;
+    return by_type(p, [&](auto* tag) -> ps_status {
+      using T = std::remove_pointer_t<decltype(tag)>;
+      size_t so = 0;
+      for (size_t i = 0; i < p->boxes.size(); ++i) {
+        auto& b = p->boxes[i];
+        Seq<T> q{p, b, p->stream};
+        ps_status st = q.spectrum((const ps::C2<T>*)fhat + b.cplx_off, nfields, spec_dev + so, totals_dev + 3 * i);
+        if (st) return st;
+        so += b.nshell;
+      }
+      return PS_OK;
+    });
+  });
+}
+
+ps_status ps_plan_set_timing(ps_plan p, int enable) {
+  if (ps_status st = validate_plan(p)) return st;
+  p->timing = enable != 0;
+  return PS_OK;
+}
+
+ps_status ps_plan_set_graphs(ps_plan p, int enable) {
+  if (ps_status st = validate_plan(p)) return st;
+  p->graphs = enable != 0;
+  return PS_OK;
+}
+
+ps_status ps_plan_timing_reset(ps_plan p) {
+  if (ps_status st = validate_plan(p)) return st;
+  ps_status st = sync_timing(p);
+  p->stats.clear();
+  p->kind_index.clear();
+  return st;
+}
+
+int ps_plan_timing_count(ps_plan p) {
+  if (!p) return PS_ERR_ARG;
+  if (ps_status st = sync_timing(p)) return st;
+  return (int)p->stats.size();
+}
+
+ps_status ps_plan_timing_get(ps_plan p, int idx, const char** name, double* total_ms, long* launches,
+                             double* bytes_per_launch) {
+  if (ps_status st = validate_plan(p)) return st;
+  if (ps_status st = sync_timing(p)) return st;
+  if (idx < 0 || idx >= (int)p->stats.size()) return fail(PS_ERR_ARG, "timing index out of range");
+  const KindStat& k = p->stats[idx];
+  if (name) *name = k.name.c_str();
+  if (total_ms) *total_ms = k.ms;
+  if (launches) *launches = k.launches;
+  if (bytes_per_launch) *bytes_per_launch = k.bytes;
+  return PS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,293 @@
+// ps_device.hpp -- device-side building blocks for the gfx950 pseudospectral
+// kernels: interleaved complex values, small-radix DFT butterflies and a
+// Stockham autosort FFT engine that stages its exchanges through LDS.
+//
+// The transform computed is the plain DFT of the method's Fourier-Galerkin
+// discretisation (Sec. 2 of the paper: every field is a truncated Fourier
+// series and its derivatives, products and transforms are evaluated through
+// fast Fourier transforms).  The engine reaches the DFT exactly up to
+// rounding; twiddles are read from tables computed on the host in extended
+// precision and rounded once to the working type.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ps {
+
+template <typename T>
+struct alignas(2 * sizeof(T)) C2 {
+  T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ C2<T> mk(T a, T b) { return C2<T>{a, b}; }
+template <typename T>
+__device__ __forceinline__ C2<T> operator+(C2<T> a, C2<T> b) { return C2<T>{a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ __forceinline__ C2<T> operator-(C2<T> a, C2<T> b) { return C2<T>{a.x - b.x, a.y - b.y}; }
+template <typename T>
+__device__ __forceinline__ C2<T> operator*(T s, C2<T> a) { return C2<T>{s * a.x, s * a.y}; }
+template <typename T>
+__device__ __forceinline__ C2<T> cmul(C2<T> a, C2<T> b) {
+  return C2<T>{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// a * conj(b)
+template <typename T>
+__device__ __forceinline__ C2<T> cmulc(C2<T> a, C2<T> b) {
+  return C2<T>{a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+template <typename T>
+__device__ __forceinline__ C2<T> conj(C2<T> a) { return C2<T>{a.x, -a.y}; }
+// multiply by +i and -i
+template <typename T>
+__device__ __forceinline__ C2<T> mul_i(C2<T> a) { return C2<T>{-a.y, a.x}; }
+template <typename T>
+__device__ __forceinline__ C2<T> mul_mi(C2<T> a) { return C2<T>{a.y, -a.x}; }
+template <typename T>
+__device__ __forceinline__ C2<T> zero2() { return C2<T>{T(0), T(0)}; }
+
+// Direction: FWD computes sum x_j exp(-2 pi i j k / n), INV uses exp(+...).
+enum { FWD = 0, INV = 1 };
+
+// multiply by -i (FWD) or +i (INV): the quarter-turn of the DFT kernel
+template <int DIR, typename T>
+__device__ __forceinline__ C2<T> rot4(C2<T> a) { return DIR == FWD ? mul_mi(a) : mul_i(a); }
+
+// twiddle w(e) = exp(-+ 2 pi i e / L) from a table tw[e] = exp(-2 pi i e / L)
+template <int DIR, typename T>
+__device__ __forceinline__ C2<T> tw_apply(C2<T> a, C2<T> w) { return DIR == FWD ? cmul(a, w) : cmulc(a, w); }
+
+// ---------------------------------------------------------------------------
+// Small DFTs in registers.  dft<R, DIR>(a) replaces a[0..R) by its R-point DFT.
+// ---------------------------------------------------------------------------
+template <int R, int DIR, typename T>
+struct Dft;
+
+template <int DIR, typename T>
+struct Dft<2, DIR, T> {
+  __device__ __forceinline__ static void run(C2<T>* a) {
+    C2<T> t = a[0] - a[1];
+    a[0] = a[0] + a[1];
+    a[1] = t;
+  }
+};
+
+template <int DIR, typename T>
+struct Dft<3, DIR, T> {
+  __device__ __forceinline__ static void run(C2<T>* a) {
+    const T c = T(-0.5);
+    const T s = T(0.86602540378443864676372317075293618);  // sin(2 pi / 3)
+    C2<T> t1 = a[1] + a[2];
+    C2<T> t2 = a[1] - a[2];
+    C2<T> m = a[0] + c * t1;
+    // FWD: y1 = m - i s t2, y2 = m + i s t2
+    C2<T> r = s * (DIR == FWD ? mul_mi(t2) : mul_i(t2));
+    a[0] = a[0] + t1;
+    a[1] = m + r;
+    a[2] = m - r;
+  }
+};
+
+template <int DIR, typename T>
+struct Dft<4, DIR, T> {
+  __device__ __forceinline__ static void run(C2<T>* a) {
+    C2<T> t0 = a[0] + a[2];
+    C2<T> t1 = a[0] - a[2];
+    C2<T> t2 = a[1] + a[3];
+    C2<T> t3 = rot4<DIR>(a[1] - a[3]);
+    a[0] = t0 + t2;
+    a[2] = t0 - t2;
+    a[1] = t1 + t3;
+    a[3] = t1 - t3;
+  }
+};
+
+template <int DIR, typename T>
+struct Dft<8, DIR, T> {
+  __device__ __forceinline__ static void run(C2<T>* a) {
+    const T h = T(0.70710678118654752440084436210484904);
+    C2<T> e[4] = {a[0], a[2], a[4], a[6]};
+    C2<T> o[4] = {a[1], a[3], a[5], a[7]};
+    Dft<4, DIR, T>::run(e);
+    Dft<4, DIR, T>::run(o);
+    // o[k] *= W8^k, W8 = exp(-+ i pi / 4)
+    {
+      C2<T> v = o[1];
+      // FWD: (1 - i)/sqrt2 ; INV: (1 + i)/sqrt2
+      o[1] = DIR == FWD ? C2<T>{h * (v.x + v.y), h * (v.y - v.x)} : C2<T>{h * (v.x - v.y), h * (v.y + v.x)};
+      o[2] = rot4<DIR>(o[2]);
+      v = o[3];
+      // FWD: (-1 - i)/sqrt2 ; INV: (-1 + i)/sqrt2
+      o[3] = DIR == FWD ? C2<T>{h * (v.y - v.x), -h * (v.x + v.y)} : C2<T>{-h * (v.x + v.y), h * (v.x - v.y)};
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      a[k] = e[k] + o[k];
+      a[k + 4] = e[k] - o[k];
+    }
+  }
+};
+
+template <int R, int DIR, typename T>
+__device__ __forceinline__ void dft(C2<T>* a) { Dft<R, DIR, T>::run(a); }
+
+// ---------------------------------------------------------------------------
+// Radix schedules
+// ---------------------------------------------------------------------------
+template <int... Rs>
+struct Radices {};
+
+template <class RL>
+struct RadixInfo;
+template <int R0, int... Rs>
+struct RadixInfo<Radices<R0, Rs...>> {
+  static constexpr int first = R0;
+  static constexpr int count = 1 + sizeof...(Rs);
+  static constexpr int product = R0 * RadixInfo<Radices<Rs...>>::product;
+  static constexpr int last = RadixInfo<Radices<Rs...>>::count == 0 ? R0 : RadixInfo<Radices<Rs...>>::last;
+};
+template <>
+struct RadixInfo<Radices<>> {
+  static constexpr int first = 1;
+  static constexpr int count = 0;
+  static constexpr int product = 1;
+  static constexpr int last = 1;
+};
+
+constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
+
+// ---------------------------------------------------------------------------
+// Stockham autosort FFT of length L done by TQ cooperating threads.
+//
+// Stage with radix R after Ns points have been combined: butterfly j
+// (0 <= j < L/R) reads x[j + m L/R], m < R, multiplies input m by
+// w^{m (j mod Ns)} with w = exp(-+ 2 pi i / (Ns R)), takes the R-point DFT
+// and writes output m to position (j div Ns) Ns R + (j mod Ns) + m Ns.
+// The result comes out in natural order.  Thread q runs butterflies
+// j = q + TQ b.  The first stage reads its inputs through a caller functor
+// ld(slot, idx); intermediate stages exchange through LDS (element idx at
+// lds[idx * ls]); the last stage leaves its outputs in registers:
+// v[b * Rlast + m] holds output index q + TQ b + m (L / Rlast) (valid when
+// q + TQ b < L / Rlast).
+//
+// Barrier discipline: every stage that writes LDS first waits until all
+// threads finished reading the previous contents, so consecutive transforms
+// (and in-place exchanges) can reuse one LDS buffer.
+// ---------------------------------------------------------------------------
+template <typename T, int L, int TQ, int DIR, class RL>
+struct Stockham {
+  static constexpr int R1 = RadixInfo<RL>::first;
+  static constexpr int RL_ = RadixInfo<RL>::last;
+  static constexpr int NSTAGE = RadixInfo<RL>::count;
+  static_assert(RadixInfo<RL>::product == L, "radix schedule must multiply to L");
+  // register slots: enough for the widest stage
+  template <class RR>
+  struct MaxSlots;
+  template <int... Rs>
+  struct MaxSlots<Radices<Rs...>> {
+    static constexpr int value = [] {
+      int m = 0;
+      int rs[] = {Rs...};
+      for (int r : rs) {
+        int s = cdiv(L / r, TQ) * r;
+        m = s > m ? s : m;
+      }
+      return m;
+    }();
+  };
+  static constexpr int SLOTS = MaxSlots<RL>::value;
+  static constexpr int FIRST_SLOTS = cdiv(L / R1, TQ) * R1;
+  static constexpr int LAST_NB = cdiv(L / RL_, TQ);
+
+  // index of first-stage input for (slot) -- used by callers that preload
+  __device__ __forceinline__ static int first_index(int q, int slot) {
+    const int b = slot / R1, m = slot % R1;
+    return q + TQ * b + m * (L / R1);
+  }
+  __device__ __forceinline__ static bool first_valid(int q, int slot) {
+    return (L / R1) % TQ == 0 || q + TQ * (slot / R1) < L / R1;
+  }
+  // output index of last-stage slot
+  __device__ __forceinline__ static int last_index(int q, int slot) {
+    const int b = slot / RL_, m = slot % RL_;
+    return q + TQ * b + m * (L / RL_);
+  }
+  __device__ __forceinline__ static bool last_valid(int q, int slot) {
+    return (L / RL_) % TQ == 0 || q + TQ * (slot / RL_) < L / RL_;
+  }
+
+  template <int NS, int R, bool FIRST, bool LAST, class Ld>
+  __device__ __forceinline__ static void stage(C2<T> (&v)[SLOTS], C2<T>* lds, int ls, int q,
+                                               const C2<T>* __restrict__ tw, int twmul, Ld& ld) {
+    constexpr int NB = cdiv(L / R, TQ);
+    constexpr bool EXACT = (L / R) % TQ == 0;
+    // ---- gather inputs
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int j = q + TQ * b;
+      const bool ok = EXACT || j < L / R;
+#pragma unroll
+      for (int m = 0; m < R; ++m) {
+        const int idx = j + m * (L / R);
+        if constexpr (FIRST) {
+          v[b * R + m] = ok ? ld(b * R + m, idx) : zero2<T>();
+        } else {
+          v[b * R + m] = ok ? lds[idx * ls] : zero2<T>();
+        }
+      }
+    }
+    // ---- twiddle and butterfly
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int j = q + TQ * b;
+      C2<T>* a = &v[b * R];
+      if constexpr (NS > 1) {
+        const int k = j % NS;
+        constexpr int STEP = L / (NS * R);
+#pragma unroll
+        for (int m = 1; m < R; ++m) a[m] = tw_apply<DIR>(a[m], tw[(m * k * STEP) * twmul]);
+      }
+      dft<R, DIR>(a);
+    }
+    if constexpr (!LAST) {
+      __syncthreads();  // all reads of the previous LDS contents are done
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int j = q + TQ * b;
+        if (EXACT || j < L / R) {
+          const int base = (j / NS) * NS * R + (j % NS);
+#pragma unroll
+          for (int m = 0; m < R; ++m) lds[(base + m * NS) * ls] = v[b * R + m];
+        }
+      }
+      __syncthreads();  // writes visible before the next stage gathers
+    }
+  }
+
+  template <int NS, class Ld, int R, int... Rest>
+  __device__ __forceinline__ static void chain(C2<T> (&v)[SLOTS], C2<T>* lds, int ls, int q,
+                                               const C2<T>* __restrict__ tw, int twmul, Ld& ld,
+                                               Radices<R, Rest...>) {
+    stage<NS, R, NS == 1, sizeof...(Rest) == 0>(v, lds, ls, q, tw, twmul, ld);
+    if constexpr (sizeof...(Rest) > 0) chain<NS * R>(v, lds, ls, q, tw, twmul, ld, Radices<Rest...>{});
+  }
+
+  // tw: table of exp(-2 pi i e / (L * twmul)), e < L * twmul.
+  template <class Ld>
+  __device__ __forceinline__ static void run(C2<T> (&v)[SLOTS], C2<T>* lds, int ls, int q,
+                                             const C2<T>* __restrict__ tw, int twmul, Ld ld) {
+    chain<1>(v, lds, ls, q, tw, twmul, ld, RL{});
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Wavenumbers
+// ---------------------------------------------------------------------------
+// signed wavenumber of a ky/kz storage index (N/2 -> -N/2)
+__device__ __forceinline__ int wav(int i, int N) { return i < N / 2 ? i : i - N; }
+// derivative wavenumber: zero at the Nyquist index
+__device__ __forceinline__ int dwav(int i, int N) { return 2 * i == N ? 0 : wav(i, N); }
+__device__ __forceinline__ int dwavx(int i, int N) { return 2 * i == N ? 0 : i; }
+
+}  // namespace ps

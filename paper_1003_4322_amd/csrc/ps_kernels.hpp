@@ -1,0 +1,544 @@
+// ps_kernels.hpp -- gfx950 kernels of the pseudospectral step.
+//
+// The step evaluates the nonlinear term of the incompressible Navier-Stokes
+// (Eq. 1-2 of the paper) or MHD equations by the Fourier-Galerkin
+// pseudospectral method of Sec. 2: the spectral state is transformed to
+// physical space, products are formed there and transformed back, then
+// projected onto divergence-free fields and dealiased (the 2/3 rule).  The
+// 3D real transforms are done one axis per kernel ("pass"), as the paper's
+// slab algorithm does per axis (Fig. 1), but on one GPU the whole box is
+// local, so no transpose ever leaves the device:
+//
+//   z pass  strided complex FFT along kz (columns: (ky, kx), stride N*pitch)
+//   y pass  strided complex FFT along ky (columns: (z, kx),  stride pitch)
+//   x pass  contiguous real<->half-complex FFT along x (rows of N reals)
+//
+// A strided pass reads a tile of TX adjacent kx columns per workgroup, so
+// every global access is a TX-element contiguous segment; the column FFTs
+// run through the Stockham engine with LDS exchanges (the in-LDS transpose
+// replaces the paper's cache-blocked local transpose of Sec. 3).
+//
+// Fusion (each is one kernel, data touch HBM once per pass):
+//   inverse z pass + spectral curl prologue       (state -> u, w [, b, j])
+//   x pass: inverse real FFTs + cross products + forward real FFTs
+//   forward z pass + 1/N^3 + dealias + projection (+ induction curl)
+//                  + explicit midpoint RK2 stage update
+#pragma once
+
+#include "ps_device.hpp"
+
+namespace ps {
+
+// Workgroups are handed to the 8 XCDs round robin; remap so that each XCD
+// receives a contiguous range of logical tiles (neighbouring tiles share
+// cache lines at misaligned row starts, and each XCD has its own L2).
+__device__ __forceinline__ int xcd_remap(int bid, int n) {
+  const int q = n >> 3, r = n & 7;
+  const int x = bid & 7, i = bid >> 3;
+  return x * q + (x < r ? x : r) + i;
+}
+
+// ---------------------------------------------------------------------------
+// Strided complex pass (plain), used for y and z.
+// Field f, line l, column c (0 <= c < ncols), element idx:
+//   in[f * in_fs + l * in_ls + c + idx * in_es]
+// ---------------------------------------------------------------------------
+template <typename T>
+struct StridedArgs {
+  const C2<T>* in;
+  C2<T>* out;
+  const C2<T>* tw;  // exp(-2 pi i e / L), e < L
+  long in_fs, in_ls, in_es;
+  long out_fs, out_ls, out_es;
+  int ncols, ntile, nlines, nf;
+};
+
+template <typename T, int L, int TQ, int TX, int DIR, class RL>
+__global__ __launch_bounds__(TX* TQ) void k_strided(StridedArgs<T> a) {
+  using E = Stockham<T, L, TQ, DIR, RL>;
+  __shared__ C2<T> smem[L * TX];
+  const int tid = threadIdx.x, c = tid % TX, q = tid / TX;
+  int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int tile = blk % a.ntile;
+  blk /= a.ntile;
+  const int line = blk % a.nlines, f = blk / a.nlines;
+  const int col = tile * TX + c;
+  const bool ok = col < a.ncols;
+  const C2<T>* in = a.in + f * a.in_fs + line * a.in_ls + col;
+  C2<T>* out = a.out + f * a.out_fs + line * a.out_ls + col;
+  C2<T> v[E::SLOTS];
+  E::run(v, smem + c, TX, q, a.tw, 1,
+         [&](int, int idx) { return ok ? in[idx * a.in_es] : zero2<T>(); });
+  if constexpr (E::NSTAGE == 1) __syncthreads();  // in place: all reads before any write
+#pragma unroll
+  for (int s = 0; s < E::LAST_NB * E::RL_; ++s)
+    if (ok && E::last_valid(q, s)) out[E::last_index(q, s) * a.out_es] = v[s];
+}
+
+// ---------------------------------------------------------------------------
+// Inverse z pass with the spectral curl prologue.
+// NS : in = u^ (3 fields)  -> out = [u, w]            (6 fields)
+// MHD: in = z+^, z-^ (6)   -> out = [u, w, b, j]      (12 fields)
+// with u = (z+ + z-)/2, b = (z+ - z-)/2, w = i k_d x u, j = i k_d x b.
+// Column (kx, ky) is fixed per thread; idx is kz.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct ZCurlArgs {
+  const C2<T>* in;
+  C2<T>* out;
+  const C2<T>* tw;
+  long in_fs, in_pitch;   // field stride, kx pitch of the input (line = ky)
+  long out_fs, out_pitch;
+  int N, ntile;
+};
+
+template <typename T, int L, int TQ, int TX, class RL, bool MHD>
+__global__ __launch_bounds__(TX* TQ) void k_z_curl(ZCurlArgs<T> a) {
+  using E = Stockham<T, L, TQ, INV, RL>;
+  constexpr int NS_ = E::FIRST_SLOTS;
+  constexpr int NOUT = MHD ? 12 : 6;
+  __shared__ C2<T> smem[L * TX];
+  const int tid = threadIdx.x, c = tid % TX, q = tid / TX;
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int tile = blk % a.ntile, ky = blk / a.ntile;
+  const int N = L;
+  const int col = tile * TX + c;
+  const bool ok = col < N / 2 + 1;
+  const long in_es = (long)N * a.in_pitch, out_es = (long)N * a.out_pitch;
+  const C2<T>* in = a.in + ky * a.in_pitch + col;
+  C2<T>* out = a.out + ky * a.out_pitch + col;
+  const T kx = (T)dwavx(col, N), kyd = (T)dwav(ky, N);
+
+  C2<T> u[3][NS_];
+  C2<T> b[MHD ? 3 : 1][NS_];
+#pragma unroll
+  for (int s = 0; s < NS_; ++s) {
+    const bool v = ok && E::first_valid(q, s);
+    const long off = (long)E::first_index(q, s) * in_es;
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+      if constexpr (MHD) {
+        const C2<T> zp = v ? in[f * a.in_fs + off] : zero2<T>();
+        const C2<T> zm = v ? in[(3 + f) * a.in_fs + off] : zero2<T>();
+        u[f][s] = T(0.5) * (zp + zm);
+        b[f][s] = T(0.5) * (zp - zm);
+      } else {
+        u[f][s] = v ? in[f * a.in_fs + off] : zero2<T>();
+      }
+    }
+  }
+
+#pragma unroll
+  for (int f = 0; f < NOUT; ++f) {
+    const int grp = f / 3, comp = f % 3;
+    C2<T> v[E::SLOTS];
+    E::run(v, smem + c, TX, q, a.tw, 1, [&](int s, int idx) -> C2<T> {
+      auto src = [&](int ff) -> C2<T> {
+        if constexpr (MHD) return grp < 2 ? u[ff][s] : b[ff][s];
+        return u[ff][s];
+      };
+      if ((grp & 1) == 0) return src(comp);
+      const T kz = (T)dwav(idx, N);
+      C2<T> r;
+      if (comp == 0)
+        r = kyd * src(2) - kz * src(1);
+      else if (comp == 1)
+        r = kz * src(0) - kx * src(2);
+      else
+        r = kx * src(1) - kyd * src(0);
+      return mul_i(r);
+    });
+    if constexpr (E::NSTAGE == 1) __syncthreads();
+#pragma unroll
+    for (int s = 0; s < E::LAST_NB * E::RL_; ++s)
+      if (ok && E::last_valid(q, s)) out[f * a.out_fs + E::last_index(q, s) * out_es] = v[s];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Forward z pass with the nonlinear-term epilogue.
+// in: products transformed along x and y (NS: u x w; MHD: u x w + j x b, u x b)
+// N^ = D(k) P(k) F[n] / N^3;  MHD: N+- = D(k) [P(k) F[nL] +- i k_d x F[e]] / N^3
+// mode 0: out = N^
+// mode 1: out (= z*) = z^n + h (N^ - V(z^n))          h = dt/2
+// mode 2: st0 (= z^n, in place) = z^n + h (N^ - V(z*)), h = dt; z* = st1
+// V(z) = nu |k|^2 z (NS);  V(z+-) = |k|^2 (nua z+- + nub z-+) (MHD)
+// ---------------------------------------------------------------------------
+template <typename T>
+struct ZEpiArgs {
+  const C2<T>* in;
+  C2<T>* out;
+  const C2<T>* st0;
+  const C2<T>* st1;
+  const C2<T>* tw;
+  long in_fs, in_pitch;
+  long out_fs, out_pitch;  // out, st0 and st1 share this layout
+  T scale, h, nua, nub;
+  int N, ntile, mode;
+};
+
+template <typename T, int L, int TQ, int TX, class RL, bool MHD>
+__global__ __launch_bounds__(TX* TQ) void k_z_epi(ZEpiArgs<T> a) {
+  using E = Stockham<T, L, TQ, FWD, RL>;
+  constexpr int NF = MHD ? 6 : 3;
+  constexpr int NO = E::LAST_NB * E::RL_;
+  __shared__ C2<T> smem[L * TX];
+  const int tid = threadIdx.x, c = tid % TX, q = tid / TX;
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int tile = blk % a.ntile, ky = blk / a.ntile;
+  const int N = L;
+  const int col = tile * TX + c;
+  const bool ok = col < N / 2 + 1;
+  const long in_es = (long)N * a.in_pitch, out_es = (long)N * a.out_pitch;
+  const C2<T>* in = a.in + ky * a.in_pitch + col;
+
+  C2<T> r[NF][NO];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+    C2<T> v[E::SLOTS];
+    E::run(v, smem + c, TX, q, a.tw, 1,
+           [&](int, int idx) { return ok ? in[f * a.in_fs + idx * in_es] : zero2<T>(); });
+#pragma unroll
+    for (int s = 0; s < NO; ++s) r[f][s] = v[s];
+  }
+  if (!ok) return;  // no barrier follows
+
+  const long base = ky * a.out_pitch + col;
+  const int ikx = col, iky = wav(ky, N);
+  const T kxd = (T)dwavx(col, N), kyd = (T)dwav(ky, N);
+#pragma unroll
+  for (int s = 0; s < NO; ++s) {
+    if (!E::last_valid(q, s)) continue;
+    const int kzi = E::last_index(q, s);
+    const int ikz = wav(kzi, N);
+    const long k2i = (long)ikx * ikx + (long)iky * iky + (long)ikz * ikz;
+    const bool keep = k2i > 0 && 9 * k2i < (long)N * N;
+    const T k2 = (T)k2i;
+    const T kx = (T)ikx, ky_ = (T)iky, kz = (T)ikz;
+    C2<T> nh[NF];
+    if (keep) {
+      const T ik2 = T(1) / k2;
+      C2<T> n0 = a.scale * r[0][s], n1 = a.scale * r[1][s], n2 = a.scale * r[2][s];
+      const C2<T> kn = kx * n0 + ky_ * n1 + kz * n2;
+      n0 = n0 - (kx * ik2) * kn;
+      n1 = n1 - (ky_ * ik2) * kn;
+      n2 = n2 - (kz * ik2) * kn;
+      if constexpr (MHD) {
+        const C2<T> e0 = a.scale * r[3][s], e1 = a.scale * r[4][s], e2 = a.scale * r[5][s];
+        const T kzd = (T)dwav(kzi, N);
+        const C2<T> c0 = mul_i(kyd * e2 - kzd * e1);
+        const C2<T> c1 = mul_i(kzd * e0 - kxd * e2);
+        const C2<T> c2 = mul_i(kxd * e1 - kyd * e0);
+        nh[0] = n0 + c0; nh[1] = n1 + c1; nh[2] = n2 + c2;
+        nh[3] = n0 - c0; nh[4] = n1 - c1; nh[5] = n2 - c2;
+      } else {
+        nh[0] = n0; nh[1] = n1; nh[2] = n2;
+      }
+    } else {
+#pragma unroll
+      for (int f = 0; f < NF; ++f) nh[f] = zero2<T>();
+    }
+    const long pos = base + kzi * out_es;
+    if (a.mode == 0) {
+#pragma unroll
+      for (int f = 0; f < NF; ++f) a.out[f * a.out_fs + pos] = nh[f];
+    } else {
+      const C2<T>* zv = a.mode == 1 ? a.st0 : a.st1;  // field the viscous term acts on
+      C2<T> zz[NF], z0[NF];
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        zz[f] = zv[f * a.out_fs + pos];
+        z0[f] = a.mode == 1 ? zz[f] : a.st0[f * a.out_fs + pos];
+      }
+      C2<T>* dst = a.mode == 1 ? a.out : const_cast<C2<T>*>(a.st0);
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        C2<T> vis = (a.nua * k2) * zz[f];
+        if constexpr (MHD) vis = vis + (a.nub * k2) * zz[f < 3 ? f + 3 : f - 3];
+        dst[f * a.out_fs + pos] = z0[f] + a.h * (nh[f] - vis);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Contiguous x pass.  A row holds N reals or N/2+1 complex coefficients.
+// Half-length method: with M = N/2, z[n] = x[2n] + i x[2n+1],
+//   inverse: Z[k] = (X[k] + X[k+M]) + i e^{+2 pi i k/N} (X[k] - X[k+M]),
+//            X[k+M] = conj X[M-k], and Re X[0], Re X[M] at k = 0;
+//            z = unnormalised inverse M-point DFT of Z.
+//   forward: Z = M-point DFT of z;
+//            X[k] = (Z[k] + conj Z[M-k])/2 - (i/2) e^{-2 pi i k/N} (Z[k] - conj Z[M-k]),
+//            Z[M] := Z[0].
+// The table tw has length N (the M-point transform reads every other entry).
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ C2<T> c2r_pre(const C2<T>* buf, int k, int M, const C2<T>* __restrict__ tw) {
+  C2<T> xk, xm;
+  if (k == 0) {
+    xk = C2<T>{buf[0].x, T(0)};
+    xm = C2<T>{buf[M].x, T(0)};
+  } else {
+    xk = buf[k];
+    xm = conj(buf[M - k]);
+  }
+  return (xk + xm) + mul_i(cmulc(xk - xm, tw[k]));  // conj(tw[k]) = e^{+2 pi i k/N}
+}
+
+template <typename T>
+__device__ __forceinline__ C2<T> r2c_post(const C2<T>* buf, int k, int M, const C2<T>* __restrict__ tw) {
+  const C2<T> zk = buf[k == M ? 0 : k];
+  const C2<T> zm = conj(buf[k == 0 ? 0 : M - k]);
+  const C2<T> e = T(0.5) * (zk + zm);
+  const C2<T> o = T(0.5) * mul_mi(zk - zm);
+  return e + cmul(o, tw[k]);
+}
+
+template <typename T>
+struct XArgs {
+  const C2<T>* in;   // complex rows (pitch in_pitch) or real rows viewed as M complex
+  C2<T>* out;
+  const C2<T>* tw;   // length N
+  long in_fs, in_pitch, out_fs, out_pitch;  // per-row pitch in complex elements
+  long rows;         // rows per field (N*N)
+  int nf;
+};
+
+// plain inverse: complex rows (pitch in_pitch) -> real rows (N reals, pitch out_pitch complex = M)
+template <typename T, int M, int TQ, int G, class RL>
+__global__ __launch_bounds__(G* TQ) void k_x_c2r(XArgs<T> a) {
+  using E = Stockham<T, M, TQ, INV, RL>;
+  constexpr int LP = M + 1;
+  __shared__ C2<T> smem[G * LP];
+  const int tid = threadIdx.x, g = tid / TQ, q = tid % TQ;
+  const long row0 = (long)xcd_remap(blockIdx.x, gridDim.x) * G;
+  const long total = a.rows * a.nf;
+  for (int i = tid; i < G * LP; i += G * TQ) {
+    const int gg = i / LP, k = i % LP;
+    const long row = row0 + gg;
+    C2<T> val = zero2<T>();
+    if (row < total) {
+      const long f = row / a.rows, r = row % a.rows;
+      val = a.in[f * a.in_fs + r * a.in_pitch + k];
+    }
+    smem[i] = val;
+  }
+  __syncthreads();
+  C2<T>* buf = smem + g * LP;
+  C2<T> v[E::SLOTS];
+  E::run(v, buf, 1, q, a.tw, 2, [&](int, int k) { return c2r_pre(buf, k, M, a.tw); });
+  const long row = row0 + g;
+  if (row >= total) return;
+  const long f = row / a.rows, r = row % a.rows;
+  C2<T>* out = a.out + f * a.out_fs + r * a.out_pitch;
+#pragma unroll
+  for (int s = 0; s < E::LAST_NB * E::RL_; ++s)
+    if (E::last_valid(q, s)) out[E::last_index(q, s)] = v[s];
+}
+
+// plain forward: real rows (as M complex, pitch in_pitch) -> complex rows (M+1, pitch out_pitch)
+template <typename T, int M, int TQ, int G, class RL>
+__global__ __launch_bounds__(G* TQ) void k_x_r2c(XArgs<T> a) {
+  using E = Stockham<T, M, TQ, FWD, RL>;
+  constexpr int LP = M + 1;
+  __shared__ C2<T> smem[G * LP];
+  const int tid = threadIdx.x, g = tid / TQ, q = tid % TQ;
+  const long row0 = (long)xcd_remap(blockIdx.x, gridDim.x) * G;
+  const long total = a.rows * a.nf;
+  const long row = row0 + g;
+  const bool ok = row < total;
+  const long f = ok ? row / a.rows : 0, r = ok ? row % a.rows : 0;
+  const C2<T>* in = a.in + f * a.in_fs + r * a.in_pitch;
+  C2<T>* buf = smem + g * LP;
+  C2<T> v[E::SLOTS];
+  E::run(v, buf, 1, q, a.tw, 2, [&](int, int n) { return ok ? in[n] : zero2<T>(); });
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < E::LAST_NB * E::RL_; ++s)
+    if (E::last_valid(q, s)) buf[E::last_index(q, s)] = v[s];
+  __syncthreads();
+  for (int i = tid; i < G * LP; i += G * TQ) {
+    const int gg = i / LP, k = i % LP;
+    const long rw = row0 + gg;
+    if (rw < total) {
+      const long ff = rw / a.rows, rr = rw % a.rows;
+      a.out[ff * a.out_fs + rr * a.out_pitch + k] = r2c_post(smem + gg * LP, k, M, a.tw);
+    }
+  }
+}
+
+// fused: FIN complex input fields -> inverse real FFTs -> cross products ->
+// forward real FFTs -> FOUT complex output fields.  RB rows per workgroup.
+// NS : in [u0 u1 u2 w0 w1 w2]             out [u x w]
+// MHD: in [u0..2 w0..2 b0..2 j0..2]       out [u x w + j x b, u x b]
+template <typename T, int M, int TQ, int RB, class RL, bool MHD>
+__global__ __launch_bounds__((MHD ? 12 : 6) * RB * TQ) void k_x_prod(XArgs<T> a) {
+  constexpr int FIN = MHD ? 12 : 6, FOUT = MHD ? 6 : 3;
+  constexpr int G = FIN * RB, NT = G * TQ;
+  using EI = Stockham<T, M, TQ, INV, RL>;
+  using EF = Stockham<T, M, TQ, FWD, RL>;
+  constexpr int LP = M + 1;
+  __shared__ C2<T> smem[G * LP];
+  const int tid = threadIdx.x, g = tid / TQ, q = tid % TQ;
+  const long row0 = (long)xcd_remap(blockIdx.x, gridDim.x) * RB;
+  // ---- load FIN x RB rows; slot (f, rb) at smem[(f * RB + rb) * LP]
+  for (int i = tid; i < G * LP; i += NT) {
+    const int gr = i / LP, k = i % LP;
+    const int f = gr / RB, rb = gr % RB;
+    const long row = row0 + rb;
+    smem[i] = row < a.rows ? a.in[f * a.in_fs + row * a.in_pitch + k] : zero2<T>();
+  }
+  __syncthreads();
+  // ---- inverse real FFTs, physical values back into the same slot
+  C2<T>* buf = smem + g * LP;
+  {
+    C2<T> v[EI::SLOTS];
+    EI::run(v, buf, 1, q, a.tw, 2, [&](int, int k) { return c2r_pre(buf, k, M, a.tw); });
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < EI::LAST_NB * EI::RL_; ++s)
+      if (EI::last_valid(q, s)) buf[EI::last_index(q, s)] = v[s];
+  }
+  __syncthreads();
+  // ---- products; each C2 holds two neighbouring grid points
+  for (int i = tid; i < RB * M; i += NT) {
+    const int rb = i / M, n = i % M;
+    auto at = [&](int f) -> C2<T>& { return smem[(f * RB + rb) * LP + n]; };
+    const C2<T> u0 = at(0), u1 = at(1), u2 = at(2);
+    const C2<T> w0 = at(3), w1 = at(4), w2 = at(5);
+    auto cx = [](C2<T> a1, C2<T> a2, C2<T> b1, C2<T> b2) {  // a1 b2 - a2 b1 per point
+      return C2<T>{a1.x * b2.x - a2.x * b1.x, a1.y * b2.y - a2.y * b1.y};
+    };
+    C2<T> n0 = cx(u1, u2, w1, w2), n1 = cx(u2, u0, w2, w0), n2 = cx(u0, u1, w0, w1);
+    if constexpr (MHD) {
+      const C2<T> b0 = at(6), b1 = at(7), b2 = at(8);
+      const C2<T> j0 = at(9), j1 = at(10), j2 = at(11);
+      n0 = n0 + cx(j1, j2, b1, b2);
+      n1 = n1 + cx(j2, j0, b2, b0);
+      n2 = n2 + cx(j0, j1, b0, b1);
+      at(3) = cx(u1, u2, b1, b2);
+      at(4) = cx(u2, u0, b2, b0);
+      at(5) = cx(u0, u1, b0, b1);
+    }
+    at(0) = n0;
+    at(1) = n1;
+    at(2) = n2;
+  }
+  __syncthreads();
+  // ---- forward real FFTs of the FOUT product fields (other groups idle on own slots)
+  const bool active = g < FOUT * RB;
+  {
+    C2<T> v[EF::SLOTS];
+    EF::run(v, buf, 1, q, a.tw, 2, [&](int, int n) { return buf[n]; });
+    __syncthreads();
+    if (active) {
+#pragma unroll
+      for (int s = 0; s < EF::LAST_NB * EF::RL_; ++s)
+        if (EF::last_valid(q, s)) buf[EF::last_index(q, s)] = v[s];
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < FOUT * RB * LP; i += NT) {
+    const int gr = i / LP, k = i % LP;
+    const int f = gr / RB, rb = gr % RB;
+    const long row = row0 + rb;
+    if (row < a.rows) a.out[f * a.out_fs + row * a.out_pitch + k] = r2c_post(smem + gr * LP, k, M, a.tw);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Shell spectrum, deterministic.  Kernel 1: one workgroup per kz plane; the
+// thread owning shell s visits, for every ky of the plane, the contiguous kx
+// run of modes with round(|k|) = s and accumulates E(s) and Z(s) with
+// Neumaier compensation in a fixed order.  Kernel 2 sums the per-plane
+// partials over planes in order.  No atomics, so results are bitwise
+// reproducible.
+// ---------------------------------------------------------------------------
+struct NSum {
+  double s, c;
+};
+__device__ __forceinline__ void nadd(NSum& a, double x) {
+  const double t = a.s + x;
+  if (fabs(a.s) >= fabs(x))
+    a.c += (a.s - t) + x;
+  else
+    a.c += (x - t) + a.s;
+  a.s = t;
+}
+
+__device__ __forceinline__ long isqrt_floor(long n) {  // n >= 0
+  long r = (long)sqrt((double)n);
+  while (r > 0 && r * r > n) --r;
+  while ((r + 1) * (r + 1) <= n) ++r;
+  return r;
+}
+
+template <typename T>
+struct SpecArgs {
+  const C2<T>* f;
+  double* part;     // [N][nshell][2] (E, Z) per plane
+  double* pmax;     // [N] max |k_d . f| per plane
+  long fs, pitch;   // field stride, kx pitch
+  int N, nf, nshell;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_spec_planes(SpecArgs<T> a) {
+  const int kz = blockIdx.x, N = a.N, H = N / 2 + 1;
+  const long izw = wav(kz, N);
+  const T kzd = (T)dwav(kz, N);
+  __shared__ double red[256];
+  double mx = 0;
+  for (int s = threadIdx.x; s < a.nshell; s += blockDim.x) {
+    NSum E{0, 0}, Z{0, 0};
+    const long lo2 = (long)(2 * s - 1) * (2 * s - 1);  // shell s: lo2 <= 4|k|^2 < hi2
+    const long hi2 = (long)(2 * s + 1) * (2 * s + 1);
+    for (int ky = 0; ky < N; ++ky) {
+      const long iyw = wav(ky, N);
+      const long A4 = 4 * (iyw * iyw + izw * izw);
+      if (A4 >= hi2) continue;
+      long kx0 = 0;
+      if (s > 0 && lo2 - A4 > 0) {  // smallest kx with 4 kx^2 >= lo2 - A4
+        const long B = lo2 - A4;
+        long t = isqrt_floor(B);
+        if (t * t < B) ++t;  // ceil sqrt
+        kx0 = (t + 1) / 2;
+      }
+      long kx1 = isqrt_floor(hi2 - A4 - 1) / 2;  // largest kx with 4 kx^2 < hi2 - A4
+      if (kx1 > H - 1) kx1 = H - 1;
+      const C2<T>* row = a.f + (long)kz * N * a.pitch + (long)ky * a.pitch;
+      const T kyd = (T)dwav(ky, N);
+      for (long kx = kx0; kx <= kx1; ++kx) {
+        double e = 0;
+        for (int ff = 0; ff < a.nf; ++ff) {
+          const C2<T> v = row[ff * a.fs + kx];
+          e += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+        }
+        const double w = (kx == 0 || 2 * kx == N) ? 0.5 : 1.0;  // (1/2) * weight
+        const long k2 = kx * kx + (iyw * iyw + izw * izw);
+        nadd(E, w * e);
+        nadd(Z, w * (double)k2 * e);
+        const T kxd = (T)dwavx((int)kx, N);
+        for (int ff = 0; ff + 2 < a.nf; ff += 3) {
+          const C2<T> v0 = row[ff * a.fs + kx], v1 = row[(ff + 1) * a.fs + kx], v2 = row[(ff + 2) * a.fs + kx];
+          const double dx = (double)kxd * v0.x + (double)kyd * v1.x + (double)kzd * v2.x;
+          const double dy = (double)kxd * v0.y + (double)kyd * v1.y + (double)kzd * v2.y;
+          const double d = sqrt(dx * dx + dy * dy);
+          mx = d > mx ? d : mx;
+        }
+      }
+    }
+    double* p = a.part + ((long)kz * a.nshell + s) * 2;
+    p[0] = E.s + E.c;
+    p[1] = Z.s + Z.c;
+  }
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) a.pmax[kz] = red[0];
+}
+
+}  // namespace ps

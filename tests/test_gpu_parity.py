@@ -1,0 +1,126 @@
+"""HIP path against the FP64 oracle, element by element, at sizes the oracle
+finishes in seconds (several tiles and a ragged kx tail in every pass).
+
+Tolerances (relative L2 over all stored values):
+  FP64: 1e-13 for transforms, 1e-12 for nonlinear terms and RK2 steps
+        (the bar the method's FP64 form is held to);
+  FP32: transforms 2e-6 (rounding eps32 = 6e-8 times O(log N) butterfly
+        levels with headroom), nonlinear terms 2e-5 (two transforms and a
+        product; the term is a difference of O(1) quantities), RK2 state after
+        one step 2e-6 from identical FP32 inputs.
+"""
+import numpy as np
+import pytest
+
+from gpu_util import DEV, host, rel_l2, rel_l2_w, rounded, say, to_dev
+from oracle.psref import MHD, NS
+from paper_1003_4322_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL_FFT = {"f64": 1e-13, "f32": 2e-6}
+TOL_NL = {"f64": 1e-12, "f32": 2e-5}
+TOL_STEP = {"f64": 1e-12, "f32": 2e-6}
+
+FFT_SIZES = [8, 12, 16, 24, 32, 48, 64, 96, 128]
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_1003_4322_amd import binding
+    binding.lib()
+    return binding
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("N", FFT_SIZES)
+def test_fft_r2c(B, ref, N, dt):
+    say("fft_r2c", N, dt)
+    rng = np.random.default_rng(100 + N)
+    u = rounded(rng.standard_normal((3, N, N, N)), dt)
+    p = B.Plan(N, 3, dt)
+    got = host(p.fft_r2c(to_dev(u, dt, "r")))
+    want = ref.fft_r2c(u)
+    assert rel_l2(got, want) < TOL_FFT[dt], rel_l2(got, want)
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("N", FFT_SIZES)
+def test_fft_c2r(B, ref, N, dt):
+    say("fft_c2r", N, dt)
+    rng = np.random.default_rng(200 + N)
+    s = (3, N, N, N // 2 + 1)
+    X = rounded(rng.standard_normal(s) + 1j * rng.standard_normal(s), dt)  # not Hermitian
+    p = B.Plan(N, 3, dt)
+    xd = to_dev(X, dt)
+    got = host(p.fft_c2r(xd))
+    want = ref.fft_c2r(X)
+    assert rel_l2(got, want) < TOL_FFT[dt], rel_l2(got, want)
+    assert np.array_equal(host(xd), X)  # input preserved
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("N", [8, 16, 24, 32, 48, 64])
+def test_nonlinear_ns(B, ref, N, dt):
+    say("nonlinear_ns", N, dt)
+    u = rounded(synth.random_ns(N, 1000 + N, 2.0 if N < 32 else 3.0), dt)
+    p = B.Plan(N, 3, dt)
+    got = host(p.nonlinear_ns(to_dev(u, dt)))
+    want = ref.nonlinear_ns(u)
+    assert rel_l2_w(got, want) < TOL_NL[dt], rel_l2_w(got, want)
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("N", [8, 16, 24, 32, 48])
+def test_nonlinear_mhd(B, ref, N, dt):
+    say("nonlinear_mhd", N, dt)
+    z = rounded(synth.random_mhd(N, 2000 + N, 3000 + N, 2.0), dt)
+    p = B.Plan(N, 6, dt)
+    got = host(p.nonlinear_mhd(to_dev(z, dt)))
+    want = ref.nonlinear_mhd(z)
+    assert rel_l2_w(got, want) < TOL_NL[dt], rel_l2_w(got, want)
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_rk2_ns_32_one_step(B, ref, dt):
+    """NS 32^3, nu = 0.02, dt = 1e-3, seed 1, k0 = 2, E = 0.5: one RK2 step."""
+    say("rk2 ns 32", dt)
+    u0 = rounded(synth.random_ns(32, 1, 2.0), dt)
+    p = B.Plan(32, 3, dt)
+    s = to_dev(u0, dt)
+    p.rk2_step(s, B.PS_NS, 0.02, 0.0, 1e-3, 1)
+    got = host(s)
+    want = ref.rk2_step(u0, NS, 0.02, 0.0, 1e-3, 1)
+    assert rel_l2_w(got, want) < TOL_STEP[dt], rel_l2_w(got, want)
+    # increment error, informational bar: the change over the step itself
+    inc = rel_l2_w(got - u0, want - u0)
+    assert inc < (1e-10 if dt == "f64" else 1e-3), inc
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("graphs", [True, False])
+def test_rk2_mhd_steps(B, ref, dt, graphs):
+    say("rk2 mhd 24", dt, graphs)
+    N = 24
+    z0 = rounded(synth.random_mhd(N, 3, 4, 2.0), dt)
+    p = B.Plan(N, 6, dt)
+    p.set_graphs(graphs)
+    s = to_dev(z0, dt)
+    p.rk2_step(s, B.PS_MHD, 0.02, 0.01, 2e-3, 3)
+    got = host(s)
+    want = ref.rk2_step(z0, MHD, 0.02, 0.01, 2e-3, 3)
+    assert rel_l2_w(got, want) < 3 * TOL_STEP[dt], rel_l2_w(got, want)
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("N", [8, 16, 32, 48])
+def test_spectrum(B, ref, N, dt):
+    say("spectrum", N, dt)
+    rng = np.random.default_rng(300 + N)
+    s = (3, N, N, N // 2 + 1)
+    F = rounded(rng.standard_normal(s) + 1j * rng.standard_normal(s), dt)
+    p = B.Plan(N, 3, dt)
+    spec, tot = p.energy_spectrum(to_dev(F, dt))
+    ws, wt = ref.energy_spectrum(F)
+    assert np.allclose(host(spec), ws, rtol=1e-13, atol=0)
+    assert np.allclose(host(tot), wt, rtol=1e-12, atol=0)
