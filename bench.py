@@ -1,0 +1,312 @@
+#!/usr/bin/env python3
+"""Benchmark of the pseudospectral RK2 hot path on one MI355X.
+
+Default workload: incompressible MHD in Elsasser variables on a 512^3 box,
+6 fields batched, nu = eta = 5e-4, dt = 1e-3; u and b independent
+random-phase solenoidal fields (seeds 3 and 4) with E(k) ~ k^4 exp(-2 (k/3)^2)
+and E_u = E_b = 1/2.  The FP32 form is the headline; the FP64 form runs the
+same steps from the same (FP32-representable) initial state, and the relative
+L2 distance between the two is reported.
+
+One JSON line goes to stdout; progress goes to stderr.  The timed region is
+K RK2 steps bracketed by torch.cuda.synchronize(), with a HIP event pair
+around every kernel on the plan's stream; per-kernel average durations and
+the library's algorithmic byte counts give the achieved GB/s per pass.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "RK2 steps/s + FFT GB/s (%HBM peak) at 512^3, FP32 vs FP64 at stated L2 err"
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    # name: (N, model, nu, eta, dt, seeds, k0)
+    "mhd512": dict(N=512, model="mhd", nu=5e-4, eta=5e-4, dt=1e-3, seeds=(3, 4), k0=3.0),
+    "ns256": dict(N=256, model="ns", nu=1e-3, eta=0.0, dt=2e-3, seeds=(2,), k0=4.0),
+    "ns1024": dict(N=1024, model="ns", nu=2e-4, eta=0.0, dt=5e-4, seeds=(5,), k0=4.0),
+    "ns32": dict(N=32, model="ns", nu=0.02, eta=0.0, dt=1e-3, seeds=(1,), k0=2.0),
+    "ns512": dict(N=512, model="ns", nu=5e-4, eta=0.0, dt=1e-3, seeds=(3,), k0=3.0),
+}
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def src_hash() -> str:
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_1003_4322_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".hpp", ".cpp")):
+            h.update(f.encode())
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def initial_state(w, dtype_c, device):
+    """Sparse low-wavenumber cube from the generator, scattered on the GPU."""
+    import numpy as np
+    import torch
+
+    from paper_1003_4322_amd import synth
+
+    N = w["N"]
+    if w["model"] == "mhd":
+        sf = synth.mhd_sparse(N, w["seeds"][0], w["seeds"][1], w["k0"])
+    else:
+        sf = synth.random_solenoidal(N, w["seeds"][0], w["k0"])
+    nf = sf.values.shape[0]
+    st = torch.zeros((nf, N, N, N // 2 + 1), dtype=dtype_c, device=device)
+    iz, iy, ix = sf.index_arrays()
+    vals = torch.from_numpy(np.ascontiguousarray(sf.values)).to(device=device, dtype=dtype_c)
+    fi = torch.arange(nf, device=device).view(-1, 1, 1, 1)
+    zi = torch.as_tensor(iz, device=device).view(1, -1, 1, 1)
+    yi = torch.as_tensor(iy, device=device).view(1, 1, -1, 1)
+    xi = torch.as_tensor(ix, device=device).view(1, 1, 1, -1)
+    st.index_put_((fi, zi, yi, xi), vals)
+    return st, sf
+
+
+def rel_l2_w(a, b):
+    import torch
+    N = a.shape[-2]
+    w = torch.full((N // 2 + 1,), 2.0, dtype=torch.float64, device=a.device)
+    w[0] = 1.0
+    w[-1] = 1.0
+    d = (a.to(torch.complex128) - b.to(torch.complex128)).abs() ** 2
+    n = b.to(torch.complex128).abs() ** 2
+    return math.sqrt(float((d * w).sum() / (n * w).sum()))
+
+
+def run_timed(plan, state, model, w, steps, warmup):
+    """Warmup (graph replay), then the timed region with per-kernel events.
+    Returns (ms_per_step, per-kernel stats, ms_per_step_graph)."""
+    import torch
+
+    plan.set_timing(False)
+    plan.rk2_step(state, model, w["nu"], w["eta"], w["dt"], warmup)
+    torch.cuda.synchronize()
+    # graph-replay rate (informational; the reported value is the timed region below)
+    t0 = time.perf_counter()
+    plan.rk2_step(state, model, w["nu"], w["eta"], w["dt"], steps)
+    torch.cuda.synchronize()
+    ms_graph = (time.perf_counter() - t0) * 1e3 / max(steps, 1)
+    plan.set_timing(True)
+    plan.timing_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.rk2_step(state, model, w["nu"], w["eta"], w["dt"], steps)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / max(steps, 1)
+    stats = plan.timings()
+    plan.set_timing(False)
+    return ms, stats, ms_graph
+
+
+def pass_table(stats):
+    out = {}
+    for k, s in stats.items():
+        avg = s["total_ms"] / max(s["launches"], 1)
+        gbs = s["bytes_per_launch"] / (avg * 1e-3) / 1e9 if avg > 0 else 0.0
+        out[k] = {"avg_ms": round(avg, 5), "launches": s["launches"],
+                  "GB_per_launch": round(s["bytes_per_launch"] / 1e9, 6),
+                  "GB/s": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4),
+                  "share_of_time": None}
+    tot = sum(s["total_ms"] for s in stats.values()) or 1.0
+    for k, s in stats.items():
+        out[k]["share_of_time"] = round(s["total_ms"] / tot, 4)
+    return out
+
+
+def load_traffic(kernel_kind, workload, dtype):
+    """HBM traffic per launch from committed rocprofv3 counter runs, only if
+    the kernel sources are unchanged since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+    except Exception:
+        return None
+    key = f"{workload}/{dtype}/{kernel_kind}"
+    r = rec.get(key)
+    if not r or r.get("src_hash") != src_hash():
+        return None
+    return r.get("bytes_per_launch")
+
+
+def device_copy(nbytes: int = 1 << 31, reps: int = 10):
+    """A plain device-to-device copy of known size (torch copy kernel): the
+    practical HBM rate on this device and the reference for scaling the
+    FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+
+    n = nbytes // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        y.copy_(x)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    del x, y
+    torch.cuda.empty_cache()
+    return {"bytes_read": nbytes, "bytes_written": nbytes, "ms": round(ms, 4),
+            "GB/s": round(2 * nbytes / (ms * 1e-3) / 1e9, 1)}
+
+
+def cpu_baseline(w, sample_N):
+    """The FP64 oracle timed on this host for one RK2 step at sample_N^3 of
+    the same workload recipe, scaled to the workload's N by N^3 log N."""
+    import numpy as np
+
+    from oracle.psref import MHD, NS, oracle
+    from paper_1003_4322_amd import synth
+
+    o = oracle()
+    threads = o.set_threads(0)
+    if w["model"] == "mhd":
+        z = synth.random_mhd(sample_N, w["seeds"][0], w["seeds"][1], w["k0"], dtype=np.complex64)
+        model = MHD
+    else:
+        z = synth.random_ns(sample_N, w["seeds"][0], w["k0"], dtype=np.complex64)
+        model = NS
+    z = z.astype(np.complex128)
+    t0 = time.perf_counter()
+    o.rk2_step(z, model, w["nu"], w["eta"], w["dt"], 1)
+    t = time.perf_counter() - t0
+    N = w["N"]
+    scale = (N / sample_N) ** 3 * math.log(N) / math.log(sample_N)
+    return {"value": 1.0 / (t * scale), "unit": "steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"one FP64 RK2 step of the same recipe at {sample_N}^3 took {t:.2f} s; "
+                      f"scaled to {N}^3 by (N/{sample_N})^3 log N / log {sample_N} = {scale:.2f}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="mhd512", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=256)
+    ap.add_argument("--copy-only", action="store_true",
+                    help="only the reference device copy (for counter scaling)")
+    ap.add_argument("--no-tune", action="store_true", help="default kernel variants")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: the hot path keeps the whole box on one device "
+              f"and has no multi-GPU path (asked for --gpus {args.gpus}).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1003_4322_amd import binding
+
+    w = WORKLOADS[args.workload]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    if args.copy_only:
+        print(json.dumps({"device_copy": device_copy()}), flush=True)
+        return
+    copy_ref = device_copy()
+    log(f"device copy: {copy_ref['GB/s']} GB/s")
+    model = binding.PS_MHD if w["model"] == "mhd" else binding.PS_NS
+    nf = 6 if w["model"] == "mhd" else 3
+    N = w["N"]
+    log(f"workload {args.workload}: N={N} fields={nf} steps={args.steps} warmup={args.warmup}")
+
+    s32, _ = initial_state(w, torch.complex64, dev)
+    s32_0 = s32.clone()
+    plan32 = binding.Plan(N, nf, "f32", device=dev)
+    log("fp32 plan ready, workspace GB", plan32.workspace_bytes() / 1e9)
+    tuned32 = None if args.no_tune else plan32.autotune(s32, model, 3)
+    log("fp32 variants", tuned32)
+    ms, stats, ms_graph = run_timed(plan32, s32, model, w, args.steps, args.warmup)
+    passes32 = pass_table(stats)
+    log(f"fp32: {ms:.3f} ms/step (graph replay {ms_graph:.3f})")
+
+    dom = max(stats, key=lambda k: stats[k]["total_ms"])
+    d = passes32[dom]
+    traffic = load_traffic(dom, args.workload, "f32")
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": d["GB/s"], "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(d["GB/s"] / HBM_PEAK_GBS, 4),
+                "traffic": traffic}
+
+    fp64 = None
+    if not args.no_fp64:
+        s64 = s32_0.to(torch.complex128)
+        s64_0 = s64.clone()
+        del plan32
+        torch.cuda.empty_cache()
+        plan64 = binding.Plan(N, nf, "f64", device=dev)
+        tuned64 = None if args.no_tune else plan64.autotune(s64, model, 3)
+        log("fp64 variants", tuned64)
+        ms64, stats64, ms64_graph = run_timed(plan64, s64, model, w, args.steps, args.warmup)
+        log(f"fp64: {ms64:.3f} ms/step (graph replay {ms64_graph:.3f})")
+        # same number of steps from the same initial state in both precisions
+        l2_run = rel_l2_w(s32, s64)
+        # one step from the identical initial state
+        a, b = s32_0.clone(), s64_0.clone()
+        plan64.rk2_step(b, model, w["nu"], w["eta"], w["dt"], 1)
+        del plan64
+        torch.cuda.empty_cache()
+        plan32 = binding.Plan(N, nf, "f32", device=dev)
+        for k, v in (tuned32 or {}).items():
+            plan32.set_variant(k, v)
+        plan32.rk2_step(a, model, w["nu"], w["eta"], w["dt"], 1)
+        torch.cuda.synchronize()
+        l2_1 = rel_l2_w(a, b)
+        inc = rel_l2_w(a.to(torch.complex128) - s64_0, b - s64_0)
+        fp64 = {"steps_per_s": round(1e3 / ms64, 3), "ms_per_step": round(ms64, 3),
+                "ms_per_step_graph": round(ms64_graph, 3), "passes": pass_table(stats64),
+                "variants": tuned64,
+                "l2_f32_vs_f64_one_step": l2_1,
+                "l2_f32_vs_f64_increment_one_step": inc,
+                f"l2_f32_vs_f64_after_{args.warmup + 2 * args.steps}_steps": l2_run,
+                "tolerance_per_step": 2e-6}
+        log(f"fp32 vs fp64: one step {l2_1:.3e}, increment {inc:.3e}, run {l2_run:.3e}")
+
+    cpu = None
+    if not args.no_cpu:
+        log(f"cpu baseline: oracle, one step at {args.cpu_sample}^3")
+        cpu = cpu_baseline(w, args.cpu_sample)
+
+    line = {
+        "metric": METRIC, "value": round(1e3 / ms, 3), "unit": "steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{'MHD Elsasser' if nf == 6 else 'NS'} {N}^3 RK2, {nf} fields "
+                               f"batched, nu={w['nu']}, eta={w['eta']}, dt={w['dt']}, "
+                               f"random-phase k0={w['k0']} seeds {list(w['seeds'])}",
+                   "N": N, "fields": nf},
+        "ms_per_step_graph": round(ms_graph, 4),
+        "variants": tuned32,
+        "passes": passes32,
+        "device_copy": copy_ref,
+        "roofline": roofline,
+        "fp64": fp64,
+        "cpu_baseline": cpu,
+        "src_hash": src_hash(),
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -135,6 +135,20 @@ ps_status ps_rk2_step(ps_plan p, void *state, ps_model m, double nu, double eta,
 ps_status ps_energy_spectrum(ps_plan p, const void *fhat, int nfields, double *spec_dev,
                              double *totals_dev);
 
+/* Kernel variants.  Pass kinds: "y", "z" (plain strided passes), "z_curl",
+ * "z_epi", "x_prod".  Variant 0 is the default; others change the tile width
+ * or the register/LDS trade-off of a pass (results are identical up to
+ * rounding order).  Setting a variant drops a cached graph. */
+ps_status ps_plan_set_variant(ps_plan p, const char *kind, int variant);
+int ps_plan_get_variant(ps_plan p, const char *kind);
+int ps_plan_variant_count(ps_plan p, const char *kind);
+
+/* Autotuner: times every variant of the RK2 passes (z_curl, y, x_prod, z_epi)
+ * reps times on the caller's state for model m and keeps the fastest.  Reads
+ * state, writes only the workspace; synchronises the plan's stream.  Plan
+ * time, like FFT planning, is not part of a step. */
+ps_status ps_plan_autotune(ps_plan p, const void *state, ps_model m, int reps);
+
 /* Per-kernel timing with HIP events on the plan's stream (disables graph
  * replay while on).  Statistics accumulate until ps_plan_timing_reset. */
 ps_status ps_plan_set_timing(ps_plan p, int enable);

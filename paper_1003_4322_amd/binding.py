@@ -39,6 +39,10 @@ _SIGS = [
     ("ps_nonlinear_mhd", _i, [_vp, _vp, _vp]),
     ("ps_rk2_step", _i, [_vp, _vp, _i, _d, _d, _d, _i]),
     ("ps_energy_spectrum", _i, [_vp, _vp, _i, _vp, _vp]),
+    ("ps_plan_set_variant", _i, [_vp, ctypes.c_char_p, _i]),
+    ("ps_plan_get_variant", _i, [_vp, ctypes.c_char_p]),
+    ("ps_plan_variant_count", _i, [_vp, ctypes.c_char_p]),
+    ("ps_plan_autotune", _i, [_vp, _vp, _i, _i]),
     ("ps_plan_set_timing", _i, [_vp, _i]),
     ("ps_plan_set_graphs", _i, [_vp, _i]),
     ("ps_plan_timing_reset", _i, [_vp]),
@@ -258,6 +262,27 @@ class Plan:
         _check(lib().ps_energy_spectrum(self.handle, _ptr(fhat), nf, _ptr(spec), _ptr(tot)),
                "ps_energy_spectrum")
         return spec, tot
+
+    # -- variants and autotuning ---------------------------------------------------
+    KINDS = ("y", "z", "z_curl", "z_epi", "x_prod")
+
+    def set_variant(self, kind: str, v: int):
+        _check(lib().ps_plan_set_variant(self.handle, kind.encode(), int(v)), "set_variant")
+
+    def variant(self, kind: str) -> int:
+        return int(lib().ps_plan_get_variant(self.handle, kind.encode()))
+
+    def variant_count(self, kind: str) -> int:
+        return int(lib().ps_plan_variant_count(self.handle, kind.encode()))
+
+    def variants(self) -> Dict[str, int]:
+        return {k: self.variant(k) for k in self.KINDS}
+
+    def autotune(self, state: torch.Tensor, model: int, reps: int = 3) -> Dict[str, int]:
+        self._need(state, "c", "state")
+        self._stream()
+        _check(lib().ps_plan_autotune(self.handle, _ptr(state), int(model), int(reps)), "autotune")
+        return self.variants()
 
     # -- timing ----------------------------------------------------------------
     def set_timing(self, on: bool):

@@ -17,7 +17,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libps.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["k_zpass.hip", "k_xpass.hip", "k_strided.hip", "k_spectrum.hip", "ps_api.cpp"]
+SOURCES = [f"k_{p}_{t}.hip" for p in ("zcurl", "zepi", "xpass", "strided") for t in ("f32", "f64")] + [
+    "k_spectrum.hip", "ps_api.cpp"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

@@ -1,8 +1,31 @@
 // Deterministic FP64 shell spectrum.
+#include <cstring>
+
 #include "ps_config.hpp"
 #include "ps_launch.hpp"
 
 namespace ps {
+
+bool size_supported(int N) {
+  switch (N) {
+#define PS_CASE(NN) case NN:
+    PS_FOR_EACH_N(PS_CASE)
+#undef PS_CASE
+    return true;
+    default:
+      return false;
+  }
+}
+
+int variant_count(const char* kind, int N, bool mhd) {
+  (void)mhd;
+  if (!has_variants(N)) return 1;
+  if (!strcmp(kind, "z_curl")) return NZCURL;
+  if (!strcmp(kind, "z_epi")) return NZEPI;
+  if (!strcmp(kind, "y") || !strcmp(kind, "z")) return NSTR;
+  if (!strcmp(kind, "x_prod")) return NXPROD;
+  return 1;
+}
 
 // Second stage: per-shell sums over planes in plane order, then the totals in
 // shell order, all Neumaier-compensated (one workgroup).

@@ -1,0 +1,6 @@
+// Fused inverse z pass + spectral curl prologue, float.
+#include "ps_launch_impl.hpp"
+
+namespace ps {
+template hipError_t launch_z_curl<float>(int, bool, int, ZCurlArgs<float>, hipStream_t);
+}  // namespace ps

@@ -1,0 +1,6 @@
+// Fused inverse z pass + spectral curl prologue, double.
+#include "ps_launch_impl.hpp"
+
+namespace ps {
+template hipError_t launch_z_curl<double>(int, bool, int, ZCurlArgs<double>, hipStream_t);
+}  // namespace ps

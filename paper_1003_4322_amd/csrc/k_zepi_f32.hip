@@ -1,0 +1,6 @@
+// Fused forward z pass + dealias / projection / induction / RK2 epilogue, float.
+#include "ps_launch_impl.hpp"
+
+namespace ps {
+template hipError_t launch_z_epi<float>(int, bool, int, ZEpiArgs<float>, hipStream_t);
+}  // namespace ps

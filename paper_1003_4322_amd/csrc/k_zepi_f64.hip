@@ -1,0 +1,6 @@
+// Fused forward z pass + dealias / projection / induction / RK2 epilogue, double.
+#include "ps_launch_impl.hpp"
+
+namespace ps {
+template hipError_t launch_z_epi<double>(int, bool, int, ZEpiArgs<double>, hipStream_t);
+}  // namespace ps

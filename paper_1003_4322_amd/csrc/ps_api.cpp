@@ -82,6 +82,8 @@ struct ps_plan_s {
   bool graphs = true;
   hipGraphExec_t gexec = nullptr;
   std::string gkey;
+  // kernel variants per pass kind (chosen by ps_plan_autotune or by hand)
+  std::map<std::string, int> var;
   // timing
   bool timing = false;
   std::vector<TimingRec> pending;
@@ -92,6 +94,13 @@ struct ps_plan_s {
 namespace {
 
 size_t csize(const ps_plan_s* p) { return p->dtype == PS_F32 ? 8 : 16; }
+
+const char* const KINDS[] = {"y", "z", "z_curl", "z_epi", "x_prod"};
+
+int var_of(const ps_plan_s* p, const char* kind) {
+  auto it = p->var.find(kind);
+  return it == p->var.end() ? 0 : it->second;
+}
 size_t rsize(const ps_plan_s* p) { return p->dtype == PS_F32 ? 4 : 8; }
 
 template <typename T>
@@ -196,8 +205,9 @@ struct Seq {
     a.in_es = a.out_es = pitch;
     a.ncols = (int)b.H; a.nlines = b.N; a.nf = nf;
     const double bytes = 2.0 * nf * b.nc * cs();
+    const int v = var_of(p, "y");
     return enqueue(p, s, dir == ps::FWD ? "y_fwd" : "y_inv", bytes,
-                   [&](hipStream_t st) { return ps::launch_strided<T>(b.N, dir, a, st); });
+                   [&](hipStream_t st) { return ps::launch_strided<T>(b.N, dir, v, a, st); });
   }
   ps_status zpass(const C* in, long in_pitch, C* out, long out_pitch, int nf, int dir) {
     ps::StridedArgs<T> a{};
@@ -207,8 +217,9 @@ struct Seq {
     a.in_es = (long)b.N * in_pitch; a.out_es = (long)b.N * out_pitch;
     a.ncols = (int)b.H; a.nlines = b.N; a.nf = nf;
     const double bytes = 2.0 * nf * b.nc * cs();
+    const int v = var_of(p, "z");
     return enqueue(p, s, dir == ps::FWD ? "z_fwd" : "z_inv", bytes,
-                   [&](hipStream_t st) { return ps::launch_strided<T>(b.N, dir, a, st); });
+                   [&](hipStream_t st) { return ps::launch_strided<T>(b.N, dir, v, a, st); });
   }
 
   ps_status r2c(const T* real_in, C* out) {
@@ -240,33 +251,58 @@ struct Seq {
     return enqueue(p, s, "x_c2r", bytes, [&](hipStream_t q) { return ps::launch_x_c2r<T>(b.N, a, q); });
   }
 
-  // nonlinear right-hand side, epilogue mode 0/1/2 (see k_z_epi)
-  ps_status rhs(const C* src, bool mhd, int mode, C* out, const C* st0, const C* st1, T h, T nua, T nub) {
-    const int nin = mhd ? 6 : 3, nphys = mhd ? 12 : 6, nprod = mhd ? 6 : 3;
-    C* w = work();
+  // the five passes of one right-hand side evaluation
+  ps_status pass_zcurl(const C* src, bool mhd) {
+    const int nin = mhd ? 6 : 3, nphys = mhd ? 12 : 6;
     ps::ZCurlArgs<T> ca{};
-    ca.in = src; ca.out = w; ca.tw = tw();
+    ca.in = src; ca.out = work(); ca.tw = tw();
     ca.in_fs = b.nc; ca.in_pitch = b.H; ca.out_fs = b.ncp; ca.out_pitch = b.P; ca.N = b.N;
-    ps_status st = enqueue(p, s, "z_curl", (nin + nphys) * b.nc * cs(),
-                           [&](hipStream_t q) { return ps::launch_z_curl<T>(b.N, mhd, ca, q); });
-    if (st) return st;
-    if ((st = ypass(w, b.P, nphys, ps::INV))) return st;
+    const int v = var_of(p, "z_curl");
+    return enqueue(p, s, "z_curl", (nin + nphys) * b.nc * cs(),
+                   [&](hipStream_t q) { return ps::launch_z_curl<T>(b.N, mhd, v, ca, q); });
+  }
+  ps_status pass_xprod(bool mhd) {
+    const int nphys = mhd ? 12 : 6, nprod = mhd ? 6 : 3;
     ps::XArgs<T> xa{};
-    xa.in = w; xa.out = w; xa.tw = tw();
+    xa.in = work(); xa.out = work(); xa.tw = tw();
     xa.in_pitch = xa.out_pitch = b.P; xa.in_fs = xa.out_fs = b.ncp;
     xa.rows = (long)b.N * b.N; xa.nf = nphys;
-    st = enqueue(p, s, "x_prod", (nphys + nprod) * b.nc * cs(),
-                 [&](hipStream_t q) { return ps::launch_x_prod<T>(b.N, mhd, xa, q); });
-    if (st) return st;
-    if ((st = ypass(w, b.P, nprod, ps::FWD))) return st;
+    const int v = var_of(p, "x_prod");
+    return enqueue(p, s, "x_prod", (nphys + nprod) * b.nc * cs(),
+                   [&](hipStream_t q) { return ps::launch_x_prod<T>(b.N, mhd, v, xa, q); });
+  }
+  ps_status pass_zepi(bool mhd, int mode, C* out, const C* st0, const C* st1, T h, T nua, T nub) {
+    const int nprod = mhd ? 6 : 3;
     ps::ZEpiArgs<T> ea{};
-    ea.in = w; ea.out = out; ea.st0 = st0; ea.st1 = st1; ea.tw = tw();
+    ea.in = work(); ea.out = out; ea.st0 = st0; ea.st1 = st1; ea.tw = tw();
     ea.in_fs = b.ncp; ea.in_pitch = b.P; ea.out_fs = b.nc; ea.out_pitch = b.H;
     ea.scale = (T)(1.0 / ((double)b.N * b.N * b.N));
     ea.h = h; ea.nua = nua; ea.nub = nub; ea.N = b.N; ea.mode = mode;
     const int nrw = mode == 0 ? 0 : (mode == 1 ? 1 : 2);
+    const int v = var_of(p, "z_epi");
     return enqueue(p, s, "z_epi", (nprod + nprod + nrw * nprod) * b.nc * cs(),
-                   [&](hipStream_t q) { return ps::launch_z_epi<T>(b.N, mhd, ea, q); });
+                   [&](hipStream_t q) { return ps::launch_z_epi<T>(b.N, mhd, v, ea, q); });
+  }
+
+  // nonlinear right-hand side, epilogue mode 0/1/2 (see k_z_epi)
+  ps_status rhs(const C* src, bool mhd, int mode, C* out, const C* st0, const C* st1, T h, T nua, T nub) {
+    const int nphys = mhd ? 12 : 6, nprod = mhd ? 6 : 3;
+    ps_status st = pass_zcurl(src, mhd);
+    if (st) return st;
+    if ((st = ypass(work(), b.P, nphys, ps::INV))) return st;
+    if ((st = pass_xprod(mhd))) return st;
+    if ((st = ypass(work(), b.P, nprod, ps::FWD))) return st;
+    return pass_zepi(mhd, mode, out, st0, st1, h, nua, nub);
+  }
+
+  // one launch of pass `kind` on the plan's buffers (tuning); only the
+  // workspace is written
+  ps_status tune_launch(const char* kind, const C* state, bool mhd) {
+    if (!strcmp(kind, "z_curl")) return pass_zcurl(state, mhd);
+    if (!strcmp(kind, "y")) return ypass(work(), b.P, mhd ? 12 : 6, ps::INV);
+    if (!strcmp(kind, "x_prod")) return pass_xprod(mhd);
+    if (!strcmp(kind, "z_epi")) return pass_zepi(mhd, 0, zstar(), nullptr, nullptr, T(0), T(0), T(0));
+    return fail(PS_ERR_ARG, std::string("no tuning launch for kind ") + kind);
   }
 
   ps_status rk2(C* state, bool mhd, double nu, double eta, double dt) {
@@ -439,6 +475,15 @@ ps_status ps_plan_create_batch(ps_plan* out, int nbox, const int* Ns, int nfield
         return st;
       }
       b.tw = p->tables[b.N];
+    }
+    // measured defaults at 512^3 (the autotuner refines them per workload)
+    bool any_var = false;
+    for (auto& b : p->boxes) any_var |= ps::variant_count("z_curl", b.N, nfields == 6) > 1;
+    if (any_var) {
+      p->var["z_curl"] = 1;
+      p->var["z_epi"] = 1;
+      p->var["x_prod"] = dtype == PS_F32 ? 1 : 2;
+      p->var["y"] = dtype == PS_F32 ? 2 : 0;
     }
     e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
     if (e != hipSuccess) {
@@ -652,6 +697,97 @@ ps_status ps_energy_spectrum(ps_plan p, const void* fhat, int nfields, double* s
       }
       return PS_OK;
     });
+  });
+}
+
+ps_status ps_plan_set_variant(ps_plan p, const char* kind, int v) {
+  if (ps_status st = validate_plan(p)) return st;
+  if (!kind) return fail(PS_ERR_ARG, "kind is NULL");
+  bool known = false;
+  for (const char* k : KINDS) known |= !strcmp(k, kind);
+  if (!known) return fail(PS_ERR_ARG, std::string("unknown pass kind ") + kind);
+  int n = 1;
+  for (auto& b : p->boxes) n = std::max(n, ps::variant_count(kind, b.N, p->nfields == 6));
+  if (v < 0 || v >= n) return fail(PS_ERR_ARG, "variant out of range");
+  p->var[kind] = v;
+  if (p->gexec) {
+    hipGraphExecDestroy(p->gexec);
+    p->gexec = nullptr;
+    p->gkey.clear();
+  }
+  return PS_OK;
+}
+
+int ps_plan_get_variant(ps_plan p, const char* kind) {
+  if (!p || !kind) return PS_ERR_ARG;
+  return var_of(p, kind);
+}
+
+int ps_plan_variant_count(ps_plan p, const char* kind) {
+  if (!p || !kind) return PS_ERR_ARG;
+  int n = 1;
+  for (auto& b : p->boxes) n = std::max(n, ps::variant_count(kind, b.N, p->nfields == 6));
+  return n;
+}
+
+ps_status ps_plan_autotune(ps_plan p, const void* state, ps_model m, int reps) {
+  return guarded([&]() -> ps_status {
+    if (ps_status st = validate_plan(p)) return st;
+    if (m != PS_NS && m != PS_MHD) return fail(PS_ERR_ARG, "model must be PS_NS or PS_MHD");
+    const bool mhd = m == PS_MHD;
+    if (p->nfields != (mhd ? 6 : 3)) return fail(PS_ERR_ARG, "model does not match the plan's nfields");
+    if (reps < 1) return fail(PS_ERR_ARG, "reps < 1");
+    if (ps_status st = need_ws(p)) return st;
+    if (ps_status st = check_dev(state, p->cplx_total * csize(p), "state")) return st;
+    if (ps_status st = set_device(p)) return st;
+    const bool timing = p->timing;
+    p->timing = false;
+    ps_status res = by_type(p, [&](auto* tag) -> ps_status {
+      using T = std::remove_pointer_t<decltype(tag)>;
+      size_t bi = 0;
+      for (size_t i = 1; i < p->boxes.size(); ++i)
+        if (p->boxes[i].N > p->boxes[bi].N) bi = i;
+      const Box& b = p->boxes[bi];
+      Seq<T> q{p, b, p->stream};
+      const auto* st = (const ps::C2<T>*)state + b.cplx_off;
+      hipEvent_t e0, e1;
+      if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(PS_ERR_HIP, "hipEventCreate failed");
+      ps_status out = PS_OK;
+      for (const char* kind : {"z_curl", "y", "x_prod", "z_epi"}) {
+        const int n = ps::variant_count(kind, b.N, mhd);
+        if (n <= 1) continue;
+        int best = 0;
+        float best_ms = 1e30f;
+        for (int v = 0; v < n && out == PS_OK; ++v) {
+          p->var[kind] = v;
+          if ((out = q.tune_launch(kind, st, mhd))) break;  // warm-up
+          hipEventRecord(e0, p->stream);
+          for (int r = 0; r < reps && out == PS_OK; ++r) out = q.tune_launch(kind, st, mhd);
+          hipEventRecord(e1, p->stream);
+          hipError_t e = hipEventSynchronize(e1);
+          float ms = 0;
+          if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+          if (e != hipSuccess && out == PS_OK) out = hip_fail(e, "autotune timing");
+          if (ms < best_ms) {
+            best_ms = ms;
+            best = v;
+          }
+        }
+        p->var[kind] = best;
+        if (out) break;
+      }
+      hipEventDestroy(e0);
+      hipEventDestroy(e1);
+      return out;
+    });
+    p->timing = timing;
+    if (p->gexec) {
+      hipGraphExecDestroy(p->gexec);
+      p->gexec = nullptr;
+      p->gkey.clear();
+    }
+    return res;
   });
 }
 

@@ -36,32 +36,116 @@ PS_LEN(384, 48, 8, 4, 4, 3)
 PS_LEN(512, 64, 8, 8, 8)
 PS_LEN(768, 96, 8, 8, 4, 3)
 PS_LEN(1024, 128, 8, 8, 4, 4)
+
+// Alternate schedules with radix-16 stages (fewer LDS exchanges, 16 values
+// per thread), used by the kernel variants for N >= 256.
+template <int L>
+struct LenAlt : LenCfg<L> {};
+#define PS_ALT(L_, TQ_, ...)                     \
+  template <>                                    \
+  struct LenAlt<L_> {                            \
+    using RL = Radices<__VA_ARGS__>;             \
+    static constexpr int TQ = TQ_;               \
+  };
+PS_ALT(128, 8, 16, 8)
+PS_ALT(192, 12, 16, 4, 3)
+PS_ALT(256, 16, 16, 16)
+PS_ALT(384, 24, 16, 8, 3)
+PS_ALT(512, 32, 16, 8, 4)
+PS_ALT(768, 48, 16, 16, 3)
+PS_ALT(1024, 64, 16, 8, 8)
+#undef PS_ALT
+
+// Schedules for the register-resident product pass: first radix equal to the
+// last, so a thread's output points of the inverse transform are exactly its
+// input points of the forward one.  A: ~8 values per thread, B: ~4.
+template <int L>
+struct LenXA : LenCfg<L> {};
+template <int L>
+struct LenXB : LenCfg<L> {};
+#define PS_XA(L_, TQ_, ...) \
+  template <>               \
+  struct LenXA<L_> {        \
+    using RL = Radices<__VA_ARGS__>; \
+    static constexpr int TQ = TQ_;   \
+  };
+#define PS_XB(L_, TQ_, ...) \
+  template <>               \
+  struct LenXB<L_> {        \
+    using RL = Radices<__VA_ARGS__>; \
+    static constexpr int TQ = TQ_;   \
+  };
+PS_XA(128, 16, 8, 2, 8)
+PS_XB(128, 32, 4, 8, 4)
+PS_XA(192, 24, 8, 3, 8)
+PS_XA(256, 32, 8, 4, 8)
+PS_XB(256, 64, 4, 4, 4, 4)
+PS_XA(384, 48, 8, 2, 3, 8)
+PS_XA(512, 64, 8, 8, 8)
+PS_XB(512, 128, 4, 8, 4, 4)
+#undef PS_XA
+#undef PS_XB
 #undef PS_LEN
 
 // grid sizes with a compiled configuration
 #define PS_FOR_EACH_N(X) \
   X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024)
 
-template <typename T, int N>
-struct StridedCfg {
-  static constexpr int TQ = LenCfg<N>::TQ;
-  static constexpr int TX0 = sizeof(T) == 4 ? 16 : 8;
-  static constexpr int TXL = (65536 / (N * 2 * (int)sizeof(T)));  // LDS cap
+// Tile width of a strided pass: 16 columns (FP32) or 8 (FP64), halved SH
+// times, capped by 64 KB of LDS and 1024 threads.
+template <typename T, int N, int TQ, int SH>
+struct StridedTX {
+  static constexpr int TX0 = (sizeof(T) == 4 ? 16 : 8) >> SH;
+  static constexpr int TXL = (65536 / (N * 2 * (int)sizeof(T)));
   static constexpr int TX1 = TX0 < TXL ? TX0 : TXL;
-  static constexpr int TX = (TX1 * TQ > 1024) ? 1024 / TQ : TX1;
-  static_assert(TX >= 1, "tile");
+  static constexpr int TX2 = (TX1 * TQ > 1024) ? 1024 / TQ : TX1;
+  static constexpr int value = TX2 < 1 ? 1 : TX2;
 };
 
-template <typename T, int N>
+constexpr bool has_variants(int N) { return N >= 256; }
+
+// x passes: rows live in LDS with the padded layout (pad8), M + M/8 + 1 slots.
+template <typename T, int M, int TQ, int RBSH>
 struct XCfg {
-  static constexpr int M = N / 2;
-  static constexpr int TQ = LenCfg<M>::TQ;
-  // plain passes: G rows per workgroup, ~256 threads
-  static constexpr int G = (256 / TQ) < 1 ? 1 : 256 / TQ;
-  // fused product pass: RB rows of every field per workgroup, <= ~384 threads
-  static constexpr int RB_NS = (384 / (6 * TQ)) < 1 ? 1 : 384 / (6 * TQ);
-  static constexpr int RB_MHD = (384 / (12 * TQ)) < 1 ? 1 : 384 / (12 * TQ);
-  static constexpr bool MHD_OK = 12 * RB_MHD * (M + 1) * 2 * (int)sizeof(T) <= 65536;
+  static constexpr int SLOTS = M + M / 8 + 1;
+  static constexpr int G = (256 / TQ) < 1 ? 1 : 256 / TQ;  // plain passes: rows per workgroup
+  static constexpr bool fits(int f, int rb) {
+    return f * rb * SLOTS * 2 * (int)sizeof(T) <= 65536 && f * rb * TQ <= 1024;
+  }
+  static constexpr int rb(int f) {
+    int r = ((384 / (f * TQ)) < 1 ? 1 : 384 / (f * TQ)) << RBSH;
+    while (r > 1 && !fits(f, r)) r >>= 1;
+    return r;
+  }
+  static constexpr int RB_NS = rb(6);
+  static constexpr int RB_MHD = rb(12);
+  static constexpr bool MHD_OK = fits(12, RB_MHD);
 };
+
+// Kernel variant tables.  Strided-pass variants: tile shift, two-phase reload
+// (MHD curl), minimum waves per SIMD requested from the register allocator,
+// alternate (radix-16) schedule.  Product-pass variants: rows shift, schedule.
+struct ZV {
+  int sh;
+  bool reload;
+  int minw;
+  bool alt;
+};
+struct XV {
+  int rbsh;  // LDS-staged kernel: rows shift; register-resident kernel: rows per workgroup
+  bool alt;
+  int kind;  // 0: LDS-staged k_x_prod, 1: register-resident k_x_prod2 with LenXA, 2: with LenXB
+};
+constexpr ZV ZCURL_V[] = {{0, false, 1, false}, {1, false, 1, false}, {1, true, 4, false},
+                          {2, true, 4, false},  {1, false, 1, true},  {1, true, 4, true}};
+constexpr ZV ZEPI_V[] = {{0, false, 1, false}, {1, false, 1, false}, {1, false, 4, false},
+                         {2, false, 4, false}, {1, false, 1, true},  {2, false, 4, true}};
+constexpr ZV STR_V[] = {{0, false, 1, false}, {1, false, 1, false}, {0, false, 1, true}, {1, false, 1, true}};
+constexpr XV XPROD_V[] = {{0, false, 0}, {1, false, 0}, {0, true, 0}, {1, true, 0},
+                          {2, false, 1}, {4, false, 1}, {1, false, 2}, {2, false, 2}};
+constexpr int NZCURL = sizeof(ZCURL_V) / sizeof(ZV);
+constexpr int NZEPI = sizeof(ZEPI_V) / sizeof(ZV);
+constexpr int NSTR = sizeof(STR_V) / sizeof(ZV);
+constexpr int NXPROD = sizeof(XPROD_V) / sizeof(XV);
 
 }  // namespace ps

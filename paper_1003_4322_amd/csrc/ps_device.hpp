@@ -129,6 +129,58 @@ struct Dft<8, DIR, T> {
   }
 };
 
+// multiply by w16^m = exp(-+ 2 pi i m / 16), m a compile-time constant
+template <int m, int DIR, typename T>
+__device__ __forceinline__ C2<T> w16(C2<T> v) {
+  constexpr double C[16] = {1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
+                            0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
+                            -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173,
+                            0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613};
+  constexpr int ms = m & 15;
+  constexpr T c = (T)C[ms];
+  constexpr T sn = (T)C[(ms + 12) & 15];  // sin(2 pi m / 16) = cos(2 pi (m - 4) / 16)
+  if constexpr (ms == 0) return v;
+  if constexpr (ms == 4) return rot4<DIR>(v);
+  if constexpr (ms == 8) return C2<T>{-v.x, -v.y};
+  // FWD: v * (c - i sn); INV: v * (c + i sn)
+  if constexpr (DIR == FWD)
+    return C2<T>{c * v.x + sn * v.y, c * v.y - sn * v.x};
+  else
+    return C2<T>{c * v.x - sn * v.y, c * v.y + sn * v.x};
+}
+
+// radix 16 as 4 x 4: inner 4-point DFTs over a[4 n1 + n2], twiddle
+// w16^{n2 k1}, outer 4-point DFTs over n2; output index k1 + 4 k2.
+template <int DIR, typename T>
+struct Dft<16, DIR, T> {
+  __device__ __forceinline__ static void run(C2<T>* a) {
+    C2<T> b[4][4];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+      C2<T> t[4] = {a[n2], a[4 + n2], a[8 + n2], a[12 + n2]};
+      Dft<4, DIR, T>::run(t);
+#pragma unroll
+      for (int k1 = 0; k1 < 4; ++k1) b[n2][k1] = t[k1];
+    }
+    b[1][1] = w16<1, DIR>(b[1][1]);
+    b[1][2] = w16<2, DIR>(b[1][2]);
+    b[1][3] = w16<3, DIR>(b[1][3]);
+    b[2][1] = w16<2, DIR>(b[2][1]);
+    b[2][2] = w16<4, DIR>(b[2][2]);
+    b[2][3] = w16<6, DIR>(b[2][3]);
+    b[3][1] = w16<3, DIR>(b[3][1]);
+    b[3][2] = w16<6, DIR>(b[3][2]);
+    b[3][3] = w16<9, DIR>(b[3][3]);
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+      C2<T> t[4] = {b[0][k1], b[1][k1], b[2][k1], b[3][k1]};
+      Dft<4, DIR, T>::run(t);
+#pragma unroll
+      for (int k2 = 0; k2 < 4; ++k2) a[k1 + 4 * k2] = t[k2];
+    }
+  }
+};
+
 template <int R, int DIR, typename T>
 __device__ __forceinline__ void dft(C2<T>* a) { Dft<R, DIR, T>::run(a); }
 
@@ -157,6 +209,19 @@ struct RadixInfo<Radices<>> {
 
 constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
 
+// LDS layouts of one transform's exchange buffer: element idx lives at
+// lds[Lay::off(idx, ls)].  LayStride serves column tiles (ls = tile width);
+// LayPad8 serves contiguous rows and inserts one pad slot after every 8
+// elements, so the stride-R scatter of the first Stockham stage hits
+// distinct LDS banks.
+struct LayStride {
+  __device__ __forceinline__ static int off(int i, int ls) { return i * ls; }
+};
+struct LayPad8 {
+  __device__ __forceinline__ static int off(int i, int) { return i + (i >> 3); }
+};
+__host__ __device__ constexpr int pad8(int i) { return i + (i >> 3); }
+
 // ---------------------------------------------------------------------------
 // Stockham autosort FFT of length L done by TQ cooperating threads.
 //
@@ -167,7 +232,7 @@ constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
 // The result comes out in natural order.  Thread q runs butterflies
 // j = q + TQ b.  The first stage reads its inputs through a caller functor
 // ld(slot, idx); intermediate stages exchange through LDS (element idx at
-// lds[idx * ls]); the last stage leaves its outputs in registers:
+// lds[Lay::off(idx, ls)]); the last stage leaves its outputs in registers:
 // v[b * Rlast + m] holds output index q + TQ b + m (L / Rlast) (valid when
 // q + TQ b < L / Rlast).
 //
@@ -217,7 +282,7 @@ struct Stockham {
     return (L / RL_) % TQ == 0 || q + TQ * (slot / RL_) < L / RL_;
   }
 
-  template <int NS, int R, bool FIRST, bool LAST, class Ld>
+  template <int NS, int R, bool FIRST, bool LAST, class Lay, class Ld>
   __device__ __forceinline__ static void stage(C2<T> (&v)[SLOTS], C2<T>* lds, int ls, int q,
                                                const C2<T>* __restrict__ tw, int twmul, Ld& ld) {
     constexpr int NB = cdiv(L / R, TQ);
@@ -233,7 +298,7 @@ struct Stockham {
         if constexpr (FIRST) {
           v[b * R + m] = ok ? ld(b * R + m, idx) : zero2<T>();
         } else {
-          v[b * R + m] = ok ? lds[idx * ls] : zero2<T>();
+          v[b * R + m] = ok ? lds[Lay::off(idx, ls)] : zero2<T>();
         }
       }
     }
@@ -258,26 +323,26 @@ struct Stockham {
         if (EXACT || j < L / R) {
           const int base = (j / NS) * NS * R + (j % NS);
 #pragma unroll
-          for (int m = 0; m < R; ++m) lds[(base + m * NS) * ls] = v[b * R + m];
+          for (int m = 0; m < R; ++m) lds[Lay::off(base + m * NS, ls)] = v[b * R + m];
         }
       }
       __syncthreads();  // writes visible before the next stage gathers
     }
   }
 
-  template <int NS, class Ld, int R, int... Rest>
+  template <int NS, class Lay, class Ld, int R, int... Rest>
   __device__ __forceinline__ static void chain(C2<T> (&v)[SLOTS], C2<T>* lds, int ls, int q,
                                                const C2<T>* __restrict__ tw, int twmul, Ld& ld,
                                                Radices<R, Rest...>) {
-    stage<NS, R, NS == 1, sizeof...(Rest) == 0>(v, lds, ls, q, tw, twmul, ld);
-    if constexpr (sizeof...(Rest) > 0) chain<NS * R>(v, lds, ls, q, tw, twmul, ld, Radices<Rest...>{});
+    stage<NS, R, NS == 1, sizeof...(Rest) == 0, Lay>(v, lds, ls, q, tw, twmul, ld);
+    if constexpr (sizeof...(Rest) > 0) chain<NS * R, Lay>(v, lds, ls, q, tw, twmul, ld, Radices<Rest...>{});
   }
 
   // tw: table of exp(-2 pi i e / (L * twmul)), e < L * twmul.
-  template <class Ld>
+  template <class Lay = LayStride, class Ld>
   __device__ __forceinline__ static void run(C2<T> (&v)[SLOTS], C2<T>* lds, int ls, int q,
                                              const C2<T>* __restrict__ tw, int twmul, Ld ld) {
-    chain<1>(v, lds, ls, q, tw, twmul, ld, RL{});
+    chain<1, Lay>(v, lds, ls, q, tw, twmul, ld, RL{});
   }
 };
 

@@ -53,8 +53,8 @@ struct StridedArgs {
   int ncols, ntile, nlines, nf;
 };
 
-template <typename T, int L, int TQ, int TX, int DIR, class RL>
-__global__ __launch_bounds__(TX* TQ) void k_strided(StridedArgs<T> a) {
+template <typename T, int L, int TQ, int TX, int DIR, class RL, int MINW = 1>
+__global__ __launch_bounds__(TX* TQ, MINW) void k_strided(StridedArgs<T> a) {
   using E = Stockham<T, L, TQ, DIR, RL>;
   __shared__ C2<T> smem[L * TX];
   const int tid = threadIdx.x, c = tid % TX, q = tid / TX;
@@ -92,8 +92,10 @@ struct ZCurlArgs {
   int N, ntile;
 };
 
-template <typename T, int L, int TQ, int TX, class RL, bool MHD>
-__global__ __launch_bounds__(TX* TQ) void k_z_curl(ZCurlArgs<T> a) {
+// RELOAD (MHD only): two phases, u-derived fields then b-derived fields, each
+// re-reading z+- so that only three components stay in registers.
+template <typename T, int L, int TQ, int TX, class RL, bool MHD, bool RELOAD, int MINW = 1>
+__global__ __launch_bounds__(TX* TQ, MINW) void k_z_curl(ZCurlArgs<T> a) {
   using E = Stockham<T, L, TQ, INV, RL>;
   constexpr int NS_ = E::FIRST_SLOTS;
   constexpr int NOUT = MHD ? 12 : 6;
@@ -109,49 +111,71 @@ __global__ __launch_bounds__(TX* TQ) void k_z_curl(ZCurlArgs<T> a) {
   C2<T>* out = a.out + ky * a.out_pitch + col;
   const T kx = (T)dwavx(col, N), kyd = (T)dwav(ky, N);
 
-  C2<T> u[3][NS_];
-  C2<T> b[MHD ? 3 : 1][NS_];
-#pragma unroll
-  for (int s = 0; s < NS_; ++s) {
-    const bool v = ok && E::first_valid(q, s);
-    const long off = (long)E::first_index(q, s) * in_es;
-#pragma unroll
-    for (int f = 0; f < 3; ++f) {
-      if constexpr (MHD) {
-        const C2<T> zp = v ? in[f * a.in_fs + off] : zero2<T>();
-        const C2<T> zm = v ? in[(3 + f) * a.in_fs + off] : zero2<T>();
-        u[f][s] = T(0.5) * (zp + zm);
-        b[f][s] = T(0.5) * (zp - zm);
-      } else {
-        u[f][s] = v ? in[f * a.in_fs + off] : zero2<T>();
-      }
-    }
-  }
-
-#pragma unroll
-  for (int f = 0; f < NOUT; ++f) {
-    const int grp = f / 3, comp = f % 3;
+  // one output field: FFT of component `comp` of `src` (grp even) or of its curl (grp odd)
+  auto emit = [&](auto& src, int grp, int comp, int fout) {
     C2<T> v[E::SLOTS];
     E::run(v, smem + c, TX, q, a.tw, 1, [&](int s, int idx) -> C2<T> {
-      auto src = [&](int ff) -> C2<T> {
-        if constexpr (MHD) return grp < 2 ? u[ff][s] : b[ff][s];
-        return u[ff][s];
-      };
-      if ((grp & 1) == 0) return src(comp);
+      if ((grp & 1) == 0) return src[comp][s];
       const T kz = (T)dwav(idx, N);
       C2<T> r;
       if (comp == 0)
-        r = kyd * src(2) - kz * src(1);
+        r = kyd * src[2][s] - kz * src[1][s];
       else if (comp == 1)
-        r = kz * src(0) - kx * src(2);
+        r = kz * src[0][s] - kx * src[2][s];
       else
-        r = kx * src(1) - kyd * src(0);
+        r = kx * src[1][s] - kyd * src[0][s];
       return mul_i(r);
     });
     if constexpr (E::NSTAGE == 1) __syncthreads();
 #pragma unroll
     for (int s = 0; s < E::LAST_NB * E::RL_; ++s)
-      if (ok && E::last_valid(q, s)) out[f * a.out_fs + E::last_index(q, s) * out_es] = v[s];
+      if (ok && E::last_valid(q, s)) out[fout * a.out_fs + E::last_index(q, s) * out_es] = v[s];
+  };
+  // load u (sign = +1) or b (sign = -1) from z+- (MHD), or u (NS)
+  auto load = [&](C2<T> (&dst)[3][NS_], T sign) {
+#pragma unroll
+    for (int s = 0; s < NS_; ++s) {
+      const bool v = ok && E::first_valid(q, s);
+      const long off = (long)E::first_index(q, s) * in_es;
+#pragma unroll
+      for (int f = 0; f < 3; ++f) {
+        if constexpr (MHD) {
+          const C2<T> zp = v ? in[f * a.in_fs + off] : zero2<T>();
+          const C2<T> zm = v ? in[(3 + f) * a.in_fs + off] : zero2<T>();
+          dst[f][s] = T(0.5) * (zp + sign * zm);
+        } else {
+          dst[f][s] = v ? in[f * a.in_fs + off] : zero2<T>();
+        }
+      }
+    }
+  };
+
+  if constexpr (MHD && RELOAD) {
+#pragma unroll
+    for (int ph = 0; ph < 2; ++ph) {
+      C2<T> w[3][NS_];
+      load(w, ph == 0 ? T(1) : T(-1));
+#pragma unroll
+      for (int f = 0; f < 6; ++f) emit(w, f / 3, f % 3, 6 * ph + f);
+      __syncthreads();
+    }
+  } else {
+    C2<T> u[3][NS_];
+    C2<T> b[MHD ? 3 : 1][NS_];
+    load(u, T(1));
+    if constexpr (MHD) load(b, T(-1));
+#pragma unroll
+    for (int f = 0; f < NOUT; ++f) {
+      const int grp = f / 3;
+      if constexpr (MHD) {
+        if (grp < 2)
+          emit(u, grp, f % 3, f);
+        else
+          emit(b, grp, f % 3, f);
+      } else {
+        emit(u, grp, f % 3, f);
+      }
+    }
   }
 }
 
@@ -177,8 +201,8 @@ struct ZEpiArgs {
   int N, ntile, mode;
 };
 
-template <typename T, int L, int TQ, int TX, class RL, bool MHD>
-__global__ __launch_bounds__(TX* TQ) void k_z_epi(ZEpiArgs<T> a) {
+template <typename T, int L, int TQ, int TX, class RL, bool MHD, int MINW = 1>
+__global__ __launch_bounds__(TX* TQ, MINW) void k_z_epi(ZEpiArgs<T> a) {
   using E = Stockham<T, L, TQ, FWD, RL>;
   constexpr int NF = MHD ? 6 : 3;
   constexpr int NO = E::LAST_NB * E::RL_;
@@ -272,23 +296,27 @@ __global__ __launch_bounds__(TX* TQ) void k_z_epi(ZEpiArgs<T> a) {
 //            Z[M] := Z[0].
 // The table tw has length N (the M-point transform reads every other entry).
 // ---------------------------------------------------------------------------
+// Rows in LDS use the padded layout (element i at pad8(i)); RowLen(M) slots
+// hold M+1 values.
+__host__ __device__ constexpr int row_slots(int M) { return pad8(M) + 1; }
+
 template <typename T>
 __device__ __forceinline__ C2<T> c2r_pre(const C2<T>* buf, int k, int M, const C2<T>* __restrict__ tw) {
   C2<T> xk, xm;
   if (k == 0) {
     xk = C2<T>{buf[0].x, T(0)};
-    xm = C2<T>{buf[M].x, T(0)};
+    xm = C2<T>{buf[pad8(M)].x, T(0)};
   } else {
-    xk = buf[k];
-    xm = conj(buf[M - k]);
+    xk = buf[pad8(k)];
+    xm = conj(buf[pad8(M - k)]);
   }
   return (xk + xm) + mul_i(cmulc(xk - xm, tw[k]));  // conj(tw[k]) = e^{+2 pi i k/N}
 }
 
 template <typename T>
 __device__ __forceinline__ C2<T> r2c_post(const C2<T>* buf, int k, int M, const C2<T>* __restrict__ tw) {
-  const C2<T> zk = buf[k == M ? 0 : k];
-  const C2<T> zm = conj(buf[k == 0 ? 0 : M - k]);
+  const C2<T> zk = buf[pad8(k == M ? 0 : k)];
+  const C2<T> zm = conj(buf[pad8(k == 0 ? 0 : M - k)]);
   const C2<T> e = T(0.5) * (zk + zm);
   const C2<T> o = T(0.5) * mul_mi(zk - zm);
   return e + cmul(o, tw[k]);
@@ -308,25 +336,25 @@ struct XArgs {
 template <typename T, int M, int TQ, int G, class RL>
 __global__ __launch_bounds__(G* TQ) void k_x_c2r(XArgs<T> a) {
   using E = Stockham<T, M, TQ, INV, RL>;
-  constexpr int LP = M + 1;
+  constexpr int LP = row_slots(M);
   __shared__ C2<T> smem[G * LP];
   const int tid = threadIdx.x, g = tid / TQ, q = tid % TQ;
   const long row0 = (long)xcd_remap(blockIdx.x, gridDim.x) * G;
   const long total = a.rows * a.nf;
-  for (int i = tid; i < G * LP; i += G * TQ) {
-    const int gg = i / LP, k = i % LP;
+  for (int i = tid; i < G * (M + 1); i += G * TQ) {
+    const int gg = i / (M + 1), k = i % (M + 1);
     const long row = row0 + gg;
     C2<T> val = zero2<T>();
     if (row < total) {
       const long f = row / a.rows, r = row % a.rows;
       val = a.in[f * a.in_fs + r * a.in_pitch + k];
     }
-    smem[i] = val;
+    smem[gg * LP + pad8(k)] = val;
   }
   __syncthreads();
   C2<T>* buf = smem + g * LP;
   C2<T> v[E::SLOTS];
-  E::run(v, buf, 1, q, a.tw, 2, [&](int, int k) { return c2r_pre(buf, k, M, a.tw); });
+  E::template run<LayPad8>(v, buf, 1, q, a.tw, 2, [&](int, int k) { return c2r_pre(buf, k, M, a.tw); });
   const long row = row0 + g;
   if (row >= total) return;
   const long f = row / a.rows, r = row % a.rows;
@@ -340,7 +368,7 @@ __global__ __launch_bounds__(G* TQ) void k_x_c2r(XArgs<T> a) {
 template <typename T, int M, int TQ, int G, class RL>
 __global__ __launch_bounds__(G* TQ) void k_x_r2c(XArgs<T> a) {
   using E = Stockham<T, M, TQ, FWD, RL>;
-  constexpr int LP = M + 1;
+  constexpr int LP = row_slots(M);
   __shared__ C2<T> smem[G * LP];
   const int tid = threadIdx.x, g = tid / TQ, q = tid % TQ;
   const long row0 = (long)xcd_remap(blockIdx.x, gridDim.x) * G;
@@ -351,14 +379,14 @@ __global__ __launch_bounds__(G* TQ) void k_x_r2c(XArgs<T> a) {
   const C2<T>* in = a.in + f * a.in_fs + r * a.in_pitch;
   C2<T>* buf = smem + g * LP;
   C2<T> v[E::SLOTS];
-  E::run(v, buf, 1, q, a.tw, 2, [&](int, int n) { return ok ? in[n] : zero2<T>(); });
+  E::template run<LayPad8>(v, buf, 1, q, a.tw, 2, [&](int, int n) { return ok ? in[n] : zero2<T>(); });
   __syncthreads();
 #pragma unroll
   for (int s = 0; s < E::LAST_NB * E::RL_; ++s)
-    if (E::last_valid(q, s)) buf[E::last_index(q, s)] = v[s];
+    if (E::last_valid(q, s)) buf[pad8(E::last_index(q, s))] = v[s];
   __syncthreads();
-  for (int i = tid; i < G * LP; i += G * TQ) {
-    const int gg = i / LP, k = i % LP;
+  for (int i = tid; i < G * (M + 1); i += G * TQ) {
+    const int gg = i / (M + 1), k = i % (M + 1);
     const long rw = row0 + gg;
     if (rw < total) {
       const long ff = rw / a.rows, rr = rw % a.rows;
@@ -377,33 +405,33 @@ __global__ __launch_bounds__((MHD ? 12 : 6) * RB * TQ) void k_x_prod(XArgs<T> a)
   constexpr int G = FIN * RB, NT = G * TQ;
   using EI = Stockham<T, M, TQ, INV, RL>;
   using EF = Stockham<T, M, TQ, FWD, RL>;
-  constexpr int LP = M + 1;
+  constexpr int LP = row_slots(M);
   __shared__ C2<T> smem[G * LP];
   const int tid = threadIdx.x, g = tid / TQ, q = tid % TQ;
   const long row0 = (long)xcd_remap(blockIdx.x, gridDim.x) * RB;
   // ---- load FIN x RB rows; slot (f, rb) at smem[(f * RB + rb) * LP]
-  for (int i = tid; i < G * LP; i += NT) {
-    const int gr = i / LP, k = i % LP;
+  for (int i = tid; i < G * (M + 1); i += NT) {
+    const int gr = i / (M + 1), k = i % (M + 1);
     const int f = gr / RB, rb = gr % RB;
     const long row = row0 + rb;
-    smem[i] = row < a.rows ? a.in[f * a.in_fs + row * a.in_pitch + k] : zero2<T>();
+    smem[gr * LP + pad8(k)] = row < a.rows ? a.in[f * a.in_fs + row * a.in_pitch + k] : zero2<T>();
   }
   __syncthreads();
   // ---- inverse real FFTs, physical values back into the same slot
   C2<T>* buf = smem + g * LP;
   {
     C2<T> v[EI::SLOTS];
-    EI::run(v, buf, 1, q, a.tw, 2, [&](int, int k) { return c2r_pre(buf, k, M, a.tw); });
+    EI::template run<LayPad8>(v, buf, 1, q, a.tw, 2, [&](int, int k) { return c2r_pre(buf, k, M, a.tw); });
     __syncthreads();
 #pragma unroll
     for (int s = 0; s < EI::LAST_NB * EI::RL_; ++s)
-      if (EI::last_valid(q, s)) buf[EI::last_index(q, s)] = v[s];
+      if (EI::last_valid(q, s)) buf[pad8(EI::last_index(q, s))] = v[s];
   }
   __syncthreads();
   // ---- products; each C2 holds two neighbouring grid points
   for (int i = tid; i < RB * M; i += NT) {
     const int rb = i / M, n = i % M;
-    auto at = [&](int f) -> C2<T>& { return smem[(f * RB + rb) * LP + n]; };
+    auto at = [&](int f) -> C2<T>& { return smem[(f * RB + rb) * LP + pad8(n)]; };
     const C2<T> u0 = at(0), u1 = at(1), u2 = at(2);
     const C2<T> w0 = at(3), w1 = at(4), w2 = at(5);
     auto cx = [](C2<T> a1, C2<T> a2, C2<T> b1, C2<T> b2) {  // a1 b2 - a2 b1 per point
@@ -429,20 +457,141 @@ __global__ __launch_bounds__((MHD ? 12 : 6) * RB * TQ) void k_x_prod(XArgs<T> a)
   const bool active = g < FOUT * RB;
   {
     C2<T> v[EF::SLOTS];
-    EF::run(v, buf, 1, q, a.tw, 2, [&](int, int n) { return buf[n]; });
+    EF::template run<LayPad8>(v, buf, 1, q, a.tw, 2, [&](int, int n) { return buf[pad8(n)]; });
     __syncthreads();
     if (active) {
 #pragma unroll
       for (int s = 0; s < EF::LAST_NB * EF::RL_; ++s)
-        if (EF::last_valid(q, s)) buf[EF::last_index(q, s)] = v[s];
+        if (EF::last_valid(q, s)) buf[pad8(EF::last_index(q, s))] = v[s];
     }
   }
   __syncthreads();
-  for (int i = tid; i < FOUT * RB * LP; i += NT) {
-    const int gr = i / LP, k = i % LP;
+  for (int i = tid; i < FOUT * RB * (M + 1); i += NT) {
+    const int gr = i / (M + 1), k = i % (M + 1);
     const int f = gr / RB, rb = gr % RB;
     const long row = row0 + rb;
     if (row < a.rows) a.out[f * a.out_fs + row * a.out_pitch + k] = r2c_post(smem + gr * LP, k, M, a.tw);
+  }
+}
+
+// Fused product pass, register-resident variant: one group of TQ threads per
+// row transforms every field of that row in turn (inputs read straight from
+// global memory), keeps its own points of u (and b) in registers and
+// accumulates the cross products there; LDS only carries the FFT exchanges.
+// Reads all inputs of a row before writing any output (in place is safe).
+// Output fields: NS [u x w]; MHD [u x w + j x b, u x b].
+template <typename T, int M, int TQ, class RL, bool MHD, int RPW>
+__global__ __launch_bounds__(RPW* TQ) void k_x_prod2(XArgs<T> a) {
+  using EI = Stockham<T, M, TQ, INV, RL>;
+  using EF = Stockham<T, M, TQ, FWD, RL>;
+  constexpr int LP = row_slots(M);
+  constexpr int NO = EI::LAST_NB * EI::RL_;
+  constexpr bool DIRECT = EI::R1 == EI::RL_;  // last-stage slots == first-stage slots
+  __shared__ C2<T> smem[RPW * LP];
+  const int tid = threadIdx.x, g = tid / TQ, q = tid % TQ;
+  const long row = (long)xcd_remap(blockIdx.x, gridDim.x) * RPW + g;
+  const bool ok = row < a.rows;
+  C2<T>* buf = smem + g * LP;
+  const C2<T>* in = a.in + (ok ? row : 0) * a.in_pitch;
+  C2<T>* outp = a.out + (ok ? row : 0) * a.out_pitch;
+
+  // inverse real transform of input field f into this thread's point slots
+  auto inv = [&](int f, C2<T> (&dst)[NO]) {
+    const C2<T>* src = in + f * a.in_fs;
+    C2<T> v[EI::SLOTS];
+    EI::template run<LayPad8>(v, buf, 1, q, a.tw, 2, [&](int, int k) -> C2<T> {
+      if (!ok) return zero2<T>();
+      C2<T> xk, xm;
+      if (k == 0) {
+        xk = C2<T>{src[0].x, T(0)};
+        xm = C2<T>{src[M].x, T(0)};
+      } else {
+        xk = src[k];
+        xm = conj(src[M - k]);
+      }
+      return (xk + xm) + mul_i(cmulc(xk - xm, a.tw[k]));
+    });
+#pragma unroll
+    for (int s = 0; s < NO; ++s) dst[s] = v[s];
+  };
+  // forward real transform of point values val(s) and store as output field fo
+  auto fwd = [&](int fo, auto&& val) {
+    C2<T> v[EF::SLOTS];
+    if constexpr (DIRECT) {
+      EF::template run<LayPad8>(v, buf, 1, q, a.tw, 2, [&](int s, int) { return val(s); });
+    } else {
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < NO; ++s)
+        if (EI::last_valid(q, s)) buf[pad8(EI::last_index(q, s))] = val(s);
+      __syncthreads();
+      EF::template run<LayPad8>(v, buf, 1, q, a.tw, 2, [&](int, int n) { return buf[pad8(n)]; });
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < EF::LAST_NB * EF::RL_; ++s)
+      if (EF::last_valid(q, s)) buf[pad8(EF::last_index(q, s))] = v[s];
+    __syncthreads();
+    if (ok) {
+      C2<T>* dst = outp + fo * a.out_fs;
+      for (int k = q; k <= M; k += TQ) dst[k] = r2c_post(buf, k, M, a.tw);
+    }
+  };
+  // cross-product component c of (x, y) per pair of points
+  auto cx = [](C2<T> a1, C2<T> a2, C2<T> b1, C2<T> b2) {
+    return C2<T>{a1.x * b2.x - a2.x * b1.x, a1.y * b2.y - a2.y * b1.y};
+  };
+  auto cross_c = [&](int c, const C2<T> (&x)[3][NO], const C2<T> (&y)[3][NO], int s) {
+    const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+    return cx(x[c1][s], x[c2][s], y[c1][s], y[c2][s]);
+  };
+
+  C2<T> U[3][NO], Nn[3][NO];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) inv(c, U[c]);
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int s = 0; s < NO; ++s) Nn[c][s] = zero2<T>();
+  // n += sgn (x x w), one w component at a time: w_c enters
+  // (x x w)_{c+1} as +x_{c+2} w_c and (x x w)_{c+2} as -x_{c+1} w_c
+  auto acc_cross = [&](const C2<T> (&x)[3][NO], int c, const C2<T> (&wc)[NO], T sgn) {
+    const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+#pragma unroll
+    for (int s = 0; s < NO; ++s) {
+      Nn[c1][s] = Nn[c1][s] + sgn * C2<T>{x[c2][s].x * wc[s].x, x[c2][s].y * wc[s].y};
+      Nn[c2][s] = Nn[c2][s] - sgn * C2<T>{x[c1][s].x * wc[s].x, x[c1][s].y * wc[s].y};
+    }
+  };
+  if constexpr (MHD) {
+    C2<T> Bf[3][NO];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) inv(6 + c, Bf[c]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      C2<T> w[NO];
+      inv(3 + c, w);
+      acc_cross(U, c, w, T(1));  // u x w
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      C2<T> j[NO];
+      inv(9 + c, j);
+      acc_cross(Bf, c, j, T(-1));  // j x b = -(b x j)
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) fwd(c, [&](int s) { return Nn[c][s]; });
+#pragma unroll
+    for (int c = 0; c < 3; ++c) fwd(3 + c, [&](int s) { return cross_c(c, U, Bf, s); });
+  } else {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      C2<T> w[NO];
+      inv(3 + c, w);
+      acc_cross(U, c, w, T(1));
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) fwd(c, [&](int s) { return Nn[c][s]; });
   }
 }
 

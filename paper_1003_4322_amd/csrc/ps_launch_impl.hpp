@@ -1,0 +1,241 @@
+// ps_launch_impl.hpp -- launcher definitions, included by one translation
+// unit per pass kind and dtype (k_<pass>_<dtype>.hip).
+#pragma once
+
+#include <cstring>
+#include <type_traits>
+#include <utility>
+
+#include "ps_config.hpp"
+#include "ps_launch.hpp"
+
+namespace ps {
+
+template <int N, bool ALT>
+using Sched = std::conditional_t<ALT, LenAlt<N>, LenCfg<N>>;
+
+// run f<I>() for the I == var of 0..n-1
+template <int... I, class F>
+hipError_t pick(int var, std::integer_sequence<int, I...>, F&& f) {
+  hipError_t r = hipErrorInvalidValue;
+  ((var == I ? (void)(r = f(std::integral_constant<int, I>{})) : (void)0), ...);
+  return r;
+}
+
+// ---------------- strided plain passes ----------------
+template <typename T, int N, int I>
+hipError_t strided_v(int dir, StridedArgs<T> a, hipStream_t s) {
+  constexpr ZV v = STR_V[I];
+  using LC = Sched<N, v.alt>;
+  constexpr int TX = StridedTX<T, N, LC::TQ, v.sh>::value;
+  a.ntile = cdiv(a.ncols, TX);
+  const long grid = (long)a.ntile * a.nlines * a.nf;
+  if (grid <= 0) return hipSuccess;
+  if (dir == FWD)
+    k_strided<T, N, LC::TQ, TX, FWD, typename LC::RL, v.minw><<<dim3((unsigned)grid), dim3(TX * LC::TQ), 0, s>>>(a);
+  else
+    k_strided<T, N, LC::TQ, TX, INV, typename LC::RL, v.minw><<<dim3((unsigned)grid), dim3(TX * LC::TQ), 0, s>>>(a);
+  return hipGetLastError();
+}
+
+template <typename T, int N>
+hipError_t strided_n(int dir, int var, StridedArgs<T> a, hipStream_t s) {
+  if constexpr (has_variants(N))
+    return pick(var, std::make_integer_sequence<int, NSTR>{},
+                [&](auto I) { return strided_v<T, N, decltype(I)::value>(dir, a, s); });
+  else
+    return strided_v<T, N, 0>(dir, a, s);
+}
+
+template <typename T>
+hipError_t launch_strided(int N, int dir, int var, StridedArgs<T> a, hipStream_t s) {
+  switch (N) {
+#define PS_CASE(NN) \
+  case NN:          \
+    return strided_n<T, NN>(dir, var, a, s);
+    PS_FOR_EACH_N(PS_CASE)
+#undef PS_CASE
+  }
+  return hipErrorInvalidValue;
+}
+
+// ---------------- inverse z pass + curl ----------------
+template <typename T, int N, int I, bool MHD>
+hipError_t z_curl_v(ZCurlArgs<T> a, hipStream_t s) {
+  constexpr ZV v = ZCURL_V[I];
+  using LC = Sched<N, v.alt>;
+  constexpr int TX = StridedTX<T, N, LC::TQ, v.sh>::value;
+  a.ntile = cdiv(N / 2 + 1, TX);
+  const long grid = (long)a.ntile * N;
+  k_z_curl<T, N, LC::TQ, TX, typename LC::RL, MHD, MHD && v.reload, v.minw>
+      <<<dim3((unsigned)grid), dim3(TX * LC::TQ), 0, s>>>(a);
+  return hipGetLastError();
+}
+
+template <typename T, int N>
+hipError_t z_curl_n(bool mhd, int var, ZCurlArgs<T> a, hipStream_t s) {
+  if constexpr (has_variants(N))
+    return pick(var, std::make_integer_sequence<int, NZCURL>{}, [&](auto I) {
+      constexpr int i = decltype(I)::value;
+      return mhd ? z_curl_v<T, N, i, true>(a, s) : z_curl_v<T, N, i, false>(a, s);
+    });
+  else
+    return mhd ? z_curl_v<T, N, 0, true>(a, s) : z_curl_v<T, N, 0, false>(a, s);
+}
+
+template <typename T>
+hipError_t launch_z_curl(int N, bool mhd, int var, ZCurlArgs<T> a, hipStream_t s) {
+  switch (N) {
+#define PS_CASE(NN) \
+  case NN:          \
+    return z_curl_n<T, NN>(mhd, var, a, s);
+    PS_FOR_EACH_N(PS_CASE)
+#undef PS_CASE
+  }
+  return hipErrorInvalidValue;
+}
+
+// ---------------- forward z pass + epilogue ----------------
+template <typename T, int N, int I, bool MHD>
+hipError_t z_epi_v(ZEpiArgs<T> a, hipStream_t s) {
+  constexpr ZV v = ZEPI_V[I];
+  using LC = Sched<N, v.alt>;
+  constexpr int TX = StridedTX<T, N, LC::TQ, v.sh>::value;
+  a.ntile = cdiv(N / 2 + 1, TX);
+  const long grid = (long)a.ntile * N;
+  k_z_epi<T, N, LC::TQ, TX, typename LC::RL, MHD, v.minw><<<dim3((unsigned)grid), dim3(TX * LC::TQ), 0, s>>>(a);
+  return hipGetLastError();
+}
+
+template <typename T, int N>
+hipError_t z_epi_n(bool mhd, int var, ZEpiArgs<T> a, hipStream_t s) {
+  if constexpr (has_variants(N))
+    return pick(var, std::make_integer_sequence<int, NZEPI>{}, [&](auto I) {
+      constexpr int i = decltype(I)::value;
+      return mhd ? z_epi_v<T, N, i, true>(a, s) : z_epi_v<T, N, i, false>(a, s);
+    });
+  else
+    return mhd ? z_epi_v<T, N, 0, true>(a, s) : z_epi_v<T, N, 0, false>(a, s);
+}
+
+template <typename T>
+hipError_t launch_z_epi(int N, bool mhd, int var, ZEpiArgs<T> a, hipStream_t s) {
+  switch (N) {
+#define PS_CASE(NN) \
+  case NN:          \
+    return z_epi_n<T, NN>(mhd, var, a, s);
+    PS_FOR_EACH_N(PS_CASE)
+#undef PS_CASE
+  }
+  return hipErrorInvalidValue;
+}
+
+// ---------------- x passes ----------------
+template <typename T, int N>
+hipError_t x_c2r_n(XArgs<T> a, hipStream_t s) {
+  using LC = LenCfg<N / 2>;
+  using X = XCfg<T, N / 2, LC::TQ, 0>;
+  const long grid = (a.rows * a.nf + X::G - 1) / X::G;
+  k_x_c2r<T, N / 2, LC::TQ, X::G, typename LC::RL><<<dim3((unsigned)grid), dim3(X::G * LC::TQ), 0, s>>>(a);
+  return hipGetLastError();
+}
+
+template <typename T, int N>
+hipError_t x_r2c_n(XArgs<T> a, hipStream_t s) {
+  using LC = LenCfg<N / 2>;
+  using X = XCfg<T, N / 2, LC::TQ, 0>;
+  const long grid = (a.rows * a.nf + X::G - 1) / X::G;
+  k_x_r2c<T, N / 2, LC::TQ, X::G, typename LC::RL><<<dim3((unsigned)grid), dim3(X::G * LC::TQ), 0, s>>>(a);
+  return hipGetLastError();
+}
+
+template <typename T, int N, int I>
+hipError_t x_prod_v(bool mhd, XArgs<T> a, hipStream_t s) {
+  constexpr XV v = XPROD_V[I];
+  if constexpr (v.kind == 0) {
+    using LC = Sched<N / 2, v.alt>;
+    using X = XCfg<T, N / 2, LC::TQ, v.rbsh>;
+    if (mhd) {
+      if constexpr (X::MHD_OK) {
+        const long grid = (a.rows + X::RB_MHD - 1) / X::RB_MHD;
+        k_x_prod<T, N / 2, LC::TQ, X::RB_MHD, typename LC::RL, true>
+            <<<dim3((unsigned)grid), dim3(12 * X::RB_MHD * LC::TQ), 0, s>>>(a);
+        return hipGetLastError();
+      } else {
+        return hipErrorInvalidValue;
+      }
+    }
+    const long grid = (a.rows + X::RB_NS - 1) / X::RB_NS;
+    k_x_prod<T, N / 2, LC::TQ, X::RB_NS, typename LC::RL, false>
+        <<<dim3((unsigned)grid), dim3(6 * X::RB_NS * LC::TQ), 0, s>>>(a);
+    return hipGetLastError();
+  } else {
+    using LC = std::conditional_t<v.kind == 1, LenXA<N / 2>, LenXB<N / 2>>;
+    constexpr int RPW = (v.rbsh * LC::TQ > 1024) ? 1024 / LC::TQ : v.rbsh;
+    const long grid = (a.rows + RPW - 1) / RPW;
+    if (mhd)
+      k_x_prod2<T, N / 2, LC::TQ, typename LC::RL, true, RPW><<<dim3((unsigned)grid), dim3(RPW * LC::TQ), 0, s>>>(a);
+    else
+      k_x_prod2<T, N / 2, LC::TQ, typename LC::RL, false, RPW><<<dim3((unsigned)grid), dim3(RPW * LC::TQ), 0, s>>>(a);
+    return hipGetLastError();
+  }
+}
+
+template <typename T, int N>
+hipError_t x_prod_n(bool mhd, int var, XArgs<T> a, hipStream_t s) {
+  if constexpr (has_variants(N))
+    return pick(var, std::make_integer_sequence<int, NXPROD>{},
+                [&](auto I) { return x_prod_v<T, N, decltype(I)::value>(mhd, a, s); });
+  else
+    return x_prod_v<T, N, 0>(mhd, a, s);
+}
+
+template <typename T>
+bool mhd_supported(int N) {
+  switch (N) {
+#define PS_CASE(NN) \
+  case NN:          \
+    return XCfg<T, NN / 2, LenCfg<NN / 2>::TQ, 0>::MHD_OK;
+    PS_FOR_EACH_N(PS_CASE)
+#undef PS_CASE
+  }
+  return false;
+}
+
+template <typename T>
+hipError_t launch_x_c2r(int N, XArgs<T> a, hipStream_t s) {
+  switch (N) {
+#define PS_CASE(NN) \
+  case NN:          \
+    return x_c2r_n<T, NN>(a, s);
+    PS_FOR_EACH_N(PS_CASE)
+#undef PS_CASE
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_x_r2c(int N, XArgs<T> a, hipStream_t s) {
+  switch (N) {
+#define PS_CASE(NN) \
+  case NN:          \
+    return x_r2c_n<T, NN>(a, s);
+    PS_FOR_EACH_N(PS_CASE)
+#undef PS_CASE
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_x_prod(int N, bool mhd, int var, XArgs<T> a, hipStream_t s) {
+  switch (N) {
+#define PS_CASE(NN) \
+  case NN:          \
+    return x_prod_n<T, NN>(mhd, var, a, s);
+    PS_FOR_EACH_N(PS_CASE)
+#undef PS_CASE
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace ps
