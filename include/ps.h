@@ -136,9 +136,11 @@ ps_status ps_energy_spectrum(ps_plan p, const void *fhat, int nfields, double *s
                              double *totals_dev);
 
 /* Kernel variants.  Pass kinds: "y", "z" (plain strided passes), "z_curl",
- * "z_epi", "x_prod".  Variant 0 is the default; others change the tile width
- * or the register/LDS trade-off of a pass (results are identical up to
- * rounding order).  Setting a variant drops a cached graph. */
+ * "z_epi", "x_prod"; the tile width, radix schedule or register/LDS trade-off
+ * of a pass (results are identical up to rounding order).  Kind "batch":
+ * 0 = one launch per pass for each run of consecutive equal-size boxes
+ * (default), 1 = one launch per box (baseline).  Setting a variant drops a
+ * cached graph. */
 ps_status ps_plan_set_variant(ps_plan p, const char *kind, int variant);
 int ps_plan_get_variant(ps_plan p, const char *kind);
 int ps_plan_variant_count(ps_plan p, const char *kind);

@@ -1,12 +1,15 @@
 // ps_api.cpp -- C ABI of libps.so: plans, workspace layout, pass sequencing,
 // graph capture of the RK2 step and per-kernel timing.
 //
-// One plan covers one box or an ensemble of independent boxes.  A box of
-// size N with F fields uses, inside the caller's workspace:
+// One plan covers one box or an ensemble of independent boxes.  Consecutive
+// boxes of equal size form a class; every pass runs as one launch per class
+// (or, as a baseline, one launch per box).  A box of size N with F fields
+// uses, inside its class's part of the caller's workspace:
 //   zstar  F half spectra, dense pitch H = N/2+1       (RK2 midpoint state)
 //   work   2F half spectra, pitch P (H rounded up to 128 bytes)
 //          (physical-space passes: u, w [, b, j] and then the products)
 //   spec   N * nshell * 2 + N doubles                  (spectrum partials)
+// laid out [zstar of all boxes][work of all boxes][spec of all boxes].
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -32,14 +35,22 @@ ps_status fail(ps_status s, const std::string& msg) {
 
 struct Box {
   int N = 0;
+  size_t real_off = 0, cplx_off = 0;  // element offsets in user field sets
+  int nshell = 0;
+  int cls = 0, idx = 0;  // class and index within it
+};
+
+// a run of consecutive boxes of equal size
+struct Class {
+  int N = 0, first = 0, nb = 0;
   long H = 0, P = 0;
   long nc = 0;    // N*N*H   valid complex values per field
   long ncp = 0;   // N*N*P   pitched complex values per field
   long n3 = 0;    // N^3
-  size_t real_off = 0, cplx_off = 0;  // element offsets in user field sets
-  size_t ws_off = 0;                  // byte offset of this box's workspace
-  size_t zs_bytes = 0, work_bytes = 0, spec_bytes = 0;
   int nshell = 0;
+  size_t real_off = 0, cplx_off = 0;   // of the first box
+  size_t ws_off = 0;                   // byte offset of the class workspace
+  size_t zs_box = 0, work_box = 0, spec_box = 0;  // bytes per box
   void* tw = nullptr;  // device twiddle table (length N), owned by the plan
 };
 
@@ -72,6 +83,8 @@ struct ps_plan_s {
   ps_dtype dtype = PS_F32;
   int device = 0;
   std::vector<Box> boxes;
+  std::vector<Class> classes;
+  bool per_box = false;  // baseline: one launch per box instead of per class
   std::map<int, void*> tables;
   hipStream_t stream = nullptr;
   hipStream_t cap = nullptr;  // private stream used only for graph capture
@@ -95,7 +108,7 @@ namespace {
 
 size_t csize(const ps_plan_s* p) { return p->dtype == PS_F32 ? 8 : 16; }
 
-const char* const KINDS[] = {"y", "z", "z_curl", "z_epi", "x_prod"};
+const char* const KINDS[] = {"y", "z", "z_curl", "z_epi", "x_prod", "batch"};
 
 int var_of(const ps_plan_s* p, const char* kind) {
   auto it = p->var.find(kind);
@@ -187,67 +200,73 @@ ps_status enqueue(ps_plan_s* p, hipStream_t s, const char* kind, double bytes, F
 template <typename T>
 struct Seq {
   ps_plan_s* p;
-  const Box& b;
+  const Class& b;
+  int b0, nb;  // boxes [b0, b0 + nb) of the class
   hipStream_t s;
   using C = ps::C2<T>;
   const C* tw() const { return (const C*)b.tw; }
-  C* zstar() const { return (C*)((char*)p->ws + b.ws_off); }
-  C* work() const { return (C*)((char*)p->ws + b.ws_off + b.zs_bytes); }
-  double* spec_part() const { return (double*)((char*)p->ws + b.ws_off + b.zs_bytes + b.work_bytes); }
+  int nf() const { return p->nfields; }
+  long st_bs() const { return nf() * b.nc; }      // state / zstar box stride
+  long wk_bs() const { return 2 * nf() * b.ncp; }  // work box stride
+  C* zstar() const { return (C*)((char*)p->ws + b.ws_off) + b0 * st_bs(); }
+  C* work() const { return (C*)((char*)p->ws + b.ws_off + b.zs_box * b.nb) + b0 * wk_bs(); }
+  double* spec_part(int i) const {
+    return (double*)((char*)p->ws + b.ws_off + (b.zs_box + b.work_box) * b.nb + (b0 + i) * b.spec_box);
+  }
   double cs() const { return (double)sizeof(C); }
 
-  // strided pass in place on nf fields, line = z (y pass) or ky (z pass)
-  ps_status ypass(C* x, long pitch, int nf, int dir) {
+  // strided pass in place on the first nfl fields of every box, line = z
+  ps_status ypass(C* x, long pitch, long bs, int nfl, int dir) {
     ps::StridedArgs<T> a{};
     a.in = x; a.out = x; a.tw = tw();
     a.in_fs = a.out_fs = (long)b.N * b.N * pitch;
     a.in_ls = a.out_ls = (long)b.N * pitch;
     a.in_es = a.out_es = pitch;
-    a.ncols = (int)b.H; a.nlines = b.N; a.nf = nf;
-    const double bytes = 2.0 * nf * b.nc * cs();
+    a.in_bs = a.out_bs = bs;
+    a.ncols = (int)b.H; a.nlines = b.N; a.nf = nfl; a.nb = nb;
+    const double bytes = 2.0 * nfl * nb * b.nc * cs();
     const int v = var_of(p, "y");
     return enqueue(p, s, dir == ps::FWD ? "y_fwd" : "y_inv", bytes,
                    [&](hipStream_t st) { return ps::launch_strided<T>(b.N, dir, v, a, st); });
   }
-  ps_status zpass(const C* in, long in_pitch, C* out, long out_pitch, int nf, int dir) {
+  ps_status zpass(const C* in, long in_pitch, long in_bs, C* out, long out_pitch, long out_bs, int dir) {
     ps::StridedArgs<T> a{};
     a.in = in; a.out = out; a.tw = tw();
     a.in_fs = (long)b.N * b.N * in_pitch; a.out_fs = (long)b.N * b.N * out_pitch;
     a.in_ls = in_pitch; a.out_ls = out_pitch;
     a.in_es = (long)b.N * in_pitch; a.out_es = (long)b.N * out_pitch;
-    a.ncols = (int)b.H; a.nlines = b.N; a.nf = nf;
-    const double bytes = 2.0 * nf * b.nc * cs();
+    a.in_bs = in_bs; a.out_bs = out_bs;
+    a.ncols = (int)b.H; a.nlines = b.N; a.nf = nf(); a.nb = nb;
+    const double bytes = 2.0 * nf() * nb * b.nc * cs();
     const int v = var_of(p, "z");
     return enqueue(p, s, dir == ps::FWD ? "z_fwd" : "z_inv", bytes,
                    [&](hipStream_t st) { return ps::launch_strided<T>(b.N, dir, v, a, st); });
   }
 
   ps_status r2c(const T* real_in, C* out) {
-    const int nf = p->nfields;
     ps::XArgs<T> a{};
     a.in = (const C*)real_in; a.out = out; a.tw = tw();
-    a.in_pitch = b.N / 2; a.in_fs = (long)b.N * b.N * (b.N / 2);
-    a.out_pitch = b.H; a.out_fs = b.nc;
-    a.rows = (long)b.N * b.N; a.nf = nf;
-    const double bytes = nf * (b.n3 * (double)sizeof(T) + b.nc * cs());
+    a.in_pitch = b.N / 2; a.in_fs = (long)b.N * b.N * (b.N / 2); a.in_bs = nf() * a.in_fs;
+    a.out_pitch = b.H; a.out_fs = b.nc; a.out_bs = st_bs();
+    a.rows = (long)b.N * b.N; a.nf = nf(); a.nb = nb;
+    const double bytes = nf() * nb * (b.n3 * (double)sizeof(T) + b.nc * cs());
     ps_status st = enqueue(p, s, "x_r2c", bytes, [&](hipStream_t q) { return ps::launch_x_r2c<T>(b.N, a, q); });
     if (st) return st;
-    if ((st = ypass(out, b.H, nf, ps::FWD))) return st;
-    return zpass(out, b.H, out, b.H, nf, ps::FWD);
+    if ((st = ypass(out, b.H, st_bs(), nf(), ps::FWD))) return st;
+    return zpass(out, b.H, st_bs(), out, b.H, st_bs(), ps::FWD);
   }
 
   ps_status c2r(const C* in, T* real_out) {
-    const int nf = p->nfields;
     C* w = work();
-    ps_status st = zpass(in, b.H, w, b.P, nf, ps::INV);
+    ps_status st = zpass(in, b.H, st_bs(), w, b.P, wk_bs(), ps::INV);
     if (st) return st;
-    if ((st = ypass(w, b.P, nf, ps::INV))) return st;
+    if ((st = ypass(w, b.P, wk_bs(), nf(), ps::INV))) return st;
     ps::XArgs<T> a{};
     a.in = w; a.out = (C*)real_out; a.tw = tw();
-    a.in_pitch = b.P; a.in_fs = b.ncp;
-    a.out_pitch = b.N / 2; a.out_fs = (long)b.N * b.N * (b.N / 2);
-    a.rows = (long)b.N * b.N; a.nf = nf;
-    const double bytes = nf * (b.n3 * (double)sizeof(T) + b.nc * cs());
+    a.in_pitch = b.P; a.in_fs = b.ncp; a.in_bs = wk_bs();
+    a.out_pitch = b.N / 2; a.out_fs = (long)b.N * b.N * (b.N / 2); a.out_bs = nf() * a.out_fs;
+    a.rows = (long)b.N * b.N; a.nf = nf(); a.nb = nb;
+    const double bytes = nf() * nb * (b.n3 * (double)sizeof(T) + b.nc * cs());
     return enqueue(p, s, "x_c2r", bytes, [&](hipStream_t q) { return ps::launch_x_c2r<T>(b.N, a, q); });
   }
 
@@ -257,8 +276,9 @@ struct Seq {
     ps::ZCurlArgs<T> ca{};
     ca.in = src; ca.out = work(); ca.tw = tw();
     ca.in_fs = b.nc; ca.in_pitch = b.H; ca.out_fs = b.ncp; ca.out_pitch = b.P; ca.N = b.N;
+    ca.in_bs = st_bs(); ca.out_bs = wk_bs(); ca.nb = nb;
     const int v = var_of(p, "z_curl");
-    return enqueue(p, s, "z_curl", (nin + nphys) * b.nc * cs(),
+    return enqueue(p, s, "z_curl", (double)(nin + nphys) * nb * b.nc * cs(),
                    [&](hipStream_t q) { return ps::launch_z_curl<T>(b.N, mhd, v, ca, q); });
   }
   ps_status pass_xprod(bool mhd) {
@@ -266,9 +286,10 @@ struct Seq {
     ps::XArgs<T> xa{};
     xa.in = work(); xa.out = work(); xa.tw = tw();
     xa.in_pitch = xa.out_pitch = b.P; xa.in_fs = xa.out_fs = b.ncp;
-    xa.rows = (long)b.N * b.N; xa.nf = nphys;
+    xa.in_bs = xa.out_bs = wk_bs();
+    xa.rows = (long)b.N * b.N; xa.nf = nphys; xa.nb = nb;
     const int v = var_of(p, "x_prod");
-    return enqueue(p, s, "x_prod", (nphys + nprod) * b.nc * cs(),
+    return enqueue(p, s, "x_prod", (double)(nphys + nprod) * nb * b.nc * cs(),
                    [&](hipStream_t q) { return ps::launch_x_prod<T>(b.N, mhd, v, xa, q); });
   }
   ps_status pass_zepi(bool mhd, int mode, C* out, const C* st0, const C* st1, T h, T nua, T nub) {
@@ -276,11 +297,12 @@ struct Seq {
     ps::ZEpiArgs<T> ea{};
     ea.in = work(); ea.out = out; ea.st0 = st0; ea.st1 = st1; ea.tw = tw();
     ea.in_fs = b.ncp; ea.in_pitch = b.P; ea.out_fs = b.nc; ea.out_pitch = b.H;
+    ea.in_bs = wk_bs(); ea.out_bs = st_bs(); ea.nb = nb;
     ea.scale = (T)(1.0 / ((double)b.N * b.N * b.N));
     ea.h = h; ea.nua = nua; ea.nub = nub; ea.N = b.N; ea.mode = mode;
     const int nrw = mode == 0 ? 0 : (mode == 1 ? 1 : 2);
     const int v = var_of(p, "z_epi");
-    return enqueue(p, s, "z_epi", (nprod + nprod + nrw * nprod) * b.nc * cs(),
+    return enqueue(p, s, "z_epi", (double)(nprod + nprod + nrw * nprod) * nb * b.nc * cs(),
                    [&](hipStream_t q) { return ps::launch_z_epi<T>(b.N, mhd, v, ea, q); });
   }
 
@@ -289,9 +311,9 @@ struct Seq {
     const int nphys = mhd ? 12 : 6, nprod = mhd ? 6 : 3;
     ps_status st = pass_zcurl(src, mhd);
     if (st) return st;
-    if ((st = ypass(work(), b.P, nphys, ps::INV))) return st;
+    if ((st = ypass(work(), b.P, wk_bs(), nphys, ps::INV))) return st;
     if ((st = pass_xprod(mhd))) return st;
-    if ((st = ypass(work(), b.P, nprod, ps::FWD))) return st;
+    if ((st = ypass(work(), b.P, wk_bs(), nprod, ps::FWD))) return st;
     return pass_zepi(mhd, mode, out, st0, st1, h, nua, nub);
   }
 
@@ -299,7 +321,7 @@ struct Seq {
   // workspace is written
   ps_status tune_launch(const char* kind, const C* state, bool mhd) {
     if (!strcmp(kind, "z_curl")) return pass_zcurl(state, mhd);
-    if (!strcmp(kind, "y")) return ypass(work(), b.P, mhd ? 12 : 6, ps::INV);
+    if (!strcmp(kind, "y")) return ypass(work(), b.P, wk_bs(), mhd ? 12 : 6, ps::INV);
     if (!strcmp(kind, "x_prod")) return pass_xprod(mhd);
     if (!strcmp(kind, "z_epi")) return pass_zepi(mhd, 0, zstar(), nullptr, nullptr, T(0), T(0), T(0));
     return fail(PS_ERR_ARG, std::string("no tuning launch for kind ") + kind);
@@ -313,14 +335,32 @@ struct Seq {
     return rhs(zs, mhd, 2, nullptr, state, zs, (T)dt, nua, nub);
   }
 
-  ps_status spectrum(const C* f, int nf, double* spec, double* totals) {
+  ps_status spectrum(int i, const C* f, int nfl, double* spec, double* totals) {
     ps::SpecArgs<T> a{};
-    a.f = f; a.part = spec_part(); a.pmax = a.part + (long)b.N * b.nshell * 2;
-    a.fs = b.nc; a.pitch = b.H; a.N = b.N; a.nf = nf; a.nshell = b.nshell;
-    return enqueue(p, s, "spectrum", nf * b.nc * cs(),
+    a.f = f; a.part = spec_part(i); a.pmax = a.part + (long)b.N * b.nshell * 2;
+    a.fs = b.nc; a.pitch = b.H; a.N = b.N; a.nf = nfl; a.nshell = b.nshell;
+    return enqueue(p, s, "spectrum", nfl * b.nc * cs(),
                    [&](hipStream_t q) { return ps::launch_spectrum<T>(a, spec, totals, q); });
   }
 };
+
+// Run f(seq, first_box_index) over the plan: one Seq per class, or per box
+// in the one-box-per-launch baseline.
+template <typename T, class F>
+ps_status for_each_launch(ps_plan_s* p, hipStream_t s, F&& f) {
+  for (auto& c : p->classes) {
+    if (p->per_box) {
+      for (int i = 0; i < c.nb; ++i) {
+        Seq<T> q{p, c, i, 1, s};
+        if (ps_status st = f(q, c.first + i)) return st;
+      }
+    } else {
+      Seq<T> q{p, c, 0, c.nb, s};
+      if (ps_status st = f(q, c.first)) return st;
+    }
+  }
+  return PS_OK;
+}
 
 ps_status validate_plan(ps_plan p) {
   if (!p) return fail(PS_ERR_ARG, "plan is NULL");
@@ -443,38 +483,53 @@ ps_status ps_plan_create_batch(ps_plan* out, int nbox, const int* Ns, int nfield
       return hip_fail(e, "hipGetDevice");
     }
     const size_t cs = csize(p);
-    size_t ws = 0, roff = 0, coff = 0;
+    size_t roff = 0, coff = 0;
     for (int i = 0; i < nbox; ++i) {
       Box b;
       b.N = Ns[i];
-      b.H = b.N / 2 + 1;
-      const long align = 128 / (long)cs;
-      b.P = (b.H + align - 1) / align * align;
-      b.nc = (long)b.N * b.N * b.H;
-      b.ncp = (long)b.N * b.N * b.P;
-      b.n3 = (long)b.N * b.N * b.N;
       b.real_off = roff;
       b.cplx_off = coff;
-      roff += (size_t)nfields * b.n3;
-      coff += (size_t)nfields * b.nc;
+      roff += (size_t)nfields * b.N * b.N * b.N;
+      coff += (size_t)nfields * b.N * b.N * (b.N / 2 + 1);
       b.nshell = (int)shell_of(3L * (b.N / 2) * (b.N / 2)) + 1;
-      b.zs_bytes = align256((size_t)nfields * b.nc * cs);
-      b.work_bytes = align256((size_t)2 * nfields * b.ncp * cs);
-      b.spec_bytes = align256(((size_t)b.N * b.nshell * 2 + b.N) * sizeof(double));
-      b.ws_off = ws;
-      ws += b.zs_bytes + b.work_bytes + b.spec_bytes;
+      if (p->classes.empty() || p->classes.back().N != b.N) {
+        Class c;
+        c.N = b.N;
+        c.first = i;
+        c.nb = 0;
+        c.H = c.N / 2 + 1;
+        const long align = 128 / (long)cs;
+        c.P = (c.H + align - 1) / align * align;
+        c.nc = (long)c.N * c.N * c.H;
+        c.ncp = (long)c.N * c.N * c.P;
+        c.n3 = (long)c.N * c.N * c.N;
+        c.nshell = b.nshell;
+        c.real_off = b.real_off;
+        c.cplx_off = b.cplx_off;
+        c.zs_box = (size_t)nfields * c.nc * cs;
+        c.work_box = (size_t)2 * nfields * c.ncp * cs;
+        c.spec_box = align256(((size_t)c.N * c.nshell * 2 + c.N) * sizeof(double));
+        p->classes.push_back(c);
+      }
+      b.cls = (int)p->classes.size() - 1;
+      b.idx = p->classes.back().nb++;
       p->boxes.push_back(b);
+    }
+    size_t ws = 0;
+    for (auto& c : p->classes) {
+      c.ws_off = ws;
+      ws += align256((c.zs_box + c.work_box) * c.nb) + c.spec_box * c.nb;
     }
     p->ws_need = ws;
     p->real_total = roff;
     p->cplx_total = coff;
-    for (auto& b : p->boxes) {
-      ps_status st = dtype == PS_F32 ? upload_table<float>(p, b.N) : upload_table<double>(p, b.N);
+    for (auto& c : p->classes) {
+      ps_status st = dtype == PS_F32 ? upload_table<float>(p, c.N) : upload_table<double>(p, c.N);
       if (st) {
         free_plan(p);
         return st;
       }
-      b.tw = p->tables[b.N];
+      c.tw = p->tables[c.N];
     }
     // measured defaults at 512^3 (the autotuner refines them per workload)
     bool any_var = false;
@@ -552,12 +607,10 @@ ps_status ps_fft_r2c(ps_plan p, const void* real_in, void* cplx_out) {
     if (ps_status st = set_device(p)) return st;
     return by_type(p, [&](auto* tag) -> ps_status {
       using T = std::remove_pointer_t<decltype(tag)>;
-      for (auto& b : p->boxes) {
-        Seq<T> q{p, b, p->stream};
-        ps_status st = q.r2c((const T*)real_in + b.real_off, (ps::C2<T>*)cplx_out + b.cplx_off);
-        if (st) return st;
-      }
-      return PS_OK;
+      return for_each_launch<T>(p, p->stream, [&](Seq<T>& q, int bi) {
+        const Box& b = p->boxes[bi];
+        return q.r2c((const T*)real_in + b.real_off, (ps::C2<T>*)cplx_out + b.cplx_off);
+      });
     });
   });
 }
@@ -571,12 +624,10 @@ ps_status ps_fft_c2r(ps_plan p, const void* cplx_in, void* real_out) {
     if (ps_status st = set_device(p)) return st;
     return by_type(p, [&](auto* tag) -> ps_status {
       using T = std::remove_pointer_t<decltype(tag)>;
-      for (auto& b : p->boxes) {
-        Seq<T> q{p, b, p->stream};
-        ps_status st = q.c2r((const ps::C2<T>*)cplx_in + b.cplx_off, (T*)real_out + b.real_off);
-        if (st) return st;
-      }
-      return PS_OK;
+      return for_each_launch<T>(p, p->stream, [&](Seq<T>& q, int bi) {
+        const Box& b = p->boxes[bi];
+        return q.c2r((const ps::C2<T>*)cplx_in + b.cplx_off, (T*)real_out + b.real_off);
+      });
     });
   });
 }
@@ -592,14 +643,13 @@ static ps_status nonlinear(ps_plan p, const void* in, void* out, bool mhd) {
     if (ps_status st = set_device(p)) return st;
     return by_type(p, [&](auto* tag) -> ps_status {
       using T = std::remove_pointer_t<decltype(tag)>;
-      for (auto& b : p->boxes) {
-        if (mhd && !ps::mhd_supported<T>(b.N)) return fail(PS_ERR_SIZE, "MHD not supported at this N and dtype");
-        Seq<T> q{p, b, p->stream};
+      for (auto& c : p->classes)
+        if (mhd && !ps::mhd_supported<T>(c.N)) return fail(PS_ERR_SIZE, "MHD not supported at this N and dtype");
+      return for_each_launch<T>(p, p->stream, [&](Seq<T>& q, int bi) {
+        const Box& b = p->boxes[bi];
         ps::C2<T>* o = (ps::C2<T>*)out + b.cplx_off;
-        ps_status st = q.rhs((const ps::C2<T>*)in + b.cplx_off, mhd, 0, o, nullptr, nullptr, T(0), T(0), T(0));
-        if (st) return st;
-      }
-      return PS_OK;
+        return q.rhs((const ps::C2<T>*)in + b.cplx_off, mhd, 0, o, nullptr, nullptr, T(0), T(0), T(0));
+      });
     });
   });
 }
@@ -622,15 +672,12 @@ ps_status ps_rk2_step(ps_plan p, void* state, ps_model m, double nu, double eta,
     if (nsteps == 0) return PS_OK;
     return by_type(p, [&](auto* tag) -> ps_status {
       using T = std::remove_pointer_t<decltype(tag)>;
-      for (auto& b : p->boxes)
-        if (mhd && !ps::mhd_supported<T>(b.N)) return fail(PS_ERR_SIZE, "MHD not supported at this N and dtype");
+      for (auto& c : p->classes)
+        if (mhd && !ps::mhd_supported<T>(c.N)) return fail(PS_ERR_SIZE, "MHD not supported at this N and dtype");
       auto one_step = [&](hipStream_t s) -> ps_status {
-        for (auto& b : p->boxes) {
-          Seq<T> q{p, b, s};
-          ps_status st = q.rk2((ps::C2<T>*)state + b.cplx_off, mhd, nu, eta, dt);
-          if (st) return st;
-        }
-        return PS_OK;
+        return for_each_launch<T>(p, s, [&](Seq<T>& q, int bi) {
+          return q.rk2((ps::C2<T>*)state + p->boxes[bi].cplx_off, mhd, nu, eta, dt);
+        });
       };
       if (!p->graphs || p->timing) {
         for (int i = 0; i < nsteps; ++i)
@@ -679,8 +726,9 @@ ps_status ps_energy_spectrum(ps_plan p, const void* fhat, int nfields, double* s
     size_t nsh = 0;
     for (auto& b : p->boxes) nsh += b.nshell;
     // the input holds nfields fields per box at the plan's box offsets
+    const Class& lc = p->classes.back();
     if (ps_status st = check_dev(fhat, p->cplx_total * csize(p) - (size_t)(p->nfields - nfields) *
-                                           p->boxes.back().nc * csize(p), "fhat"))
+                                           lc.nc * csize(p), "fhat"))
       return st;
     if (ps_status st = check_dev(spec_dev, nsh * sizeof(double), "spec")) return st;
     if (ps_status st = check_dev(totals_dev, 3 * p->boxes.size() * sizeof(double), "totals")) return st;
@@ -690,8 +738,9 @@ ps_status ps_energy_spectrum(ps_plan p, const void* fhat, int nfields, double* s
       size_t so = 0;
       for (size_t i = 0; i < p->boxes.size(); ++i) {
         auto& b = p->boxes[i];
-        Seq<T> q{p, b, p->stream};
-        ps_status st = q.spectrum((const ps::C2<T>*)fhat + b.cplx_off, nfields, spec_dev + so, totals_dev + 3 * i);
+        Seq<T> q{p, p->classes[b.cls], 0, p->classes[b.cls].nb, p->stream};
+        ps_status st = q.spectrum(b.idx, (const ps::C2<T>*)fhat + b.cplx_off, nfields, spec_dev + so,
+                                  totals_dev + 3 * i);
         if (st) return st;
         so += b.nshell;
       }
@@ -708,8 +757,10 @@ ps_status ps_plan_set_variant(ps_plan p, const char* kind, int v) {
   if (!known) return fail(PS_ERR_ARG, std::string("unknown pass kind ") + kind);
   int n = 1;
   for (auto& b : p->boxes) n = std::max(n, ps::variant_count(kind, b.N, p->nfields == 6));
+  if (!strcmp(kind, "batch")) n = 2;
   if (v < 0 || v >= n) return fail(PS_ERR_ARG, "variant out of range");
   p->var[kind] = v;
+  p->per_box = var_of(p, "batch") == 1;
   if (p->gexec) {
     hipGraphExecDestroy(p->gexec);
     p->gexec = nullptr;
@@ -725,6 +776,7 @@ int ps_plan_get_variant(ps_plan p, const char* kind) {
 
 int ps_plan_variant_count(ps_plan p, const char* kind) {
   if (!p || !kind) return PS_ERR_ARG;
+  if (!strcmp(kind, "batch")) return 2;
   int n = 1;
   for (auto& b : p->boxes) n = std::max(n, ps::variant_count(kind, b.N, p->nfields == 6));
   return n;
@@ -744,11 +796,11 @@ ps_status ps_plan_autotune(ps_plan p, const void* state, ps_model m, int reps) {
     p->timing = false;
     ps_status res = by_type(p, [&](auto* tag) -> ps_status {
       using T = std::remove_pointer_t<decltype(tag)>;
-      size_t bi = 0;
-      for (size_t i = 1; i < p->boxes.size(); ++i)
-        if (p->boxes[i].N > p->boxes[bi].N) bi = i;
-      const Box& b = p->boxes[bi];
-      Seq<T> q{p, b, p->stream};
+      size_t ci = 0;
+      for (size_t i = 1; i < p->classes.size(); ++i)
+        if (p->classes[i].N > p->classes[ci].N) ci = i;
+      const Class& b = p->classes[ci];
+      Seq<T> q{p, b, 0, b.nb, p->stream};
       const auto* st = (const ps::C2<T>*)state + b.cplx_off;
       hipEvent_t e0, e1;
       if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)

@@ -40,8 +40,8 @@ __device__ __forceinline__ int xcd_remap(int bid, int n) {
 
 // ---------------------------------------------------------------------------
 // Strided complex pass (plain), used for y and z.
-// Field f, line l, column c (0 <= c < ncols), element idx:
-//   in[f * in_fs + l * in_ls + c + idx * in_es]
+// Box b, field f, line l, column c (0 <= c < ncols), element idx:
+//   in[b * in_bs + f * in_fs + l * in_ls + c + idx * in_es]
 // ---------------------------------------------------------------------------
 template <typename T>
 struct StridedArgs {
@@ -50,7 +50,8 @@ struct StridedArgs {
   const C2<T>* tw;  // exp(-2 pi i e / L), e < L
   long in_fs, in_ls, in_es;
   long out_fs, out_ls, out_es;
-  int ncols, ntile, nlines, nf;
+  long in_bs, out_bs;  // box strides (ensembles of equal-size boxes)
+  int ncols, ntile, nlines, nf, nb;
 };
 
 template <typename T, int L, int TQ, int TX, int DIR, class RL, int MINW = 1>
@@ -61,11 +62,13 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_strided(StridedArgs<T> a) {
   int blk = xcd_remap(blockIdx.x, gridDim.x);
   const int tile = blk % a.ntile;
   blk /= a.ntile;
-  const int line = blk % a.nlines, f = blk / a.nlines;
+  const int line = blk % a.nlines;
+  blk /= a.nlines;
+  const int f = blk % a.nf, box = blk / a.nf;
   const int col = tile * TX + c;
   const bool ok = col < a.ncols;
-  const C2<T>* in = a.in + f * a.in_fs + line * a.in_ls + col;
-  C2<T>* out = a.out + f * a.out_fs + line * a.out_ls + col;
+  const C2<T>* in = a.in + box * a.in_bs + f * a.in_fs + line * a.in_ls + col;
+  C2<T>* out = a.out + box * a.out_bs + f * a.out_fs + line * a.out_ls + col;
   C2<T> v[E::SLOTS];
   E::run(v, smem + c, TX, q, a.tw, 1,
          [&](int, int idx) { return ok ? in[idx * a.in_es] : zero2<T>(); });
@@ -89,7 +92,8 @@ struct ZCurlArgs {
   const C2<T>* tw;
   long in_fs, in_pitch;   // field stride, kx pitch of the input (line = ky)
   long out_fs, out_pitch;
-  int N, ntile;
+  long in_bs, out_bs;     // box strides
+  int N, ntile, nb;
 };
 
 // RELOAD (MHD only): two phases, u-derived fields then b-derived fields, each
@@ -102,13 +106,13 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_z_curl(ZCurlArgs<T> a) {
   __shared__ C2<T> smem[L * TX];
   const int tid = threadIdx.x, c = tid % TX, q = tid / TX;
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
-  const int tile = blk % a.ntile, ky = blk / a.ntile;
   const int N = L;
+  const int tile = blk % a.ntile, ky = (blk / a.ntile) % N, box = blk / (a.ntile * N);
   const int col = tile * TX + c;
   const bool ok = col < N / 2 + 1;
   const long in_es = (long)N * a.in_pitch, out_es = (long)N * a.out_pitch;
-  const C2<T>* in = a.in + ky * a.in_pitch + col;
-  C2<T>* out = a.out + ky * a.out_pitch + col;
+  const C2<T>* in = a.in + box * a.in_bs + ky * a.in_pitch + col;
+  C2<T>* out = a.out + box * a.out_bs + ky * a.out_pitch + col;
   const T kx = (T)dwavx(col, N), kyd = (T)dwav(ky, N);
 
   // one output field: FFT of component `comp` of `src` (grp even) or of its curl (grp odd)
@@ -197,8 +201,9 @@ struct ZEpiArgs {
   const C2<T>* tw;
   long in_fs, in_pitch;
   long out_fs, out_pitch;  // out, st0 and st1 share this layout
+  long in_bs, out_bs;      // box strides
   T scale, h, nua, nub;
-  int N, ntile, mode;
+  int N, ntile, mode, nb;
 };
 
 template <typename T, int L, int TQ, int TX, class RL, bool MHD, int MINW = 1>
@@ -209,12 +214,12 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_z_epi(ZEpiArgs<T> a) {
   __shared__ C2<T> smem[L * TX];
   const int tid = threadIdx.x, c = tid % TX, q = tid / TX;
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
-  const int tile = blk % a.ntile, ky = blk / a.ntile;
   const int N = L;
+  const int tile = blk % a.ntile, ky = (blk / a.ntile) % N, box = blk / (a.ntile * N);
   const int col = tile * TX + c;
   const bool ok = col < N / 2 + 1;
   const long in_es = (long)N * a.in_pitch, out_es = (long)N * a.out_pitch;
-  const C2<T>* in = a.in + ky * a.in_pitch + col;
+  const C2<T>* in = a.in + box * a.in_bs + ky * a.in_pitch + col;
 
   C2<T> r[NF][NO];
 #pragma unroll
@@ -227,7 +232,7 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_z_epi(ZEpiArgs<T> a) {
   }
   if (!ok) return;  // no barrier follows
 
-  const long base = ky * a.out_pitch + col;
+  const long base = box * a.out_bs + ky * a.out_pitch + col;
   const int ikx = col, iky = wav(ky, N);
   const T kxd = (T)dwavx(col, N), kyd = (T)dwav(ky, N);
 #pragma unroll
@@ -328,8 +333,9 @@ struct XArgs {
   C2<T>* out;
   const C2<T>* tw;   // length N
   long in_fs, in_pitch, out_fs, out_pitch;  // per-row pitch in complex elements
+  long in_bs, out_bs;  // box strides
   long rows;         // rows per field (N*N)
-  int nf;
+  int nf, nb;
 };
 
 // plain inverse: complex rows (pitch in_pitch) -> real rows (N reals, pitch out_pitch complex = M)
@@ -340,14 +346,15 @@ __global__ __launch_bounds__(G* TQ) void k_x_c2r(XArgs<T> a) {
   __shared__ C2<T> smem[G * LP];
   const int tid = threadIdx.x, g = tid / TQ, q = tid % TQ;
   const long row0 = (long)xcd_remap(blockIdx.x, gridDim.x) * G;
-  const long total = a.rows * a.nf;
+  const long total = a.rows * a.nf * a.nb;
   for (int i = tid; i < G * (M + 1); i += G * TQ) {
     const int gg = i / (M + 1), k = i % (M + 1);
     const long row = row0 + gg;
     C2<T> val = zero2<T>();
     if (row < total) {
-      const long f = row / a.rows, r = row % a.rows;
-      val = a.in[f * a.in_fs + r * a.in_pitch + k];
+      const long fb = row / a.rows, r = row % a.rows;
+      const long f = fb % a.nf, b = fb / a.nf;
+      val = a.in[b * a.in_bs + f * a.in_fs + r * a.in_pitch + k];
     }
     smem[gg * LP + pad8(k)] = val;
   }
@@ -357,8 +364,9 @@ __global__ __launch_bounds__(G* TQ) void k_x_c2r(XArgs<T> a) {
   E::template run<LayPad8>(v, buf, 1, q, a.tw, 2, [&](int, int k) { return c2r_pre(buf, k, M, a.tw); });
   const long row = row0 + g;
   if (row >= total) return;
-  const long f = row / a.rows, r = row % a.rows;
-  C2<T>* out = a.out + f * a.out_fs + r * a.out_pitch;
+  const long fb = row / a.rows, r = row % a.rows;
+  const long f = fb % a.nf, b = fb / a.nf;
+  C2<T>* out = a.out + b * a.out_bs + f * a.out_fs + r * a.out_pitch;
 #pragma unroll
   for (int s = 0; s < E::LAST_NB * E::RL_; ++s)
     if (E::last_valid(q, s)) out[E::last_index(q, s)] = v[s];
@@ -372,11 +380,11 @@ __global__ __launch_bounds__(G* TQ) void k_x_r2c(XArgs<T> a) {
   __shared__ C2<T> smem[G * LP];
   const int tid = threadIdx.x, g = tid / TQ, q = tid % TQ;
   const long row0 = (long)xcd_remap(blockIdx.x, gridDim.x) * G;
-  const long total = a.rows * a.nf;
+  const long total = a.rows * a.nf * a.nb;
   const long row = row0 + g;
   const bool ok = row < total;
-  const long f = ok ? row / a.rows : 0, r = ok ? row % a.rows : 0;
-  const C2<T>* in = a.in + f * a.in_fs + r * a.in_pitch;
+  const long fb = ok ? row / a.rows : 0, r = ok ? row % a.rows : 0;
+  const C2<T>* in = a.in + (fb / a.nf) * a.in_bs + (fb % a.nf) * a.in_fs + r * a.in_pitch;
   C2<T>* buf = smem + g * LP;
   C2<T> v[E::SLOTS];
   E::template run<LayPad8>(v, buf, 1, q, a.tw, 2, [&](int, int n) { return ok ? in[n] : zero2<T>(); });
@@ -389,8 +397,9 @@ __global__ __launch_bounds__(G* TQ) void k_x_r2c(XArgs<T> a) {
     const int gg = i / (M + 1), k = i % (M + 1);
     const long rw = row0 + gg;
     if (rw < total) {
-      const long ff = rw / a.rows, rr = rw % a.rows;
-      a.out[ff * a.out_fs + rr * a.out_pitch + k] = r2c_post(smem + gg * LP, k, M, a.tw);
+      const long fb = rw / a.rows, rr = rw % a.rows;
+      a.out[(fb / a.nf) * a.out_bs + (fb % a.nf) * a.out_fs + rr * a.out_pitch + k] =
+          r2c_post(smem + gg * LP, k, M, a.tw);
     }
   }
 }
@@ -409,12 +418,16 @@ __global__ __launch_bounds__((MHD ? 12 : 6) * RB * TQ) void k_x_prod(XArgs<T> a)
   __shared__ C2<T> smem[G * LP];
   const int tid = threadIdx.x, g = tid / TQ, q = tid % TQ;
   const long row0 = (long)xcd_remap(blockIdx.x, gridDim.x) * RB;
+  const long total = a.rows * a.nb;
+  // row index over boxes: box = row / rows; offset of (row, field f)
+  auto in_at = [&](long row, int f) { return (row / a.rows) * a.in_bs + f * a.in_fs + (row % a.rows) * a.in_pitch; };
+  auto out_at = [&](long row, int f) { return (row / a.rows) * a.out_bs + f * a.out_fs + (row % a.rows) * a.out_pitch; };
   // ---- load FIN x RB rows; slot (f, rb) at smem[(f * RB + rb) * LP]
   for (int i = tid; i < G * (M + 1); i += NT) {
     const int gr = i / (M + 1), k = i % (M + 1);
     const int f = gr / RB, rb = gr % RB;
     const long row = row0 + rb;
-    smem[gr * LP + pad8(k)] = row < a.rows ? a.in[f * a.in_fs + row * a.in_pitch + k] : zero2<T>();
+    smem[gr * LP + pad8(k)] = row < total ? a.in[in_at(row, f) + k] : zero2<T>();
   }
   __syncthreads();
   // ---- inverse real FFTs, physical values back into the same slot
@@ -470,7 +483,7 @@ __global__ __launch_bounds__((MHD ? 12 : 6) * RB * TQ) void k_x_prod(XArgs<T> a)
     const int gr = i / (M + 1), k = i % (M + 1);
     const int f = gr / RB, rb = gr % RB;
     const long row = row0 + rb;
-    if (row < a.rows) a.out[f * a.out_fs + row * a.out_pitch + k] = r2c_post(smem + gr * LP, k, M, a.tw);
+    if (row < total) a.out[out_at(row, f) + k] = r2c_post(smem + gr * LP, k, M, a.tw);
   }
 }
 
@@ -490,10 +503,11 @@ __global__ __launch_bounds__(RPW* TQ) void k_x_prod2(XArgs<T> a) {
   __shared__ C2<T> smem[RPW * LP];
   const int tid = threadIdx.x, g = tid / TQ, q = tid % TQ;
   const long row = (long)xcd_remap(blockIdx.x, gridDim.x) * RPW + g;
-  const bool ok = row < a.rows;
+  const bool ok = row < a.rows * a.nb;
   C2<T>* buf = smem + g * LP;
-  const C2<T>* in = a.in + (ok ? row : 0) * a.in_pitch;
-  C2<T>* outp = a.out + (ok ? row : 0) * a.out_pitch;
+  const long rr = ok ? row : 0;
+  const C2<T>* in = a.in + (rr / a.rows) * a.in_bs + (rr % a.rows) * a.in_pitch;
+  C2<T>* outp = a.out + (rr / a.rows) * a.out_bs + (rr % a.rows) * a.out_pitch;
 
   // inverse real transform of input field f into this thread's point slots
   auto inv = [&](int f, C2<T> (&dst)[NO]) {

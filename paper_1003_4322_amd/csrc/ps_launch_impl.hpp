@@ -29,7 +29,7 @@ hipError_t strided_v(int dir, StridedArgs<T> a, hipStream_t s) {
   using LC = Sched<N, v.alt>;
   constexpr int TX = StridedTX<T, N, LC::TQ, v.sh>::value;
   a.ntile = cdiv(a.ncols, TX);
-  const long grid = (long)a.ntile * a.nlines * a.nf;
+  const long grid = (long)a.ntile * a.nlines * a.nf * a.nb;
   if (grid <= 0) return hipSuccess;
   if (dir == FWD)
     k_strided<T, N, LC::TQ, TX, FWD, typename LC::RL, v.minw><<<dim3((unsigned)grid), dim3(TX * LC::TQ), 0, s>>>(a);
@@ -66,7 +66,7 @@ hipError_t z_curl_v(ZCurlArgs<T> a, hipStream_t s) {
   using LC = Sched<N, v.alt>;
   constexpr int TX = StridedTX<T, N, LC::TQ, v.sh>::value;
   a.ntile = cdiv(N / 2 + 1, TX);
-  const long grid = (long)a.ntile * N;
+  const long grid = (long)a.ntile * N * a.nb;
   k_z_curl<T, N, LC::TQ, TX, typename LC::RL, MHD, MHD && v.reload, v.minw>
       <<<dim3((unsigned)grid), dim3(TX * LC::TQ), 0, s>>>(a);
   return hipGetLastError();
@@ -102,7 +102,7 @@ hipError_t z_epi_v(ZEpiArgs<T> a, hipStream_t s) {
   using LC = Sched<N, v.alt>;
   constexpr int TX = StridedTX<T, N, LC::TQ, v.sh>::value;
   a.ntile = cdiv(N / 2 + 1, TX);
-  const long grid = (long)a.ntile * N;
+  const long grid = (long)a.ntile * N * a.nb;
   k_z_epi<T, N, LC::TQ, TX, typename LC::RL, MHD, v.minw><<<dim3((unsigned)grid), dim3(TX * LC::TQ), 0, s>>>(a);
   return hipGetLastError();
 }
@@ -135,7 +135,7 @@ template <typename T, int N>
 hipError_t x_c2r_n(XArgs<T> a, hipStream_t s) {
   using LC = LenCfg<N / 2>;
   using X = XCfg<T, N / 2, LC::TQ, 0>;
-  const long grid = (a.rows * a.nf + X::G - 1) / X::G;
+  const long grid = (a.rows * a.nf * a.nb + X::G - 1) / X::G;
   k_x_c2r<T, N / 2, LC::TQ, X::G, typename LC::RL><<<dim3((unsigned)grid), dim3(X::G * LC::TQ), 0, s>>>(a);
   return hipGetLastError();
 }
@@ -144,7 +144,7 @@ template <typename T, int N>
 hipError_t x_r2c_n(XArgs<T> a, hipStream_t s) {
   using LC = LenCfg<N / 2>;
   using X = XCfg<T, N / 2, LC::TQ, 0>;
-  const long grid = (a.rows * a.nf + X::G - 1) / X::G;
+  const long grid = (a.rows * a.nf * a.nb + X::G - 1) / X::G;
   k_x_r2c<T, N / 2, LC::TQ, X::G, typename LC::RL><<<dim3((unsigned)grid), dim3(X::G * LC::TQ), 0, s>>>(a);
   return hipGetLastError();
 }
@@ -157,7 +157,7 @@ hipError_t x_prod_v(bool mhd, XArgs<T> a, hipStream_t s) {
     using X = XCfg<T, N / 2, LC::TQ, v.rbsh>;
     if (mhd) {
       if constexpr (X::MHD_OK) {
-        const long grid = (a.rows + X::RB_MHD - 1) / X::RB_MHD;
+        const long grid = (a.rows * a.nb + X::RB_MHD - 1) / X::RB_MHD;
         k_x_prod<T, N / 2, LC::TQ, X::RB_MHD, typename LC::RL, true>
             <<<dim3((unsigned)grid), dim3(12 * X::RB_MHD * LC::TQ), 0, s>>>(a);
         return hipGetLastError();
@@ -165,14 +165,14 @@ hipError_t x_prod_v(bool mhd, XArgs<T> a, hipStream_t s) {
         return hipErrorInvalidValue;
       }
     }
-    const long grid = (a.rows + X::RB_NS - 1) / X::RB_NS;
+    const long grid = (a.rows * a.nb + X::RB_NS - 1) / X::RB_NS;
     k_x_prod<T, N / 2, LC::TQ, X::RB_NS, typename LC::RL, false>
         <<<dim3((unsigned)grid), dim3(6 * X::RB_NS * LC::TQ), 0, s>>>(a);
     return hipGetLastError();
   } else {
     using LC = std::conditional_t<v.kind == 1, LenXA<N / 2>, LenXB<N / 2>>;
     constexpr int RPW = (v.rbsh * LC::TQ > 1024) ? 1024 / LC::TQ : v.rbsh;
-    const long grid = (a.rows + RPW - 1) / RPW;
+    const long grid = (a.rows * a.nb + RPW - 1) / RPW;
     if (mhd)
       k_x_prod2<T, N / 2, LC::TQ, typename LC::RL, true, RPW><<<dim3((unsigned)grid), dim3(RPW * LC::TQ), 0, s>>>(a);
     else
