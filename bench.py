@@ -169,6 +169,105 @@ def device_copy(nbytes: int = 1 << 31, reps: int = 10):
             "GB/s": round(2 * nbytes / (ms * 1e-3) / 1e9, 1)}
 
 
+def ensemble_run(steps: int = 100, warmup: int = 5):
+    """48 NS boxes of 64^3 + 16 of 96^3 + 4 of 128^3, FP32, nu = 5e-3,
+    dt = 2e-3, each seeded separately (seed 1000 + i, k0 uniform in [2, 5]):
+    autotuned class-batched launches vs one box per launch, both replayed
+    from captured graphs."""
+    import numpy as np
+    import torch
+
+    from paper_1003_4322_amd import binding, synth
+
+    sizes = [64] * 48 + [96] * 16 + [128] * 4
+    plan = binding.Plan(sizes, 3, "f32", device="cuda:0")
+    st = torch.empty(plan.n_complex(), dtype=torch.complex64, device="cuda:0")
+    for i, N in enumerate(sizes):
+        f = synth.random_ns(N, 1000 + i, synth.ensemble_k0(1000 + i), dtype=np.complex64)
+        st[plan.cplx_off[i]:plan.cplx_off[i] + f.size] = torch.from_numpy(f.ravel()).to("cuda:0")
+    out = {"boxes": "48 x 64^3 + 16 x 96^3 + 4 x 128^3 NS FP32", "steps": steps}
+    tuned = plan.autotune(st, binding.PS_NS, 3)
+    for mode, name in ((0, "batched"), (1, "per_box")):
+        plan.set_variant("batch", mode)
+        s = st.clone()
+        plan.rk2_step(s, binding.PS_NS, 5e-3, 0.0, 2e-3, warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.rk2_step(s, binding.PS_NS, 5e-3, 0.0, 2e-3, steps)
+        torch.cuda.synchronize()
+        dt_ = time.perf_counter() - t0
+        out[name] = {"steps_per_s": round(steps / dt_, 2), "ms_per_step": round(dt_ * 1e3 / steps, 4)}
+    # per-kernel timing of the batched mode
+    plan.set_variant("batch", 0)
+    plan.set_timing(True)
+    plan.timing_reset()
+    s = st.clone()
+    plan.rk2_step(s, binding.PS_NS, 5e-3, 0.0, 2e-3, 10)
+    torch.cuda.synchronize()
+    out["passes_batched"] = pass_table(plan.timings())
+    plan.set_timing(False)
+    out["variants"] = tuned
+    out["speedup_batched_vs_per_box"] = round(out["batched"]["steps_per_s"] / out["per_box"]["steps_per_s"], 3)
+    bytes_step = sum(v["GB_per_launch"] * v["launches"] for v in out["passes_batched"].values()) / 10
+    out["GB_per_step"] = round(bytes_step, 4)
+    out["effective_GB/s_batched"] = round(bytes_step * out["batched"]["steps_per_s"], 1)
+    plan.close()
+    return out
+
+
+def precision_pair(wname: str, steps: int, warmup: int = 2, spectra_every: int = 0):
+    """FP32 and FP64 forms of a workload from the same FP32-representable
+    initial state: steps/s of each and the FP32-vs-FP64 distance; optional
+    energy spectra every few steps (FP64, deterministic)."""
+    import torch
+
+    from paper_1003_4322_amd import binding
+
+    w = WORKLOADS[wname]
+    dev = torch.device("cuda:0")
+    model = binding.PS_MHD if w["model"] == "mhd" else binding.PS_NS
+    nf = 6 if w["model"] == "mhd" else 3
+    s32, _ = initial_state(w, torch.complex64, dev)
+    res = {"N": w["N"], "fields": nf, "steps": steps}
+    finals = {}
+    for dt in ("f32", "f64"):
+        s = s32.clone() if dt == "f32" else s32.to(torch.complex128)
+        plan = binding.Plan(w["N"], nf, dt, device=dev)
+        tuned = plan.autotune(s, model, 2)
+        one = s.clone()  # one step from the identical initial state
+        plan.rk2_step(one, model, w["nu"], w["eta"], w["dt"], 1)
+        plan.rk2_step(s, model, w["nu"], w["eta"], w["dt"], warmup)
+        torch.cuda.synchronize()
+        spectra = []
+        t0 = time.perf_counter()
+        if spectra_every:
+            done = 0
+            while done < steps:
+                k = min(spectra_every, steps - done)
+                plan.rk2_step(s, model, w["nu"], w["eta"], w["dt"], k)
+                done += k
+                spectra.append(plan.energy_spectrum(s))
+        else:
+            plan.rk2_step(s, model, w["nu"], w["eta"], w["dt"], steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        r = {"steps_per_s": round(steps / el, 3), "ms_per_step": round(el * 1e3 / steps, 3),
+             "variants": tuned}
+        if spectra:
+            r["energy_every_%d_steps" % spectra_every] = [float(t[1][0].item()) for t in spectra]
+            r["spectrum_last_first_16_shells"] = [float(x) for x in spectra[-1][0][:16].cpu()]
+        finals[dt] = (s, one)
+        res[dt] = r
+        del plan
+        torch.cuda.empty_cache()
+    a, b = finals["f32"], finals["f64"]
+    res["l2_f32_vs_f64_one_step"] = rel_l2_w(a[1], b[1])
+    del s32
+    res[f"l2_f32_vs_f64_after_{warmup + steps}_steps"] = rel_l2_w(a[0], b[0])
+    res["tolerance_per_step"] = 2e-6
+    return res
+
+
 def cpu_baseline(w, sample_N):
     """The FP64 oracle timed on this host for one RK2 step at sample_N^3 of
     the same workload recipe, scaled to the workload's N by N^3 log N."""
@@ -196,40 +295,11 @@ def cpu_baseline(w, sample_N):
                       f"scaled to {N}^3 by (N/{sample_N})^3 log N / log {sample_N} = {scale:.2f}"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="mhd512", choices=sorted(WORKLOADS))
-    ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=256)
-    ap.add_argument("--copy-only", action="store_true",
-                    help="only the reference device copy (for counter scaling)")
-    ap.add_argument("--no-tune", action="store_true", help="default kernel variants")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only: the hot path keeps the whole box on one device "
-              f"and has no multi-GPU path (asked for --gpus {args.gpus}).", file=sys.stderr)
-        sys.exit(2)
-
+def run_primary(args, w, model, nf, N, dev):
+    """The headline workload: FP32 timed region (+ FP64 side by side)."""
     import torch
 
     from paper_1003_4322_amd import binding
-
-    w = WORKLOADS[args.workload]
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    if args.copy_only:
-        print(json.dumps({"device_copy": device_copy()}), flush=True)
-        return
-    copy_ref = device_copy()
-    log(f"device copy: {copy_ref['GB/s']} GB/s")
-    model = binding.PS_MHD if w["model"] == "mhd" else binding.PS_NS
-    nf = 6 if w["model"] == "mhd" else 3
-    N = w["N"]
-    log(f"workload {args.workload}: N={N} fields={nf} steps={args.steps} warmup={args.warmup}")
 
     s32, _ = initial_state(w, torch.complex64, dev)
     s32_0 = s32.clone()
@@ -282,6 +352,61 @@ def main():
                 "tolerance_per_step": 2e-6}
         log(f"fp32 vs fp64: one step {l2_1:.3e}, increment {inc:.3e}, run {l2_run:.3e}")
 
+    return ms, ms_graph, tuned32, passes32, roofline, fp64
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="mhd512", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=256)
+    ap.add_argument("--copy-only", action="store_true",
+                    help="only the reference device copy (for counter scaling)")
+    ap.add_argument("--no-tune", action="store_true", help="default kernel variants")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the 256^3, 1024^3, ensemble and 32^3 workloads")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: the hot path keeps the whole box on one device "
+              f"and has no multi-GPU path (asked for --gpus {args.gpus}).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1003_4322_amd import binding
+
+    w = WORKLOADS[args.workload]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    if args.copy_only:
+        print(json.dumps({"device_copy": device_copy()}), flush=True)
+        return
+    copy_ref = device_copy()
+    log(f"device copy: {copy_ref['GB/s']} GB/s")
+    model = binding.PS_MHD if w["model"] == "mhd" else binding.PS_NS
+    nf = 6 if w["model"] == "mhd" else 3
+    N = w["N"]
+    log(f"workload {args.workload}: N={N} fields={nf} steps={args.steps} warmup={args.warmup}")
+
+    ms, ms_graph, tuned32, passes32, roofline, fp64 = run_primary(args, w, model, nf, N, dev)
+    torch.cuda.empty_cache()
+
+    extras = None
+    if not args.no_extras:
+        extras = {}
+        log("extra: NS 256^3 FP32/FP64, 50 steps, spectra every 10")
+        extras["ns256"] = precision_pair("ns256", 50, spectra_every=10)
+        log("extra: NS 1024^3 FP32 vs FP64, 10 steps")
+        extras["ns1024"] = precision_pair("ns1024", 10)
+        log("extra: ensemble")
+        extras["ensemble"] = ensemble_run()
+        log("extra: NS 32^3 FP64 latency")
+        extras["ns32"] = precision_pair("ns32", 200)
+
     cpu = None
     if not args.no_cpu:
         log(f"cpu baseline: oracle, one step at {args.cpu_sample}^3")
@@ -302,6 +427,7 @@ def main():
         "device_copy": copy_ref,
         "roofline": roofline,
         "fp64": fp64,
+        "extras": extras,
         "cpu_baseline": cpu,
         "src_hash": src_hash(),
     }
