@@ -181,6 +181,7 @@ def ensemble_run(steps: int = 100, warmup: int = 5):
 
     sizes = [64] * 48 + [96] * 16 + [128] * 4
     plan = binding.Plan(sizes, 3, "f32", device="cuda:0")
+    plan.set_variant("prune", PRUNE)
     st = torch.empty(plan.n_complex(), dtype=torch.complex64, device="cuda:0")
     for i, N in enumerate(sizes):
         f = synth.random_ns(N, 1000 + i, synth.ensemble_k0(1000 + i), dtype=np.complex64)
@@ -215,6 +216,9 @@ def ensemble_run(steps: int = 100, warmup: int = 5):
     return out
 
 
+PRUNE = 1
+
+
 def precision_pair(wname: str, steps: int, warmup: int = 2, spectra_every: int = 0):
     """FP32 and FP64 forms of a workload from the same FP32-representable
     initial state: steps/s of each and the FP32-vs-FP64 distance; optional
@@ -233,6 +237,7 @@ def precision_pair(wname: str, steps: int, warmup: int = 2, spectra_every: int =
     for dt in ("f32", "f64"):
         s = s32.clone() if dt == "f32" else s32.to(torch.complex128)
         plan = binding.Plan(w["N"], nf, dt, device=dev)
+        plan.set_variant("prune", PRUNE)
         tuned = plan.autotune(s, model, 2)
         one = s.clone()  # one step from the identical initial state
         plan.rk2_step(one, model, w["nu"], w["eta"], w["dt"], 1)
@@ -304,6 +309,7 @@ def run_primary(args, w, model, nf, N, dev):
     s32, _ = initial_state(w, torch.complex64, dev)
     s32_0 = s32.clone()
     plan32 = binding.Plan(N, nf, "f32", device=dev)
+    plan32.set_variant("prune", 0 if args.no_prune else 1)
     log("fp32 plan ready, workspace GB", plan32.workspace_bytes() / 1e9)
     tuned32 = None if args.no_tune else plan32.autotune(s32, model, 3)
     log("fp32 variants", tuned32)
@@ -325,6 +331,7 @@ def run_primary(args, w, model, nf, N, dev):
         del plan32
         torch.cuda.empty_cache()
         plan64 = binding.Plan(N, nf, "f64", device=dev)
+        plan64.set_variant("prune", 0 if args.no_prune else 1)
         tuned64 = None if args.no_tune else plan64.autotune(s64, model, 3)
         log("fp64 variants", tuned64)
         ms64, stats64, ms64_graph = run_timed(plan64, s64, model, w, args.steps, args.warmup)
@@ -337,6 +344,7 @@ def run_primary(args, w, model, nf, N, dev):
         del plan64
         torch.cuda.empty_cache()
         plan32 = binding.Plan(N, nf, "f32", device=dev)
+        plan32.set_variant("prune", 0 if args.no_prune else 1)
         for k, v in (tuned32 or {}).items():
             plan32.set_variant(k, v)
         plan32.rk2_step(a, model, w["nu"], w["eta"], w["dt"], 1)
@@ -367,6 +375,8 @@ def main():
     ap.add_argument("--copy-only", action="store_true",
                     help="only the reference device copy (for counter scaling)")
     ap.add_argument("--no-tune", action="store_true", help="default kernel variants")
+    ap.add_argument("--no-prune", action="store_true",
+                    help="transform every pencil (no dealias-sphere pruning)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the 256^3, 1024^3, ensemble and 32^3 workloads")
     args = ap.parse_args()
@@ -379,6 +389,8 @@ def main():
 
     from paper_1003_4322_amd import binding
 
+    global PRUNE
+    PRUNE = 0 if args.no_prune else 1
     w = WORKLOADS[args.workload]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -420,7 +432,8 @@ def main():
         "config": {"workload": f"{'MHD Elsasser' if nf == 6 else 'NS'} {N}^3 RK2, {nf} fields "
                                f"batched, nu={w['nu']}, eta={w['eta']}, dt={w['dt']}, "
                                f"random-phase k0={w['k0']} seeds {list(w['seeds'])}",
-                   "N": N, "fields": nf},
+                   "N": N, "fields": nf, "workload_key": args.workload,
+                   "prune": PRUNE},
         "ms_per_step_graph": round(ms_graph, 4),
         "variants": tuned32,
         "passes": passes32,

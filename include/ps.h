@@ -139,8 +139,13 @@ ps_status ps_energy_spectrum(ps_plan p, const void *fhat, int nfields, double *s
  * "z_epi", "x_prod"; the tile width, radix schedule or register/LDS trade-off
  * of a pass (results are identical up to rounding order).  Kind "batch":
  * 0 = one launch per pass for each run of consecutive equal-size boxes
- * (default), 1 = one launch per box (baseline).  Setting a variant drops a
- * cached graph. */
+ * (default), 1 = one launch per box (baseline).  Kind "prune": 1 = the
+ * step and the nonlinear terms skip everything the 2/3 rule makes zero (pencils
+ * and modes outside the sphere 9|k|^2 < N^2 are neither read nor transformed);
+ * valid when the input is zero outside that sphere (a dealiased state stays
+ * dealiased under the step), and modes outside it are then left untouched by
+ * ps_rk2_step (ps_nonlinear_* still writes zeros there).  Setting a variant
+ * drops a cached graph. */
 ps_status ps_plan_set_variant(ps_plan p, const char *kind, int variant);
 int ps_plan_get_variant(ps_plan p, const char *kind);
 int ps_plan_variant_count(ps_plan p, const char *kind);

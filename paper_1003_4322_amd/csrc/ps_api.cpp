@@ -48,6 +48,8 @@ struct Class {
   long ncp = 0;   // N*N*P   pitched complex values per field
   long n3 = 0;    // N^3
   int nshell = 0;
+  // counts inside the 2/3 sphere (half storage): modes, (kx, ky) columns, kx values
+  long n_sphere = 0, n_disk = 0, kx_keep = 0;
   size_t real_off = 0, cplx_off = 0;   // of the first box
   size_t ws_off = 0;                   // byte offset of the class workspace
   size_t zs_box = 0, work_box = 0, spec_box = 0;  // bytes per box
@@ -85,6 +87,7 @@ struct ps_plan_s {
   std::vector<Box> boxes;
   std::vector<Class> classes;
   bool per_box = false;  // baseline: one launch per box instead of per class
+  bool prune = false;    // dealias-sphere pruning of the step (state zero outside the sphere)
   std::map<int, void*> tables;
   hipStream_t stream = nullptr;
   hipStream_t cap = nullptr;  // private stream used only for graph capture
@@ -108,7 +111,7 @@ namespace {
 
 size_t csize(const ps_plan_s* p) { return p->dtype == PS_F32 ? 8 : 16; }
 
-const char* const KINDS[] = {"y", "z", "z_curl", "z_epi", "x_prod", "batch"};
+const char* const KINDS[] = {"y", "z", "z_curl", "z_epi", "x_prod", "batch", "prune"};
 
 int var_of(const ps_plan_s* p, const char* kind) {
   auto it = p->var.find(kind);
@@ -216,15 +219,17 @@ struct Seq {
   double cs() const { return (double)sizeof(C); }
 
   // strided pass in place on the first nfl fields of every box, line = z
-  ps_status ypass(C* x, long pitch, long bs, int nfl, int dir) {
+  ps_status ypass(C* x, long pitch, long bs, int nfl, int dir, int prune = 0) {
     ps::StridedArgs<T> a{};
+    a.prune = prune;
     a.in = x; a.out = x; a.tw = tw();
     a.in_fs = a.out_fs = (long)b.N * b.N * pitch;
     a.in_ls = a.out_ls = (long)b.N * pitch;
     a.in_es = a.out_es = pitch;
     a.in_bs = a.out_bs = bs;
     a.ncols = (int)b.H; a.nlines = b.N; a.nf = nfl; a.nb = nb;
-    const double bytes = 2.0 * nfl * nb * b.nc * cs();
+    const double full = (double)b.N * b.N * b.kx_keep, disk = (double)b.N * b.n_disk;
+    const double bytes = prune == 0 ? 2.0 * nfl * nb * b.nc * cs() : (double)nfl * nb * (full + disk) * cs();
     const int v = var_of(p, "y");
     return enqueue(p, s, dir == ps::FWD ? "y_fwd" : "y_inv", bytes,
                    [&](hipStream_t st) { return ps::launch_strided<T>(b.N, dir, v, a, st); });
@@ -277,8 +282,11 @@ struct Seq {
     ca.in = src; ca.out = work(); ca.tw = tw();
     ca.in_fs = b.nc; ca.in_pitch = b.H; ca.out_fs = b.ncp; ca.out_pitch = b.P; ca.N = b.N;
     ca.in_bs = st_bs(); ca.out_bs = wk_bs(); ca.nb = nb;
+    ca.prune = p->prune;
     const int v = var_of(p, "z_curl");
-    return enqueue(p, s, "z_curl", (double)(nin + nphys) * nb * b.nc * cs(),
+    const double bytes = p->prune ? ((double)nin * b.n_sphere + (double)nphys * b.n_disk * b.N) * nb * cs()
+                                  : (double)(nin + nphys) * nb * b.nc * cs();
+    return enqueue(p, s, "z_curl", bytes,
                    [&](hipStream_t q) { return ps::launch_z_curl<T>(b.N, mhd, v, ca, q); });
   }
   ps_status pass_xprod(bool mhd) {
@@ -288,8 +296,10 @@ struct Seq {
     xa.in_pitch = xa.out_pitch = b.P; xa.in_fs = xa.out_fs = b.ncp;
     xa.in_bs = xa.out_bs = wk_bs();
     xa.rows = (long)b.N * b.N; xa.nf = nphys; xa.nb = nb;
+    xa.kmax = p->prune ? (int)b.kx_keep - 1 : b.N / 2;
     const int v = var_of(p, "x_prod");
-    return enqueue(p, s, "x_prod", (double)(nphys + nprod) * nb * b.nc * cs(),
+    const double per = p->prune ? (double)b.N * b.N * b.kx_keep : (double)b.nc;
+    return enqueue(p, s, "x_prod", (double)(nphys + nprod) * nb * per * cs(),
                    [&](hipStream_t q) { return ps::launch_x_prod<T>(b.N, mhd, v, xa, q); });
   }
   ps_status pass_zepi(bool mhd, int mode, C* out, const C* st0, const C* st1, T h, T nua, T nub) {
@@ -300,9 +310,14 @@ struct Seq {
     ea.in_bs = wk_bs(); ea.out_bs = st_bs(); ea.nb = nb;
     ea.scale = (T)(1.0 / ((double)b.N * b.N * b.N));
     ea.h = h; ea.nua = nua; ea.nub = nub; ea.N = b.N; ea.mode = mode;
+    ea.prune = p->prune;
     const int nrw = mode == 0 ? 0 : (mode == 1 ? 1 : 2);
     const int v = var_of(p, "z_epi");
-    return enqueue(p, s, "z_epi", (double)(nprod + nprod + nrw * nprod) * nb * b.nc * cs(),
+    double bytes = (double)(nprod + nprod + nrw * nprod) * nb * b.nc * cs();
+    if (p->prune)
+      bytes = ((double)nprod * b.n_disk * b.N +
+               (mode == 0 ? (double)nprod * b.nc : (double)(1 + nrw) * nprod * b.n_sphere)) * nb * cs();
+    return enqueue(p, s, "z_epi", bytes,
                    [&](hipStream_t q) { return ps::launch_z_epi<T>(b.N, mhd, v, ea, q); });
   }
 
@@ -311,9 +326,9 @@ struct Seq {
     const int nphys = mhd ? 12 : 6, nprod = mhd ? 6 : 3;
     ps_status st = pass_zcurl(src, mhd);
     if (st) return st;
-    if ((st = ypass(work(), b.P, wk_bs(), nphys, ps::INV))) return st;
+    if ((st = ypass(work(), b.P, wk_bs(), nphys, ps::INV, p->prune ? 1 : 0))) return st;
     if ((st = pass_xprod(mhd))) return st;
-    if ((st = ypass(work(), b.P, wk_bs(), nprod, ps::FWD))) return st;
+    if ((st = ypass(work(), b.P, wk_bs(), nprod, ps::FWD, p->prune ? 2 : 0))) return st;
     return pass_zepi(mhd, mode, out, st0, st1, h, nua, nub);
   }
 
@@ -321,7 +336,7 @@ struct Seq {
   // workspace is written
   ps_status tune_launch(const char* kind, const C* state, bool mhd) {
     if (!strcmp(kind, "z_curl")) return pass_zcurl(state, mhd);
-    if (!strcmp(kind, "y")) return ypass(work(), b.P, wk_bs(), mhd ? 12 : 6, ps::INV);
+    if (!strcmp(kind, "y")) return ypass(work(), b.P, wk_bs(), mhd ? 12 : 6, ps::INV, p->prune ? 1 : 0);
     if (!strcmp(kind, "x_prod")) return pass_xprod(mhd);
     if (!strcmp(kind, "z_epi")) return pass_zepi(mhd, 0, zstar(), nullptr, nullptr, T(0), T(0), T(0));
     return fail(PS_ERR_ARG, std::string("no tuning launch for kind ") + kind);
@@ -504,6 +519,18 @@ ps_status ps_plan_create_batch(ps_plan* out, int nbox, const int* Ns, int nfield
         c.ncp = (long)c.N * c.N * c.P;
         c.n3 = (long)c.N * c.N * c.N;
         c.nshell = b.nshell;
+        {
+          const long N = c.N, N2 = N * N;
+          auto w = [N](long i) { return i < N / 2 ? i : i - N; };
+          for (long kx = 0; kx < c.H; ++kx)
+            for (long ky = 0; ky < N; ++ky) {
+              const long p2 = kx * kx + w(ky) * w(ky);
+              if (9 * p2 >= N2) continue;
+              ++c.n_disk;
+              for (long kz = 0; kz < N; ++kz) c.n_sphere += 9 * (p2 + w(kz) * w(kz)) < N2;
+            }
+          c.kx_keep = (N - 1) / 3 + 1;
+        }
         c.real_off = b.real_off;
         c.cplx_off = b.cplx_off;
         c.zs_box = (size_t)nfields * c.nc * cs;
@@ -757,10 +784,11 @@ ps_status ps_plan_set_variant(ps_plan p, const char* kind, int v) {
   if (!known) return fail(PS_ERR_ARG, std::string("unknown pass kind ") + kind);
   int n = 1;
   for (auto& b : p->boxes) n = std::max(n, ps::variant_count(kind, b.N, p->nfields == 6));
-  if (!strcmp(kind, "batch")) n = 2;
+  if (!strcmp(kind, "batch") || !strcmp(kind, "prune")) n = 2;
   if (v < 0 || v >= n) return fail(PS_ERR_ARG, "variant out of range");
   p->var[kind] = v;
   p->per_box = var_of(p, "batch") == 1;
+  p->prune = var_of(p, "prune") == 1;
   if (p->gexec) {
     hipGraphExecDestroy(p->gexec);
     p->gexec = nullptr;
@@ -776,7 +804,7 @@ int ps_plan_get_variant(ps_plan p, const char* kind) {
 
 int ps_plan_variant_count(ps_plan p, const char* kind) {
   if (!p || !kind) return PS_ERR_ARG;
-  if (!strcmp(kind, "batch")) return 2;
+  if (!strcmp(kind, "batch") || !strcmp(kind, "prune")) return 2;
   int n = 1;
   for (auto& b : p->boxes) n = std::max(n, ps::variant_count(kind, b.N, p->nfields == 6));
   return n;

@@ -104,22 +104,21 @@ struct StridedTX {
 
 constexpr bool has_variants(int N) { return N >= 256; }
 
-// x passes: rows live in LDS with the padded layout (pad8), M + M/8 + 1 slots.
-template <typename T, int M, int TQ, int RBSH>
+// x passes: rows live in LDS with the padded layout (pad8), M + M/8 + 1 slots;
+// the fused pass also stages the twiddle table (2M values).
+template <typename T, int M, int TQ>
 struct XCfg {
   static constexpr int SLOTS = M + M / 8 + 1;
   static constexpr int G = (256 / TQ) < 1 ? 1 : 256 / TQ;  // plain passes: rows per workgroup
   static constexpr bool fits(int f, int rb) {
-    return f * rb * SLOTS * 2 * (int)sizeof(T) <= 65536 && f * rb * TQ <= 1024;
+    return (f * rb * SLOTS + 2 * M) * 2 * (int)sizeof(T) <= 65536 && f * rb * TQ <= 1024;
   }
-  static constexpr int rb(int f) {
-    int r = ((384 / (f * TQ)) < 1 ? 1 : 384 / (f * TQ)) << RBSH;
+  static constexpr int rb(int f, int want) {
+    int r = want < 1 ? 1 : want;
     while (r > 1 && !fits(f, r)) r >>= 1;
     return r;
   }
-  static constexpr int RB_NS = rb(6);
-  static constexpr int RB_MHD = rb(12);
-  static constexpr bool MHD_OK = fits(12, RB_MHD);
+  static constexpr bool MHD_OK = fits(12, 1);
 };
 
 // Kernel variant tables.  Strided-pass variants: tile shift, two-phase reload
@@ -132,17 +131,17 @@ struct ZV {
   bool alt;
 };
 struct XV {
-  int rbsh;  // LDS-staged kernel: rows shift; register-resident kernel: rows per workgroup
-  bool alt;
-  int kind;  // 0: LDS-staged k_x_prod, 1: register-resident k_x_prod2 with LenXA, 2: with LenXB
+  int rb_ns, rb_mhd;  // rows per workgroup (reduced while the LDS tile would not fit)
+  bool alt;           // LDS-staged kernel: radix-16 schedule
+  int kind;           // 0: LDS-staged k_x_prod, 1: register-resident k_x_prod2 with LenXA, 2: with LenXB
 };
 constexpr ZV ZCURL_V[] = {{0, false, 1, false}, {1, false, 1, false}, {1, true, 4, false},
                           {2, true, 4, false},  {1, false, 1, true},  {1, true, 4, true}};
 constexpr ZV ZEPI_V[] = {{0, false, 1, false}, {1, false, 1, false}, {1, false, 4, false},
                          {2, false, 4, false}, {1, false, 1, true},  {2, false, 4, true}};
 constexpr ZV STR_V[] = {{0, false, 1, false}, {1, false, 1, false}, {0, false, 1, true}, {1, false, 1, true}};
-constexpr XV XPROD_V[] = {{0, false, 0}, {1, false, 0}, {0, true, 0}, {1, true, 0},
-                          {2, false, 1}, {4, false, 1}, {1, false, 2}, {2, false, 2}};
+constexpr XV XPROD_V[] = {{2, 1, false, 0}, {4, 2, false, 0}, {4, 2, true, 0}, {2, 1, true, 0},
+                          {2, 2, false, 1}, {4, 4, false, 1}, {1, 1, false, 2}, {2, 2, false, 2}};
 constexpr int NZCURL = sizeof(ZCURL_V) / sizeof(ZV);
 constexpr int NZEPI = sizeof(ZEPI_V) / sizeof(ZV);
 constexpr int NSTR = sizeof(STR_V) / sizeof(ZV);

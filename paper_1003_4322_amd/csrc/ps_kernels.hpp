@@ -52,6 +52,11 @@ struct StridedArgs {
   long out_fs, out_ls, out_es;
   long in_bs, out_bs;  // box strides (ensembles of equal-size boxes)
   int ncols, ntile, nlines, nf, nb;
+  // dealias-sphere pruning of a y pass (columns kx, elements ky):
+  // 0 none; 1 input zero outside the disk 9(kx^2+ky^2) < N^2 (inverse pass);
+  // 2 only outputs inside the disk are needed (forward pass).  Tiles with
+  // every kx >= N/3 are skipped.
+  int prune;
 };
 
 template <typename T, int L, int TQ, int TX, int DIR, class RL, int MINW = 1>
@@ -66,16 +71,25 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_strided(StridedArgs<T> a) {
   blk /= a.nlines;
   const int f = blk % a.nf, box = blk / a.nf;
   const int col = tile * TX + c;
-  const bool ok = col < a.ncols;
+  constexpr int N = L;
+  if (a.prune && 9 * (tile * TX) * (tile * TX) >= N * N) return;  // whole tile outside
+  const bool ok = col < a.ncols && (!a.prune || 9 * col * col < N * N);
+  auto in_disk = [&](int idx) {
+    const int k = wav(idx, N);
+    return 9 * (col * col + k * k) < N * N;
+  };
   const C2<T>* in = a.in + box * a.in_bs + f * a.in_fs + line * a.in_ls + col;
   C2<T>* out = a.out + box * a.out_bs + f * a.out_fs + line * a.out_ls + col;
   C2<T> v[E::SLOTS];
-  E::run(v, smem + c, TX, q, a.tw, 1,
-         [&](int, int idx) { return ok ? in[idx * a.in_es] : zero2<T>(); });
+  E::run(v, smem + c, TX, q, a.tw, 1, [&](int, int idx) {
+    return ok && (a.prune != 1 || in_disk(idx)) ? in[idx * a.in_es] : zero2<T>();
+  });
   if constexpr (E::NSTAGE == 1) __syncthreads();  // in place: all reads before any write
 #pragma unroll
-  for (int s = 0; s < E::LAST_NB * E::RL_; ++s)
-    if (ok && E::last_valid(q, s)) out[E::last_index(q, s) * a.out_es] = v[s];
+  for (int s = 0; s < E::LAST_NB * E::RL_; ++s) {
+    const int idx = E::last_index(q, s);
+    if (ok && E::last_valid(q, s) && (a.prune != 2 || in_disk(idx))) out[idx * a.out_es] = v[s];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -94,6 +108,7 @@ struct ZCurlArgs {
   long out_fs, out_pitch;
   long in_bs, out_bs;     // box strides
   int N, ntile, nb;
+  int prune;  // 1: state zero outside the 2/3 sphere; only disk columns are produced
 };
 
 // RELOAD (MHD only): two phases, u-derived fields then b-derived fields, each
@@ -109,11 +124,14 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_z_curl(ZCurlArgs<T> a) {
   const int N = L;
   const int tile = blk % a.ntile, ky = (blk / a.ntile) % N, box = blk / (a.ntile * N);
   const int col = tile * TX + c;
-  const bool ok = col < N / 2 + 1;
+  const int kyw = wav(ky, N);
+  if (a.prune && 9 * ((tile * TX) * (tile * TX) + kyw * kyw) >= N * N) return;  // tile outside the disk
+  const bool ok = col < N / 2 + 1 && (!a.prune || 9 * (col * col + kyw * kyw) < N * N);
   const long in_es = (long)N * a.in_pitch, out_es = (long)N * a.out_pitch;
   const C2<T>* in = a.in + box * a.in_bs + ky * a.in_pitch + col;
   C2<T>* out = a.out + box * a.out_bs + ky * a.out_pitch + col;
   const T kx = (T)dwavx(col, N), kyd = (T)dwav(ky, N);
+  const int kperp2 = col * col + kyw * kyw;
 
   // one output field: FFT of component `comp` of `src` (grp even) or of its curl (grp odd)
   auto emit = [&](auto& src, int grp, int comp, int fout) {
@@ -139,8 +157,9 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_z_curl(ZCurlArgs<T> a) {
   auto load = [&](C2<T> (&dst)[3][NS_], T sign) {
 #pragma unroll
     for (int s = 0; s < NS_; ++s) {
-      const bool v = ok && E::first_valid(q, s);
-      const long off = (long)E::first_index(q, s) * in_es;
+      const int kzi = E::first_index(q, s), kzw = wav(kzi, N);
+      const bool v = ok && E::first_valid(q, s) && (!a.prune || 9 * (kperp2 + kzw * kzw) < N * N);
+      const long off = (long)kzi * in_es;
 #pragma unroll
       for (int f = 0; f < 3; ++f) {
         if constexpr (MHD) {
@@ -204,6 +223,7 @@ struct ZEpiArgs {
   long in_bs, out_bs;      // box strides
   T scale, h, nua, nub;
   int N, ntile, mode, nb;
+  int prune;  // 1: only modes inside the 2/3 sphere are read or updated (mode 0 still writes zeros)
 };
 
 template <typename T, int L, int TQ, int TX, class RL, bool MHD, int MINW = 1>
@@ -217,7 +237,10 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_z_epi(ZEpiArgs<T> a) {
   const int N = L;
   const int tile = blk % a.ntile, ky = (blk / a.ntile) % N, box = blk / (a.ntile * N);
   const int col = tile * TX + c;
+  const int kyw0 = wav(ky, N);
+  if (a.prune && a.mode != 0 && 9 * ((tile * TX) * (tile * TX) + kyw0 * kyw0) >= N * N) return;
   const bool ok = col < N / 2 + 1;
+  const bool disk = !a.prune || 9 * (col * col + kyw0 * kyw0) < N * N;
   const long in_es = (long)N * a.in_pitch, out_es = (long)N * a.out_pitch;
   const C2<T>* in = a.in + box * a.in_bs + ky * a.in_pitch + col;
 
@@ -226,7 +249,7 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_z_epi(ZEpiArgs<T> a) {
   for (int f = 0; f < NF; ++f) {
     C2<T> v[E::SLOTS];
     E::run(v, smem + c, TX, q, a.tw, 1,
-           [&](int, int idx) { return ok ? in[f * a.in_fs + idx * in_es] : zero2<T>(); });
+           [&](int, int idx) { return ok && disk ? in[f * a.in_fs + idx * in_es] : zero2<T>(); });
 #pragma unroll
     for (int s = 0; s < NO; ++s) r[f][s] = v[s];
   }
@@ -241,7 +264,9 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_z_epi(ZEpiArgs<T> a) {
     const int kzi = E::last_index(q, s);
     const int ikz = wav(kzi, N);
     const long k2i = (long)ikx * ikx + (long)iky * iky + (long)ikz * ikz;
-    const bool keep = k2i > 0 && 9 * k2i < (long)N * N;
+    const bool sphere = 9 * k2i < (long)N * N;
+    if (a.prune && !sphere && a.mode != 0) continue;  // stays zero
+    const bool keep = k2i > 0 && sphere;
     const T k2 = (T)k2i;
     const T kx = (T)ikx, ky_ = (T)iky, kz = (T)ikz;
     C2<T> nh[NF];
@@ -336,6 +361,7 @@ struct XArgs {
   long in_bs, out_bs;  // box strides
   long rows;         // rows per field (N*N)
   int nf, nb;
+  int kmax;  // fused passes: coefficients kx > kmax are zero on input and not needed on output
 };
 
 // plain inverse: complex rows (pitch in_pitch) -> real rows (N reals, pitch out_pitch complex = M)
@@ -415,26 +441,26 @@ __global__ __launch_bounds__((MHD ? 12 : 6) * RB * TQ) void k_x_prod(XArgs<T> a)
   using EI = Stockham<T, M, TQ, INV, RL>;
   using EF = Stockham<T, M, TQ, FWD, RL>;
   constexpr int LP = row_slots(M);
-  __shared__ C2<T> smem[G * LP];
+  // rows of every field, then the twiddle table (length N = 2M) staged in LDS
+  __shared__ C2<T> smem[G * LP + 2 * M];
+  C2<T>* twl = smem + G * LP;
   const int tid = threadIdx.x, g = tid / TQ, q = tid % TQ;
-  const long row0 = (long)xcd_remap(blockIdx.x, gridDim.x) * RB;
-  const long total = a.rows * a.nb;
-  // row index over boxes: box = row / rows; offset of (row, field f)
-  auto in_at = [&](long row, int f) { return (row / a.rows) * a.in_bs + f * a.in_fs + (row % a.rows) * a.in_pitch; };
-  auto out_at = [&](long row, int f) { return (row / a.rows) * a.out_bs + f * a.out_fs + (row % a.rows) * a.out_pitch; };
-  // ---- load FIN x RB rows; slot (f, rb) at smem[(f * RB + rb) * LP]
-  for (int i = tid; i < G * (M + 1); i += NT) {
-    const int gr = i / (M + 1), k = i % (M + 1);
-    const int f = gr / RB, rb = gr % RB;
-    const long row = row0 + rb;
-    smem[gr * LP + pad8(k)] = row < total ? a.in[in_at(row, f) + k] : zero2<T>();
+  const int f = g / RB, rb = g % RB;  // group g owns field f of row rb (slot g)
+  const long row = (long)xcd_remap(blockIdx.x, gridDim.x) * RB + rb;
+  const bool rok = row < a.rows * a.nb;
+  const long rr = rok ? row : 0;
+  const long boxi = rr / a.rows, rloc = rr % a.rows;
+  for (int i = tid; i < 2 * M; i += NT) twl[i] = a.tw[i];
+  C2<T>* buf = smem + g * LP;
+  {
+    const C2<T>* src = a.in + boxi * a.in_bs + f * a.in_fs + rloc * a.in_pitch;
+    for (int k = q; k <= M; k += TQ) buf[pad8(k)] = rok && k <= a.kmax ? src[k] : zero2<T>();
   }
   __syncthreads();
   // ---- inverse real FFTs, physical values back into the same slot
-  C2<T>* buf = smem + g * LP;
   {
     C2<T> v[EI::SLOTS];
-    EI::template run<LayPad8>(v, buf, 1, q, a.tw, 2, [&](int, int k) { return c2r_pre(buf, k, M, a.tw); });
+    EI::template run<LayPad8>(v, buf, 1, q, twl, 2, [&](int, int k) { return c2r_pre(buf, k, M, twl); });
     __syncthreads();
 #pragma unroll
     for (int s = 0; s < EI::LAST_NB * EI::RL_; ++s)
@@ -443,8 +469,8 @@ __global__ __launch_bounds__((MHD ? 12 : 6) * RB * TQ) void k_x_prod(XArgs<T> a)
   __syncthreads();
   // ---- products; each C2 holds two neighbouring grid points
   for (int i = tid; i < RB * M; i += NT) {
-    const int rb = i / M, n = i % M;
-    auto at = [&](int f) -> C2<T>& { return smem[(f * RB + rb) * LP + pad8(n)]; };
+    const int r = i / M, n = i % M;
+    auto at = [&](int ff) -> C2<T>& { return smem[(ff * RB + r) * LP + pad8(n)]; };
     const C2<T> u0 = at(0), u1 = at(1), u2 = at(2);
     const C2<T> w0 = at(3), w1 = at(4), w2 = at(5);
     auto cx = [](C2<T> a1, C2<T> a2, C2<T> b1, C2<T> b2) {  // a1 b2 - a2 b1 per point
@@ -467,10 +493,10 @@ __global__ __launch_bounds__((MHD ? 12 : 6) * RB * TQ) void k_x_prod(XArgs<T> a)
   }
   __syncthreads();
   // ---- forward real FFTs of the FOUT product fields (other groups idle on own slots)
-  const bool active = g < FOUT * RB;
+  const bool active = f < FOUT;
   {
     C2<T> v[EF::SLOTS];
-    EF::template run<LayPad8>(v, buf, 1, q, a.tw, 2, [&](int, int n) { return buf[pad8(n)]; });
+    EF::template run<LayPad8>(v, buf, 1, q, twl, 2, [&](int, int n) { return buf[pad8(n)]; });
     __syncthreads();
     if (active) {
 #pragma unroll
@@ -479,11 +505,9 @@ __global__ __launch_bounds__((MHD ? 12 : 6) * RB * TQ) void k_x_prod(XArgs<T> a)
     }
   }
   __syncthreads();
-  for (int i = tid; i < FOUT * RB * (M + 1); i += NT) {
-    const int gr = i / (M + 1), k = i % (M + 1);
-    const int f = gr / RB, rb = gr % RB;
-    const long row = row0 + rb;
-    if (row < total) a.out[out_at(row, f) + k] = r2c_post(smem + gr * LP, k, M, a.tw);
+  if (active && rok) {
+    C2<T>* dst = a.out + boxi * a.out_bs + f * a.out_fs + rloc * a.out_pitch;
+    for (int k = q; k <= M && k <= a.kmax; k += TQ) dst[k] = r2c_post(buf, k, M, twl);
   }
 }
 
@@ -516,12 +540,13 @@ __global__ __launch_bounds__(RPW* TQ) void k_x_prod2(XArgs<T> a) {
     EI::template run<LayPad8>(v, buf, 1, q, a.tw, 2, [&](int, int k) -> C2<T> {
       if (!ok) return zero2<T>();
       C2<T> xk, xm;
+      const int km = M - k;
       if (k == 0) {
         xk = C2<T>{src[0].x, T(0)};
-        xm = C2<T>{src[M].x, T(0)};
+        xm = C2<T>{M <= a.kmax ? src[M].x : T(0), T(0)};
       } else {
-        xk = src[k];
-        xm = conj(src[M - k]);
+        xk = k <= a.kmax ? src[k] : zero2<T>();
+        xm = km <= a.kmax ? conj(src[km]) : zero2<T>();
       }
       return (xk + xm) + mul_i(cmulc(xk - xm, a.tw[k]));
     });
@@ -548,7 +573,7 @@ __global__ __launch_bounds__(RPW* TQ) void k_x_prod2(XArgs<T> a) {
     __syncthreads();
     if (ok) {
       C2<T>* dst = outp + fo * a.out_fs;
-      for (int k = q; k <= M; k += TQ) dst[k] = r2c_post(buf, k, M, a.tw);
+      for (int k = q; k <= M && k <= a.kmax; k += TQ) dst[k] = r2c_post(buf, k, M, a.tw);
     }
   };
   // cross-product component c of (x, y) per pair of points

@@ -134,7 +134,7 @@ hipError_t launch_z_epi(int N, bool mhd, int var, ZEpiArgs<T> a, hipStream_t s) 
 template <typename T, int N>
 hipError_t x_c2r_n(XArgs<T> a, hipStream_t s) {
   using LC = LenCfg<N / 2>;
-  using X = XCfg<T, N / 2, LC::TQ, 0>;
+  using X = XCfg<T, N / 2, LC::TQ>;
   const long grid = (a.rows * a.nf * a.nb + X::G - 1) / X::G;
   k_x_c2r<T, N / 2, LC::TQ, X::G, typename LC::RL><<<dim3((unsigned)grid), dim3(X::G * LC::TQ), 0, s>>>(a);
   return hipGetLastError();
@@ -143,7 +143,7 @@ hipError_t x_c2r_n(XArgs<T> a, hipStream_t s) {
 template <typename T, int N>
 hipError_t x_r2c_n(XArgs<T> a, hipStream_t s) {
   using LC = LenCfg<N / 2>;
-  using X = XCfg<T, N / 2, LC::TQ, 0>;
+  using X = XCfg<T, N / 2, LC::TQ>;
   const long grid = (a.rows * a.nf * a.nb + X::G - 1) / X::G;
   k_x_r2c<T, N / 2, LC::TQ, X::G, typename LC::RL><<<dim3((unsigned)grid), dim3(X::G * LC::TQ), 0, s>>>(a);
   return hipGetLastError();
@@ -154,24 +154,26 @@ hipError_t x_prod_v(bool mhd, XArgs<T> a, hipStream_t s) {
   constexpr XV v = XPROD_V[I];
   if constexpr (v.kind == 0) {
     using LC = Sched<N / 2, v.alt>;
-    using X = XCfg<T, N / 2, LC::TQ, v.rbsh>;
+    using X = XCfg<T, N / 2, LC::TQ>;
     if (mhd) {
       if constexpr (X::MHD_OK) {
-        const long grid = (a.rows * a.nb + X::RB_MHD - 1) / X::RB_MHD;
-        k_x_prod<T, N / 2, LC::TQ, X::RB_MHD, typename LC::RL, true>
-            <<<dim3((unsigned)grid), dim3(12 * X::RB_MHD * LC::TQ), 0, s>>>(a);
+        constexpr int RB = X::rb(12, v.rb_mhd);
+        const long grid = (a.rows * a.nb + RB - 1) / RB;
+        k_x_prod<T, N / 2, LC::TQ, RB, typename LC::RL, true>
+            <<<dim3((unsigned)grid), dim3(12 * RB * LC::TQ), 0, s>>>(a);
         return hipGetLastError();
       } else {
         return hipErrorInvalidValue;
       }
     }
-    const long grid = (a.rows * a.nb + X::RB_NS - 1) / X::RB_NS;
-    k_x_prod<T, N / 2, LC::TQ, X::RB_NS, typename LC::RL, false>
-        <<<dim3((unsigned)grid), dim3(6 * X::RB_NS * LC::TQ), 0, s>>>(a);
+    constexpr int RB = X::rb(6, v.rb_ns);
+    const long grid = (a.rows * a.nb + RB - 1) / RB;
+    k_x_prod<T, N / 2, LC::TQ, RB, typename LC::RL, false><<<dim3((unsigned)grid), dim3(6 * RB * LC::TQ), 0, s>>>(a);
     return hipGetLastError();
   } else {
     using LC = std::conditional_t<v.kind == 1, LenXA<N / 2>, LenXB<N / 2>>;
-    constexpr int RPW = (v.rbsh * LC::TQ > 1024) ? 1024 / LC::TQ : v.rbsh;
+    constexpr int RPW0 = v.rb_mhd;
+    constexpr int RPW = (RPW0 * LC::TQ > 1024) ? 1024 / LC::TQ : RPW0;
     const long grid = (a.rows * a.nb + RPW - 1) / RPW;
     if (mhd)
       k_x_prod2<T, N / 2, LC::TQ, typename LC::RL, true, RPW><<<dim3((unsigned)grid), dim3(RPW * LC::TQ), 0, s>>>(a);
@@ -195,7 +197,7 @@ bool mhd_supported(int N) {
   switch (N) {
 #define PS_CASE(NN) \
   case NN:          \
-    return XCfg<T, NN / 2, LenCfg<NN / 2>::TQ, 0>::MHD_OK;
+    return XCfg<T, NN / 2, LenCfg<NN / 2>::TQ>::MHD_OK;
     PS_FOR_EACH_N(PS_CASE)
 #undef PS_CASE
   }

@@ -60,6 +60,7 @@ def test_mhd512_nonlinear_sampled(B, ref, dt):
         sf = synth.SparseField(N, sf.K, sf.values.astype(np.complex64).astype(np.complex128))
     z = sparse_to_dev(sf, cdt)
     p = B.Plan(N, 6, dt)
+    p.set_variant("prune", 1)
     say("autotune", p.autotune(z, B.PS_MHD, 2))
     out = p.nonlinear_mhd(z)
     kx = np.array([s[0] for s in SAMPLE]); ky = np.array([s[1] for s in SAMPLE])
@@ -94,6 +95,7 @@ def test_rk2_embedding(B, ref, case):
     want_full = ref.rk2_step(small.dense(), MHD if model == "mhd" else NS, nu, eta, dtime, steps)
     z = sparse_to_dev(big, cdt)
     p = B.Plan(N, nf, dt)
+    p.set_variant("prune", 1)
     say("autotune", p.autotune(z, pm, 2))
     p.rk2_step(z, pm, nu, eta, dtime, steps)
     Kc = 4 * K  # support after two steps
@@ -139,6 +141,7 @@ def test_ensemble_full_config(B, ref):
     say("ensemble full config")
     sizes = [64] * 48 + [96] * 16 + [128] * 4
     p = B.Plan(sizes, 3, "f32")
+    p.set_variant("prune", 1)
     st = torch.empty(p.n_complex(), dtype=torch.complex64, device=DEV)
     fields = {}
     for i, N in enumerate(sizes):

@@ -11,8 +11,9 @@ Tolerances (relative L2 over all stored values):
 """
 import numpy as np
 import pytest
+import torch
 
-from gpu_util import DEV, host, rel_l2, rel_l2_w, rounded, say, to_dev
+from gpu_util import CDT, DEV, host, rel_l2, rel_l2_w, rounded, say, to_dev
 from oracle.psref import MHD, NS
 from paper_1003_4322_amd import synth
 
@@ -59,34 +60,42 @@ def test_fft_c2r(B, ref, N, dt):
     assert np.array_equal(host(xd), X)  # input preserved
 
 
+@pytest.mark.parametrize("prune", [0, 1])
 @pytest.mark.parametrize("dt", ["f64", "f32"])
 @pytest.mark.parametrize("N", [8, 16, 24, 32, 48, 64])
-def test_nonlinear_ns(B, ref, N, dt):
-    say("nonlinear_ns", N, dt)
+def test_nonlinear_ns(B, ref, N, dt, prune):
+    say("nonlinear_ns", N, dt, prune)
     u = rounded(synth.random_ns(N, 1000 + N, 2.0 if N < 32 else 3.0), dt)
     p = B.Plan(N, 3, dt)
-    got = host(p.nonlinear_ns(to_dev(u, dt)))
+    p.set_variant("prune", prune)
+    out = torch.full(u.shape, 1e30, dtype=CDT[dt], device=DEV)
+    got = host(p.nonlinear_ns(to_dev(u, dt), out))
     want = ref.nonlinear_ns(u)
     assert rel_l2_w(got, want) < TOL_NL[dt], rel_l2_w(got, want)
 
 
+@pytest.mark.parametrize("prune", [0, 1])
 @pytest.mark.parametrize("dt", ["f64", "f32"])
 @pytest.mark.parametrize("N", [8, 16, 24, 32, 48])
-def test_nonlinear_mhd(B, ref, N, dt):
-    say("nonlinear_mhd", N, dt)
+def test_nonlinear_mhd(B, ref, N, dt, prune):
+    say("nonlinear_mhd", N, dt, prune)
     z = rounded(synth.random_mhd(N, 2000 + N, 3000 + N, 2.0), dt)
     p = B.Plan(N, 6, dt)
-    got = host(p.nonlinear_mhd(to_dev(z, dt)))
+    p.set_variant("prune", prune)
+    out = torch.full(z.shape, 1e30, dtype=CDT[dt], device=DEV)
+    got = host(p.nonlinear_mhd(to_dev(z, dt), out))
     want = ref.nonlinear_mhd(z)
     assert rel_l2_w(got, want) < TOL_NL[dt], rel_l2_w(got, want)
 
 
+@pytest.mark.parametrize("prune", [0, 1])
 @pytest.mark.parametrize("dt", ["f64", "f32"])
-def test_rk2_ns_32_one_step(B, ref, dt):
+def test_rk2_ns_32_one_step(B, ref, dt, prune):
     """NS 32^3, nu = 0.02, dt = 1e-3, seed 1, k0 = 2, E = 0.5: one RK2 step."""
-    say("rk2 ns 32", dt)
+    say("rk2 ns 32", dt, prune)
     u0 = rounded(synth.random_ns(32, 1, 2.0), dt)
     p = B.Plan(32, 3, dt)
+    p.set_variant("prune", prune)
     s = to_dev(u0, dt)
     p.rk2_step(s, B.PS_NS, 0.02, 0.0, 1e-3, 1)
     got = host(s)
@@ -97,14 +106,16 @@ def test_rk2_ns_32_one_step(B, ref, dt):
     assert inc < (1e-10 if dt == "f64" else 1e-3), inc
 
 
+@pytest.mark.parametrize("prune", [0, 1])
 @pytest.mark.parametrize("dt", ["f64", "f32"])
 @pytest.mark.parametrize("graphs", [True, False])
-def test_rk2_mhd_steps(B, ref, dt, graphs):
-    say("rk2 mhd 24", dt, graphs)
+def test_rk2_mhd_steps(B, ref, dt, graphs, prune):
+    say("rk2 mhd 24", dt, graphs, prune)
     N = 24
     z0 = rounded(synth.random_mhd(N, 3, 4, 2.0), dt)
     p = B.Plan(N, 6, dt)
     p.set_graphs(graphs)
+    p.set_variant("prune", prune)
     s = to_dev(z0, dt)
     p.rk2_step(s, B.PS_MHD, 0.02, 0.01, 2e-3, 3)
     got = host(s)

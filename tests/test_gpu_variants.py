@@ -58,27 +58,31 @@ def test_fft_variants(B, ref, fft_case, kind, dt):
         assert e1 < TOL_FFT[dt] and e2 < TOL_FFT[dt], (kind, v, e1, e2)
 
 
+@pytest.mark.parametrize("prune", [0, 1])
 @pytest.mark.parametrize("dt", ["f32", "f64"])
 @pytest.mark.parametrize("kind", ["y", "z_curl", "x_prod", "z_epi"])
-def test_nonlinear_ns_variants(B, ns_case, kind, dt):
+def test_nonlinear_ns_variants(B, ns_case, kind, dt, prune):
     u, want = ns_case[dt]
     p = B.Plan(N, 3, dt)
+    p.set_variant("prune", prune)
     ud = to_dev(u, dt)
     for v in range(p.variant_count(kind)):
-        say("ns variant", kind, v, dt)
+        say("ns variant", kind, v, dt, prune)
         p.set_variant(kind, v)
         e = rel_l2_w(host(p.nonlinear_ns(ud)), want)
         assert e < TOL_NL[dt], (kind, v, e)
 
 
+@pytest.mark.parametrize("prune", [0, 1])
 @pytest.mark.parametrize("dt", ["f32", "f64"])
 @pytest.mark.parametrize("kind", ["y", "z_curl", "x_prod", "z_epi"])
-def test_nonlinear_mhd_variants(B, mhd_case, kind, dt):
+def test_nonlinear_mhd_variants(B, mhd_case, kind, dt, prune):
     z, want = mhd_case[dt]
     p = B.Plan(N, 6, dt)
+    p.set_variant("prune", prune)
     zd = to_dev(z, dt)
     for v in range(p.variant_count(kind)):
-        say("mhd variant", kind, v, dt)
+        say("mhd variant", kind, v, dt, prune)
         p.set_variant(kind, v)
         e = rel_l2_w(host(p.nonlinear_mhd(zd)), want)
         assert e < TOL_NL[dt], (kind, v, e)
@@ -92,6 +96,7 @@ def test_autotuned_step_matches_default(B, dt):
     a, b = to_dev(z, dt), to_dev(z, dt)
     p0 = B.Plan(N, 6, dt)
     p1 = B.Plan(N, 6, dt)
+    p1.set_variant("prune", 1)
     say("autotune", dt, p1.autotune(b, B.PS_MHD, 2))
     p0.rk2_step(a, B.PS_MHD, 5e-4, 5e-4, 1e-3, 2)
     p1.rk2_step(b, B.PS_MHD, 5e-4, 5e-4, 1e-3, 2)
