@@ -562,7 +562,7 @@ ps_status ps_plan_create_batch(ps_plan* out, int nbox, const int* Ns, int nfield
     bool any_var = false;
     for (auto& b : p->boxes) any_var |= ps::variant_count("z_curl", b.N, nfields == 6) > 1;
     if (any_var) {
-      p->var["z_curl"] = 1;
+      p->var["z_curl"] = 0;
       p->var["z_epi"] = 1;
       p->var["x_prod"] = dtype == PS_F32 ? 1 : 2;
       p->var["y"] = dtype == PS_F32 ? 2 : 0;

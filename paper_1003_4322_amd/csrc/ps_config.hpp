@@ -125,24 +125,32 @@ struct XCfg {
 // (MHD curl), minimum waves per SIMD requested from the register allocator,
 // alternate (radix-16) schedule.  Product-pass variants: rows shift, schedule.
 struct ZV {
-  int sh;
-  bool reload;
-  int minw;
-  bool alt;
+  int sh;       // tile width shift
+  int split;    // z_curl: workgroups per tile sharing the output groups (1, 2 or 4; NS caps at 2)
+  int minb;     // workgroups per CU the register allocator must leave room for (1: no request)
+  bool alt;     // radix-16 schedule
+  bool direct;  // z_curl: gather inputs per output field instead of holding them in registers
 };
 struct XV {
   int rb_ns, rb_mhd;  // rows per workgroup (reduced while the LDS tile would not fit)
   bool alt;           // LDS-staged kernel: radix-16 schedule
   int kind;           // 0: LDS-staged k_x_prod, 1: register-resident k_x_prod2 with LenXA, 2: with LenXB
 };
-constexpr ZV ZCURL_V[] = {{0, false, 1, false}, {1, false, 1, false}, {1, true, 4, false},
-                          {2, true, 4, false},  {1, false, 1, true},  {1, true, 4, true}};
-constexpr ZV ZEPI_V[] = {{0, false, 1, false}, {1, false, 1, false}, {1, false, 4, false},
-                         {2, false, 4, false}, {1, false, 1, true},  {2, false, 4, true}};
-constexpr ZV STR_V[] = {{0, false, 1, false}, {1, false, 1, false}, {0, false, 1, true}, {1, false, 1, true}};
+constexpr ZV ZCURL_V[] = {{1, 1, 1, false, false}, {1, 2, 1, false, false}, {1, 2, 2, false, false},
+                          {1, 2, 1, true, false},  {1, 1, 1, false, true},  {1, 1, 3, false, true},
+                          {1, 1, 4, false, true},  {1, 2, 4, false, true},  {1, 1, 4, true, true},
+                          {2, 1, 4, false, true}};
+constexpr ZV ZEPI_V[] = {{0, 1, 1, false}, {1, 1, 1, false}, {1, 1, 2, false},
+                         {2, 1, 4, false}, {1, 1, 1, true},  {2, 1, 8, true}};
+constexpr ZV STR_V[] = {{0, 1, 1, false}, {1, 1, 1, false}, {0, 1, 1, true}, {1, 1, 1, true}};
 constexpr XV XPROD_V[] = {{2, 1, false, 0}, {4, 2, false, 0}, {4, 2, true, 0}, {2, 1, true, 0},
                           {2, 2, false, 1}, {4, 4, false, 1}, {1, 1, false, 2}, {2, 2, false, 2}};
 constexpr int NZCURL = sizeof(ZCURL_V) / sizeof(ZV);
+// waves per SIMD that minb workgroups of `threads` threads occupy (4 SIMDs per CU)
+constexpr int waves_per_simd(int minb, int threads) {
+  const int w = minb * ((threads + 63) / 64) / 4;
+  return w < 1 ? 1 : w;
+}
 constexpr int NZEPI = sizeof(ZEPI_V) / sizeof(ZV);
 constexpr int NSTR = sizeof(STR_V) / sizeof(ZV);
 constexpr int NXPROD = sizeof(XPROD_V) / sizeof(XV);

@@ -221,6 +221,12 @@ struct LayPad8 {
   __device__ __forceinline__ static int off(int i, int) { return i + (i >> 3); }
 };
 __host__ __device__ constexpr int pad8(int i) { return i + (i >> 3); }
+// column tiles (TX columns side by side): row idx of the tile padded by one
+// row per eight, so that a first stage writing rows j R + m from lanes of
+// consecutive j spreads over the LDS banks instead of hitting one
+struct LayColPad8 {
+  __device__ __forceinline__ static int off(int i, int ls) { return (i + (i >> 3)) * ls; }
+};
 
 // ---------------------------------------------------------------------------
 // Stockham autosort FFT of length L done by TQ cooperating threads.

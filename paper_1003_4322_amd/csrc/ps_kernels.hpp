@@ -24,6 +24,7 @@
 //   forward z pass + 1/N^3 + dealias + projection (+ induction curl)
 //                  + explicit midpoint RK2 stage update
 #pragma once
+#include <type_traits>
 
 #include "ps_device.hpp"
 
@@ -37,6 +38,22 @@ __device__ __forceinline__ int xcd_remap(int bid, int n) {
   const int x = bid & 7, i = bid >> 3;
   return x * q + (x < r ? x : r) + i;
 }
+
+// LDS tile of TX columns of length L, padded (LayColPad8) when the padded
+// tile plus EXTRA further values fits in 64 KB.
+template <typename T, int L, int TX, int EXTRA>
+struct ColTile {
+  static constexpr int ROWS_PAD = pad8(L - 1) + 1;
+  static constexpr bool PAD = (ROWS_PAD * TX + EXTRA) * (int)sizeof(C2<T>) <= 65536;
+  static constexpr int ROWS = PAD ? ROWS_PAD : L;
+  using Lay = std::conditional_t<PAD, LayColPad8, LayStride>;
+  // a table of L twiddles fits beside the tile without lowering the number
+  // of workgroups that fit in a CU's 160 KB of LDS
+  static constexpr int BYTES = ROWS * TX * (int)sizeof(C2<T>);
+  static constexpr bool TW_FITS =
+      BYTES + L * (int)sizeof(C2<T>) <= 65536 &&
+      163840 / (BYTES + L * (int)sizeof(C2<T>)) == 163840 / BYTES;
+};
 
 // ---------------------------------------------------------------------------
 // Strided complex pass (plain), used for y and z.
@@ -62,7 +79,8 @@ struct StridedArgs {
 template <typename T, int L, int TQ, int TX, int DIR, class RL, int MINW = 1>
 __global__ __launch_bounds__(TX* TQ, MINW) void k_strided(StridedArgs<T> a) {
   using E = Stockham<T, L, TQ, DIR, RL>;
-  __shared__ C2<T> smem[L * TX];
+  using CT = ColTile<T, L, TX, 0>;
+  __shared__ C2<T> smem[CT::ROWS * TX];
   const int tid = threadIdx.x, c = tid % TX, q = tid / TX;
   int blk = xcd_remap(blockIdx.x, gridDim.x);
   const int tile = blk % a.ntile;
@@ -81,7 +99,7 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_strided(StridedArgs<T> a) {
   const C2<T>* in = a.in + box * a.in_bs + f * a.in_fs + line * a.in_ls + col;
   C2<T>* out = a.out + box * a.out_bs + f * a.out_fs + line * a.out_ls + col;
   C2<T> v[E::SLOTS];
-  E::run(v, smem + c, TX, q, a.tw, 1, [&](int, int idx) {
+  E::template run<typename CT::Lay>(v, smem + c, TX, q, a.tw, 1, [&](int, int idx) {
     return ok && (a.prune != 1 || in_disk(idx)) ? in[idx * a.in_es] : zero2<T>();
   });
   if constexpr (E::NSTAGE == 1) __syncthreads();  // in place: all reads before any write
@@ -111,16 +129,28 @@ struct ZCurlArgs {
   int prune;  // 1: state zero outside the 2/3 sphere; only disk columns are produced
 };
 
-// RELOAD (MHD only): two phases, u-derived fields then b-derived fields, each
-// re-reading z+- so that only three components stay in registers.
-template <typename T, int L, int TQ, int TX, class RL, bool MHD, bool RELOAD, int MINW = 1>
+// Output groups: 0 u, 1 w = curl u (NS and MHD), 2 b, 3 j = curl b (MHD).
+// SPLIT > 1 hands the groups of a tile to SPLIT workgroups (adjacent block
+// ids, so they share the tile's input lines in L2).  Without DIRECT the
+// workgroup first loads the base fields (u, and b for MHD) its groups derive
+// from into registers; with DIRECT every output field gathers what it needs
+// straight from memory in the first FFT stage (re-reads hit the cache), which
+// keeps register use, and so occupancy, near that of a plain FFT.  The
+// twiddle table is staged in LDS when that costs no occupancy.
+template <typename T, int L, int TQ, int TX, class RL, bool MHD, int SPLIT, bool DIRECT, int MINW = 1>
 __global__ __launch_bounds__(TX* TQ, MINW) void k_z_curl(ZCurlArgs<T> a) {
   using E = Stockham<T, L, TQ, INV, RL>;
+  using CT = ColTile<T, L, TX, 0>;
+  using Lay = typename CT::Lay;
   constexpr int NS_ = E::FIRST_SLOTS;
-  constexpr int NOUT = MHD ? 12 : 6;
-  __shared__ C2<T> smem[L * TX];
+  constexpr int NG = MHD ? 4 : 2;
+  static_assert(NG % SPLIT == 0, "split must divide the output groups");
+  constexpr int GPP = NG / SPLIT;
+  constexpr bool TWL = CT::TW_FITS;
+  __shared__ C2<T> smem[CT::ROWS * TX + (TWL ? L : 0)];
   const int tid = threadIdx.x, c = tid % TX, q = tid / TX;
-  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int blk0 = xcd_remap(blockIdx.x, gridDim.x);
+  const int part = blk0 % SPLIT, blk = blk0 / SPLIT;
   const int N = L;
   const int tile = blk % a.ntile, ky = (blk / a.ntile) % N, box = blk / (a.ntile * N);
   const int col = tile * TX + c;
@@ -132,72 +162,107 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_z_curl(ZCurlArgs<T> a) {
   C2<T>* out = a.out + box * a.out_bs + ky * a.out_pitch + col;
   const T kx = (T)dwavx(col, N), kyd = (T)dwav(ky, N);
   const int kperp2 = col * col + kyw * kyw;
-
-  // one output field: FFT of component `comp` of `src` (grp even) or of its curl (grp odd)
-  auto emit = [&](auto& src, int grp, int comp, int fout) {
-    C2<T> v[E::SLOTS];
-    E::run(v, smem + c, TX, q, a.tw, 1, [&](int s, int idx) -> C2<T> {
-      if ((grp & 1) == 0) return src[comp][s];
-      const T kz = (T)dwav(idx, N);
-      C2<T> r;
-      if (comp == 0)
-        r = kyd * src[2][s] - kz * src[1][s];
-      else if (comp == 1)
-        r = kz * src[0][s] - kx * src[2][s];
-      else
-        r = kx * src[1][s] - kyd * src[0][s];
-      return mul_i(r);
-    });
+  const C2<T>* tw = a.tw;
+  if constexpr (TWL) {
+    for (int i = tid; i < L; i += TX * TQ) smem[CT::ROWS * TX + i] = a.tw[i];
+    __syncthreads();
+    tw = smem + CT::ROWS * TX;
+  }
+  // element kz of the column is stored (nonzero) input
+  auto live = [&](int kzi) {
+    const int kzw = wav(kzi, N);
+    return ok && (!a.prune || 9 * (kperp2 + kzw * kzw) < N * N);
+  };
+  // component f of u (sign +1) or b (sign -1) at kz row offset off
+  auto base_at = [&](int f, long off, T sign) -> C2<T> {
+    if constexpr (MHD)
+      return T(0.5) * (in[f * a.in_fs + off] + sign * in[(3 + f) * a.in_fs + off]);
+    else
+      return in[f * a.in_fs + off];
+  };
+  // component comp of group grp (even: the base itself, odd: its curl) from
+  // a getter g(f) of the base's components at wavenumber index kzi
+  auto field_of = [&](int grp, int comp, int kzi, auto g) -> C2<T> {
+    if ((grp & 1) == 0) return g(comp);
+    const T kz = (T)dwav(kzi, N);
+    C2<T> r;
+    if (comp == 0)
+      r = kyd * g(2) - kz * g(1);
+    else if (comp == 1)
+      r = kz * g(0) - kx * g(2);
+    else
+      r = kx * g(1) - kyd * g(0);
+    return mul_i(r);
+  };
+  auto store = [&](C2<T> (&v)[E::SLOTS], int fout) {
     if constexpr (E::NSTAGE == 1) __syncthreads();
 #pragma unroll
     for (int s = 0; s < E::LAST_NB * E::RL_; ++s)
       if (ok && E::last_valid(q, s)) out[fout * a.out_fs + E::last_index(q, s) * out_es] = v[s];
   };
-  // load u (sign = +1) or b (sign = -1) from z+- (MHD), or u (NS)
-  auto load = [&](C2<T> (&dst)[3][NS_], T sign) {
-#pragma unroll
-    for (int s = 0; s < NS_; ++s) {
-      const int kzi = E::first_index(q, s), kzw = wav(kzi, N);
-      const bool v = ok && E::first_valid(q, s) && (!a.prune || 9 * (kperp2 + kzw * kzw) < N * N);
-      const long off = (long)kzi * in_es;
-#pragma unroll
-      for (int f = 0; f < 3; ++f) {
-        if constexpr (MHD) {
-          const C2<T> zp = v ? in[f * a.in_fs + off] : zero2<T>();
-          const C2<T> zm = v ? in[(3 + f) * a.in_fs + off] : zero2<T>();
-          dst[f][s] = T(0.5) * (zp + sign * zm);
-        } else {
-          dst[f][s] = v ? in[f * a.in_fs + off] : zero2<T>();
-        }
-      }
-    }
-  };
 
-  if constexpr (MHD && RELOAD) {
-#pragma unroll
-    for (int ph = 0; ph < 2; ++ph) {
-      C2<T> w[3][NS_];
-      load(w, ph == 0 ? T(1) : T(-1));
-#pragma unroll
-      for (int f = 0; f < 6; ++f) emit(w, f / 3, f % 3, 6 * ph + f);
-      __syncthreads();
+  if constexpr (DIRECT) {
+    // one output field per iteration, kept rolled so that no load address
+    // or coefficient of another field stays live across the FFT
+#pragma unroll 1
+    for (int fo = part * 3 * GPP; fo < (part + 1) * 3 * GPP; ++fo) {
+      const int grp = fo / 3, comp = fo % 3;
+      const T sign = (MHD && grp >= 2) ? T(-1) : T(1);
+      const bool curl = grp & 1;
+      // curl component comp = ka g(ca) - kb g(cb), with kz in one of ka, kb
+      const int ca = comp == 0 ? 2 : comp == 1 ? 0 : 1;
+      const int cb = comp == 0 ? 1 : comp == 1 ? 2 : 0;
+      const T kA = comp == 0 ? kyd : kx, kB = comp == 1 ? kx : kyd;
+      C2<T> v[E::SLOTS];
+      E::template run<Lay>(v, smem + c, TX, q, tw, 1, [&](int, int kzi) -> C2<T> {
+        if (!live(kzi)) return zero2<T>();
+        const long off = (long)kzi * in_es;
+        if (!curl) return base_at(comp, off, sign);
+        const T kz = (T)dwav(kzi, N);
+        const T ka = comp == 1 ? kz : kA, kb = comp == 0 ? kz : kB;
+        return mul_i(ka * base_at(ca, off, sign) - kb * base_at(cb, off, sign));
+      });
+      store(v, fo);
     }
   } else {
-    C2<T> u[3][NS_];
-    C2<T> b[MHD ? 3 : 1][NS_];
-    load(u, T(1));
-    if constexpr (MHD) load(b, T(-1));
+    // hold the base fields in registers, indexed by first-stage slot
+    auto load = [&](C2<T> (&dst)[3][NS_], T sign) {
 #pragma unroll
-    for (int f = 0; f < NOUT; ++f) {
-      const int grp = f / 3;
-      if constexpr (MHD) {
-        if (grp < 2)
-          emit(u, grp, f % 3, f);
-        else
-          emit(b, grp, f % 3, f);
-      } else {
-        emit(u, grp, f % 3, f);
+      for (int s = 0; s < NS_; ++s) {
+        const int kzi = E::first_index(q, s);
+        const bool v = E::first_valid(q, s) && live(kzi);
+        const long off = (long)kzi * in_es;
+#pragma unroll
+        for (int f = 0; f < 3; ++f) dst[f][s] = v ? base_at(f, off, sign) : zero2<T>();
       }
+    };
+    auto emit = [&](C2<T> (&src)[3][NS_], int grp, int comp) {
+      C2<T> v[E::SLOTS];
+      E::template run<Lay>(v, smem + c, TX, q, tw, 1, [&](int s, int kzi) -> C2<T> {
+        return field_of(grp, comp, kzi, [&](int f) { return src[f][s]; });
+      });
+      store(v, 3 * grp + comp);
+    };
+    if constexpr (MHD && SPLIT == 1) {
+      C2<T> u[3][NS_], b[3][NS_];
+      load(u, T(1));
+      load(b, T(-1));
+#pragma unroll
+      for (int f = 0; f < 12; ++f) {
+        if (f < 6)
+          emit(u, f / 3, f % 3);
+        else
+          emit(b, f / 3, f % 3);
+      }
+    } else {
+      // groups [g0, g0 + GPP) all derive from one base field
+      const int g0 = part * GPP;
+      C2<T> w[3][NS_];
+      load(w, (MHD && g0 >= 2) ? T(-1) : T(1));
+#pragma unroll
+      for (int gi = 0; gi < GPP; ++gi)
+#pragma unroll
+        for (int comp = 0; comp < 3; ++comp) emit(w, g0 + gi, comp);
     }
   }
 }
@@ -231,7 +296,9 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_z_epi(ZEpiArgs<T> a) {
   using E = Stockham<T, L, TQ, FWD, RL>;
   constexpr int NF = MHD ? 6 : 3;
   constexpr int NO = E::LAST_NB * E::RL_;
-  __shared__ C2<T> smem[L * TX];
+  using CT = ColTile<T, L, TX, 0>;
+  constexpr bool TWL = CT::TW_FITS;
+  __shared__ C2<T> smem[CT::ROWS * TX + (TWL ? L : 0)];
   const int tid = threadIdx.x, c = tid % TX, q = tid / TX;
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const int N = L;
@@ -243,12 +310,18 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_z_epi(ZEpiArgs<T> a) {
   const bool disk = !a.prune || 9 * (col * col + kyw0 * kyw0) < N * N;
   const long in_es = (long)N * a.in_pitch, out_es = (long)N * a.out_pitch;
   const C2<T>* in = a.in + box * a.in_bs + ky * a.in_pitch + col;
+  const C2<T>* tw = a.tw;
+  if constexpr (TWL) {
+    for (int i = tid; i < L; i += TX * TQ) smem[CT::ROWS * TX + i] = a.tw[i];
+    __syncthreads();
+    tw = smem + CT::ROWS * TX;
+  }
 
   C2<T> r[NF][NO];
 #pragma unroll
   for (int f = 0; f < NF; ++f) {
     C2<T> v[E::SLOTS];
-    E::run(v, smem + c, TX, q, a.tw, 1,
+    E::template run<typename CT::Lay>(v, smem + c, TX, q, tw, 1,
            [&](int, int idx) { return ok && disk ? in[f * a.in_fs + idx * in_es] : zero2<T>(); });
 #pragma unroll
     for (int s = 0; s < NO; ++s) r[f][s] = v[s];

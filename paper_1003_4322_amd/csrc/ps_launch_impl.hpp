@@ -32,9 +32,9 @@ hipError_t strided_v(int dir, StridedArgs<T> a, hipStream_t s) {
   const long grid = (long)a.ntile * a.nlines * a.nf * a.nb;
   if (grid <= 0) return hipSuccess;
   if (dir == FWD)
-    k_strided<T, N, LC::TQ, TX, FWD, typename LC::RL, v.minw><<<dim3((unsigned)grid), dim3(TX * LC::TQ), 0, s>>>(a);
+    k_strided<T, N, LC::TQ, TX, FWD, typename LC::RL, waves_per_simd(v.minb, TX * LC::TQ)><<<dim3((unsigned)grid), dim3(TX * LC::TQ), 0, s>>>(a);
   else
-    k_strided<T, N, LC::TQ, TX, INV, typename LC::RL, v.minw><<<dim3((unsigned)grid), dim3(TX * LC::TQ), 0, s>>>(a);
+    k_strided<T, N, LC::TQ, TX, INV, typename LC::RL, waves_per_simd(v.minb, TX * LC::TQ)><<<dim3((unsigned)grid), dim3(TX * LC::TQ), 0, s>>>(a);
   return hipGetLastError();
 }
 
@@ -65,9 +65,10 @@ hipError_t z_curl_v(ZCurlArgs<T> a, hipStream_t s) {
   constexpr ZV v = ZCURL_V[I];
   using LC = Sched<N, v.alt>;
   constexpr int TX = StridedTX<T, N, LC::TQ, v.sh>::value;
+  constexpr int SPLIT = MHD ? v.split : (v.split > 2 ? 2 : v.split);
   a.ntile = cdiv(N / 2 + 1, TX);
-  const long grid = (long)a.ntile * N * a.nb;
-  k_z_curl<T, N, LC::TQ, TX, typename LC::RL, MHD, MHD && v.reload, v.minw>
+  const long grid = (long)a.ntile * N * a.nb * SPLIT;
+  k_z_curl<T, N, LC::TQ, TX, typename LC::RL, MHD, SPLIT, v.direct, waves_per_simd(v.minb, TX * LC::TQ)>
       <<<dim3((unsigned)grid), dim3(TX * LC::TQ), 0, s>>>(a);
   return hipGetLastError();
 }
@@ -103,7 +104,7 @@ hipError_t z_epi_v(ZEpiArgs<T> a, hipStream_t s) {
   constexpr int TX = StridedTX<T, N, LC::TQ, v.sh>::value;
   a.ntile = cdiv(N / 2 + 1, TX);
   const long grid = (long)a.ntile * N * a.nb;
-  k_z_epi<T, N, LC::TQ, TX, typename LC::RL, MHD, v.minw><<<dim3((unsigned)grid), dim3(TX * LC::TQ), 0, s>>>(a);
+  k_z_epi<T, N, LC::TQ, TX, typename LC::RL, MHD, waves_per_simd(v.minb, TX * LC::TQ)><<<dim3((unsigned)grid), dim3(TX * LC::TQ), 0, s>>>(a);
   return hipGetLastError();
 }
 
