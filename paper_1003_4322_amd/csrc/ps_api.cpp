@@ -17,6 +17,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <set>
 #include <new>
 #include <string>
 #include <vector>
@@ -54,6 +55,7 @@ struct Class {
   size_t ws_off = 0;                   // byte offset of the class workspace
   size_t zs_box = 0, work_box = 0, spec_box = 0;  // bytes per box
   void* tw = nullptr;  // device twiddle table (length N), owned by the plan
+  const ps::DiskTiles* dt = nullptr;  // z-pass disk tile lists, owned by the plan
 };
 
 struct TimingRec {
@@ -89,6 +91,8 @@ struct ps_plan_s {
   bool per_box = false;  // baseline: one launch per box instead of per class
   bool prune = false;    // dealias-sphere pruning of the step (state zero outside the sphere)
   std::map<int, void*> tables;
+  std::map<int, ps::DiskTiles> dtiles;  // per grid size: z-pass tiles meeting the 2/3 disk
+  std::vector<void*> dbufs;             // device lists behind dtiles
   hipStream_t stream = nullptr;
   hipStream_t cap = nullptr;  // private stream used only for graph capture
   void* ws = nullptr;
@@ -287,7 +291,7 @@ struct Seq {
     const double bytes = p->prune ? ((double)nin * b.n_sphere + (double)nphys * b.n_disk * b.N) * nb * cs()
                                   : (double)(nin + nphys) * nb * b.nc * cs();
     return enqueue(p, s, "z_curl", bytes,
-                   [&](hipStream_t q) { return ps::launch_z_curl<T>(b.N, mhd, v, ca, q); });
+                   [&](hipStream_t q) { return ps::launch_z_curl<T>(b.N, mhd, v, ca, b.dt, q); });
   }
   ps_status pass_xprod(bool mhd) {
     const int nphys = mhd ? 12 : 6, nprod = mhd ? 6 : 3;
@@ -318,7 +322,7 @@ struct Seq {
       bytes = ((double)nprod * b.n_disk * b.N +
                (mode == 0 ? (double)nprod * b.nc : (double)(1 + nrw) * nprod * b.n_sphere)) * nb * cs();
     return enqueue(p, s, "z_epi", bytes,
-                   [&](hipStream_t q) { return ps::launch_z_epi<T>(b.N, mhd, v, ea, q); });
+                   [&](hipStream_t q) { return ps::launch_z_epi<T>(b.N, mhd, v, ea, b.dt, q); });
   }
 
   // nonlinear right-hand side, epilogue mode 0/1/2 (see k_z_epi)
@@ -403,7 +407,41 @@ void free_plan(ps_plan p) {
   if (p->gexec) hipGraphExecDestroy(p->gexec);
   if (p->cap) hipStreamDestroy(p->cap);
   for (auto& kv : p->tables) hipFree(kv.second);
+  for (void* d : p->dbufs) hipFree(d);
   delete p;
+}
+
+// For every tile width a z-pass variant of size N can use, the list of tiles
+// (tile | ky << 16, ky-major, tile fastest) whose first column lies inside the
+// disk 9 (kx^2 + ky^2) < N^2; the kernels skip exactly the other tiles.
+template <typename T>
+ps_status upload_disk_tiles(ps_plan p, int N) {
+  if (p->dtiles.count(N)) return PS_OK;
+  ps::DiskTiles& dt = p->dtiles[N];
+  const bool mhd = p->nfields == 6;
+  std::set<int> widths;
+  for (int v = 0; v < ps::variant_count("z_curl", N, mhd); ++v) widths.insert(ps::z_curl_tx<T>(N, v));
+  for (int v = 0; v < ps::variant_count("z_epi", N, mhd); ++v) widths.insert(ps::z_epi_tx<T>(N, v));
+  const long H = N / 2 + 1;
+  for (int tx : widths) {
+    if (tx < 1 || tx > ps::DiskTiles::MAXTX) return fail(PS_ERR_STATE, "z-pass tile width out of range");
+    std::vector<int> list;
+    const long ntile = (H + tx - 1) / tx;
+    for (long ky = 0; ky < N; ++ky) {
+      const long kyw = ky < N / 2 ? ky : ky - N;
+      for (long t = 0; t < ntile; ++t)
+        if (9 * (t * tx * t * tx + kyw * kyw) < (long)N * N) list.push_back((int)(t | ky << 16));
+    }
+    void* d = nullptr;
+    hipError_t e = hipMalloc(&d, list.size() * sizeof(int));
+    if (e != hipSuccess) return fail(PS_ERR_NOMEM, std::string("disk tile list: ") + hipGetErrorString(e));
+    p->dbufs.push_back(d);
+    e = hipMemcpy(d, list.data(), list.size() * sizeof(int), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "disk tile upload");
+    dt.list[tx] = (const int*)d;
+    dt.count[tx] = (int)list.size();
+  }
+  return PS_OK;
 }
 
 template <typename T>
@@ -552,11 +590,13 @@ ps_status ps_plan_create_batch(ps_plan* out, int nbox, const int* Ns, int nfield
     p->cplx_total = coff;
     for (auto& c : p->classes) {
       ps_status st = dtype == PS_F32 ? upload_table<float>(p, c.N) : upload_table<double>(p, c.N);
+      if (!st) st = dtype == PS_F32 ? upload_disk_tiles<float>(p, c.N) : upload_disk_tiles<double>(p, c.N);
       if (st) {
         free_plan(p);
         return st;
       }
       c.tw = p->tables[c.N];
+      c.dt = &p->dtiles[c.N];
     }
     // measured defaults at 512^3 (the autotuner refines them per workload)
     bool any_var = false;

@@ -137,9 +137,7 @@ struct XV {
   int kind;           // 0: LDS-staged k_x_prod, 1: register-resident k_x_prod2 with LenXA, 2: with LenXB
 };
 constexpr ZV ZCURL_V[] = {{1, 1, 1, false, false}, {1, 2, 1, false, false}, {1, 2, 2, false, false},
-                          {1, 2, 1, true, false},  {1, 1, 1, false, true},  {1, 1, 3, false, true},
-                          {1, 1, 4, false, true},  {1, 2, 4, false, true},  {1, 1, 4, true, true},
-                          {2, 1, 4, false, true}};
+                          {1, 2, 1, true, false},  {1, 1, 1, false, true}};
 constexpr ZV ZEPI_V[] = {{0, 1, 1, false}, {1, 1, 1, false}, {1, 1, 2, false},
                          {2, 1, 4, false}, {1, 1, 1, true},  {2, 1, 8, true}};
 constexpr ZV STR_V[] = {{0, 1, 1, false}, {1, 1, 1, false}, {0, 1, 1, true}, {1, 1, 1, true}};

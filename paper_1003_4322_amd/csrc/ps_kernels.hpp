@@ -127,7 +127,23 @@ struct ZCurlArgs {
   long in_bs, out_bs;     // box strides
   int N, ntile, nb;
   int prune;  // 1: state zero outside the 2/3 sphere; only disk columns are produced
+  // pruned launches: the ntl tiles (tile | ky << 16) that meet the disk, so
+  // that no workgroup is spent on, and no XCD is left idle by, empty tiles
+  const int* tiles;
+  int ntl;
 };
+
+// tile, ky and box of a z-pass workgroup
+struct ZTile {
+  int tile, ky, box;
+};
+__device__ __forceinline__ ZTile z_tile(int blk, int ntile, int N, const int* tiles, int ntl) {
+  if (tiles) {
+    const int e = tiles[blk % ntl];
+    return {e & 0xffff, e >> 16, blk / ntl};
+  }
+  return {blk % ntile, (blk / ntile) % N, blk / (ntile * N)};
+}
 
 // Output groups: 0 u, 1 w = curl u (NS and MHD), 2 b, 3 j = curl b (MHD).
 // SPLIT > 1 hands the groups of a tile to SPLIT workgroups (adjacent block
@@ -152,7 +168,8 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_z_curl(ZCurlArgs<T> a) {
   const int blk0 = xcd_remap(blockIdx.x, gridDim.x);
   const int part = blk0 % SPLIT, blk = blk0 / SPLIT;
   const int N = L;
-  const int tile = blk % a.ntile, ky = (blk / a.ntile) % N, box = blk / (a.ntile * N);
+  const ZTile zt = z_tile(blk, a.ntile, N, a.prune ? a.tiles : nullptr, a.ntl);
+  const int tile = zt.tile, ky = zt.ky, box = zt.box;
   const int col = tile * TX + c;
   const int kyw = wav(ky, N);
   if (a.prune && 9 * ((tile * TX) * (tile * TX) + kyw * kyw) >= N * N) return;  // tile outside the disk
@@ -289,6 +306,8 @@ struct ZEpiArgs {
   T scale, h, nua, nub;
   int N, ntile, mode, nb;
   int prune;  // 1: only modes inside the 2/3 sphere are read or updated (mode 0 still writes zeros)
+  const int* tiles;  // as in ZCurlArgs; used by pruned launches with mode != 0
+  int ntl;
 };
 
 template <typename T, int L, int TQ, int TX, class RL, bool MHD, int MINW = 1>
@@ -302,7 +321,8 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_z_epi(ZEpiArgs<T> a) {
   const int tid = threadIdx.x, c = tid % TX, q = tid / TX;
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const int N = L;
-  const int tile = blk % a.ntile, ky = (blk / a.ntile) % N, box = blk / (a.ntile * N);
+  const ZTile zt = z_tile(blk, a.ntile, N, a.prune && a.mode != 0 ? a.tiles : nullptr, a.ntl);
+  const int tile = zt.tile, ky = zt.ky, box = zt.box;
   const int col = tile * TX + c;
   const int kyw0 = wav(ky, N);
   if (a.prune && a.mode != 0 && 9 * ((tile * TX) * (tile * TX) + kyw0 * kyw0) >= N * N) return;

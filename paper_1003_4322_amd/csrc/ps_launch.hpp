@@ -18,10 +18,23 @@ int variant_count(const char* kind, int N, bool mhd);
 
 template <typename T>
 hipError_t launch_strided(int N, int dir, int var, StridedArgs<T> a, hipStream_t s);
+// Tiles of a z pass that meet the dealiasing disk 9 (kx^2 + ky^2) < N^2,
+// one device list per tile width (entries tile | ky << 16, ky-major).
+struct DiskTiles {
+  static constexpr int MAXTX = 16;
+  const int* list[MAXTX + 1] = {};
+  int count[MAXTX + 1] = {};
+};
+// tile width (columns per workgroup) of a z-pass variant
 template <typename T>
-hipError_t launch_z_curl(int N, bool mhd, int var, ZCurlArgs<T> a, hipStream_t s);
+int z_curl_tx(int N, int var);
 template <typename T>
-hipError_t launch_z_epi(int N, bool mhd, int var, ZEpiArgs<T> a, hipStream_t s);
+int z_epi_tx(int N, int var);
+
+template <typename T>
+hipError_t launch_z_curl(int N, bool mhd, int var, ZCurlArgs<T> a, const DiskTiles* dt, hipStream_t s);
+template <typename T>
+hipError_t launch_z_epi(int N, bool mhd, int var, ZEpiArgs<T> a, const DiskTiles* dt, hipStream_t s);
 template <typename T>
 hipError_t launch_x_c2r(int N, XArgs<T> a, hipStream_t s);
 template <typename T>

@@ -29,6 +29,10 @@ hipError_t strided_v(int dir, StridedArgs<T> a, hipStream_t s) {
   using LC = Sched<N, v.alt>;
   constexpr int TX = StridedTX<T, N, LC::TQ, v.sh>::value;
   a.ntile = cdiv(a.ncols, TX);
+  // pruned passes: launch only the tiles whose first column kx = tile TX
+  // satisfies 9 kx^2 < N^2 (the kernel skips the others)
+  if (a.prune)
+    while (a.ntile > 0 && 9L * ((a.ntile - 1) * TX) * ((a.ntile - 1) * TX) >= (long)N * N) --a.ntile;
   const long grid = (long)a.ntile * a.nlines * a.nf * a.nb;
   if (grid <= 0) return hipSuccess;
   if (dir == FWD)
@@ -60,75 +64,140 @@ hipError_t launch_strided(int N, int dir, int var, StridedArgs<T> a, hipStream_t
 }
 
 // ---------------- inverse z pass + curl ----------------
+template <typename T, int N, int I>
+constexpr int zcurl_tx_of() {
+  constexpr ZV v = ZCURL_V[I];
+  return StridedTX<T, N, Sched<N, v.alt>::TQ, v.sh>::value;
+}
+template <typename T, int N, int I>
+constexpr int zepi_tx_of() {
+  constexpr ZV v = ZEPI_V[I];
+  return StridedTX<T, N, Sched<N, v.alt>::TQ, v.sh>::value;
+}
+
+// grid of a z pass: every tile, or only those in the disk list
+template <int TX>
+long z_grid(int N, int ntile, int nb, bool listed, const DiskTiles* dt, const int*& tiles, int& ntl) {
+  static_assert(TX <= DiskTiles::MAXTX, "disk tile lists cover widths up to 16");
+  if (listed && dt && dt->list[TX]) {
+    tiles = dt->list[TX];
+    ntl = dt->count[TX];
+    return (long)ntl * nb;
+  }
+  tiles = nullptr;
+  ntl = 0;
+  return (long)ntile * N * nb;
+}
+
 template <typename T, int N, int I, bool MHD>
-hipError_t z_curl_v(ZCurlArgs<T> a, hipStream_t s) {
+hipError_t z_curl_v(ZCurlArgs<T> a, const DiskTiles* dt, hipStream_t s) {
   constexpr ZV v = ZCURL_V[I];
   using LC = Sched<N, v.alt>;
   constexpr int TX = StridedTX<T, N, LC::TQ, v.sh>::value;
   constexpr int SPLIT = MHD ? v.split : (v.split > 2 ? 2 : v.split);
   a.ntile = cdiv(N / 2 + 1, TX);
-  const long grid = (long)a.ntile * N * a.nb * SPLIT;
+  const long grid = z_grid<TX>(N, a.ntile, a.nb, a.prune != 0, dt, a.tiles, a.ntl) * SPLIT;
   k_z_curl<T, N, LC::TQ, TX, typename LC::RL, MHD, SPLIT, v.direct, waves_per_simd(v.minb, TX * LC::TQ)>
       <<<dim3((unsigned)grid), dim3(TX * LC::TQ), 0, s>>>(a);
   return hipGetLastError();
 }
 
 template <typename T, int N>
-hipError_t z_curl_n(bool mhd, int var, ZCurlArgs<T> a, hipStream_t s) {
+hipError_t z_curl_n(bool mhd, int var, ZCurlArgs<T> a, const DiskTiles* dt, hipStream_t s) {
   if constexpr (has_variants(N))
     return pick(var, std::make_integer_sequence<int, NZCURL>{}, [&](auto I) {
       constexpr int i = decltype(I)::value;
-      return mhd ? z_curl_v<T, N, i, true>(a, s) : z_curl_v<T, N, i, false>(a, s);
+      return mhd ? z_curl_v<T, N, i, true>(a, dt, s) : z_curl_v<T, N, i, false>(a, dt, s);
     });
   else
-    return mhd ? z_curl_v<T, N, 0, true>(a, s) : z_curl_v<T, N, 0, false>(a, s);
+    return mhd ? z_curl_v<T, N, 0, true>(a, dt, s) : z_curl_v<T, N, 0, false>(a, dt, s);
 }
 
 template <typename T>
-hipError_t launch_z_curl(int N, bool mhd, int var, ZCurlArgs<T> a, hipStream_t s) {
+hipError_t launch_z_curl(int N, bool mhd, int var, ZCurlArgs<T> a, const DiskTiles* dt, hipStream_t s) {
   switch (N) {
 #define PS_CASE(NN) \
   case NN:          \
-    return z_curl_n<T, NN>(mhd, var, a, s);
+    return z_curl_n<T, NN>(mhd, var, a, dt, s);
     PS_FOR_EACH_N(PS_CASE)
 #undef PS_CASE
   }
   return hipErrorInvalidValue;
 }
 
+template <typename T>
+int z_curl_tx(int N, int var) {
+  int tx = 0;
+  switch (N) {
+#define PS_CASE(NN)                                                                         \
+  case NN:                                                                                  \
+    if constexpr (has_variants(NN))                                                         \
+      pick(var, std::make_integer_sequence<int, NZCURL>{}, [&](auto I) {                    \
+        tx = zcurl_tx_of<T, NN, decltype(I)::value>();                                      \
+        return hipSuccess;                                                                  \
+      });                                                                                   \
+    else                                                                                    \
+      tx = zcurl_tx_of<T, NN, 0>();                                                         \
+    break;
+    PS_FOR_EACH_N(PS_CASE)
+#undef PS_CASE
+  }
+  return tx;
+}
+
 // ---------------- forward z pass + epilogue ----------------
 template <typename T, int N, int I, bool MHD>
-hipError_t z_epi_v(ZEpiArgs<T> a, hipStream_t s) {
+hipError_t z_epi_v(ZEpiArgs<T> a, const DiskTiles* dt, hipStream_t s) {
   constexpr ZV v = ZEPI_V[I];
   using LC = Sched<N, v.alt>;
   constexpr int TX = StridedTX<T, N, LC::TQ, v.sh>::value;
   a.ntile = cdiv(N / 2 + 1, TX);
-  const long grid = (long)a.ntile * N * a.nb;
+  const long grid = z_grid<TX>(N, a.ntile, a.nb, a.prune && a.mode != 0, dt, a.tiles, a.ntl);
   k_z_epi<T, N, LC::TQ, TX, typename LC::RL, MHD, waves_per_simd(v.minb, TX * LC::TQ)><<<dim3((unsigned)grid), dim3(TX * LC::TQ), 0, s>>>(a);
   return hipGetLastError();
 }
 
 template <typename T, int N>
-hipError_t z_epi_n(bool mhd, int var, ZEpiArgs<T> a, hipStream_t s) {
+hipError_t z_epi_n(bool mhd, int var, ZEpiArgs<T> a, const DiskTiles* dt, hipStream_t s) {
   if constexpr (has_variants(N))
     return pick(var, std::make_integer_sequence<int, NZEPI>{}, [&](auto I) {
       constexpr int i = decltype(I)::value;
-      return mhd ? z_epi_v<T, N, i, true>(a, s) : z_epi_v<T, N, i, false>(a, s);
+      return mhd ? z_epi_v<T, N, i, true>(a, dt, s) : z_epi_v<T, N, i, false>(a, dt, s);
     });
   else
-    return mhd ? z_epi_v<T, N, 0, true>(a, s) : z_epi_v<T, N, 0, false>(a, s);
+    return mhd ? z_epi_v<T, N, 0, true>(a, dt, s) : z_epi_v<T, N, 0, false>(a, dt, s);
 }
 
 template <typename T>
-hipError_t launch_z_epi(int N, bool mhd, int var, ZEpiArgs<T> a, hipStream_t s) {
+hipError_t launch_z_epi(int N, bool mhd, int var, ZEpiArgs<T> a, const DiskTiles* dt, hipStream_t s) {
   switch (N) {
 #define PS_CASE(NN) \
   case NN:          \
-    return z_epi_n<T, NN>(mhd, var, a, s);
+    return z_epi_n<T, NN>(mhd, var, a, dt, s);
     PS_FOR_EACH_N(PS_CASE)
 #undef PS_CASE
   }
   return hipErrorInvalidValue;
+}
+
+template <typename T>
+int z_epi_tx(int N, int var) {
+  int tx = 0;
+  switch (N) {
+#define PS_CASE(NN)                                                                         \
+  case NN:                                                                                  \
+    if constexpr (has_variants(NN))                                                         \
+      pick(var, std::make_integer_sequence<int, NZEPI>{}, [&](auto I) {                     \
+        tx = zepi_tx_of<T, NN, decltype(I)::value>();                                       \
+        return hipSuccess;                                                                  \
+      });                                                                                   \
+    else                                                                                    \
+      tx = zepi_tx_of<T, NN, 0>();                                                          \
+    break;
+    PS_FOR_EACH_N(PS_CASE)
+#undef PS_CASE
+  }
+  return tx;
 }
 
 // ---------------- x passes ----------------
