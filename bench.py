@@ -433,7 +433,9 @@ def main():
                                f"batched, nu={w['nu']}, eta={w['eta']}, dt={w['dt']}, "
                                f"random-phase k0={w['k0']} seeds {list(w['seeds'])}",
                    "N": N, "fields": nf, "workload_key": args.workload,
-                   "prune": PRUNE},
+                   "prune": PRUNE,
+                   "mhd_form": (("elsasser-divergence" if (tuned32 or {}).get("form", 1) == 1
+                                 else "rotational") if nf == 6 else None)},
         "ms_per_step_graph": round(ms_graph, 4),
         "variants": tuned32,
         "passes": passes32,

@@ -144,8 +144,13 @@ ps_status ps_energy_spectrum(ps_plan p, const void *fhat, int nfields, double *s
  * and modes outside the sphere 9|k|^2 < N^2 are neither read nor transformed);
  * valid when the input is zero outside that sphere (a dealiased state stays
  * dealiased under the step), and modes outside it are then left untouched by
- * ps_rk2_step (ps_nonlinear_* still writes zeros there).  Setting a variant
- * drops a cached graph. */
+ * ps_rk2_step (ps_nonlinear_* still writes zeros there).  Kind "form" (MHD
+ * plans only): 0 = the rotational form of Sec. 2 (products u x w + j x b and
+ * u x b of the primitive fields), 1 = the Elsasser divergence form, which
+ * takes N+- = -i P(k) k_j F[z-+_j z+-_i] from the nine products z+_i z-_j
+ * (fifteen real transforms per evaluation instead of eighteen; the default);
+ * the two agree up to rounding when z+- are solenoidal, as every state the
+ * step produces is.  Setting a variant drops a cached graph. */
 ps_status ps_plan_set_variant(ps_plan p, const char *kind, int variant);
 int ps_plan_get_variant(ps_plan p, const char *kind);
 int ps_plan_variant_count(ps_plan p, const char *kind);

@@ -264,7 +264,7 @@ class Plan:
         return spec, tot
 
     # -- variants and autotuning ---------------------------------------------------
-    KINDS = ("y", "z", "z_curl", "z_epi", "x_prod", "batch", "prune")
+    KINDS = ("y", "z", "z_curl", "z_epi", "x_prod", "batch", "prune", "form")
 
     def set_variant(self, kind: str, v: int):
         _check(lib().ps_plan_set_variant(self.handle, kind.encode(), int(v)), "set_variant")

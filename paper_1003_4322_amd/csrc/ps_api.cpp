@@ -90,6 +90,7 @@ struct ps_plan_s {
   std::vector<Class> classes;
   bool per_box = false;  // baseline: one launch per box instead of per class
   bool prune = false;    // dealias-sphere pruning of the step (state zero outside the sphere)
+  bool els = false;      // MHD nonlinear term in the Elsasser (divergence) form
   std::map<int, void*> tables;
   std::map<int, ps::DiskTiles> dtiles;  // per grid size: z-pass tiles meeting the 2/3 disk
   std::vector<void*> dbufs;             // device lists behind dtiles
@@ -115,7 +116,7 @@ namespace {
 
 size_t csize(const ps_plan_s* p) { return p->dtype == PS_F32 ? 8 : 16; }
 
-const char* const KINDS[] = {"y", "z", "z_curl", "z_epi", "x_prod", "batch", "prune"};
+const char* const KINDS[] = {"y", "z", "z_curl", "z_epi", "x_prod", "batch", "prune", "form"};
 
 int var_of(const ps_plan_s* p, const char* kind) {
   auto it = p->var.find(kind);
@@ -280,8 +281,13 @@ struct Seq {
   }
 
   // the five passes of one right-hand side evaluation
+  // fields of each stage: state, physical inputs of the products, products
+  bool els(bool mhd) const { return mhd && p->els; }
+  int nphys(bool mhd) const { return mhd ? (p->els ? 6 : 12) : 6; }
+  int nprod(bool mhd) const { return mhd ? (p->els ? 9 : 6) : 3; }
+
   ps_status pass_zcurl(const C* src, bool mhd) {
-    const int nin = mhd ? 6 : 3, nphys = mhd ? 12 : 6;
+    const int nin = mhd ? 6 : 3, nphys = this->nphys(mhd);
     ps::ZCurlArgs<T> ca{};
     ca.in = src; ca.out = work(); ca.tw = tw();
     ca.in_fs = b.nc; ca.in_pitch = b.H; ca.out_fs = b.ncp; ca.out_pitch = b.P; ca.N = b.N;
@@ -291,10 +297,10 @@ struct Seq {
     const double bytes = p->prune ? ((double)nin * b.n_sphere + (double)nphys * b.n_disk * b.N) * nb * cs()
                                   : (double)(nin + nphys) * nb * b.nc * cs();
     return enqueue(p, s, "z_curl", bytes,
-                   [&](hipStream_t q) { return ps::launch_z_curl<T>(b.N, mhd, v, ca, b.dt, q); });
+                   [&](hipStream_t q) { return ps::launch_z_curl<T>(b.N, mhd, els(mhd), v, ca, b.dt, q); });
   }
   ps_status pass_xprod(bool mhd) {
-    const int nphys = mhd ? 12 : 6, nprod = mhd ? 6 : 3;
+    const int nphys = this->nphys(mhd), nprod = this->nprod(mhd);
     ps::XArgs<T> xa{};
     xa.in = work(); xa.out = work(); xa.tw = tw();
     xa.in_pitch = xa.out_pitch = b.P; xa.in_fs = xa.out_fs = b.ncp;
@@ -304,10 +310,10 @@ struct Seq {
     const int v = var_of(p, "x_prod");
     const double per = p->prune ? (double)b.N * b.N * b.kx_keep : (double)b.nc;
     return enqueue(p, s, "x_prod", (double)(nphys + nprod) * nb * per * cs(),
-                   [&](hipStream_t q) { return ps::launch_x_prod<T>(b.N, mhd, v, xa, q); });
+                   [&](hipStream_t q) { return ps::launch_x_prod<T>(b.N, mhd, els(mhd), v, xa, q); });
   }
   ps_status pass_zepi(bool mhd, int mode, C* out, const C* st0, const C* st1, T h, T nua, T nub) {
-    const int nprod = mhd ? 6 : 3;
+    const int nprod = this->nprod(mhd), nst = mhd ? 6 : 3;
     ps::ZEpiArgs<T> ea{};
     ea.in = work(); ea.out = out; ea.st0 = st0; ea.st1 = st1; ea.tw = tw();
     ea.in_fs = b.ncp; ea.in_pitch = b.P; ea.out_fs = b.nc; ea.out_pitch = b.H;
@@ -317,17 +323,17 @@ struct Seq {
     ea.prune = p->prune;
     const int nrw = mode == 0 ? 0 : (mode == 1 ? 1 : 2);
     const int v = var_of(p, "z_epi");
-    double bytes = (double)(nprod + nprod + nrw * nprod) * nb * b.nc * cs();
+    double bytes = (double)(nprod + nst + nrw * nst) * nb * b.nc * cs();
     if (p->prune)
       bytes = ((double)nprod * b.n_disk * b.N +
-               (mode == 0 ? (double)nprod * b.nc : (double)(1 + nrw) * nprod * b.n_sphere)) * nb * cs();
+               (mode == 0 ? (double)nst * b.nc : (double)(1 + nrw) * nst * b.n_sphere)) * nb * cs();
     return enqueue(p, s, "z_epi", bytes,
-                   [&](hipStream_t q) { return ps::launch_z_epi<T>(b.N, mhd, v, ea, b.dt, q); });
+                   [&](hipStream_t q) { return ps::launch_z_epi<T>(b.N, mhd, els(mhd), v, ea, b.dt, q); });
   }
 
   // nonlinear right-hand side, epilogue mode 0/1/2 (see k_z_epi)
   ps_status rhs(const C* src, bool mhd, int mode, C* out, const C* st0, const C* st1, T h, T nua, T nub) {
-    const int nphys = mhd ? 12 : 6, nprod = mhd ? 6 : 3;
+    const int nphys = this->nphys(mhd), nprod = this->nprod(mhd);
     ps_status st = pass_zcurl(src, mhd);
     if (st) return st;
     if ((st = ypass(work(), b.P, wk_bs(), nphys, ps::INV, p->prune ? 1 : 0))) return st;
@@ -340,7 +346,7 @@ struct Seq {
   // workspace is written
   ps_status tune_launch(const char* kind, const C* state, bool mhd) {
     if (!strcmp(kind, "z_curl")) return pass_zcurl(state, mhd);
-    if (!strcmp(kind, "y")) return ypass(work(), b.P, wk_bs(), mhd ? 12 : 6, ps::INV, p->prune ? 1 : 0);
+    if (!strcmp(kind, "y")) return ypass(work(), b.P, wk_bs(), nphys(mhd), ps::INV, p->prune ? 1 : 0);
     if (!strcmp(kind, "x_prod")) return pass_xprod(mhd);
     if (!strcmp(kind, "z_epi")) return pass_zepi(mhd, 0, zstar(), nullptr, nullptr, T(0), T(0), T(0));
     return fail(PS_ERR_ARG, std::string("no tuning launch for kind ") + kind);
@@ -601,6 +607,11 @@ ps_status ps_plan_create_batch(ps_plan* out, int nbox, const int* Ns, int nfield
     // measured defaults at 512^3 (the autotuner refines them per workload)
     bool any_var = false;
     for (auto& b : p->boxes) any_var |= ps::variant_count("z_curl", b.N, nfields == 6) > 1;
+    // MHD: the Elsasser divergence form (fewer transforms, same result)
+    if (nfields == 6) {
+      p->var["form"] = 1;
+      p->els = true;
+    }
     if (any_var) {
       p->var["z_curl"] = 0;
       p->var["z_epi"] = 1;
@@ -822,13 +833,12 @@ ps_status ps_plan_set_variant(ps_plan p, const char* kind, int v) {
   bool known = false;
   for (const char* k : KINDS) known |= !strcmp(k, kind);
   if (!known) return fail(PS_ERR_ARG, std::string("unknown pass kind ") + kind);
-  int n = 1;
-  for (auto& b : p->boxes) n = std::max(n, ps::variant_count(kind, b.N, p->nfields == 6));
-  if (!strcmp(kind, "batch") || !strcmp(kind, "prune")) n = 2;
+  const int n = ps_plan_variant_count(p, kind);
   if (v < 0 || v >= n) return fail(PS_ERR_ARG, "variant out of range");
   p->var[kind] = v;
   p->per_box = var_of(p, "batch") == 1;
   p->prune = var_of(p, "prune") == 1;
+  p->els = var_of(p, "form") == 1;
   if (p->gexec) {
     hipGraphExecDestroy(p->gexec);
     p->gexec = nullptr;
@@ -845,6 +855,7 @@ int ps_plan_get_variant(ps_plan p, const char* kind) {
 int ps_plan_variant_count(ps_plan p, const char* kind) {
   if (!p || !kind) return PS_ERR_ARG;
   if (!strcmp(kind, "batch") || !strcmp(kind, "prune")) return 2;
+  if (!strcmp(kind, "form")) return p->nfields == 6 ? 2 : 1;
   int n = 1;
   for (auto& b : p->boxes) n = std::max(n, ps::variant_count(kind, b.N, p->nfields == 6));
   return n;

@@ -56,35 +56,6 @@ PS_ALT(768, 48, 16, 16, 3)
 PS_ALT(1024, 64, 16, 8, 8)
 #undef PS_ALT
 
-// Schedules for the register-resident product pass: first radix equal to the
-// last, so a thread's output points of the inverse transform are exactly its
-// input points of the forward one.  A: ~8 values per thread, B: ~4.
-template <int L>
-struct LenXA : LenCfg<L> {};
-template <int L>
-struct LenXB : LenCfg<L> {};
-#define PS_XA(L_, TQ_, ...) \
-  template <>               \
-  struct LenXA<L_> {        \
-    using RL = Radices<__VA_ARGS__>; \
-    static constexpr int TQ = TQ_;   \
-  };
-#define PS_XB(L_, TQ_, ...) \
-  template <>               \
-  struct LenXB<L_> {        \
-    using RL = Radices<__VA_ARGS__>; \
-    static constexpr int TQ = TQ_;   \
-  };
-PS_XA(128, 16, 8, 2, 8)
-PS_XB(128, 32, 4, 8, 4)
-PS_XA(192, 24, 8, 3, 8)
-PS_XA(256, 32, 8, 4, 8)
-PS_XB(256, 64, 4, 4, 4, 4)
-PS_XA(384, 48, 8, 2, 3, 8)
-PS_XA(512, 64, 8, 8, 8)
-PS_XB(512, 128, 4, 8, 4, 4)
-#undef PS_XA
-#undef PS_XB
 #undef PS_LEN
 
 // grid sizes with a compiled configuration
@@ -121,9 +92,10 @@ struct XCfg {
   static constexpr bool MHD_OK = fits(12, 1);
 };
 
-// Kernel variant tables.  Strided-pass variants: tile shift, two-phase reload
-// (MHD curl), minimum waves per SIMD requested from the register allocator,
-// alternate (radix-16) schedule.  Product-pass variants: rows shift, schedule.
+// Kernel variant tables.  Strided-pass variants: tile shift, z_curl split and
+// direct gather, minimum workgroups per CU asked of the register allocator,
+// alternate (radix-16) schedule.  Product-pass variants: rows per workgroup,
+// schedule.
 struct ZV {
   int sh;       // tile width shift
   int split;    // z_curl: workgroups per tile sharing the output groups (1, 2 or 4; NS caps at 2)
@@ -133,16 +105,14 @@ struct ZV {
 };
 struct XV {
   int rb_ns, rb_mhd;  // rows per workgroup (reduced while the LDS tile would not fit)
-  bool alt;           // LDS-staged kernel: radix-16 schedule
-  int kind;           // 0: LDS-staged k_x_prod, 1: register-resident k_x_prod2 with LenXA, 2: with LenXB
+  bool alt;           // radix-16 schedule
 };
 constexpr ZV ZCURL_V[] = {{1, 1, 1, false, false}, {1, 2, 1, false, false}, {1, 2, 2, false, false},
                           {1, 2, 1, true, false},  {1, 1, 1, false, true}};
-constexpr ZV ZEPI_V[] = {{0, 1, 1, false}, {1, 1, 1, false}, {1, 1, 2, false},
-                         {2, 1, 4, false}, {1, 1, 1, true},  {2, 1, 8, true}};
+constexpr ZV ZEPI_V[] = {{0, 1, 1, false}, {1, 1, 1, false}, {1, 1, 2, false}, {2, 1, 4, false},
+                         {1, 1, 1, true},  {2, 1, 8, true},  {2, 1, 1, false}, {2, 1, 3, false}};
 constexpr ZV STR_V[] = {{0, 1, 1, false}, {1, 1, 1, false}, {0, 1, 1, true}, {1, 1, 1, true}};
-constexpr XV XPROD_V[] = {{2, 1, false, 0}, {4, 2, false, 0}, {4, 2, true, 0}, {2, 1, true, 0},
-                          {2, 2, false, 1}, {4, 4, false, 1}, {1, 1, false, 2}, {2, 2, false, 2}};
+constexpr XV XPROD_V[] = {{2, 1, false}, {4, 2, false}, {4, 2, true}, {2, 1, true}};
 constexpr int NZCURL = sizeof(ZCURL_V) / sizeof(ZV);
 // waves per SIMD that minb workgroups of `threads` threads occupy (4 SIMDs per CU)
 constexpr int waves_per_simd(int minb, int threads) {

@@ -246,6 +246,51 @@ struct LayColPad8 {
 // threads finished reading the previous contents, so consecutive transforms
 // (and in-place exchanges) can reuse one LDS buffer.
 // ---------------------------------------------------------------------------
+// Twiddle sources of the Stockham stages.  A stage of span NS and radix R
+// multiplies input m of butterfly j by w^(m (j mod NS) L / (NS R)),
+// w = exp(-2 pi i / L).
+// TwTable: tw[e * twmul] = exp(-2 pi i e / (L twmul)), the plain table.
+template <typename T>
+struct TwTable {
+  const C2<T>* tw;
+  int twmul;
+  template <int L, int NS, int R>
+  __device__ __forceinline__ C2<T> get(int m, int k) const {
+    return tw[(m * k * (L / (NS * R))) * twmul];
+  }
+};
+// TwStaged: every stage's factors in the order the threads read them, the
+// stage of span NS at offset NS - 1 (the spans before it sum to NS - 1), entry
+// (m - 1) NS + k; consecutive k are consecutive words, so the reads of a wave
+// fall in distinct LDS banks.  L - 1 entries in all.
+template <typename T>
+struct TwStaged {
+  const C2<T>* t;
+  template <int L, int NS, int R>
+  __device__ __forceinline__ C2<T> get(int m, int k) const {
+    return t[(NS - 1) + (m - 1) * NS + k];
+  }
+};
+// fill dst[0, L - 1) with the TwStaged layout of schedule RL from a plain table
+template <typename T, int L, int... Rs>
+__device__ __forceinline__ void fill_staged(C2<T>* dst, const C2<T>* tw, int twmul, int tid, int nt,
+                                            Radices<Rs...>) {
+  constexpr int rs[] = {Rs...};
+  for (int idx = tid; idx < L - 1; idx += nt) {
+    int ns = 1;
+#pragma unroll
+    for (int st = 0; st < (int)sizeof...(Rs); ++st) {
+      const int R = rs[st];
+      if (idx < ns * R - 1) {
+        const int r = idx - (ns - 1), m = 1 + r / ns, k = r % ns;
+        dst[idx] = tw[(m * k * (L / (ns * R))) * twmul];
+        break;
+      }
+      ns *= R;
+    }
+  }
+}
+
 template <typename T, int L, int TQ, int DIR, class RL>
 struct Stockham {
   static constexpr int R1 = RadixInfo<RL>::first;
@@ -288,45 +333,48 @@ struct Stockham {
     return (L / RL_) % TQ == 0 || q + TQ * (slot / RL_) < L / RL_;
   }
 
-  template <int NS, int R, bool FIRST, bool LAST, class Lay, class Ld>
-  __device__ __forceinline__ static void stage(C2<T> (&v)[SLOTS], C2<T>* lds, int ls, int q,
-                                               const C2<T>* __restrict__ tw, int twmul, Ld& ld) {
+  // act = false: the thread only takes part in the barriers (its group has no
+  // transform to do); v is left undefined
+  template <int NS, int R, bool FIRST, bool LAST, class Lay, class TW, class Ld>
+  __device__ __forceinline__ static void stage(C2<T> (&v)[SLOTS], C2<T>* lds, int ls, int q, const TW& tw,
+                                               Ld& ld, bool act) {
     constexpr int NB = cdiv(L / R, TQ);
     constexpr bool EXACT = (L / R) % TQ == 0;
-    // ---- gather inputs
+    if (act) {
+      // ---- gather inputs
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      const int j = q + TQ * b;
-      const bool ok = EXACT || j < L / R;
+      for (int b = 0; b < NB; ++b) {
+        const int j = q + TQ * b;
+        const bool ok = EXACT || j < L / R;
 #pragma unroll
-      for (int m = 0; m < R; ++m) {
-        const int idx = j + m * (L / R);
-        if constexpr (FIRST) {
-          v[b * R + m] = ok ? ld(b * R + m, idx) : zero2<T>();
-        } else {
-          v[b * R + m] = ok ? lds[Lay::off(idx, ls)] : zero2<T>();
+        for (int m = 0; m < R; ++m) {
+          const int idx = j + m * (L / R);
+          if constexpr (FIRST) {
+            v[b * R + m] = ok ? ld(b * R + m, idx) : zero2<T>();
+          } else {
+            v[b * R + m] = ok ? lds[Lay::off(idx, ls)] : zero2<T>();
+          }
         }
       }
-    }
-    // ---- twiddle and butterfly
+      // ---- twiddle and butterfly
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      const int j = q + TQ * b;
-      C2<T>* a = &v[b * R];
-      if constexpr (NS > 1) {
-        const int k = j % NS;
-        constexpr int STEP = L / (NS * R);
+      for (int b = 0; b < NB; ++b) {
+        const int j = q + TQ * b;
+        C2<T>* a = &v[b * R];
+        if constexpr (NS > 1) {
+          const int k = j % NS;
 #pragma unroll
-        for (int m = 1; m < R; ++m) a[m] = tw_apply<DIR>(a[m], tw[(m * k * STEP) * twmul]);
+          for (int m = 1; m < R; ++m) a[m] = tw_apply<DIR>(a[m], tw.template get<L, NS, R>(m, k));
+        }
+        dft<R, DIR>(a);
       }
-      dft<R, DIR>(a);
     }
     if constexpr (!LAST) {
       __syncthreads();  // all reads of the previous LDS contents are done
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
         const int j = q + TQ * b;
-        if (EXACT || j < L / R) {
+        if (act && (EXACT || j < L / R)) {
           const int base = (j / NS) * NS * R + (j % NS);
 #pragma unroll
           for (int m = 0; m < R; ++m) lds[Lay::off(base + m * NS, ls)] = v[b * R + m];
@@ -336,19 +384,24 @@ struct Stockham {
     }
   }
 
-  template <int NS, class Lay, class Ld, int R, int... Rest>
-  __device__ __forceinline__ static void chain(C2<T> (&v)[SLOTS], C2<T>* lds, int ls, int q,
-                                               const C2<T>* __restrict__ tw, int twmul, Ld& ld,
-                                               Radices<R, Rest...>) {
-    stage<NS, R, NS == 1, sizeof...(Rest) == 0, Lay>(v, lds, ls, q, tw, twmul, ld);
-    if constexpr (sizeof...(Rest) > 0) chain<NS * R, Lay>(v, lds, ls, q, tw, twmul, ld, Radices<Rest...>{});
+  template <int NS, class Lay, class TW, class Ld, int R, int... Rest>
+  __device__ __forceinline__ static void chain(C2<T> (&v)[SLOTS], C2<T>* lds, int ls, int q, const TW& tw,
+                                               Ld& ld, bool act, Radices<R, Rest...>) {
+    stage<NS, R, NS == 1, sizeof...(Rest) == 0, Lay>(v, lds, ls, q, tw, ld, act);
+    if constexpr (sizeof...(Rest) > 0) chain<NS * R, Lay>(v, lds, ls, q, tw, ld, act, Radices<Rest...>{});
   }
 
   // tw: table of exp(-2 pi i e / (L * twmul)), e < L * twmul.
   template <class Lay = LayStride, class Ld>
   __device__ __forceinline__ static void run(C2<T> (&v)[SLOTS], C2<T>* lds, int ls, int q,
                                              const C2<T>* __restrict__ tw, int twmul, Ld ld) {
-    chain<1, Lay>(v, lds, ls, q, tw, twmul, ld, RL{});
+    chain<1, Lay>(v, lds, ls, q, TwTable<T>{tw, twmul}, ld, true, RL{});
+  }
+  // any twiddle source (TwTable, TwStaged); act as in stage()
+  template <class Lay, class TW, class Ld>
+  __device__ __forceinline__ static void run_tw(C2<T> (&v)[SLOTS], C2<T>* lds, int ls, int q, const TW& tw,
+                                                Ld ld, bool act = true) {
+    chain<1, Lay>(v, lds, ls, q, tw, ld, act, RL{});
   }
 };
 

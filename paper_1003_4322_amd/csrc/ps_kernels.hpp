@@ -152,15 +152,19 @@ __device__ __forceinline__ ZTile z_tile(int blk, int ntile, int N, const int* ti
 // from into registers; with DIRECT every output field gathers what it needs
 // straight from memory in the first FFT stage (re-reads hit the cache), which
 // keeps register use, and so occupancy, near that of a plain FFT.  The
-// twiddle table is staged in LDS when that costs no occupancy.
-template <typename T, int L, int TQ, int TX, class RL, bool MHD, int SPLIT, bool DIRECT, int MINW = 1>
+// transforms' twiddles are staged in LDS (TwStaged) when that costs no occupancy.
+//
+// ELS (MHD, Elsasser form): no curl is needed; the six fields z+, z- are
+// transformed as they are, SPLIT workgroups sharing them (SPLIT 1 or 2).
+template <typename T, int L, int TQ, int TX, class RL, bool MHD, int SPLIT, bool DIRECT, int MINW = 1,
+          bool ELS = false>
 __global__ __launch_bounds__(TX* TQ, MINW) void k_z_curl(ZCurlArgs<T> a) {
   using E = Stockham<T, L, TQ, INV, RL>;
   using CT = ColTile<T, L, TX, 0>;
   using Lay = typename CT::Lay;
   constexpr int NS_ = E::FIRST_SLOTS;
   constexpr int NG = MHD ? 4 : 2;
-  static_assert(NG % SPLIT == 0, "split must divide the output groups");
+  static_assert(NG % SPLIT == 0 && (!ELS || (MHD && SPLIT <= 2)), "split must divide the output groups");
   constexpr int GPP = NG / SPLIT;
   constexpr bool TWL = CT::TW_FITS;
   __shared__ C2<T> smem[CT::ROWS * TX + (TWL ? L : 0)];
@@ -179,12 +183,16 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_z_curl(ZCurlArgs<T> a) {
   C2<T>* out = a.out + box * a.out_bs + ky * a.out_pitch + col;
   const T kx = (T)dwavx(col, N), kyd = (T)dwav(ky, N);
   const int kperp2 = col * col + kyw * kyw;
-  const C2<T>* tw = a.tw;
   if constexpr (TWL) {
-    for (int i = tid; i < L; i += TX * TQ) smem[CT::ROWS * TX + i] = a.tw[i];
+    fill_staged<T, L>(smem + CT::ROWS * TX, a.tw, 1, tid, TX * TQ, RL{});
     __syncthreads();
-    tw = smem + CT::ROWS * TX;
   }
+  const auto tw = [&] {
+    if constexpr (TWL)
+      return TwStaged<T>{smem + CT::ROWS * TX};
+    else
+      return TwTable<T>{a.tw, 1};
+  }();
   // element kz of the column is stored (nonzero) input
   auto live = [&](int kzi) {
     const int kzw = wav(kzi, N);
@@ -218,7 +226,17 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_z_curl(ZCurlArgs<T> a) {
       if (ok && E::last_valid(q, s)) out[fout * a.out_fs + E::last_index(q, s) * out_es] = v[s];
   };
 
-  if constexpr (DIRECT) {
+  if constexpr (ELS) {
+    constexpr int PER = 6 / SPLIT;
+#pragma unroll 1
+    for (int fo = part * PER; fo < (part + 1) * PER; ++fo) {
+      C2<T> v[E::SLOTS];
+      E::template run_tw<Lay>(v, smem + c, TX, q, tw, [&](int, int kzi) -> C2<T> {
+        return live(kzi) ? in[fo * a.in_fs + (long)kzi * in_es] : zero2<T>();
+      });
+      store(v, fo);
+    }
+  } else if constexpr (DIRECT) {
     // one output field per iteration, kept rolled so that no load address
     // or coefficient of another field stays live across the FFT
 #pragma unroll 1
@@ -231,7 +249,7 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_z_curl(ZCurlArgs<T> a) {
       const int cb = comp == 0 ? 1 : comp == 1 ? 2 : 0;
       const T kA = comp == 0 ? kyd : kx, kB = comp == 1 ? kx : kyd;
       C2<T> v[E::SLOTS];
-      E::template run<Lay>(v, smem + c, TX, q, tw, 1, [&](int, int kzi) -> C2<T> {
+      E::template run_tw<Lay>(v, smem + c, TX, q, tw, [&](int, int kzi) -> C2<T> {
         if (!live(kzi)) return zero2<T>();
         const long off = (long)kzi * in_es;
         if (!curl) return base_at(comp, off, sign);
@@ -255,7 +273,7 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_z_curl(ZCurlArgs<T> a) {
     };
     auto emit = [&](C2<T> (&src)[3][NS_], int grp, int comp) {
       C2<T> v[E::SLOTS];
-      E::template run<Lay>(v, smem + c, TX, q, tw, 1, [&](int s, int kzi) -> C2<T> {
+      E::template run_tw<Lay>(v, smem + c, TX, q, tw, [&](int s, int kzi) -> C2<T> {
         return field_of(grp, comp, kzi, [&](int f) { return src[f][s]; });
       });
       store(v, 3 * grp + comp);
@@ -310,9 +328,17 @@ struct ZEpiArgs {
   int ntl;
 };
 
-template <typename T, int L, int TQ, int TX, class RL, bool MHD, int MINW = 1>
+//
+// ELS (MHD, Elsasser form): in = the nine products T_ij = z+_i z-_j (field
+// 3 i + j) transformed along x and y; with a_i = sum_j k_j T^_ij and
+// c_i = sum_j k_j T^_ji (derivative wavenumbers),
+//   N+ = -i D(k) P(k) a / N^3,  N- = -i D(k) P(k) c / N^3,
+// the divergence form of -(z-+ . grad) z+-, equal to the form above for
+// solenoidal z+-.  a and c are accumulated field by field.
+template <typename T, int L, int TQ, int TX, class RL, bool MHD, int MINW = 1, bool ELS = false>
 __global__ __launch_bounds__(TX* TQ, MINW) void k_z_epi(ZEpiArgs<T> a) {
   using E = Stockham<T, L, TQ, FWD, RL>;
+  static_assert(!ELS || MHD, "the Elsasser form is MHD only");
   constexpr int NF = MHD ? 6 : 3;
   constexpr int NO = E::LAST_NB * E::RL_;
   using CT = ColTile<T, L, TX, 0>;
@@ -330,21 +356,66 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_z_epi(ZEpiArgs<T> a) {
   const bool disk = !a.prune || 9 * (col * col + kyw0 * kyw0) < N * N;
   const long in_es = (long)N * a.in_pitch, out_es = (long)N * a.out_pitch;
   const C2<T>* in = a.in + box * a.in_bs + ky * a.in_pitch + col;
-  const C2<T>* tw = a.tw;
   if constexpr (TWL) {
-    for (int i = tid; i < L; i += TX * TQ) smem[CT::ROWS * TX + i] = a.tw[i];
+    fill_staged<T, L>(smem + CT::ROWS * TX, a.tw, 1, tid, TX * TQ, RL{});
     __syncthreads();
-    tw = smem + CT::ROWS * TX;
   }
+  const auto tw = [&] {
+    if constexpr (TWL)
+      return TwStaged<T>{smem + CT::ROWS * TX};
+    else
+      return TwTable<T>{a.tw, 1};
+  }();
 
   C2<T> r[NF][NO];
+  if constexpr (ELS) {
+    // r[0..2] = a, r[3..5] = c.  The loop over i is kept rolled (a_i is
+    // gathered in acc and moved to its place at the end of each row) so that
+    // the compiler does not stretch the nine transforms' loads across each
+    // other and run out of registers.
+    const T kxd0 = (T)dwavx(col, N), kyd0 = (T)dwav(ky, N);
 #pragma unroll
-  for (int f = 0; f < NF; ++f) {
-    C2<T> v[E::SLOTS];
-    E::template run<typename CT::Lay>(v, smem + c, TX, q, tw, 1,
-           [&](int, int idx) { return ok && disk ? in[f * a.in_fs + idx * in_es] : zero2<T>(); });
+    for (int f = 0; f < NF; ++f)
 #pragma unroll
-    for (int s = 0; s < NO; ++s) r[f][s] = v[s];
+      for (int s = 0; s < NO; ++s) r[f][s] = zero2<T>();
+#pragma unroll 1
+    for (int i3 = 0; i3 < 3; ++i3) {
+      C2<T> acc[NO];
+#pragma unroll
+      for (int s = 0; s < NO; ++s) acc[s] = zero2<T>();
+#pragma unroll
+      for (int j3 = 0; j3 < 3; ++j3) {
+        const int f = 3 * i3 + j3;
+        C2<T> v[E::SLOTS];
+        E::template run_tw<typename CT::Lay>(v, smem + c, TX, q, tw, [&](int, int idx) {
+          return ok && disk ? in[f * a.in_fs + idx * in_es] : zero2<T>();
+        });
+#pragma unroll
+        for (int s = 0; s < NO; ++s) {
+          const T kzd0 = (T)dwav(E::last_index(q, s), N);
+          const T kj = j3 == 0 ? kxd0 : j3 == 1 ? kyd0 : kzd0;
+          const T ki = i3 == 0 ? kxd0 : i3 == 1 ? kyd0 : kzd0;
+          acc[s] = acc[s] + kj * v[s];
+          r[3 + j3][s] = r[3 + j3][s] + ki * v[s];
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < NO; ++s) {
+        r[0][s] = i3 == 0 ? acc[s] : r[0][s];
+        r[1][s] = i3 == 1 ? acc[s] : r[1][s];
+        r[2][s] = i3 == 2 ? acc[s] : r[2][s];
+      }
+    }
+  } else {
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      C2<T> v[E::SLOTS];
+      E::template run_tw<typename CT::Lay>(v, smem + c, TX, q, tw, [&](int, int idx) {
+        return ok && disk ? in[f * a.in_fs + idx * in_es] : zero2<T>();
+      });
+#pragma unroll
+      for (int s = 0; s < NO; ++s) r[f][s] = v[s];
+    }
   }
   if (!ok) return;  // no barrier follows
 
@@ -363,7 +434,18 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_z_epi(ZEpiArgs<T> a) {
     const T k2 = (T)k2i;
     const T kx = (T)ikx, ky_ = (T)iky, kz = (T)ikz;
     C2<T> nh[NF];
-    if (keep) {
+    if constexpr (ELS) {
+      const T ik2 = keep ? T(1) / k2 : T(0);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        // -i P(k) applied to the accumulated divergence, scaled
+        C2<T> n0 = a.scale * r[3 * h][s], n1 = a.scale * r[3 * h + 1][s], n2 = a.scale * r[3 * h + 2][s];
+        const C2<T> kn = kx * n0 + ky_ * n1 + kz * n2;
+        nh[3 * h] = keep ? mul_i((kx * ik2) * kn - n0) : zero2<T>();
+        nh[3 * h + 1] = keep ? mul_i((ky_ * ik2) * kn - n1) : zero2<T>();
+        nh[3 * h + 2] = keep ? mul_i((kz * ik2) * kn - n2) : zero2<T>();
+      }
+    } else if (keep) {
       const T ik2 = T(1) / k2;
       C2<T> n0 = a.scale * r[0][s], n1 = a.scale * r[1][s], n2 = a.scale * r[2][s];
       const C2<T> kn = kx * n0 + ky_ * n1 + kz * n2;
@@ -405,6 +487,9 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_z_epi(ZEpiArgs<T> a) {
         dst[f * a.out_fs + pos] = z0[f] + a.h * (nh[f] - vis);
       }
     }
+    // one mode at a time: keeps the scheduler from computing every slot's
+    // results before storing any (which costs ~100 registers for MHD)
+    __builtin_amdgcn_sched_barrier(0);
   }
 }
 
@@ -422,6 +507,8 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_z_epi(ZEpiArgs<T> a) {
 // Rows in LDS use the padded layout (element i at pad8(i)); RowLen(M) slots
 // hold M+1 values.
 __host__ __device__ constexpr int row_slots(int M) { return pad8(M) + 1; }
+// rows of LDS (and thread groups) per grid row of the fused product pass
+__host__ __device__ constexpr int xprod_slots(bool mhd, bool els) { return els ? 9 : mhd ? 12 : 6; }
 
 template <typename T>
 __device__ __forceinline__ C2<T> c2r_pre(const C2<T>* buf, int k, int M, const C2<T>* __restrict__ tw) {
@@ -527,15 +614,20 @@ __global__ __launch_bounds__(G* TQ) void k_x_r2c(XArgs<T> a) {
 // forward real FFTs -> FOUT complex output fields.  RB rows per workgroup.
 // NS : in [u0 u1 u2 w0 w1 w2]             out [u x w]
 // MHD: in [u0..2 w0..2 b0..2 j0..2]       out [u x w + j x b, u x b]
-template <typename T, int M, int TQ, int RB, class RL, bool MHD>
-__global__ __launch_bounds__((MHD ? 12 : 6) * RB * TQ) void k_x_prod(XArgs<T> a) {
-  constexpr int FIN = MHD ? 12 : 6, FOUT = MHD ? 6 : 3;
-  constexpr int G = FIN * RB, NT = G * TQ;
+//
+// ELS (MHD, Elsasser form): inputs z+ (fields 0-2) and z- (3-5); outputs the
+// nine products T_ij = z+_i z-_j as field 3 i + j.
+template <typename T, int M, int TQ, int RB, class RL, bool MHD, bool ELS = false>
+__global__ __launch_bounds__(xprod_slots(MHD, ELS) * RB * TQ) void k_x_prod(XArgs<T> a) {
+  constexpr int FIN = ELS ? 6 : MHD ? 12 : 6, FOUT = ELS ? 9 : MHD ? 6 : 3;
+  constexpr int G = xprod_slots(MHD, ELS) * RB, NT = G * TQ;
   using EI = Stockham<T, M, TQ, INV, RL>;
   using EF = Stockham<T, M, TQ, FWD, RL>;
   constexpr int LP = row_slots(M);
-  // rows of every field, then the twiddle table (length N = 2M) staged in LDS
-  __shared__ C2<T> smem[G * LP + 2 * M];
+  // rows of every field, then the twiddle table (length N = 2M) and, when it
+  // fits in 64 KB, the transforms' twiddles in the bank-friendly staged order
+  constexpr bool STAGED = (G * LP + 3 * M) * (int)sizeof(C2<T>) <= 65536;
+  __shared__ C2<T> smem[G * LP + (STAGED ? 3 : 2) * M];
   C2<T>* twl = smem + G * LP;
   const int tid = threadIdx.x, g = tid / TQ, q = tid % TQ;
   const int f = g / RB, rb = g % RB;  // group g owns field f of row rb (slot g)
@@ -544,8 +636,16 @@ __global__ __launch_bounds__((MHD ? 12 : 6) * RB * TQ) void k_x_prod(XArgs<T> a)
   const long rr = rok ? row : 0;
   const long boxi = rr / a.rows, rloc = rr % a.rows;
   for (int i = tid; i < 2 * M; i += NT) twl[i] = a.tw[i];
+  if constexpr (STAGED) fill_staged<T, M>(twl + 2 * M, a.tw, 2, tid, NT, RL{});
+  const auto twf = [&] {
+    if constexpr (STAGED)
+      return TwStaged<T>{twl + 2 * M};
+    else
+      return TwTable<T>{twl, 2};
+  }();
   C2<T>* buf = smem + g * LP;
-  {
+  const bool in_act = f < FIN;
+  if (in_act) {
     const C2<T>* src = a.in + boxi * a.in_bs + f * a.in_fs + rloc * a.in_pitch;
     for (int k = q; k <= M; k += TQ) buf[pad8(k)] = rok && k <= a.kmax ? src[k] : zero2<T>();
   }
@@ -553,17 +653,33 @@ __global__ __launch_bounds__((MHD ? 12 : 6) * RB * TQ) void k_x_prod(XArgs<T> a)
   // ---- inverse real FFTs, physical values back into the same slot
   {
     C2<T> v[EI::SLOTS];
-    EI::template run<LayPad8>(v, buf, 1, q, twl, 2, [&](int, int k) { return c2r_pre(buf, k, M, twl); });
+    EI::template run_tw<LayPad8>(v, buf, 1, q, twf, [&](int, int k) { return c2r_pre(buf, k, M, twl); },
+                                 in_act);
     __syncthreads();
+    if (in_act) {
 #pragma unroll
-    for (int s = 0; s < EI::LAST_NB * EI::RL_; ++s)
-      if (EI::last_valid(q, s)) buf[pad8(EI::last_index(q, s))] = v[s];
+      for (int s = 0; s < EI::LAST_NB * EI::RL_; ++s)
+        if (EI::last_valid(q, s)) buf[pad8(EI::last_index(q, s))] = v[s];
+    }
   }
   __syncthreads();
   // ---- products; each C2 holds two neighbouring grid points
   for (int i = tid; i < RB * M; i += NT) {
     const int r = i / M, n = i % M;
     auto at = [&](int ff) -> C2<T>& { return smem[(ff * RB + r) * LP + pad8(n)]; };
+    if constexpr (ELS) {
+      C2<T> zp[3], zm[3];
+#pragma unroll
+      for (int i3 = 0; i3 < 3; ++i3) {
+        zp[i3] = at(i3);
+        zm[i3] = at(3 + i3);
+      }
+#pragma unroll
+      for (int i3 = 0; i3 < 3; ++i3)
+#pragma unroll
+        for (int j3 = 0; j3 < 3; ++j3) at(3 * i3 + j3) = C2<T>{zp[i3].x * zm[j3].x, zp[i3].y * zm[j3].y};
+      continue;
+    }
     const C2<T> u0 = at(0), u1 = at(1), u2 = at(2);
     const C2<T> w0 = at(3), w1 = at(4), w2 = at(5);
     auto cx = [](C2<T> a1, C2<T> a2, C2<T> b1, C2<T> b2) {  // a1 b2 - a2 b1 per point
@@ -585,11 +701,12 @@ __global__ __launch_bounds__((MHD ? 12 : 6) * RB * TQ) void k_x_prod(XArgs<T> a)
     at(2) = n2;
   }
   __syncthreads();
-  // ---- forward real FFTs of the FOUT product fields (other groups idle on own slots)
+  // ---- forward real FFTs of the FOUT product fields; the other groups only
+  // join the barriers (with RB even their waves skip the work entirely)
   const bool active = f < FOUT;
   {
     C2<T> v[EF::SLOTS];
-    EF::template run<LayPad8>(v, buf, 1, q, twl, 2, [&](int, int n) { return buf[pad8(n)]; });
+    EF::template run_tw<LayPad8>(v, buf, 1, q, twf, [&](int, int n) { return buf[pad8(n)]; }, active);
     __syncthreads();
     if (active) {
 #pragma unroll
@@ -601,129 +718,6 @@ __global__ __launch_bounds__((MHD ? 12 : 6) * RB * TQ) void k_x_prod(XArgs<T> a)
   if (active && rok) {
     C2<T>* dst = a.out + boxi * a.out_bs + f * a.out_fs + rloc * a.out_pitch;
     for (int k = q; k <= M && k <= a.kmax; k += TQ) dst[k] = r2c_post(buf, k, M, twl);
-  }
-}
-
-// Fused product pass, register-resident variant: one group of TQ threads per
-// row transforms every field of that row in turn (inputs read straight from
-// global memory), keeps its own points of u (and b) in registers and
-// accumulates the cross products there; LDS only carries the FFT exchanges.
-// Reads all inputs of a row before writing any output (in place is safe).
-// Output fields: NS [u x w]; MHD [u x w + j x b, u x b].
-template <typename T, int M, int TQ, class RL, bool MHD, int RPW>
-__global__ __launch_bounds__(RPW* TQ) void k_x_prod2(XArgs<T> a) {
-  using EI = Stockham<T, M, TQ, INV, RL>;
-  using EF = Stockham<T, M, TQ, FWD, RL>;
-  constexpr int LP = row_slots(M);
-  constexpr int NO = EI::LAST_NB * EI::RL_;
-  constexpr bool DIRECT = EI::R1 == EI::RL_;  // last-stage slots == first-stage slots
-  __shared__ C2<T> smem[RPW * LP];
-  const int tid = threadIdx.x, g = tid / TQ, q = tid % TQ;
-  const long row = (long)xcd_remap(blockIdx.x, gridDim.x) * RPW + g;
-  const bool ok = row < a.rows * a.nb;
-  C2<T>* buf = smem + g * LP;
-  const long rr = ok ? row : 0;
-  const C2<T>* in = a.in + (rr / a.rows) * a.in_bs + (rr % a.rows) * a.in_pitch;
-  C2<T>* outp = a.out + (rr / a.rows) * a.out_bs + (rr % a.rows) * a.out_pitch;
-
-  // inverse real transform of input field f into this thread's point slots
-  auto inv = [&](int f, C2<T> (&dst)[NO]) {
-    const C2<T>* src = in + f * a.in_fs;
-    C2<T> v[EI::SLOTS];
-    EI::template run<LayPad8>(v, buf, 1, q, a.tw, 2, [&](int, int k) -> C2<T> {
-      if (!ok) return zero2<T>();
-      C2<T> xk, xm;
-      const int km = M - k;
-      if (k == 0) {
-        xk = C2<T>{src[0].x, T(0)};
-        xm = C2<T>{M <= a.kmax ? src[M].x : T(0), T(0)};
-      } else {
-        xk = k <= a.kmax ? src[k] : zero2<T>();
-        xm = km <= a.kmax ? conj(src[km]) : zero2<T>();
-      }
-      return (xk + xm) + mul_i(cmulc(xk - xm, a.tw[k]));
-    });
-#pragma unroll
-    for (int s = 0; s < NO; ++s) dst[s] = v[s];
-  };
-  // forward real transform of point values val(s) and store as output field fo
-  auto fwd = [&](int fo, auto&& val) {
-    C2<T> v[EF::SLOTS];
-    if constexpr (DIRECT) {
-      EF::template run<LayPad8>(v, buf, 1, q, a.tw, 2, [&](int s, int) { return val(s); });
-    } else {
-      __syncthreads();
-#pragma unroll
-      for (int s = 0; s < NO; ++s)
-        if (EI::last_valid(q, s)) buf[pad8(EI::last_index(q, s))] = val(s);
-      __syncthreads();
-      EF::template run<LayPad8>(v, buf, 1, q, a.tw, 2, [&](int, int n) { return buf[pad8(n)]; });
-    }
-    __syncthreads();
-#pragma unroll
-    for (int s = 0; s < EF::LAST_NB * EF::RL_; ++s)
-      if (EF::last_valid(q, s)) buf[pad8(EF::last_index(q, s))] = v[s];
-    __syncthreads();
-    if (ok) {
-      C2<T>* dst = outp + fo * a.out_fs;
-      for (int k = q; k <= M && k <= a.kmax; k += TQ) dst[k] = r2c_post(buf, k, M, a.tw);
-    }
-  };
-  // cross-product component c of (x, y) per pair of points
-  auto cx = [](C2<T> a1, C2<T> a2, C2<T> b1, C2<T> b2) {
-    return C2<T>{a1.x * b2.x - a2.x * b1.x, a1.y * b2.y - a2.y * b1.y};
-  };
-  auto cross_c = [&](int c, const C2<T> (&x)[3][NO], const C2<T> (&y)[3][NO], int s) {
-    const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
-    return cx(x[c1][s], x[c2][s], y[c1][s], y[c2][s]);
-  };
-
-  C2<T> U[3][NO], Nn[3][NO];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) inv(c, U[c]);
-#pragma unroll
-  for (int c = 0; c < 3; ++c)
-#pragma unroll
-    for (int s = 0; s < NO; ++s) Nn[c][s] = zero2<T>();
-  // n += sgn (x x w), one w component at a time: w_c enters
-  // (x x w)_{c+1} as +x_{c+2} w_c and (x x w)_{c+2} as -x_{c+1} w_c
-  auto acc_cross = [&](const C2<T> (&x)[3][NO], int c, const C2<T> (&wc)[NO], T sgn) {
-    const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
-#pragma unroll
-    for (int s = 0; s < NO; ++s) {
-      Nn[c1][s] = Nn[c1][s] + sgn * C2<T>{x[c2][s].x * wc[s].x, x[c2][s].y * wc[s].y};
-      Nn[c2][s] = Nn[c2][s] - sgn * C2<T>{x[c1][s].x * wc[s].x, x[c1][s].y * wc[s].y};
-    }
-  };
-  if constexpr (MHD) {
-    C2<T> Bf[3][NO];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) inv(6 + c, Bf[c]);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      C2<T> w[NO];
-      inv(3 + c, w);
-      acc_cross(U, c, w, T(1));  // u x w
-    }
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      C2<T> j[NO];
-      inv(9 + c, j);
-      acc_cross(Bf, c, j, T(-1));  // j x b = -(b x j)
-    }
-#pragma unroll
-    for (int c = 0; c < 3; ++c) fwd(c, [&](int s) { return Nn[c][s]; });
-#pragma unroll
-    for (int c = 0; c < 3; ++c) fwd(3 + c, [&](int s) { return cross_c(c, U, Bf, s); });
-  } else {
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      C2<T> w[NO];
-      inv(3 + c, w);
-      acc_cross(U, c, w, T(1));
-    }
-#pragma unroll
-    for (int c = 0; c < 3; ++c) fwd(c, [&](int s) { return Nn[c][s]; });
   }
 }
 

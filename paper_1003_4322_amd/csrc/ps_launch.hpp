@@ -31,16 +31,20 @@ int z_curl_tx(int N, int var);
 template <typename T>
 int z_epi_tx(int N, int var);
 
+// els: MHD in the Elsasser (divergence) form -- z_curl transforms z+- without
+// a curl, x_prod forms the nine products z+_i z-_j, z_epi takes their divergence
 template <typename T>
-hipError_t launch_z_curl(int N, bool mhd, int var, ZCurlArgs<T> a, const DiskTiles* dt, hipStream_t s);
+hipError_t launch_z_curl(int N, bool mhd, bool els, int var, ZCurlArgs<T> a, const DiskTiles* dt,
+                         hipStream_t s);
 template <typename T>
-hipError_t launch_z_epi(int N, bool mhd, int var, ZEpiArgs<T> a, const DiskTiles* dt, hipStream_t s);
+hipError_t launch_z_epi(int N, bool mhd, bool els, int var, ZEpiArgs<T> a, const DiskTiles* dt,
+                        hipStream_t s);
 template <typename T>
 hipError_t launch_x_c2r(int N, XArgs<T> a, hipStream_t s);
 template <typename T>
 hipError_t launch_x_r2c(int N, XArgs<T> a, hipStream_t s);
 template <typename T>
-hipError_t launch_x_prod(int N, bool mhd, int var, XArgs<T> a, hipStream_t s);
+hipError_t launch_x_prod(int N, bool mhd, bool els, int var, XArgs<T> a, hipStream_t s);
 template <typename T>
 hipError_t launch_spectrum(SpecArgs<T> a, double* spec, double* totals, hipStream_t s);
 

@@ -89,36 +89,41 @@ long z_grid(int N, int ntile, int nb, bool listed, const DiskTiles* dt, const in
   return (long)ntile * N * nb;
 }
 
-template <typename T, int N, int I, bool MHD>
+template <typename T, int N, int I, bool MHD, bool ELS = false>
 hipError_t z_curl_v(ZCurlArgs<T> a, const DiskTiles* dt, hipStream_t s) {
   constexpr ZV v = ZCURL_V[I];
   using LC = Sched<N, v.alt>;
   constexpr int TX = StridedTX<T, N, LC::TQ, v.sh>::value;
-  constexpr int SPLIT = MHD ? v.split : (v.split > 2 ? 2 : v.split);
+  constexpr int SPLIT = (MHD && !ELS) ? v.split : (v.split > 2 ? 2 : v.split);
   a.ntile = cdiv(N / 2 + 1, TX);
   const long grid = z_grid<TX>(N, a.ntile, a.nb, a.prune != 0, dt, a.tiles, a.ntl) * SPLIT;
-  k_z_curl<T, N, LC::TQ, TX, typename LC::RL, MHD, SPLIT, v.direct, waves_per_simd(v.minb, TX * LC::TQ)>
+  k_z_curl<T, N, LC::TQ, TX, typename LC::RL, MHD, SPLIT, v.direct, waves_per_simd(v.minb, TX * LC::TQ), ELS>
       <<<dim3((unsigned)grid), dim3(TX * LC::TQ), 0, s>>>(a);
   return hipGetLastError();
 }
 
+template <typename T, int N, int I>
+hipError_t z_curl_m(bool mhd, bool els, ZCurlArgs<T> a, const DiskTiles* dt, hipStream_t s) {
+  if (mhd && els) return z_curl_v<T, N, I, true, true>(a, dt, s);
+  return mhd ? z_curl_v<T, N, I, true>(a, dt, s) : z_curl_v<T, N, I, false>(a, dt, s);
+}
+
 template <typename T, int N>
-hipError_t z_curl_n(bool mhd, int var, ZCurlArgs<T> a, const DiskTiles* dt, hipStream_t s) {
+hipError_t z_curl_n(bool mhd, bool els, int var, ZCurlArgs<T> a, const DiskTiles* dt, hipStream_t s) {
   if constexpr (has_variants(N))
-    return pick(var, std::make_integer_sequence<int, NZCURL>{}, [&](auto I) {
-      constexpr int i = decltype(I)::value;
-      return mhd ? z_curl_v<T, N, i, true>(a, dt, s) : z_curl_v<T, N, i, false>(a, dt, s);
-    });
+    return pick(var, std::make_integer_sequence<int, NZCURL>{},
+                [&](auto I) { return z_curl_m<T, N, decltype(I)::value>(mhd, els, a, dt, s); });
   else
-    return mhd ? z_curl_v<T, N, 0, true>(a, dt, s) : z_curl_v<T, N, 0, false>(a, dt, s);
+    return z_curl_m<T, N, 0>(mhd, els, a, dt, s);
 }
 
 template <typename T>
-hipError_t launch_z_curl(int N, bool mhd, int var, ZCurlArgs<T> a, const DiskTiles* dt, hipStream_t s) {
+hipError_t launch_z_curl(int N, bool mhd, bool els, int var, ZCurlArgs<T> a, const DiskTiles* dt,
+                         hipStream_t s) {
   switch (N) {
 #define PS_CASE(NN) \
   case NN:          \
-    return z_curl_n<T, NN>(mhd, var, a, dt, s);
+    return z_curl_n<T, NN>(mhd, els, var, a, dt, s);
     PS_FOR_EACH_N(PS_CASE)
 #undef PS_CASE
   }
@@ -146,34 +151,40 @@ int z_curl_tx(int N, int var) {
 }
 
 // ---------------- forward z pass + epilogue ----------------
-template <typename T, int N, int I, bool MHD>
+template <typename T, int N, int I, bool MHD, bool ELS = false>
 hipError_t z_epi_v(ZEpiArgs<T> a, const DiskTiles* dt, hipStream_t s) {
   constexpr ZV v = ZEPI_V[I];
   using LC = Sched<N, v.alt>;
   constexpr int TX = StridedTX<T, N, LC::TQ, v.sh>::value;
   a.ntile = cdiv(N / 2 + 1, TX);
   const long grid = z_grid<TX>(N, a.ntile, a.nb, a.prune && a.mode != 0, dt, a.tiles, a.ntl);
-  k_z_epi<T, N, LC::TQ, TX, typename LC::RL, MHD, waves_per_simd(v.minb, TX * LC::TQ)><<<dim3((unsigned)grid), dim3(TX * LC::TQ), 0, s>>>(a);
+  k_z_epi<T, N, LC::TQ, TX, typename LC::RL, MHD, waves_per_simd(v.minb, TX * LC::TQ), ELS>
+      <<<dim3((unsigned)grid), dim3(TX * LC::TQ), 0, s>>>(a);
   return hipGetLastError();
 }
 
+template <typename T, int N, int I>
+hipError_t z_epi_m(bool mhd, bool els, ZEpiArgs<T> a, const DiskTiles* dt, hipStream_t s) {
+  if (mhd && els) return z_epi_v<T, N, I, true, true>(a, dt, s);
+  return mhd ? z_epi_v<T, N, I, true>(a, dt, s) : z_epi_v<T, N, I, false>(a, dt, s);
+}
+
 template <typename T, int N>
-hipError_t z_epi_n(bool mhd, int var, ZEpiArgs<T> a, const DiskTiles* dt, hipStream_t s) {
+hipError_t z_epi_n(bool mhd, bool els, int var, ZEpiArgs<T> a, const DiskTiles* dt, hipStream_t s) {
   if constexpr (has_variants(N))
-    return pick(var, std::make_integer_sequence<int, NZEPI>{}, [&](auto I) {
-      constexpr int i = decltype(I)::value;
-      return mhd ? z_epi_v<T, N, i, true>(a, dt, s) : z_epi_v<T, N, i, false>(a, dt, s);
-    });
+    return pick(var, std::make_integer_sequence<int, NZEPI>{},
+                [&](auto I) { return z_epi_m<T, N, decltype(I)::value>(mhd, els, a, dt, s); });
   else
-    return mhd ? z_epi_v<T, N, 0, true>(a, dt, s) : z_epi_v<T, N, 0, false>(a, dt, s);
+    return z_epi_m<T, N, 0>(mhd, els, a, dt, s);
 }
 
 template <typename T>
-hipError_t launch_z_epi(int N, bool mhd, int var, ZEpiArgs<T> a, const DiskTiles* dt, hipStream_t s) {
+hipError_t launch_z_epi(int N, bool mhd, bool els, int var, ZEpiArgs<T> a, const DiskTiles* dt,
+                        hipStream_t s) {
   switch (N) {
 #define PS_CASE(NN) \
   case NN:          \
-    return z_epi_n<T, NN>(mhd, var, a, dt, s);
+    return z_epi_n<T, NN>(mhd, els, var, a, dt, s);
     PS_FOR_EACH_N(PS_CASE)
 #undef PS_CASE
   }
@@ -220,46 +231,40 @@ hipError_t x_r2c_n(XArgs<T> a, hipStream_t s) {
 }
 
 template <typename T, int N, int I>
-hipError_t x_prod_v(bool mhd, XArgs<T> a, hipStream_t s) {
+hipError_t x_prod_v(bool mhd, bool els, XArgs<T> a, hipStream_t s) {
   constexpr XV v = XPROD_V[I];
-  if constexpr (v.kind == 0) {
-    using LC = Sched<N / 2, v.alt>;
-    using X = XCfg<T, N / 2, LC::TQ>;
-    if (mhd) {
-      if constexpr (X::MHD_OK) {
-        constexpr int RB = X::rb(12, v.rb_mhd);
-        const long grid = (a.rows * a.nb + RB - 1) / RB;
-        k_x_prod<T, N / 2, LC::TQ, RB, typename LC::RL, true>
-            <<<dim3((unsigned)grid), dim3(12 * RB * LC::TQ), 0, s>>>(a);
-        return hipGetLastError();
-      } else {
-        return hipErrorInvalidValue;
-      }
-    }
-    constexpr int RB = X::rb(6, v.rb_ns);
+  using LC = Sched<N / 2, v.alt>;
+  using X = XCfg<T, N / 2, LC::TQ>;
+  auto go = [&](auto mhd_c, auto els_c, auto rb_c) {
+    constexpr bool M_ = decltype(mhd_c)::value, E_ = decltype(els_c)::value;
+    constexpr int RB = decltype(rb_c)::value;
     const long grid = (a.rows * a.nb + RB - 1) / RB;
-    k_x_prod<T, N / 2, LC::TQ, RB, typename LC::RL, false><<<dim3((unsigned)grid), dim3(6 * RB * LC::TQ), 0, s>>>(a);
+    k_x_prod<T, N / 2, LC::TQ, RB, typename LC::RL, M_, E_>
+        <<<dim3((unsigned)grid), dim3(xprod_slots(M_, E_) * RB * LC::TQ), 0, s>>>(a);
     return hipGetLastError();
-  } else {
-    using LC = std::conditional_t<v.kind == 1, LenXA<N / 2>, LenXB<N / 2>>;
-    constexpr int RPW0 = v.rb_mhd;
-    constexpr int RPW = (RPW0 * LC::TQ > 1024) ? 1024 / LC::TQ : RPW0;
-    const long grid = (a.rows * a.nb + RPW - 1) / RPW;
-    if (mhd)
-      k_x_prod2<T, N / 2, LC::TQ, typename LC::RL, true, RPW><<<dim3((unsigned)grid), dim3(RPW * LC::TQ), 0, s>>>(a);
-    else
-      k_x_prod2<T, N / 2, LC::TQ, typename LC::RL, false, RPW><<<dim3((unsigned)grid), dim3(RPW * LC::TQ), 0, s>>>(a);
-    return hipGetLastError();
+  };
+  using t_ = std::true_type;
+  using f_ = std::false_type;
+  if (mhd && els) {
+    if constexpr (X::fits(9, 1))
+      return go(t_{}, t_{}, std::integral_constant<int, X::rb(9, v.rb_mhd)>{});
+    return hipErrorInvalidValue;
   }
+  if (mhd) {
+    if constexpr (X::MHD_OK)
+      return go(t_{}, f_{}, std::integral_constant<int, X::rb(12, v.rb_mhd)>{});
+    return hipErrorInvalidValue;
+  }
+  return go(f_{}, f_{}, std::integral_constant<int, X::rb(6, v.rb_ns)>{});
 }
 
 template <typename T, int N>
-hipError_t x_prod_n(bool mhd, int var, XArgs<T> a, hipStream_t s) {
+hipError_t x_prod_n(bool mhd, bool els, int var, XArgs<T> a, hipStream_t s) {
   if constexpr (has_variants(N))
     return pick(var, std::make_integer_sequence<int, NXPROD>{},
-                [&](auto I) { return x_prod_v<T, N, decltype(I)::value>(mhd, a, s); });
+                [&](auto I) { return x_prod_v<T, N, decltype(I)::value>(mhd, els, a, s); });
   else
-    return x_prod_v<T, N, 0>(mhd, a, s);
+    return x_prod_v<T, N, 0>(mhd, els, a, s);
 }
 
 template <typename T>
@@ -299,11 +304,11 @@ hipError_t launch_x_r2c(int N, XArgs<T> a, hipStream_t s) {
 }
 
 template <typename T>
-hipError_t launch_x_prod(int N, bool mhd, int var, XArgs<T> a, hipStream_t s) {
+hipError_t launch_x_prod(int N, bool mhd, bool els, int var, XArgs<T> a, hipStream_t s) {
   switch (N) {
 #define PS_CASE(NN) \
   case NN:          \
-    return x_prod_n<T, NN>(mhd, var, a, s);
+    return x_prod_n<T, NN>(mhd, els, var, a, s);
     PS_FOR_EACH_N(PS_CASE)
 #undef PS_CASE
   }

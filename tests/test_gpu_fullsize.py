@@ -50,10 +50,11 @@ SAMPLE = [(0, 1, 0), (3, 2, 1), (5, 507, 4), (17, 30, 501), (40, 2, 9), (2, 100,
           (60, 60, 60), (1, 511, 511), (113, 0, 0), (9, 9, 500)]
 
 
+@pytest.mark.parametrize("form", [0, 1])
 @pytest.mark.parametrize("dt", ["f32", "f64"])
-def test_mhd512_nonlinear_sampled(B, ref, dt):
+def test_mhd512_nonlinear_sampled(B, ref, dt, form):
     N = 512
-    say("mhd512 nonlinear sampled", dt)
+    say("mhd512 nonlinear sampled", dt, form)
     cdt = torch.complex64 if dt == "f32" else torch.complex128
     sf = synth.mhd_sparse(N, 3, 4, 3.0)
     if dt == "f32":
@@ -61,6 +62,7 @@ def test_mhd512_nonlinear_sampled(B, ref, dt):
     z = sparse_to_dev(sf, cdt)
     p = B.Plan(N, 6, dt)
     p.set_variant("prune", 1)
+    p.set_variant("form", form)
     say("autotune", p.autotune(z, B.PS_MHD, 2))
     out = p.nonlinear_mhd(z)
     kx = np.array([s[0] for s in SAMPLE]); ky = np.array([s[1] for s in SAMPLE])
@@ -74,11 +76,11 @@ def test_mhd512_nonlinear_sampled(B, ref, dt):
     del out, z
 
 
-@pytest.mark.parametrize("case", [("mhd", 512, "f64"), ("mhd", 512, "f32"), ("ns", 1024, "f32"),
-                                  ("ns", 1024, "f64")])
+@pytest.mark.parametrize("case", [("mhd", 512, "f64", 0), ("mhd", 512, "f32", 0), ("mhd", 512, "f64", 1),
+                                  ("mhd", 512, "f32", 1), ("ns", 1024, "f32", 0), ("ns", 1024, "f64", 0)])
 def test_rk2_embedding(B, ref, case):
-    model, N, dt = case
-    say("embedding", model, N, dt)
+    model, N, dt, form = case
+    say("embedding", model, N, dt, form)
     cdt = torch.complex64 if dt == "f32" else torch.complex128
     K, n0 = 4, 64
     if model == "mhd":
@@ -96,6 +98,8 @@ def test_rk2_embedding(B, ref, case):
     z = sparse_to_dev(big, cdt)
     p = B.Plan(N, nf, dt)
     p.set_variant("prune", 1)
+    if model == "mhd":
+        p.set_variant("form", form)
     say("autotune", p.autotune(z, pm, 2))
     p.rk2_step(z, pm, nu, eta, dtime, steps)
     Kc = 4 * K  # support after two steps

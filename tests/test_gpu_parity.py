@@ -74,14 +74,18 @@ def test_nonlinear_ns(B, ref, N, dt, prune):
     assert rel_l2_w(got, want) < TOL_NL[dt], rel_l2_w(got, want)
 
 
+@pytest.mark.parametrize("form", [0, 1])
 @pytest.mark.parametrize("prune", [0, 1])
 @pytest.mark.parametrize("dt", ["f64", "f32"])
 @pytest.mark.parametrize("N", [8, 16, 24, 32, 48])
-def test_nonlinear_mhd(B, ref, N, dt, prune):
-    say("nonlinear_mhd", N, dt, prune)
+def test_nonlinear_mhd(B, ref, N, dt, prune, form):
+    """form 1 (Elsasser divergence form) against the oracle's rotational form:
+    equal up to rounding for the solenoidal inputs used here."""
+    say("nonlinear_mhd", N, dt, prune, form)
     z = rounded(synth.random_mhd(N, 2000 + N, 3000 + N, 2.0), dt)
     p = B.Plan(N, 6, dt)
     p.set_variant("prune", prune)
+    p.set_variant("form", form)
     out = torch.full(z.shape, 1e30, dtype=CDT[dt], device=DEV)
     got = host(p.nonlinear_mhd(to_dev(z, dt), out))
     want = ref.nonlinear_mhd(z)
@@ -106,16 +110,18 @@ def test_rk2_ns_32_one_step(B, ref, dt, prune):
     assert inc < (1e-10 if dt == "f64" else 1e-3), inc
 
 
+@pytest.mark.parametrize("form", [0, 1])
 @pytest.mark.parametrize("prune", [0, 1])
 @pytest.mark.parametrize("dt", ["f64", "f32"])
 @pytest.mark.parametrize("graphs", [True, False])
-def test_rk2_mhd_steps(B, ref, dt, graphs, prune):
-    say("rk2 mhd 24", dt, graphs, prune)
+def test_rk2_mhd_steps(B, ref, dt, graphs, prune, form):
+    say("rk2 mhd 24", dt, graphs, prune, form)
     N = 24
     z0 = rounded(synth.random_mhd(N, 3, 4, 2.0), dt)
     p = B.Plan(N, 6, dt)
     p.set_graphs(graphs)
     p.set_variant("prune", prune)
+    p.set_variant("form", form)
     s = to_dev(z0, dt)
     p.rk2_step(s, B.PS_MHD, 0.02, 0.01, 2e-3, 3)
     got = host(s)

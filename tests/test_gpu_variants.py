@@ -73,16 +73,18 @@ def test_nonlinear_ns_variants(B, ns_case, kind, dt, prune):
         assert e < TOL_NL[dt], (kind, v, e)
 
 
+@pytest.mark.parametrize("form", [0, 1])
 @pytest.mark.parametrize("prune", [0, 1])
 @pytest.mark.parametrize("dt", ["f32", "f64"])
 @pytest.mark.parametrize("kind", ["y", "z_curl", "x_prod", "z_epi"])
-def test_nonlinear_mhd_variants(B, mhd_case, kind, dt, prune):
+def test_nonlinear_mhd_variants(B, mhd_case, kind, dt, prune, form):
     z, want = mhd_case[dt]
     p = B.Plan(N, 6, dt)
     p.set_variant("prune", prune)
+    p.set_variant("form", form)
     zd = to_dev(z, dt)
     for v in range(p.variant_count(kind)):
-        say("mhd variant", kind, v, dt, prune)
+        say("mhd variant", kind, v, dt, prune, form)
         p.set_variant(kind, v)
         e = rel_l2_w(host(p.nonlinear_mhd(zd)), want)
         assert e < TOL_NL[dt], (kind, v, e)
