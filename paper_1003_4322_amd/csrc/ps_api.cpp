@@ -348,7 +348,8 @@ struct Seq {
     if (!strcmp(kind, "z_curl")) return pass_zcurl(state, mhd);
     if (!strcmp(kind, "y")) return ypass(work(), b.P, wk_bs(), nphys(mhd), ps::INV, p->prune ? 1 : 0);
     if (!strcmp(kind, "x_prod")) return pass_xprod(mhd);
-    if (!strcmp(kind, "z_epi")) return pass_zepi(mhd, 0, zstar(), nullptr, nullptr, T(0), T(0), T(0));
+    // as in the step's first stage (mode 1: pruned like the step, z* <- state)
+    if (!strcmp(kind, "z_epi")) return pass_zepi(mhd, 1, zstar(), state, nullptr, T(0), T(0), T(0));
     return fail(PS_ERR_ARG, std::string("no tuning launch for kind ") + kind);
   }
 
@@ -614,8 +615,8 @@ ps_status ps_plan_create_batch(ps_plan* out, int nbox, const int* Ns, int nfield
     }
     if (any_var) {
       p->var["z_curl"] = 0;
-      p->var["z_epi"] = 1;
-      p->var["x_prod"] = dtype == PS_F32 ? 1 : 2;
+      p->var["z_epi"] = nfields == 6 ? 5 : 1;  // MHD (Elsasser): z+ and z- in two workgroups
+      p->var["x_prod"] = nfields == 6 ? 0 : dtype == PS_F32 ? 1 : 2;
       p->var["y"] = dtype == PS_F32 ? 2 : 0;
     }
     e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);

@@ -98,7 +98,8 @@ struct XCfg {
 // schedule.
 struct ZV {
   int sh;       // tile width shift
-  int split;    // z_curl: workgroups per tile sharing the output groups (1, 2 or 4; NS caps at 2)
+  int split;    // z_curl: workgroups per tile sharing the output groups (1, 2 or 4; NS caps at 2);
+                // z_epi: 2 = z+ and z- updated by two workgroups (Elsasser form only)
   int minb;     // workgroups per CU the register allocator must leave room for (1: no request)
   bool alt;     // radix-16 schedule
   bool direct;  // z_curl: gather inputs per output field instead of holding them in registers
@@ -109,8 +110,8 @@ struct XV {
 };
 constexpr ZV ZCURL_V[] = {{1, 1, 1, false, false}, {1, 2, 1, false, false}, {1, 2, 2, false, false},
                           {1, 2, 1, true, false},  {1, 1, 1, false, true}};
-constexpr ZV ZEPI_V[] = {{0, 1, 1, false}, {1, 1, 1, false}, {1, 1, 2, false}, {2, 1, 4, false},
-                         {1, 1, 1, true},  {2, 1, 8, true},  {2, 1, 1, false}, {2, 1, 3, false}};
+constexpr ZV ZEPI_V[] = {{0, 1, 1, false}, {1, 1, 1, false}, {1, 1, 2, false}, {1, 1, 1, true},
+                         {2, 1, 1, false}, {1, 2, 1, false}, {1, 2, 2, false}, {2, 2, 1, false}};
 constexpr ZV STR_V[] = {{0, 1, 1, false}, {1, 1, 1, false}, {0, 1, 1, true}, {1, 1, 1, true}};
 constexpr XV XPROD_V[] = {{2, 1, false}, {4, 2, false}, {4, 2, true}, {2, 1, true}};
 constexpr int NZCURL = sizeof(ZCURL_V) / sizeof(ZV);

@@ -42,6 +42,9 @@ __device__ __forceinline__ C2<T> conj(C2<T> a) { return C2<T>{a.x, -a.y}; }
 // multiply by +i and -i
 template <typename T>
 __device__ __forceinline__ C2<T> mul_i(C2<T> a) { return C2<T>{-a.y, a.x}; }
+// c ? x : y on values
+template <typename T>
+__device__ __forceinline__ C2<T> sel(bool c, C2<T> x, C2<T> y) { return c ? x : y; }
 template <typename T>
 __device__ __forceinline__ C2<T> mul_mi(C2<T> a) { return C2<T>{a.y, -a.x}; }
 template <typename T>

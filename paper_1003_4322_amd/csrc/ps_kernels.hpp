@@ -335,17 +335,20 @@ struct ZEpiArgs {
 //   N+ = -i D(k) P(k) a / N^3,  N- = -i D(k) P(k) c / N^3,
 // the divergence form of -(z-+ . grad) z+-, equal to the form above for
 // solenoidal z+-.  a and c are accumulated field by field.
-template <typename T, int L, int TQ, int TX, class RL, bool MHD, int MINW = 1, bool ELS = false>
+template <typename T, int L, int TQ, int TX, class RL, bool MHD, int MINW = 1, bool ELS = false, int SPLIT = 1>
 __global__ __launch_bounds__(TX* TQ, MINW) void k_z_epi(ZEpiArgs<T> a) {
   using E = Stockham<T, L, TQ, FWD, RL>;
   static_assert(!ELS || MHD, "the Elsasser form is MHD only");
-  constexpr int NF = MHD ? 6 : 3;
+  static_assert(SPLIT == 1 || (ELS && SPLIT == 2), "only the Elsasser form splits z+ from z-");
+  constexpr int NF = MHD ? 6 : 3;       // state fields
+  constexpr int NOUT = NF / SPLIT;      // state fields this workgroup updates
   constexpr int NO = E::LAST_NB * E::RL_;
   using CT = ColTile<T, L, TX, 0>;
   constexpr bool TWL = CT::TW_FITS;
   __shared__ C2<T> smem[CT::ROWS * TX + (TWL ? L : 0)];
   const int tid = threadIdx.x, c = tid % TX, q = tid / TX;
-  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int blk0 = xcd_remap(blockIdx.x, gridDim.x);
+  const int part = blk0 % SPLIT, blk = blk0 / SPLIT;  // part 0: z+ (a), part 1: z- (c)
   const int N = L;
   const ZTile zt = z_tile(blk, a.ntile, N, a.prune && a.mode != 0 ? a.tiles : nullptr, a.ntl);
   const int tile = zt.tile, ky = zt.ky, box = zt.box;
@@ -366,53 +369,74 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_z_epi(ZEpiArgs<T> a) {
     else
       return TwTable<T>{a.tw, 1};
   }();
+  // first-stage loader of input field f
+  auto ld_of = [&](int f) {
+    return [&, f](int, int idx) { return ok && disk ? in[f * a.in_fs + idx * in_es] : zero2<T>(); };
+  };
 
-  C2<T> r[NF][NO];
+  // NS / rotational MHD: r[f] = transformed input field f.
+  // Elsasser: r[0..2] = a (unsplit or part 0), r[3..5] = c (unsplit); with
+  // SPLIT = 2, part 1 keeps c in r[0..2].
+  constexpr int NR = ELS ? 3 * (2 / SPLIT) : NF;
+  C2<T> r[NR][NO];
   if constexpr (ELS) {
-    // r[0..2] = a, r[3..5] = c.  The loop over i is kept rolled (a_i is
-    // gathered in acc and moved to its place at the end of each row) so that
-    // the compiler does not stretch the nine transforms' loads across each
-    // other and run out of registers.
     const T kxd0 = (T)dwavx(col, N), kyd0 = (T)dwav(ky, N);
 #pragma unroll
-    for (int f = 0; f < NF; ++f)
+    for (int f = 0; f < NR; ++f)
 #pragma unroll
       for (int s = 0; s < NO; ++s) r[f][s] = zero2<T>();
+    if constexpr (SPLIT == 1) {
+      // the loop over i stays rolled (a_i gathers in acc and moves to its
+      // place after each row) so that the nine transforms' loads are not
+      // stretched across each other
 #pragma unroll 1
-    for (int i3 = 0; i3 < 3; ++i3) {
-      C2<T> acc[NO];
+      for (int i3 = 0; i3 < 3; ++i3) {
+        C2<T> acc[NO];
 #pragma unroll
-      for (int s = 0; s < NO; ++s) acc[s] = zero2<T>();
+        for (int s = 0; s < NO; ++s) acc[s] = zero2<T>();
 #pragma unroll
-      for (int j3 = 0; j3 < 3; ++j3) {
-        const int f = 3 * i3 + j3;
+        for (int j3 = 0; j3 < 3; ++j3) {
+          C2<T> v[E::SLOTS];
+          E::template run_tw<typename CT::Lay>(v, smem + c, TX, q, tw, ld_of(3 * i3 + j3));
+#pragma unroll
+          for (int s = 0; s < NO; ++s) {
+            const T kzd0 = (T)dwav(E::last_index(q, s), N);
+            const T kj = j3 == 0 ? kxd0 : j3 == 1 ? kyd0 : kzd0;
+            const T ki = i3 == 0 ? kxd0 : i3 == 1 ? kyd0 : kzd0;
+            acc[s] = acc[s] + kj * v[s];
+            r[3 + j3][s] = r[3 + j3][s] + ki * v[s];
+          }
+        }
+#pragma unroll
+        for (int s = 0; s < NO; ++s) {
+          r[0][s] = i3 == 0 ? acc[s] : r[0][s];
+          r[1][s] = i3 == 1 ? acc[s] : r[1][s];
+          r[2][s] = i3 == 2 ? acc[s] : r[2][s];
+        }
+      }
+    } else {
+      // part 0: a_i = sum_j k_j T_ij;  part 1: c_j = sum_i k_i T_ij
+#pragma unroll 1
+      for (int f = 0; f < 9; ++f) {
+        const int i3 = f / 3, j3 = f % 3;
+        const int t = part == 0 ? i3 : j3, m = part == 0 ? j3 : i3;
         C2<T> v[E::SLOTS];
-        E::template run_tw<typename CT::Lay>(v, smem + c, TX, q, tw, [&](int, int idx) {
-          return ok && disk ? in[f * a.in_fs + idx * in_es] : zero2<T>();
-        });
+        E::template run_tw<typename CT::Lay>(v, smem + c, TX, q, tw, ld_of(f));
 #pragma unroll
         for (int s = 0; s < NO; ++s) {
           const T kzd0 = (T)dwav(E::last_index(q, s), N);
-          const T kj = j3 == 0 ? kxd0 : j3 == 1 ? kyd0 : kzd0;
-          const T ki = i3 == 0 ? kxd0 : i3 == 1 ? kyd0 : kzd0;
-          acc[s] = acc[s] + kj * v[s];
-          r[3 + j3][s] = r[3 + j3][s] + ki * v[s];
+          const T km = m == 0 ? kxd0 : m == 1 ? kyd0 : kzd0;
+          r[0][s] = r[0][s] + (t == 0 ? km : T(0)) * v[s];
+          r[1][s] = r[1][s] + (t == 1 ? km : T(0)) * v[s];
+          r[2][s] = r[2][s] + (t == 2 ? km : T(0)) * v[s];
         }
-      }
-#pragma unroll
-      for (int s = 0; s < NO; ++s) {
-        r[0][s] = i3 == 0 ? acc[s] : r[0][s];
-        r[1][s] = i3 == 1 ? acc[s] : r[1][s];
-        r[2][s] = i3 == 2 ? acc[s] : r[2][s];
       }
     }
   } else {
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
       C2<T> v[E::SLOTS];
-      E::template run_tw<typename CT::Lay>(v, smem + c, TX, q, tw, [&](int, int idx) {
-        return ok && disk ? in[f * a.in_fs + idx * in_es] : zero2<T>();
-      });
+      E::template run_tw<typename CT::Lay>(v, smem + c, TX, q, tw, ld_of(f));
 #pragma unroll
       for (int s = 0; s < NO; ++s) r[f][s] = v[s];
     }
@@ -433,11 +457,11 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_z_epi(ZEpiArgs<T> a) {
     const bool keep = k2i > 0 && sphere;
     const T k2 = (T)k2i;
     const T kx = (T)ikx, ky_ = (T)iky, kz = (T)ikz;
-    C2<T> nh[NF];
+    C2<T> nh[NOUT];
     if constexpr (ELS) {
       const T ik2 = keep ? T(1) / k2 : T(0);
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
+      for (int h = 0; h < NOUT / 3; ++h) {
         // -i P(k) applied to the accumulated divergence, scaled
         C2<T> n0 = a.scale * r[3 * h][s], n1 = a.scale * r[3 * h + 1][s], n2 = a.scale * r[3 * h + 2][s];
         const C2<T> kn = kx * n0 + ky_ * n1 + kz * n2;
@@ -465,30 +489,36 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_z_epi(ZEpiArgs<T> a) {
       }
     } else {
 #pragma unroll
-      for (int f = 0; f < NF; ++f) nh[f] = zero2<T>();
+      for (int f = 0; f < NOUT; ++f) nh[f] = zero2<T>();
     }
     const long pos = base + kzi * out_es;
+    const int fo0 = part * NOUT;  // first state field written here
     if (a.mode == 0) {
 #pragma unroll
-      for (int f = 0; f < NF; ++f) a.out[f * a.out_fs + pos] = nh[f];
+      for (int f = 0; f < NOUT; ++f) a.out[(fo0 + f) * a.out_fs + pos] = nh[f];
     } else {
       const C2<T>* zv = a.mode == 1 ? a.st0 : a.st1;  // field the viscous term acts on
-      C2<T> zz[NF], z0[NF];
+      C2<T> zz[NF];
 #pragma unroll
-      for (int f = 0; f < NF; ++f) {
-        zz[f] = zv[f * a.out_fs + pos];
-        z0[f] = a.mode == 1 ? zz[f] : a.st0[f * a.out_fs + pos];
-      }
+      for (int f = 0; f < NF; ++f) zz[f] = zv[f * a.out_fs + pos];
       C2<T>* dst = a.mode == 1 ? a.out : const_cast<C2<T>*>(a.st0);
 #pragma unroll
-      for (int f = 0; f < NF; ++f) {
-        C2<T> vis = (a.nua * k2) * zz[f];
-        if constexpr (MHD) vis = vis + (a.nub * k2) * zz[f < 3 ? f + 3 : f - 3];
-        dst[f * a.out_fs + pos] = z0[f] + a.h * (nh[f] - vis);
+      for (int f = 0; f < NOUT; ++f) {
+        // this field and (MHD) its Elsasser partner, with static indices
+        // (choices by value: a conditional between lvalues makes the compiler
+        // select an address, which puts zz in scratch memory)
+        const C2<T> self = sel(SPLIT == 2 && part == 1, zz[(f + 3) % NF], zz[f]);
+        const C2<T> z0 = a.mode == 1 ? self : C2<T>(a.st0[(fo0 + f) * a.out_fs + pos]);
+        C2<T> vis = (a.nua * k2) * self;
+        if constexpr (MHD) {
+          const C2<T> other = SPLIT == 2 ? sel(part == 1, zz[f], zz[(f + 3) % NF]) : zz[f < 3 ? f + 3 : f - 3];
+          vis = vis + (a.nub * k2) * other;
+        }
+        dst[(fo0 + f) * a.out_fs + pos] = z0 + a.h * (nh[f] - vis);
       }
     }
-    // one mode at a time: keeps the scheduler from computing every slot's
-    // results before storing any (which costs ~100 registers for MHD)
+    // one mode at a time, so the scheduler does not hold every mode's
+    // results in registers before the first store
     __builtin_amdgcn_sched_barrier(0);
   }
 }

@@ -156,9 +156,10 @@ hipError_t z_epi_v(ZEpiArgs<T> a, const DiskTiles* dt, hipStream_t s) {
   constexpr ZV v = ZEPI_V[I];
   using LC = Sched<N, v.alt>;
   constexpr int TX = StridedTX<T, N, LC::TQ, v.sh>::value;
+  constexpr int SPLIT = ELS && v.split >= 2 ? 2 : 1;
   a.ntile = cdiv(N / 2 + 1, TX);
-  const long grid = z_grid<TX>(N, a.ntile, a.nb, a.prune && a.mode != 0, dt, a.tiles, a.ntl);
-  k_z_epi<T, N, LC::TQ, TX, typename LC::RL, MHD, waves_per_simd(v.minb, TX * LC::TQ), ELS>
+  const long grid = z_grid<TX>(N, a.ntile, a.nb, a.prune && a.mode != 0, dt, a.tiles, a.ntl) * SPLIT;
+  k_z_epi<T, N, LC::TQ, TX, typename LC::RL, MHD, waves_per_simd(v.minb, TX * LC::TQ), ELS, SPLIT>
       <<<dim3((unsigned)grid), dim3(TX * LC::TQ), 0, s>>>(a);
   return hipGetLastError();
 }
