@@ -635,9 +635,43 @@ int psref_nonlinear_at(int N, int model, const double *fhat, int nk, const int *
 /*   z* = z^n + (dt/2) F(z^n),   z^{n+1} = z^n + dt F(z*)                    */
 /* F(u) = N(u) - nu |k|^2 u (NS);  for MHD in Elsasser variables             */
 /* F(z+-) = N+-(z) - (nu+eta)/2 |k|^2 z+- - (nu-eta)/2 |k|^2 z-+.            */
+/* Rotation (Sec. 5 says the code includes it; no equation is given): in a   */
+/* frame rotating at Omega the momentum equation gains the Coriolis         */
+/* acceleration -2 Omega x u, the centrifugal part going into the pressure; */
+/* projected like every other term, P(k) at k = 0 read as 0, applied to     */
+/* every mode (a linear term, like the viscous one).  For MHD it acts on    */
+/* u = (z+ + z-)/2 and so enters both Elsasser equations; b is untouched.   */
 /* ------------------------------------------------------------------------ */
 
-static int rhs(int N, int model, const cplx *z, cplx *F, double nu, double eta) {
+/* F -= P(k) (2 Omega x u) at every mode, u the velocity of state z */
+static void coriolis(int N, int model, const cplx *z, cplx *F, const double *om) {
+  const long H = N / 2 + 1, nc = (long)N * N * H;
+  const double f = MUT(14) ? 1.0 : 2.0;
+#pragma omp parallel for schedule(static)
+  for (long kz = 0; kz < N; ++kz)
+    for (long ky = 0; ky < N; ++ky)
+      for (long kx = 0; kx < H; ++kx) {
+        long m = (kz * N + ky) * H + kx;
+        long ix = wavx(kx), iy = wav(ky, N), iz = wav(kz, N);
+        long k2 = ix * ix + iy * iy + iz * iz;
+        if (k2 == 0) continue;
+        cplx u[3];
+        for (int c = 0; c < 3; ++c)
+          u[c] = model == 0 ? z[c * nc + m] : 0.5 * (z[c * nc + m] + z[(3 + c) * nc + m]);
+        cplx a[3] = {f * (om[1] * u[2] - om[2] * u[1]), f * (om[2] * u[0] - om[0] * u[2]),
+                     f * (om[0] * u[1] - om[1] * u[0])};
+        double kk[3] = {(double)ix, (double)iy, (double)iz};
+        cplx ka = kk[0] * a[0] + kk[1] * a[1] + kk[2] * a[2];
+        if (MUT(13)) ka = 0;
+        for (int c = 0; c < 3; ++c) {
+          cplx pa = a[c] - kk[c] * ka / (double)k2;
+          F[c * nc + m] -= pa;
+          if (model == 1) F[(3 + c) * nc + m] -= pa;
+        }
+      }
+}
+
+static int rhs(int N, int model, const cplx *z, cplx *F, double nu, double eta, const double *om) {
   const long H = N / 2 + 1, nc = (long)N * N * H;
   int rc = model == 0 ? psref_nonlinear_ns(N, (const double *)z, (double *)F)
                       : psref_nonlinear_mhd(N, (const double *)z, (double *)F);
@@ -661,11 +695,17 @@ static int rhs(int N, int model, const cplx *z, cplx *F, double nu, double eta) 
           }
         }
       }
+  if (om && (om[0] != 0 || om[1] != 0 || om[2] != 0)) coriolis(N, model, z, F, om);
   return 0;
 }
 
 int psref_rk2_step(int N, int model, double *state_, double nu, double eta, double dt,
                    int nsteps) {
+  return psref_rk2_step_rot(N, model, state_, nu, eta, dt, nsteps, NULL);
+}
+
+int psref_rk2_step_rot(int N, int model, double *state_, double nu, double eta, double dt,
+                       int nsteps, const double *omega) {
   if (!state_ || nsteps < 0 || (model != 0 && model != 1)) return -1;
   if (!size_ok(N)) return -2;
   const long nf = model == 0 ? 3 : 6;
@@ -679,10 +719,10 @@ int psref_rk2_step(int N, int model, double *state_, double nu, double eta, doub
     goto done;
   }
   for (int s = 0; s < nsteps; ++s) {
-    if ((rc = rhs(N, model, z, F, nu, eta))) goto done;
+    if ((rc = rhs(N, model, z, F, nu, eta, omega))) goto done;
 #pragma omp parallel for schedule(static)
     for (long m = 0; m < n; ++m) zs[m] = z[m] + (MUT(11) ? 1.0 : 0.5) * dt * F[m];
-    if ((rc = rhs(N, model, MUT(5) ? z : zs, F, nu, eta))) goto done;
+    if ((rc = rhs(N, model, MUT(5) ? z : zs, F, nu, eta, omega))) goto done;
 #pragma omp parallel for schedule(static)
     for (long m = 0; m < n; ++m) z[m] = z[m] + dt * F[m];
   }

@@ -74,6 +74,12 @@ int psref_nonlinear_at(int N, int model, const double *fhat, int nk,
 int psref_rk2_step(int N, int model, double *state, double nu, double eta,
                    double dt, int nsteps);
 
+/* The same in a frame rotating at omega[3] (NULL or all zero: no rotation):
+ * the momentum equation gains -P(k) (2 Omega x u) at every k != 0 (for MHD
+ * with u = (z+ + z-)/2, added to both Elsasser fields). */
+int psref_rk2_step_rot(int N, int model, double *state, double nu, double eta,
+                       double dt, int nsteps, const double *omega);
+
 /* Number of spectral shells: s(3 (N/2)^2) + 1. */
 int psref_num_shells(int N);
 

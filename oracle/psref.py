@@ -61,6 +61,8 @@ class Oracle:
                                          ip, dp]
         L.psref_rk2_step.argtypes = [ctypes.c_int, ctypes.c_int, dp, ctypes.c_double,
                                      ctypes.c_double, ctypes.c_double, ctypes.c_int]
+        L.psref_rk2_step_rot.argtypes = [ctypes.c_int, ctypes.c_int, dp, ctypes.c_double,
+                                         ctypes.c_double, ctypes.c_double, ctypes.c_int, dp]
         L.psref_num_shells.argtypes = [ctypes.c_int]
         L.psref_energy_spectrum.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp]
 
@@ -155,13 +157,20 @@ class Oracle:
         return out
 
     def rk2_step(self, state: np.ndarray, model: int, nu: float, eta: float, dt: float,
-                 nsteps: int = 1) -> np.ndarray:
-        """Returns a new array (the argument is not modified)."""
+                 nsteps: int = 1, omega=None) -> np.ndarray:
+        """Returns a new array (the argument is not modified).  omega: the
+        frame's rotation vector (Coriolis term), or None."""
         N = state.shape[-2]
         nf = 3 if model == NS else 6
         z = self._spec(state, N, nf).copy()
-        self._check(self.lib.psref_rk2_step(N, model, self._p(z), float(nu), float(eta),
-                                            float(dt), int(nsteps)), "rk2_step")
+        if omega is None:
+            rc = self.lib.psref_rk2_step(N, model, self._p(z), float(nu), float(eta), float(dt),
+                                         int(nsteps))
+        else:
+            om = np.ascontiguousarray(omega, dtype=np.float64).reshape(3)
+            rc = self.lib.psref_rk2_step_rot(N, model, self._p(z), float(nu), float(eta),
+                                             float(dt), int(nsteps), self._p(om))
+        self._check(rc, "rk2_step")
         return z
 
     def num_shells(self, N: int) -> int:

@@ -458,4 +458,64 @@ def pin_spectrum_generator_shape(o):
     assert abs(tot[0] - 0.5) < 1e-14
 
 
+def _helical_mode(N: int, k, s: int):
+    """One helical Fourier mode h e^{ik.x} + c.c. (kx > 0), h = e1 + i s e2 with
+    e1 perpendicular to k and e2 = k^ x e1, so that k^ x h = -i s h and
+    curl u = s|k| u (a Beltrami field: u x w = 0 pointwise)."""
+    kv = np.array(k, dtype=np.float64)
+    kh = kv / np.linalg.norm(kv)
+    t = np.array([1.0, 0.0, 0.0]) if abs(kh[0]) < 0.9 else np.array([0.0, 1.0, 0.0])
+    e1 = np.cross(kh, t)
+    e1 /= np.linalg.norm(e1)
+    e2 = np.cross(kh, e1)
+    h = e1 + 1j * s * e2
+    U = np.zeros((3, N, N, N // 2 + 1), np.complex128)
+    U[:, k[2] % N, k[1] % N, k[0]] = h
+    return U, kh
+
+
+def _rk2_factor(lam: complex, dt: float) -> complex:
+    """Midpoint RK2 applied to u' = lam u multiplies u by 1 + x + x^2/2, x = lam dt."""
+    x = lam * dt
+    return 1 + x + x * x / 2
+
+
+def pin_rk2_rotation_inertial_wave(o):
+    """Rotation: a helical mode has no nonlinear term and is an eigenvector of
+    the projected Coriolis operator, P(2 W x h) = 2 (W.k^)(k^ x h) = -2 i s (W.k^) h
+    (the part of W across k gives a vector along k, which P removes).  So
+    u' = (2 i s W.k^ - nu |k|^2) u exactly, and two RK2 steps multiply the
+    mode by the closed-form factor squared (W generic, not along k)."""
+    N, k, nu, dt = 16, (2, 1, 2), 0.01, 0.05
+    om = np.array([0.3, -0.7, 1.1])
+    for s in (1, -1):
+        U, kh = _helical_mode(N, k, s)
+        lam = 2j * s * float(om @ kh) - nu * 9.0
+        want = U * _rk2_factor(lam, dt) ** 2
+        got = o.rk2_step(U, NS, nu, 0.0, dt, 2, omega=om)
+        assert _rel(got, want) < 1e-13, (s, _rel(got, want))
+    # zero rotation is the plain step
+    U, _ = _helical_mode(N, k, 1)
+    a = o.rk2_step(U, NS, nu, 0.0, dt, 1, omega=np.zeros(3))
+    b = o.rk2_step(U, NS, nu, 0.0, dt, 1)
+    assert _rel(a, b) < 1e-15
+
+
+def pin_rk2_rotation_mhd(o):
+    """MHD in a rotating frame: the Coriolis term acts on u = (z+ + z-)/2 only.
+    With b = 0 (z+ = z- = u) both Elsasser fields follow the NS inertial wave;
+    with u = 0 (z+ = b, z- = -b, b helical) there is no nonlinear term and no
+    Coriolis term, only (nu = eta) viscous decay."""
+    N, k, nu, dt = 16, (2, 1, 2), 0.01, 0.05
+    om = np.array([0.3, -0.7, 1.1])
+    U, kh = _helical_mode(N, k, 1)
+    lam = 2j * float(om @ kh) - nu * 9.0
+    got = o.rk2_step(np.concatenate([U, U]), MHD, nu, nu, dt, 2, omega=om)
+    want = np.concatenate([U, U]) * _rk2_factor(lam, dt) ** 2
+    assert _rel(got, want) < 1e-13, _rel(got, want)
+    got = o.rk2_step(np.concatenate([U, -U]), MHD, nu, nu, dt, 2, omega=om)
+    want = np.concatenate([U, -U]) * _rk2_factor(-nu * 9.0, dt) ** 2
+    assert _rel(got, want) < 1e-13, _rel(got, want)
+
+
 ALL_PINS = [v for k, v in sorted(globals().items()) if k.startswith("pin_")]

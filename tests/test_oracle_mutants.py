@@ -23,6 +23,8 @@ MUTANTS = {
     10: "nonlinear term: w x u instead of u x w",
     11: "RK2: first stage with dt instead of dt/2",
     12: "spectrum: shells by floor(|k|)",
+    13: "rotation: Coriolis term not projected",
+    14: "rotation: Omega x u instead of 2 Omega x u",
 }
 
 
