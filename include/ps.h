@@ -126,6 +126,17 @@ ps_status ps_nonlinear_mhd(ps_plan p, const void *zhat, void *nhat);
 ps_status ps_rk2_step(ps_plan p, void *state, ps_model m, double nu, double eta, double dt,
                       int nsteps);
 
+/* Frame rotation for ps_rk2_step (Sec. 5: the code integrates the equations
+ * "including rotation"; the paper gives no formula).  In a frame rotating at
+ * angular velocity Omega = (ox, oy, oz) the momentum equation gains the
+ * Coriolis acceleration -2 Omega x u (the centrifugal part is a gradient and
+ * goes into the pressure), projected like every other term; F above gains
+ * -P(k)(2 Omega x u) at every k != 0, with u = z (NS) or u = (z+ + z-)/2 (MHD,
+ * added to both Elsasser equations; the induction equation is unchanged).
+ * Default (0, 0, 0).  Affects ps_rk2_step only, not ps_nonlinear_*.  Drops
+ * a cached graph.  PS_ERR_ARG for non-finite components. */
+ps_status ps_plan_set_rotation(ps_plan p, double ox, double oy, double oz);
+
 /* Shell spectrum of nfields fields per box (1 <= nfields <= plan nfields):
  * spec_dev[s] = 1/2 sum_{round(|k|)=s} w |f(k)|^2 (w = 1 on the kx = 0 and
  * kx = N/2 planes, 2 elsewhere) and totals_dev = [E, Z, maxdiv] with

@@ -38,6 +38,7 @@ _SIGS = [
     ("ps_nonlinear_ns", _i, [_vp, _vp, _vp]),
     ("ps_nonlinear_mhd", _i, [_vp, _vp, _vp]),
     ("ps_rk2_step", _i, [_vp, _vp, _i, _d, _d, _d, _i]),
+    ("ps_plan_set_rotation", _i, [_vp, _d, _d, _d]),
     ("ps_energy_spectrum", _i, [_vp, _vp, _i, _vp, _vp]),
     ("ps_plan_set_variant", _i, [_vp, ctypes.c_char_p, _i]),
     ("ps_plan_get_variant", _i, [_vp, ctypes.c_char_p]),
@@ -262,6 +263,11 @@ class Plan:
         _check(lib().ps_energy_spectrum(self.handle, _ptr(fhat), nf, _ptr(spec), _ptr(tot)),
                "ps_energy_spectrum")
         return spec, tot
+
+    def set_rotation(self, ox: float, oy: float, oz: float):
+        """Rotating frame for rk2_step: Coriolis term -P(k)(2 Omega x u)."""
+        _check(lib().ps_plan_set_rotation(self.handle, float(ox), float(oy), float(oz)),
+               "set_rotation")
 
     # -- variants and autotuning ---------------------------------------------------
     KINDS = ("y", "z", "z_curl", "z_epi", "x_prod", "batch", "prune", "form")

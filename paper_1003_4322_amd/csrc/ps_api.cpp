@@ -91,6 +91,7 @@ struct ps_plan_s {
   bool per_box = false;  // baseline: one launch per box instead of per class
   bool prune = false;    // dealias-sphere pruning of the step (state zero outside the sphere)
   bool els = false;      // MHD nonlinear term in the Elsasser (divergence) form
+  double omega[3] = {0, 0, 0};  // frame rotation (Coriolis term of the step)
   std::map<int, void*> tables;
   std::map<int, ps::DiskTiles> dtiles;  // per grid size: z-pass tiles meeting the 2/3 disk
   std::vector<void*> dbufs;             // device lists behind dtiles
@@ -320,6 +321,8 @@ struct Seq {
     ea.in_bs = wk_bs(); ea.out_bs = st_bs(); ea.nb = nb;
     ea.scale = (T)(1.0 / ((double)b.N * b.N * b.N));
     ea.h = h; ea.nua = nua; ea.nub = nub; ea.N = b.N; ea.mode = mode;
+    ea.rot = mode != 0 && (p->omega[0] != 0 || p->omega[1] != 0 || p->omega[2] != 0);
+    ea.w2x = (T)(2 * p->omega[0]); ea.w2y = (T)(2 * p->omega[1]); ea.w2z = (T)(2 * p->omega[2]);
     ea.prune = p->prune;
     const int nrw = mode == 0 ? 0 : (mode == 1 ? 1 : 2);
     const int v = var_of(p, "z_epi");
@@ -841,6 +844,21 @@ ps_status ps_plan_set_variant(ps_plan p, const char* kind, int v) {
   p->prune = var_of(p, "prune") == 1;
   p->els = var_of(p, "form") == 1;
   if (p->gexec) {
+    hipGraphExecDestroy(p->gexec);
+    p->gexec = nullptr;
+    p->gkey.clear();
+  }
+  return PS_OK;
+}
+
+ps_status ps_plan_set_rotation(ps_plan p, double ox, double oy, double oz) {
+  if (ps_status st = validate_plan(p)) return st;
+  if (!std::isfinite(ox) || !std::isfinite(oy) || !std::isfinite(oz))
+    return fail(PS_ERR_ARG, "rotation vector must be finite");
+  p->omega[0] = ox;
+  p->omega[1] = oy;
+  p->omega[2] = oz;
+  if (p->gexec) {  // the captured step holds the old coefficients
     hipGraphExecDestroy(p->gexec);
     p->gexec = nullptr;
     p->gkey.clear();

@@ -310,6 +310,8 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_z_curl(ZCurlArgs<T> a) {
 // mode 1: out (= z*) = z^n + h (N^ - V(z^n))          h = dt/2
 // mode 2: st0 (= z^n, in place) = z^n + h (N^ - V(z*)), h = dt; z* = st1
 // V(z) = nu |k|^2 z (NS);  V(z+-) = |k|^2 (nua z+- + nub z-+) (MHD)
+// In a rotating frame V also holds the projected Coriolis term P(k)(2 Omega x u),
+// u = z (NS) or (z+ + z-)/2 (MHD, added to both Elsasser equations).
 // ---------------------------------------------------------------------------
 template <typename T>
 struct ZEpiArgs {
@@ -326,6 +328,10 @@ struct ZEpiArgs {
   int prune;  // 1: only modes inside the 2/3 sphere are read or updated (mode 0 still writes zeros)
   const int* tiles;  // as in ZCurlArgs; used by pruned launches with mode != 0
   int ntl;
+  // rotating frame (modes 1, 2): w2 = 2 Omega; the RHS gains -P(k)(w2 x u)
+  // at every k != 0, u the velocity of the state the viscous term acts on
+  T w2x, w2y, w2z;
+  int rot;
 };
 
 //
@@ -502,6 +508,19 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_z_epi(ZEpiArgs<T> a) {
 #pragma unroll
       for (int f = 0; f < NF; ++f) zz[f] = zv[f * a.out_fs + pos];
       C2<T>* dst = a.mode == 1 ? a.out : const_cast<C2<T>*>(a.st0);
+      C2<T> cor[3] = {zero2<T>(), zero2<T>(), zero2<T>()};
+      if (a.rot && k2i > 0) {
+        C2<T> u[3];
+#pragma unroll
+        for (int c3 = 0; c3 < 3; ++c3) u[c3] = MHD ? T(0.5) * (zz[c3] + zz[(c3 + 3) % NF]) : zz[c3];
+        const C2<T> w0 = a.w2y * u[2] - a.w2z * u[1];
+        const C2<T> w1 = a.w2z * u[0] - a.w2x * u[2];
+        const C2<T> w2 = a.w2x * u[1] - a.w2y * u[0];
+        const C2<T> kw = (T(1) / k2) * (kx * w0 + ky_ * w1 + kz * w2);
+        cor[0] = w0 - kx * kw;
+        cor[1] = w1 - ky_ * kw;
+        cor[2] = w2 - kz * kw;
+      }
 #pragma unroll
       for (int f = 0; f < NOUT; ++f) {
         // this field and (MHD) its Elsasser partner, with static indices
@@ -514,6 +533,7 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_z_epi(ZEpiArgs<T> a) {
           const C2<T> other = SPLIT == 2 ? sel(part == 1, zz[f], zz[(f + 3) % NF]) : zz[f < 3 ? f + 3 : f - 3];
           vis = vis + (a.nub * k2) * other;
         }
+        vis = vis + cor[f % 3];
         dst[(fo0 + f) * a.out_fs + pos] = z0 + a.h * (nh[f] - vis);
       }
     }

@@ -141,3 +141,81 @@ def test_spectrum(B, ref, N, dt):
     ws, wt = ref.energy_spectrum(F)
     assert np.allclose(host(spec), ws, rtol=1e-13, atol=0)
     assert np.allclose(host(tot), wt, rtol=1e-12, atol=0)
+
+
+# ---------------------------------------------------------------- rotation
+OMEGA = (1.5, -2.0, 3.0)
+
+
+@pytest.mark.parametrize("prune", [0, 1])
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_rk2_ns_rotation(B, ref, dt, prune):
+    """Rotating frame: two RK2 steps of NS 32^3 with a Coriolis term strong
+    enough to matter (|2 Omega| dt ~ 0.04) against the oracle."""
+    say("rk2 ns rotation", dt, prune)
+    u0 = rounded(synth.random_ns(32, 1, 2.0), dt)
+    p = B.Plan(32, 3, dt)
+    p.set_variant("prune", prune)
+    p.set_rotation(*OMEGA)
+    s = to_dev(u0, dt)
+    p.rk2_step(s, B.PS_NS, 0.02, 0.0, 5e-3, 2)
+    got = host(s)
+    want = ref.rk2_step(u0, NS, 0.02, 0.0, 5e-3, 2, omega=OMEGA)
+    assert rel_l2_w(got, want) < TOL_STEP[dt], rel_l2_w(got, want)
+    # the rotation changed the result well beyond the tolerance
+    plain = ref.rk2_step(u0, NS, 0.02, 0.0, 5e-3, 2)
+    assert rel_l2_w(plain, want) > 1e3 * TOL_STEP[dt]
+
+
+@pytest.mark.parametrize("form", [0, 1])
+@pytest.mark.parametrize("prune", [0, 1])
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_rk2_mhd_rotation(B, ref, dt, prune, form):
+    say("rk2 mhd rotation", dt, prune, form)
+    N = 24
+    z0 = rounded(synth.random_mhd(N, 3, 4, 2.0), dt)
+    p = B.Plan(N, 6, dt)
+    p.set_variant("prune", prune)
+    p.set_variant("form", form)
+    p.set_rotation(*OMEGA)
+    s = to_dev(z0, dt)
+    p.rk2_step(s, B.PS_MHD, 0.02, 0.01, 5e-3, 2)
+    got = host(s)
+    want = ref.rk2_step(z0, MHD, 0.02, 0.01, 5e-3, 2, omega=OMEGA)
+    assert rel_l2_w(got, want) < 3 * TOL_STEP[dt], rel_l2_w(got, want)
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_rotation_inertial_wave_closed_form(B, dt):
+    """GPU step against the closed form directly: a helical mode (no
+    nonlinear term) is an eigenvector of the projected Coriolis operator, so
+    each RK2 step multiplies it by 1 + x + x^2/2, x = (2 i s W.k^ - nu|k|^2) dt."""
+    import pins
+    say("inertial wave", dt)
+    N, k, nu, step = 16, (2, 1, 2), 0.01, 0.05
+    om = np.array([0.3, -0.7, 1.1])
+    for s_ in (1, -1):
+        U, kh = pins._helical_mode(N, k, s_)
+        lam = 2j * s_ * float(om @ kh) - nu * 9.0
+        want = U * pins._rk2_factor(lam, step) ** 3
+        p = B.Plan(N, 3, dt)
+        p.set_rotation(*om)
+        d = to_dev(U, dt)
+        p.rk2_step(d, B.PS_NS, nu, 0.0, step, 3)
+        assert rel_l2(host(d), want) < (1e-13 if dt == "f64" else 2e-6)
+
+
+def test_rotation_change_drops_graph(B, ref):
+    """A step captured without rotation is not replayed after set_rotation."""
+    say("rotation graph")
+    u0 = synth.random_ns(16, 5, 2.0)
+    p = B.Plan(16, 3, "f64")
+    s = to_dev(u0, "f64")
+    p.rk2_step(s, B.PS_NS, 0.02, 0.0, 5e-3, 1)       # captures the plain step
+    p.set_rotation(*OMEGA)
+    p.rk2_step(s, B.PS_NS, 0.02, 0.0, 5e-3, 1)
+    want = ref.rk2_step(ref.rk2_step(u0, NS, 0.02, 0.0, 5e-3, 1), NS, 0.02, 0.0, 5e-3, 1,
+                        omega=OMEGA)
+    assert rel_l2_w(host(s), want) < TOL_STEP["f64"]
+    with pytest.raises(B.PsError):
+        p.set_rotation(float("nan"), 0.0, 0.0)
