@@ -217,18 +217,27 @@ constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
 // LayPad8 serves contiguous rows and inserts one pad slot after every 8
 // elements, so the stride-R scatter of the first Stockham stage hits
 // distinct LDS banks.
+// off(a + c) = off(a) + offc(c) whenever c % 8 == 0, or a % 8 == 0 and c < 8
+// (always, for the unpadded layout); the transforms use it to move the
+// constant part of an unrolled index into the LDS instruction's offset.
 struct LayStride {
+  static constexpr bool PADDED = false;
   __device__ __forceinline__ static int off(int i, int ls) { return i * ls; }
+  __device__ __forceinline__ static int offc(int c, int ls) { return c * ls; }
 };
 struct LayPad8 {
+  static constexpr bool PADDED = true;
   __device__ __forceinline__ static int off(int i, int) { return i + (i >> 3); }
+  __device__ __forceinline__ static int offc(int c, int) { return c + c / 8; }
 };
 __host__ __device__ constexpr int pad8(int i) { return i + (i >> 3); }
 // column tiles (TX columns side by side): row idx of the tile padded by one
 // row per eight, so that a first stage writing rows j R + m from lanes of
 // consecutive j spreads over the LDS banks instead of hitting one
 struct LayColPad8 {
+  static constexpr bool PADDED = true;
   __device__ __forceinline__ static int off(int i, int ls) { return (i + (i >> 3)) * ls; }
+  __device__ __forceinline__ static int offc(int c, int ls) { return (c + c / 8) * ls; }
 };
 
 // ---------------------------------------------------------------------------
@@ -345,17 +354,20 @@ struct Stockham {
     constexpr bool EXACT = (L / R) % TQ == 0;
     if (act) {
       // ---- gather inputs
+      constexpr bool SPLIT_G = !Lay::PADDED || (L / R) % 8 == 0;
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
         const int j = q + TQ * b;
         const bool ok = EXACT || j < L / R;
+        const int ja = Lay::off(j, ls);
 #pragma unroll
         for (int m = 0; m < R; ++m) {
           const int idx = j + m * (L / R);
           if constexpr (FIRST) {
             v[b * R + m] = ok ? ld(b * R + m, idx) : zero2<T>();
           } else {
-            v[b * R + m] = ok ? lds[Lay::off(idx, ls)] : zero2<T>();
+            const int o = SPLIT_G ? ja + Lay::offc(m * (L / R), ls) : Lay::off(idx, ls);
+            v[b * R + m] = ok ? lds[o] : zero2<T>();
           }
         }
       }
@@ -373,14 +385,19 @@ struct Stockham {
       }
     }
     if constexpr (!LAST) {
+      constexpr bool SPLIT_W = !Lay::PADDED || NS % 8 == 0 || (NS == 1 && R % 8 == 0);
       __syncthreads();  // all reads of the previous LDS contents are done
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
         const int j = q + TQ * b;
         if (act && (EXACT || j < L / R)) {
           const int base = (j / NS) * NS * R + (j % NS);
+          const int ba = Lay::off(base, ls);
 #pragma unroll
-          for (int m = 0; m < R; ++m) lds[Lay::off(base + m * NS, ls)] = v[b * R + m];
+          for (int m = 0; m < R; ++m) {
+            const int o = SPLIT_W ? ba + Lay::offc(m * NS, ls) : Lay::off(base + m * NS, ls);
+            lds[o] = v[b * R + m];
+          }
         }
       }
       __syncthreads();  // writes visible before the next stage gathers

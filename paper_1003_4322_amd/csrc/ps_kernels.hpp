@@ -562,15 +562,24 @@ __host__ __device__ constexpr int xprod_slots(bool mhd, bool els) { return els ?
 
 template <typename T>
 __device__ __forceinline__ C2<T> c2r_pre(const C2<T>* buf, int k, int M, const C2<T>* __restrict__ tw) {
-  C2<T> xk, xm;
-  if (k == 0) {
-    xk = C2<T>{buf[0].x, T(0)};
-    xm = C2<T>{buf[pad8(M)].x, T(0)};
-  } else {
-    xk = buf[pad8(k)];
-    xm = conj(buf[pad8(M - k)]);
-  }
+  // branch-free: at k = 0 the pair is (Re X[0], Re X[M]) (M - k = M there)
+  C2<T> xk = buf[pad8(k)], xm = conj(buf[pad8(M - k)]);
+  xk.y = k == 0 ? T(0) : xk.y;
+  xm.y = k == 0 ? T(0) : xm.y;
   return (xk + xm) + mul_i(cmulc(xk - xm, tw[k]));  // conj(tw[k]) = e^{+2 pi i k/N}
+}
+
+// the same straight from a row in global memory whose coefficients above kmax are zero
+template <typename T>
+__device__ __forceinline__ C2<T> c2r_pre_g(const C2<T>* src, int k, int M, int kmax, const C2<T>* tw) {
+  // branch-free: every load stays inside the row, zeros come from selects
+  const int km = M - k;
+  C2<T> xk = src[k < kmax ? k : kmax], xm = conj(src[km < kmax ? km : kmax]);
+  xk = sel(k <= kmax, xk, zero2<T>());
+  xm = sel(km <= kmax, xm, zero2<T>());
+  xk.y = k == 0 ? T(0) : xk.y;
+  xm.y = k == 0 ? T(0) : xm.y;
+  return (xk + xm) + mul_i(cmulc(xk - xm, tw[k]));
 }
 
 template <typename T>
@@ -674,10 +683,12 @@ __global__ __launch_bounds__(xprod_slots(MHD, ELS) * RB * TQ) void k_x_prod(XArg
   using EI = Stockham<T, M, TQ, INV, RL>;
   using EF = Stockham<T, M, TQ, FWD, RL>;
   constexpr int LP = row_slots(M);
-  // rows of every field, then the twiddle table (length N = 2M) and, when it
-  // fits in 64 KB, the transforms' twiddles in the bank-friendly staged order
-  constexpr bool STAGED = (G * LP + 3 * M) * (int)sizeof(C2<T>) <= 65536;
-  __shared__ C2<T> smem[G * LP + (STAGED ? 3 : 2) * M];
+  // rows of every field, then twiddles: the M + 1 factors e^{-2 pi i k/N} of
+  // the half-length pre- and post-processing followed by the transforms' M - 1
+  // factors in the bank-friendly staged order, or (when that would not fit in
+  // 64 KB) the plain table of length N = 2M, which serves both
+  constexpr bool STAGED = (G * LP + 2 * M) * (int)sizeof(C2<T>) <= 65536;
+  __shared__ C2<T> smem[G * LP + 2 * M];
   C2<T>* twl = smem + G * LP;
   const int tid = threadIdx.x, g = tid / TQ, q = tid % TQ;
   const int f = g / RB, rb = g % RB;  // group g owns field f of row rb (slot g)
@@ -685,26 +696,32 @@ __global__ __launch_bounds__(xprod_slots(MHD, ELS) * RB * TQ) void k_x_prod(XArg
   const bool rok = row < a.rows * a.nb;
   const long rr = rok ? row : 0;
   const long boxi = rr / a.rows, rloc = rr % a.rows;
-  for (int i = tid; i < 2 * M; i += NT) twl[i] = a.tw[i];
-  if constexpr (STAGED) fill_staged<T, M>(twl + 2 * M, a.tw, 2, tid, NT, RL{});
+  for (int i = tid; i < (STAGED ? M + 1 : 2 * M); i += NT) twl[i] = a.tw[i];
+  if constexpr (STAGED) fill_staged<T, M>(twl + M + 1, a.tw, 2, tid, NT, RL{});
   const auto twf = [&] {
     if constexpr (STAGED)
-      return TwStaged<T>{twl + 2 * M};
+      return TwStaged<T>{twl + M + 1};
     else
       return TwTable<T>{twl, 2};
   }();
   C2<T>* buf = smem + g * LP;
   const bool in_act = f < FIN;
-  if (in_act) {
-    const C2<T>* src = a.in + boxi * a.in_bs + f * a.in_fs + rloc * a.in_pitch;
+  const C2<T>* src = a.in + boxi * a.in_bs + (in_act ? f : 0) * a.in_fs + rloc * a.in_pitch;
+  if (!ELS && in_act) {
     for (int k = q; k <= M; k += TQ) buf[pad8(k)] = rok && k <= a.kmax ? src[k] : zero2<T>();
   }
   __syncthreads();
-  // ---- inverse real FFTs, physical values back into the same slot
+  // ---- inverse real FFTs, physical values back into the same slot.  ELS: the
+  // first stage gathers its pre-processed inputs straight from the row in HBM.
   {
     C2<T> v[EI::SLOTS];
-    EI::template run_tw<LayPad8>(v, buf, 1, q, twf, [&](int, int k) { return c2r_pre(buf, k, M, twl); },
-                                 in_act);
+    if constexpr (ELS)
+      EI::template run_tw<LayPad8>(
+          v, buf, 1, q, twf,
+          [&](int, int k) { return rok ? c2r_pre_g(src, k, M, a.kmax, twl) : zero2<T>(); }, in_act);
+    else
+      EI::template run_tw<LayPad8>(v, buf, 1, q, twf, [&](int, int k) { return c2r_pre(buf, k, M, twl); },
+                                   in_act);
     __syncthreads();
     if (in_act) {
 #pragma unroll
@@ -713,23 +730,11 @@ __global__ __launch_bounds__(xprod_slots(MHD, ELS) * RB * TQ) void k_x_prod(XArg
     }
   }
   __syncthreads();
-  // ---- products; each C2 holds two neighbouring grid points
-  for (int i = tid; i < RB * M; i += NT) {
+  // ---- products; each C2 holds two neighbouring grid points.  ELS: formed
+  // in the first stage of the forward transforms instead (below).
+  for (int i = tid; !ELS && i < RB * M; i += NT) {
     const int r = i / M, n = i % M;
     auto at = [&](int ff) -> C2<T>& { return smem[(ff * RB + r) * LP + pad8(n)]; };
-    if constexpr (ELS) {
-      C2<T> zp[3], zm[3];
-#pragma unroll
-      for (int i3 = 0; i3 < 3; ++i3) {
-        zp[i3] = at(i3);
-        zm[i3] = at(3 + i3);
-      }
-#pragma unroll
-      for (int i3 = 0; i3 < 3; ++i3)
-#pragma unroll
-        for (int j3 = 0; j3 < 3; ++j3) at(3 * i3 + j3) = C2<T>{zp[i3].x * zm[j3].x, zp[i3].y * zm[j3].y};
-      continue;
-    }
     const C2<T> u0 = at(0), u1 = at(1), u2 = at(2);
     const C2<T> w0 = at(3), w1 = at(4), w2 = at(5);
     auto cx = [](C2<T> a1, C2<T> a2, C2<T> b1, C2<T> b2) {  // a1 b2 - a2 b1 per point
@@ -750,13 +755,27 @@ __global__ __launch_bounds__(xprod_slots(MHD, ELS) * RB * TQ) void k_x_prod(XArg
     at(1) = n1;
     at(2) = n2;
   }
-  __syncthreads();
+  if constexpr (!ELS) __syncthreads();
   // ---- forward real FFTs of the FOUT product fields; the other groups only
   // join the barriers (with RB even their waves skip the work entirely)
   const bool active = f < FOUT;
   {
     C2<T> v[EF::SLOTS];
-    EF::template run_tw<LayPad8>(v, buf, 1, q, twf, [&](int, int n) { return buf[pad8(n)]; }, active);
+    if constexpr (ELS) {
+      // T_ij = z+_i z-_j, i = f / 3, j = f % 3; every read happens before the
+      // first stage's barrier, so overwriting the input slots after it is safe
+      const C2<T>* ra = smem + ((f / 3) * RB + rb) * LP;
+      const C2<T>* rm = smem + ((3 + f % 3) * RB + rb) * LP;
+      EF::template run_tw<LayPad8>(
+          v, buf, 1, q, twf,
+          [&](int, int n) {
+            const C2<T> x = ra[pad8(n)], y = rm[pad8(n)];
+            return C2<T>{x.x * y.x, x.y * y.y};
+          },
+          active);
+    } else {
+      EF::template run_tw<LayPad8>(v, buf, 1, q, twf, [&](int, int n) { return buf[pad8(n)]; }, active);
+    }
     __syncthreads();
     if (active) {
 #pragma unroll
