@@ -53,6 +53,22 @@ static long dwavx(long i, long N) {
   return (2 * i == N) ? 0 : i;
 }
 
+/* Box lengths.  Sec. 5 notes the method works for boxes whose aspect ratio
+ * is not unity; a box of lengths L has physical wavenumbers k = (2 pi / L) n
+ * for the signed index n, so every derivative, the projector and |k|^2 in
+ * the viscous and diagnostic terms carry the factors s = 2 pi / L.  The 2/3
+ * rule stays on the index n: aliasing belongs to the grid, not the lengths.
+ * Default: the 2 pi-periodic cube (s = 1). */
+static double g_s[3] = {1.0, 1.0, 1.0};
+
+int psref_set_box(double Lx, double Ly, double Lz) {
+  if (!(Lx > 0 && Ly > 0 && Lz > 0) || !isfinite(Lx) || !isfinite(Ly) || !isfinite(Lz)) return -1;
+  g_s[0] = TWO_PI / Lx;
+  g_s[1] = TWO_PI / Ly;
+  g_s[2] = TWO_PI / Lz;
+  return 0;
+}
+
 /* 2/3-rule dealiasing, spherical truncation: keep 9 |k|^2 < N^2 */
 static int dealias_keep(long k2, long N) {
   if (MUT(3)) return 9 * k2 <= N * N;
@@ -292,7 +308,8 @@ static void curl_fields(int N, const cplx *u, cplx *w) {
     for (long ky = 0; ky < N; ++ky)
       for (long kx = 0; kx < H; ++kx) {
         long m = (kz * N + ky) * H + kx;
-        double ax = (double)dwavx(kx, N), ay = (double)dwav(ky, N), az = (double)dwav(kz, N);
+        const double *sc = MUT(16) ? (const double[3]){1, 1, 1} : g_s;
+        double ax = sc[0] * dwavx(kx, N), ay = sc[1] * dwav(ky, N), az = sc[2] * dwav(kz, N);
         cplx ux = u[m], uy = u[nc + m], uz = u[2 * nc + m];
         w[m] = I * (ay * uz - az * uy);
         w[nc + m] = I * (az * ux - ax * uz);
@@ -323,14 +340,15 @@ static void dealias_project(int N, cplx *v) {
           v[m] = v[nc + m] = v[2 * nc + m] = 0;
           continue;
         }
-        double ax = (double)ix, ay = (double)iy, az = (double)iz;
+        double ax = g_s[0] * ix, ay = g_s[1] * iy, az = g_s[2] * iz;
+        double q2 = ax * ax + ay * ay + az * az;  /* physical |k|^2 */
         cplx vx = v[m], vy = v[nc + m], vz = v[2 * nc + m];
         cplx kv = ax * vx + ay * vy + az * vz;
         if (MUT(2)) kv = 0;
         double s = MUT(6) ? 1.0 : inv;
-        v[m] = s * (vx - ax * kv / (double)k2);
-        v[nc + m] = s * (vy - ay * kv / (double)k2);
-        v[2 * nc + m] = s * (vz - az * kv / (double)k2);
+        v[m] = s * (vx - ax * kv / q2);
+        v[nc + m] = s * (vy - ay * kv / q2);
+        v[2 * nc + m] = s * (vz - az * kv / q2);
       }
 }
 
@@ -542,9 +560,9 @@ static void cross_c(const cplx a[3], const cplx b[3], cplx o[3]) {
 
 /* i q x v with the derivative wavenumber (Nyquist components zero) */
 static void icurl_c(int N, long qx, long qy, long qz, const cplx v[3], cplx o[3]) {
-  double ax = (2 * labs(qx) == N) ? 0.0 : (double)qx;
-  double ay = (2 * labs(qy) == N) ? 0.0 : (double)qy;
-  double az = (2 * labs(qz) == N) ? 0.0 : (double)qz;
+  double ax = (2 * labs(qx) == N) ? 0.0 : g_s[0] * qx;
+  double ay = (2 * labs(qy) == N) ? 0.0 : g_s[1] * qy;
+  double az = (2 * labs(qz) == N) ? 0.0 : g_s[2] * qz;
   o[0] = I * (ay * v[2] - az * v[1]);
   o[1] = I * (az * v[0] - ax * v[2]);
   o[2] = I * (ax * v[1] - ay * v[0]);
@@ -605,10 +623,10 @@ int psref_nonlinear_at(int N, int model, const double *fhat, int nk, const int *
     long k2 = ox * ox + oy * oy + oz * oz;
     cplx res[6] = {0, 0, 0, 0, 0, 0};
     if (k2 != 0 && dealias_keep(k2, N)) {
-      double ax = (double)ox, ay = (double)oy, az = (double)oz;
+      double ax = g_s[0] * ox, ay = g_s[1] * oy, az = g_s[2] * oz;
+      double q2 = ax * ax + ay * ay + az * az;
       cplx kv = ax * accL[0] + ay * accL[1] + az * accL[2];
-      cplx pl_[3] = {accL[0] - ax * kv / (double)k2, accL[1] - ay * kv / (double)k2,
-                     accL[2] - az * kv / (double)k2};
+      cplx pl_[3] = {accL[0] - ax * kv / q2, accL[1] - ay * kv / q2, accL[2] - az * kv / q2};
       if (model == 0) {
         for (int f = 0; f < 3; ++f) res[f] = pl_[f];
       } else {
@@ -660,11 +678,12 @@ static void coriolis(int N, int model, const cplx *z, cplx *F, const double *om)
           u[c] = model == 0 ? z[c * nc + m] : 0.5 * (z[c * nc + m] + z[(3 + c) * nc + m]);
         cplx a[3] = {f * (om[1] * u[2] - om[2] * u[1]), f * (om[2] * u[0] - om[0] * u[2]),
                      f * (om[0] * u[1] - om[1] * u[0])};
-        double kk[3] = {(double)ix, (double)iy, (double)iz};
+        double kk[3] = {g_s[0] * ix, g_s[1] * iy, g_s[2] * iz};
+        double q2 = kk[0] * kk[0] + kk[1] * kk[1] + kk[2] * kk[2];
         cplx ka = kk[0] * a[0] + kk[1] * a[1] + kk[2] * a[2];
         if (MUT(13)) ka = 0;
         for (int c = 0; c < 3; ++c) {
-          cplx pa = a[c] - kk[c] * ka / (double)k2;
+          cplx pa = a[c] - kk[c] * ka / q2;
           F[c * nc + m] -= pa;
           if (model == 1) F[(3 + c) * nc + m] -= pa;
         }
@@ -684,7 +703,8 @@ static int rhs(int N, int model, const cplx *z, cplx *F, double nu, double eta, 
       for (long kx = 0; kx < H; ++kx) {
         long m = (kz * N + ky) * H + kx;
         long ix = wavx(kx), iy = wav(ky, N), iz = wav(kz, N);
-        double k2 = (double)(ix * ix + iy * iy + iz * iz);
+        const double *sc = MUT(15) ? (const double[3]){1, 1, 1} : g_s;
+        double k2 = sc[0] * sc[0] * ix * ix + sc[1] * sc[1] * iy * iy + sc[2] * sc[2] * iz * iz;
         if (model == 0) {
           for (int c = 0; c < 3; ++c) F[c * nc + m] -= a * k2 * z[c * nc + m];
         } else {
@@ -790,11 +810,12 @@ int psref_energy_spectrum(int N, int nf, const double *fhat_, double *spec, doub
           cplx a = F[f * nc + m];
           e += creal(a) * creal(a) + cimag(a) * cimag(a);
         }
-        long s = shell_of(k2);
+        long s = shell_of(k2);  /* shells of the index |n| */
+        double q2 = g_s[0] * g_s[0] * ix * ix + g_s[1] * g_s[1] * iy * iy + g_s[2] * g_s[2] * iz * iz;
         nadd(&es[s], 0.5 * w * e);
-        nadd(&Z, 0.5 * w * (double)k2 * e);
+        nadd(&Z, 0.5 * w * q2 * e);
         for (int f = 0; f + 2 < nf; f += 3) {
-          double ax = (double)dwavx(kx, N), ay = (double)dwav(ky, N), az = (double)dwav(kz, N);
+          double ax = g_s[0] * dwavx(kx, N), ay = g_s[1] * dwav(ky, N), az = g_s[2] * dwav(kz, N);
           cplx d = ax * F[f * nc + m] + ay * F[(f + 1) * nc + m] + az * F[(f + 2) * nc + m];
           if (cabs(d) > maxdiv) maxdiv = cabs(d);
         }

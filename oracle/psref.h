@@ -80,6 +80,12 @@ int psref_rk2_step(int N, int model, double *state, double nu, double eta,
 int psref_rk2_step_rot(int N, int model, double *state, double nu, double eta,
                        double dt, int nsteps, const double *omega);
 
+/* Box lengths (default 2 pi each): physical wavenumbers k = (2 pi / L) n in
+ * every derivative, in the projector and in |k|^2 of the viscous term and
+ * of the enstrophy; dealiasing and the spectral shells stay on the index n.
+ * Process-wide setting.  Returns -1 for non-positive or non-finite L. */
+int psref_set_box(double Lx, double Ly, double Lz);
+
 /* Number of spectral shells: s(3 (N/2)^2) + 1. */
 int psref_num_shells(int N);
 

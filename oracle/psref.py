@@ -12,6 +12,7 @@ real fields ``float64[nf, N, N, N]`` ([f][z][y][x]) and half spectra
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 from typing import Optional
@@ -63,6 +64,7 @@ class Oracle:
                                      ctypes.c_double, ctypes.c_double, ctypes.c_int]
         L.psref_rk2_step_rot.argtypes = [ctypes.c_int, ctypes.c_int, dp, ctypes.c_double,
                                          ctypes.c_double, ctypes.c_double, ctypes.c_int, dp]
+        L.psref_set_box.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double]
         L.psref_num_shells.argtypes = [ctypes.c_int]
         L.psref_energy_spectrum.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp]
 
@@ -172,6 +174,10 @@ class Oracle:
                                              float(dt), int(nsteps), self._p(om))
         self._check(rc, "rk2_step")
         return z
+
+    def set_box(self, Lx: float = 2 * math.pi, Ly: float = 2 * math.pi, Lz: float = 2 * math.pi):
+        """Box lengths for every later call (process-wide; default 2 pi)."""
+        self._check(self.lib.psref_set_box(float(Lx), float(Ly), float(Lz)), "set_box")
 
     def num_shells(self, N: int) -> int:
         return int(self.lib.psref_num_shells(N))

@@ -518,4 +518,62 @@ def pin_rk2_rotation_mhd(o):
     assert _rel(got, want) < 1e-13, _rel(got, want)
 
 
+def box_abc(N: int, L, A=1.0, B=0.7, C=0.4) -> np.ndarray:
+    """ABC flow of physical wavenumber 1 on a box of lengths L (each a whole
+    multiple of 2 pi), as normalised half-spectrum coefficients: a Beltrami
+    field (curl u = u) whose three sinusoids sit at different indices."""
+    x, y, z = (L[i] * np.arange(N) / N for i in range(3))
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    u = np.stack([A * np.sin(Z) + C * np.cos(Y), B * np.sin(X) + A * np.cos(Z),
+                  C * np.sin(Y) + B * np.cos(X)])
+    return np.fft.rfftn(u, axes=(1, 2, 3)) / N ** 3
+
+
+def pin_box_aspect_ratio(o):
+    """A non-cubic box (2 pi, 4 pi, 6 pi): the ABC flow of physical wavenumber 1
+    has its modes at indices 1, 2 and 3 along x, y and z.  With the box's
+    factors 2 pi / L in the derivatives it is still Beltrami (curl u = u, no
+    nonlinear term), every mode has |k|^2 = 1, so the step is pure decay by the
+    RK2 factor of -nu dt, the enstrophy equals the energy and the divergence is
+    zero; MHD with b = u / 2 likewise only decays."""
+    N, L, nu, dt = 16, (2 * math.pi, 4 * math.pi, 6 * math.pi), 0.05, 0.1
+    U = box_abc(N, L)
+    o.set_box(*L)
+    try:
+        assert _rel(o.curl(U), U) < 1e-13
+        assert np.abs(o.nonlinear_ns(U)).max() < 1e-14 * np.abs(U).max()
+        r = _rk2_factor(-nu, dt) ** 2
+        assert _rel(o.rk2_step(U, NS, nu, 0.0, dt, 2), U * r) < 1e-13
+        _, tot = o.energy_spectrum(U)
+        assert abs(tot[1] - tot[0]) < 1e-13 * tot[0] and tot[2] < 1e-13
+        Z = np.concatenate([1.5 * U, 0.5 * U])
+        assert _rel(o.rk2_step(Z, MHD, nu, nu, dt, 2), Z * r) < 1e-13
+    finally:
+        o.set_box()
+
+
+def pin_box_inertial_wave(o):
+    """Rotation in a non-cubic box: the inertial-wave closed form with the
+    physical wavenumber k = (2 pi / L) n in the helical basis, the Coriolis
+    eigenvalue and the viscous rate."""
+    N, n, nu, dt = 16, (2, 1, 2), 0.01, 0.05
+    L = (2 * math.pi, 3 * math.pi, 4 * math.pi)
+    kp = np.array([2 * math.pi / L[i] * n[i] for i in range(3)])
+    om = np.array([0.3, -0.7, 1.1])
+    U, kh = _helical_mode(N, n, 1)            # helical basis of the index vector
+    kh = kp / np.linalg.norm(kp)              # rebuild it for the physical one
+    t = np.array([1.0, 0.0, 0.0]) if abs(kh[0]) < 0.9 else np.array([0.0, 1.0, 0.0])
+    e1 = np.cross(kh, t)
+    e1 /= np.linalg.norm(e1)
+    h = e1 + 1j * np.cross(kh, e1)
+    U[:, n[2], n[1], n[0]] = h
+    lam = 2j * float(om @ kh) - nu * float(kp @ kp)
+    o.set_box(*L)
+    try:
+        got = o.rk2_step(U, NS, nu, 0.0, dt, 2, omega=om)
+        assert _rel(got, U * _rk2_factor(lam, dt) ** 2) < 1e-13, _rel(got, U * _rk2_factor(lam, dt) ** 2)
+    finally:
+        o.set_box()
+
+
 ALL_PINS = [v for k, v in sorted(globals().items()) if k.startswith("pin_")]

@@ -25,6 +25,8 @@ MUTANTS = {
     12: "spectrum: shells by floor(|k|)",
     13: "rotation: Coriolis term not projected",
     14: "rotation: Omega x u instead of 2 Omega x u",
+    15: "box: viscous term with the index |n|^2",
+    16: "box: curl without the factors 2 pi / L",
 }
 
 
