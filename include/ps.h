@@ -137,6 +137,16 @@ ps_status ps_rk2_step(ps_plan p, void *state, ps_model m, double nu, double eta,
  * a cached graph.  PS_ERR_ARG for non-finite components. */
 ps_status ps_plan_set_rotation(ps_plan p, double ox, double oy, double oz);
 
+/* Box lengths (Sec. 5: the scheme also serves domains whose aspect ratio is
+ * not unity).  Default 2 pi each.  A box of lengths (Lx, Ly, Lz) has physical
+ * wavenumbers k = (2 pi / L) n for the signed storage index n; they enter the
+ * curl, the projector P(k), the divergence form, |k|^2 of the viscous term,
+ * the Coriolis term, and the enstrophy and divergence of
+ * ps_energy_spectrum.  The 2/3 truncation and the spectral shells stay on
+ * the index n (aliasing is a property of the grid).  The grid is N^3 in every
+ * case.  Drops a cached graph.  PS_ERR_ARG for non-positive or non-finite L. */
+ps_status ps_plan_set_box(ps_plan p, double Lx, double Ly, double Lz);
+
 /* Shell spectrum of nfields fields per box (1 <= nfields <= plan nfields):
  * spec_dev[s] = 1/2 sum_{round(|k|)=s} w |f(k)|^2 (w = 1 on the kx = 0 and
  * kx = N/2 planes, 2 elsewhere) and totals_dev = [E, Z, maxdiv] with

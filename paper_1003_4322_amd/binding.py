@@ -39,6 +39,7 @@ _SIGS = [
     ("ps_nonlinear_mhd", _i, [_vp, _vp, _vp]),
     ("ps_rk2_step", _i, [_vp, _vp, _i, _d, _d, _d, _i]),
     ("ps_plan_set_rotation", _i, [_vp, _d, _d, _d]),
+    ("ps_plan_set_box", _i, [_vp, _d, _d, _d]),
     ("ps_energy_spectrum", _i, [_vp, _vp, _i, _vp, _vp]),
     ("ps_plan_set_variant", _i, [_vp, ctypes.c_char_p, _i]),
     ("ps_plan_get_variant", _i, [_vp, ctypes.c_char_p]),
@@ -268,6 +269,10 @@ class Plan:
         """Rotating frame for rk2_step: Coriolis term -P(k)(2 Omega x u)."""
         _check(lib().ps_plan_set_rotation(self.handle, float(ox), float(oy), float(oz)),
                "set_rotation")
+
+    def set_box(self, Lx: float, Ly: float, Lz: float):
+        """Box lengths (default 2 pi each): physical wavenumbers 2 pi n / L."""
+        _check(lib().ps_plan_set_box(self.handle, float(Lx), float(Ly), float(Lz)), "set_box")
 
     # -- variants and autotuning ---------------------------------------------------
     KINDS = ("y", "z", "z_curl", "z_epi", "x_prod", "batch", "prune", "form")

@@ -92,6 +92,7 @@ struct ps_plan_s {
   bool prune = false;    // dealias-sphere pruning of the step (state zero outside the sphere)
   bool els = false;      // MHD nonlinear term in the Elsasser (divergence) form
   double omega[3] = {0, 0, 0};  // frame rotation (Coriolis term of the step)
+  double bs[3] = {1, 1, 1};     // box factors 2 pi / L per axis (x, y, z)
   std::map<int, void*> tables;
   std::map<int, ps::DiskTiles> dtiles;  // per grid size: z-pass tiles meeting the 2/3 disk
   std::vector<void*> dbufs;             // device lists behind dtiles
@@ -294,6 +295,7 @@ struct Seq {
     ca.in_fs = b.nc; ca.in_pitch = b.H; ca.out_fs = b.ncp; ca.out_pitch = b.P; ca.N = b.N;
     ca.in_bs = st_bs(); ca.out_bs = wk_bs(); ca.nb = nb;
     ca.prune = p->prune;
+    ca.sx = (T)p->bs[0]; ca.sy = (T)p->bs[1]; ca.sz = (T)p->bs[2];
     const int v = var_of(p, "z_curl");
     const double bytes = p->prune ? ((double)nin * b.n_sphere + (double)nphys * b.n_disk * b.N) * nb * cs()
                                   : (double)(nin + nphys) * nb * b.nc * cs();
@@ -324,6 +326,7 @@ struct Seq {
     ea.rot = mode != 0 && (p->omega[0] != 0 || p->omega[1] != 0 || p->omega[2] != 0);
     ea.w2x = (T)(2 * p->omega[0]); ea.w2y = (T)(2 * p->omega[1]); ea.w2z = (T)(2 * p->omega[2]);
     ea.prune = p->prune;
+    ea.sx = (T)p->bs[0]; ea.sy = (T)p->bs[1]; ea.sz = (T)p->bs[2];
     const int nrw = mode == 0 ? 0 : (mode == 1 ? 1 : 2);
     const int v = var_of(p, "z_epi");
     double bytes = (double)(nprod + nst + nrw * nst) * nb * b.nc * cs();
@@ -368,6 +371,7 @@ struct Seq {
     ps::SpecArgs<T> a{};
     a.f = f; a.part = spec_part(i); a.pmax = a.part + (long)b.N * b.nshell * 2;
     a.fs = b.nc; a.pitch = b.H; a.N = b.N; a.nf = nfl; a.nshell = b.nshell;
+    a.sx = p->bs[0]; a.sy = p->bs[1]; a.sz = p->bs[2];
     return enqueue(p, s, "spectrum", nfl * b.nc * cs(),
                    [&](hipStream_t q) { return ps::launch_spectrum<T>(a, spec, totals, q); });
   }
@@ -859,6 +863,22 @@ ps_status ps_plan_set_rotation(ps_plan p, double ox, double oy, double oz) {
   p->omega[1] = oy;
   p->omega[2] = oz;
   if (p->gexec) {  // the captured step holds the old coefficients
+    hipGraphExecDestroy(p->gexec);
+    p->gexec = nullptr;
+    p->gkey.clear();
+  }
+  return PS_OK;
+}
+
+ps_status ps_plan_set_box(ps_plan p, double Lx, double Ly, double Lz) {
+  if (ps_status st = validate_plan(p)) return st;
+  if (!(Lx > 0 && Ly > 0 && Lz > 0) || !std::isfinite(Lx) || !std::isfinite(Ly) || !std::isfinite(Lz))
+    return fail(PS_ERR_ARG, "box lengths must be positive and finite");
+  const double two_pi = 6.283185307179586476925286766559;
+  p->bs[0] = two_pi / Lx;
+  p->bs[1] = two_pi / Ly;
+  p->bs[2] = two_pi / Lz;
+  if (p->gexec) {
     hipGraphExecDestroy(p->gexec);
     p->gexec = nullptr;
     p->gkey.clear();

@@ -131,6 +131,7 @@ struct ZCurlArgs {
   // that no workgroup is spent on, and no XCD is left idle by, empty tiles
   const int* tiles;
   int ntl;
+  T sx, sy, sz;  // box factors 2 pi / L: physical wavenumber = s * index
 };
 
 // tile, ky and box of a z-pass workgroup
@@ -181,7 +182,7 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_z_curl(ZCurlArgs<T> a) {
   const long in_es = (long)N * a.in_pitch, out_es = (long)N * a.out_pitch;
   const C2<T>* in = a.in + box * a.in_bs + ky * a.in_pitch + col;
   C2<T>* out = a.out + box * a.out_bs + ky * a.out_pitch + col;
-  const T kx = (T)dwavx(col, N), kyd = (T)dwav(ky, N);
+  const T kx = a.sx * (T)dwavx(col, N), kyd = a.sy * (T)dwav(ky, N);
   const int kperp2 = col * col + kyw * kyw;
   if constexpr (TWL) {
     fill_staged<T, L>(smem + CT::ROWS * TX, a.tw, 1, tid, TX * TQ, RL{});
@@ -209,7 +210,7 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_z_curl(ZCurlArgs<T> a) {
   // a getter g(f) of the base's components at wavenumber index kzi
   auto field_of = [&](int grp, int comp, int kzi, auto g) -> C2<T> {
     if ((grp & 1) == 0) return g(comp);
-    const T kz = (T)dwav(kzi, N);
+    const T kz = a.sz * (T)dwav(kzi, N);
     C2<T> r;
     if (comp == 0)
       r = kyd * g(2) - kz * g(1);
@@ -253,7 +254,7 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_z_curl(ZCurlArgs<T> a) {
         if (!live(kzi)) return zero2<T>();
         const long off = (long)kzi * in_es;
         if (!curl) return base_at(comp, off, sign);
-        const T kz = (T)dwav(kzi, N);
+        const T kz = a.sz * (T)dwav(kzi, N);
         const T ka = comp == 1 ? kz : kA, kb = comp == 0 ? kz : kB;
         return mul_i(ka * base_at(ca, off, sign) - kb * base_at(cb, off, sign));
       });
@@ -332,6 +333,7 @@ struct ZEpiArgs {
   // at every k != 0, u the velocity of the state the viscous term acts on
   T w2x, w2y, w2z;
   int rot;
+  T sx, sy, sz;  // box factors 2 pi / L: physical wavenumber = s * index (D stays on the index)
 };
 
 //
@@ -386,7 +388,7 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_z_epi(ZEpiArgs<T> a) {
   constexpr int NR = ELS ? 3 * (2 / SPLIT) : NF;
   C2<T> r[NR][NO];
   if constexpr (ELS) {
-    const T kxd0 = (T)dwavx(col, N), kyd0 = (T)dwav(ky, N);
+    const T kxd0 = a.sx * (T)dwavx(col, N), kyd0 = a.sy * (T)dwav(ky, N);
 #pragma unroll
     for (int f = 0; f < NR; ++f)
 #pragma unroll
@@ -406,7 +408,7 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_z_epi(ZEpiArgs<T> a) {
           E::template run_tw<typename CT::Lay>(v, smem + c, TX, q, tw, ld_of(3 * i3 + j3));
 #pragma unroll
           for (int s = 0; s < NO; ++s) {
-            const T kzd0 = (T)dwav(E::last_index(q, s), N);
+            const T kzd0 = a.sz * (T)dwav(E::last_index(q, s), N);
             const T kj = j3 == 0 ? kxd0 : j3 == 1 ? kyd0 : kzd0;
             const T ki = i3 == 0 ? kxd0 : i3 == 1 ? kyd0 : kzd0;
             acc[s] = acc[s] + kj * v[s];
@@ -430,7 +432,7 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_z_epi(ZEpiArgs<T> a) {
         E::template run_tw<typename CT::Lay>(v, smem + c, TX, q, tw, ld_of(f));
 #pragma unroll
         for (int s = 0; s < NO; ++s) {
-          const T kzd0 = (T)dwav(E::last_index(q, s), N);
+          const T kzd0 = a.sz * (T)dwav(E::last_index(q, s), N);
           const T km = m == 0 ? kxd0 : m == 1 ? kyd0 : kzd0;
           r[0][s] = r[0][s] + (t == 0 ? km : T(0)) * v[s];
           r[1][s] = r[1][s] + (t == 1 ? km : T(0)) * v[s];
@@ -451,7 +453,7 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_z_epi(ZEpiArgs<T> a) {
 
   const long base = box * a.out_bs + ky * a.out_pitch + col;
   const int ikx = col, iky = wav(ky, N);
-  const T kxd = (T)dwavx(col, N), kyd = (T)dwav(ky, N);
+  const T kxd = a.sx * (T)dwavx(col, N), kyd = a.sy * (T)dwav(ky, N);
 #pragma unroll
   for (int s = 0; s < NO; ++s) {
     if (!E::last_valid(q, s)) continue;
@@ -461,8 +463,9 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_z_epi(ZEpiArgs<T> a) {
     const bool sphere = 9 * k2i < (long)N * N;
     if (a.prune && !sphere && a.mode != 0) continue;  // stays zero
     const bool keep = k2i > 0 && sphere;
-    const T k2 = (T)k2i;
-    const T kx = (T)ikx, ky_ = (T)iky, kz = (T)ikz;
+    // physical wavenumber (projector, |k|^2); keep / sphere use the index
+    const T kx = a.sx * (T)ikx, ky_ = a.sy * (T)iky, kz = a.sz * (T)ikz;
+    const T k2 = kx * kx + ky_ * ky_ + kz * kz;
     C2<T> nh[NOUT];
     if constexpr (ELS) {
       const T ik2 = keep ? T(1) / k2 : T(0);
@@ -484,7 +487,7 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_z_epi(ZEpiArgs<T> a) {
       n2 = n2 - (kz * ik2) * kn;
       if constexpr (MHD) {
         const C2<T> e0 = a.scale * r[3][s], e1 = a.scale * r[4][s], e2 = a.scale * r[5][s];
-        const T kzd = (T)dwav(kzi, N);
+        const T kzd = a.sz * (T)dwav(kzi, N);
         const C2<T> c0 = mul_i(kyd * e2 - kzd * e1);
         const C2<T> c1 = mul_i(kzd * e0 - kxd * e2);
         const C2<T> c2 = mul_i(kxd * e1 - kyd * e0);
@@ -824,13 +827,15 @@ struct SpecArgs {
   double* pmax;     // [N] max |k_d . f| per plane
   long fs, pitch;   // field stride, kx pitch
   int N, nf, nshell;
+  double sx, sy, sz;  // box factors 2 pi / L (enstrophy and divergence; shells stay on the index)
 };
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_spec_planes(SpecArgs<T> a) {
   const int kz = blockIdx.x, N = a.N, H = N / 2 + 1;
   const long izw = wav(kz, N);
-  const T kzd = (T)dwav(kz, N);
+  const double kzd = a.sz * dwav(kz, N);
+  const double qz2 = a.sz * a.sz * (double)(izw * izw);
   __shared__ double red[256];
   double mx = 0;
   for (int s = threadIdx.x; s < a.nshell; s += blockDim.x) {
@@ -851,7 +856,8 @@ __global__ __launch_bounds__(256) void k_spec_planes(SpecArgs<T> a) {
       long kx1 = isqrt_floor(hi2 - A4 - 1) / 2;  // largest kx with 4 kx^2 < hi2 - A4
       if (kx1 > H - 1) kx1 = H - 1;
       const C2<T>* row = a.f + (long)kz * N * a.pitch + (long)ky * a.pitch;
-      const T kyd = (T)dwav(ky, N);
+      const double kyd = a.sy * dwav(ky, N);
+      const double qyz2 = a.sy * a.sy * (double)(iyw * iyw) + qz2;
       for (long kx = kx0; kx <= kx1; ++kx) {
         double e = 0;
         for (int ff = 0; ff < a.nf; ++ff) {
@@ -859,14 +865,14 @@ __global__ __launch_bounds__(256) void k_spec_planes(SpecArgs<T> a) {
           e += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
         }
         const double w = (kx == 0 || 2 * kx == N) ? 0.5 : 1.0;  // (1/2) * weight
-        const long k2 = kx * kx + (iyw * iyw + izw * izw);
+        const double q2 = a.sx * a.sx * (double)(kx * kx) + qyz2;  // physical |k|^2
         nadd(E, w * e);
-        nadd(Z, w * (double)k2 * e);
-        const T kxd = (T)dwavx((int)kx, N);
+        nadd(Z, w * q2 * e);
+        const double kxd = a.sx * dwavx((int)kx, N);
         for (int ff = 0; ff + 2 < a.nf; ff += 3) {
           const C2<T> v0 = row[ff * a.fs + kx], v1 = row[(ff + 1) * a.fs + kx], v2 = row[(ff + 2) * a.fs + kx];
-          const double dx = (double)kxd * v0.x + (double)kyd * v1.x + (double)kzd * v2.x;
-          const double dy = (double)kxd * v0.y + (double)kyd * v1.y + (double)kzd * v2.y;
+          const double dx = kxd * v0.x + kyd * v1.x + kzd * v2.x;
+          const double dy = kxd * v0.y + kyd * v1.y + kzd * v2.y;
           const double d = sqrt(dx * dx + dy * dy);
           mx = d > mx ? d : mx;
         }

@@ -219,3 +219,96 @@ def test_rotation_change_drops_graph(B, ref):
     assert rel_l2_w(host(s), want) < TOL_STEP["f64"]
     with pytest.raises(B.PsError):
         p.set_rotation(float("nan"), 0.0, 0.0)
+
+
+# ---------------------------------------------------------------- non-cubic box
+BOX = (2 * np.pi, 3 * np.pi, 5 * np.pi)
+
+
+def box_solenoidal(z, L):
+    """Remove the divergence of each 3-vector group in the box's metric
+    (physical wavenumbers 2 pi n / L): states of a stretched box must be
+    solenoidal there for the two MHD forms to agree."""
+    N = z.shape[-2]
+    n = np.fft.fftfreq(N, 1.0 / N)
+    k = [2 * np.pi / L[0] * np.arange(N // 2 + 1)[None, None, :],
+         2 * np.pi / L[1] * n[None, :, None], 2 * np.pi / L[2] * n[:, None, None]]
+    k2 = k[0] ** 2 + k[1] ** 2 + k[2] ** 2
+    k2[0, 0, 0] = 1.0
+    out = z.copy()
+    for g in range(0, z.shape[0], 3):
+        kv = sum(k[c] * z[g + c] for c in range(3))
+        for c in range(3):
+            out[g + c] = z[g + c] - k[c] * kv / k2
+    return out
+
+
+@pytest.fixture
+def boxed(ref):
+    ref.set_box(*BOX)
+    yield ref
+    ref.set_box()
+
+
+@pytest.mark.parametrize("prune", [0, 1])
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_box_nonlinear_ns(B, boxed, dt, prune):
+    say("box nonlinear ns", dt, prune)
+    N = 24
+    u = rounded(synth.random_ns(N, 41, 2.0), dt)
+    p = B.Plan(N, 3, dt)
+    p.set_variant("prune", prune)
+    p.set_box(*BOX)
+    got = host(p.nonlinear_ns(to_dev(u, dt)))
+    assert rel_l2_w(got, boxed.nonlinear_ns(u)) < TOL_NL[dt]
+
+
+@pytest.mark.parametrize("form", [0, 1])
+@pytest.mark.parametrize("prune", [0, 1])
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_box_rk2_mhd_rotation(B, boxed, dt, prune, form):
+    """Everything at once: stretched box, rotation, MHD in both forms."""
+    say("box rk2 mhd rotation", dt, prune, form)
+    N = 24
+    z0 = rounded(box_solenoidal(synth.random_mhd(N, 43, 44, 2.0), BOX), dt)
+    p = B.Plan(N, 6, dt)
+    p.set_variant("prune", prune)
+    p.set_variant("form", form)
+    p.set_box(*BOX)
+    p.set_rotation(*OMEGA)
+    s = to_dev(z0, dt)
+    p.rk2_step(s, B.PS_MHD, 0.02, 0.01, 5e-3, 2)
+    want = boxed.rk2_step(z0, MHD, 0.02, 0.01, 5e-3, 2, omega=OMEGA)
+    assert rel_l2_w(host(s), want) < 3 * TOL_STEP[dt], rel_l2_w(host(s), want)
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_box_spectrum(B, boxed, dt):
+    say("box spectrum", dt)
+    N = 32
+    u = rounded(synth.random_ns(N, 45, 3.0), dt)
+    p = B.Plan(N, 3, dt)
+    p.set_box(*BOX)
+    spec, tot = p.energy_spectrum(to_dev(u, dt))
+    ws, wt = boxed.energy_spectrum(u)
+    spec, tot = spec.cpu().numpy(), tot.cpu().numpy()
+    assert np.abs(spec - ws).max() <= 1e-12 * ws.max()
+    assert abs(tot[0] - wt[0]) <= 1e-12 * wt[0] and abs(tot[1] - wt[1]) <= 1e-12 * wt[1]
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_box_abc_closed_form(B, dt):
+    """GPU against the closed form: the ABC flow of physical wavenumber 1 in
+    a (2 pi, 4 pi, 6 pi) box only decays, by the RK2 factor of -nu dt."""
+    import pins
+    say("box abc", dt)
+    N, L, nu, step = 16, (2 * np.pi, 4 * np.pi, 6 * np.pi), 0.05, 0.1
+    U = pins.box_abc(N, L)
+    p = B.Plan(N, 3, dt)
+    p.set_box(*L)
+    d = to_dev(U, dt)
+    p.rk2_step(d, B.PS_NS, nu, 0.0, step, 2)
+    want = U * pins._rk2_factor(-nu, step) ** 2
+    assert rel_l2(host(d), want) < (1e-13 if dt == "f64" else 2e-6)
+    with pytest.raises(B.PsError):
+        p.set_box(0.0, 1.0, 1.0)
