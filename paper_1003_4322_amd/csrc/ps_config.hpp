@@ -75,11 +75,13 @@ struct StridedTX {
 
 constexpr bool has_variants(int N) { return N >= 256; }
 
-// x passes: rows live in LDS with the padded layout (pad8), M + M/8 + 1 slots;
-// the fused pass also stages the twiddle table (2M values).
+// x passes: rows live in LDS with the padded layout (pad8, M + M/8 + 1 slots)
+// or, in the fused pass's swizzled variants, LaySwz32 (32 (M/32 + 1) slots);
+// the fused pass also stages twiddles (2M values).
 template <typename T, int M, int TQ>
 struct XCfg {
-  static constexpr int SLOTS = M + M / 8 + 1;
+  // LDS slots per row: the larger of the padded and swizzled layouts
+  static constexpr int SLOTS = (M + M / 8 + 1) > 32 * (M / 32 + 1) ? (M + M / 8 + 1) : 32 * (M / 32 + 1);
   static constexpr int G = (256 / TQ) < 1 ? 1 : 256 / TQ;  // plain passes: rows per workgroup
   static constexpr bool fits(int f, int rb) {
     return (f * rb * SLOTS + 2 * M) * 2 * (int)sizeof(T) <= 65536 && f * rb * TQ <= 1024;
@@ -107,13 +109,15 @@ struct ZV {
 struct XV {
   int rb_ns, rb_mhd;  // rows per workgroup (reduced while the LDS tile would not fit)
   bool alt;           // radix-16 schedule
+  bool swz;           // rows in LDS swizzled (LaySwz32) instead of padded (LayPad8)
 };
 constexpr ZV ZCURL_V[] = {{1, 1, 1, false, false}, {1, 2, 1, false, false}, {1, 2, 2, false, false},
                           {1, 2, 1, true, false},  {1, 1, 1, false, true}};
 constexpr ZV ZEPI_V[] = {{0, 1, 1, false}, {1, 1, 1, false}, {1, 1, 2, false}, {1, 1, 1, true},
                          {2, 1, 1, false}, {1, 2, 1, false}, {1, 2, 2, false}, {2, 2, 1, false}};
 constexpr ZV STR_V[] = {{0, 1, 1, false}, {1, 1, 1, false}, {0, 1, 1, true}, {1, 1, 1, true}};
-constexpr XV XPROD_V[] = {{2, 1, false}, {4, 2, false}, {4, 2, true}, {2, 1, true}};
+constexpr XV XPROD_V[] = {{2, 1, false, false}, {4, 2, false, false}, {4, 2, true, false},
+                          {2, 1, true, false},  {2, 1, false, true},  {4, 2, false, true}};
 constexpr int NZCURL = sizeof(ZCURL_V) / sizeof(ZV);
 // waves per SIMD that minb workgroups of `threads` threads occupy (4 SIMDs per CU)
 constexpr int waves_per_simd(int minb, int threads) {

@@ -217,25 +217,40 @@ constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
 // LayPad8 serves contiguous rows and inserts one pad slot after every 8
 // elements, so the stride-R scatter of the first Stockham stage hits
 // distinct LDS banks.
-// off(a + c) = off(a) + offc(c) whenever c % 8 == 0, or a % 8 == 0 and c < 8
-// (always, for the unpadded layout); the transforms use it to move the
-// constant part of an unrolled index into the LDS instruction's offset.
+// SPLIT 2: off(a + c) = off(a) + offc(c) always; 1: whenever c % 8 == 0, or
+// a % 8 == 0 and c < 8; 0: never.  The transforms use it to move the constant
+// part of an unrolled index into the LDS instruction's offset.
 struct LayStride {
-  static constexpr bool PADDED = false;
+  static constexpr int SPLIT = 2;
   __device__ __forceinline__ static int off(int i, int ls) { return i * ls; }
   __device__ __forceinline__ static int offc(int c, int ls) { return c * ls; }
 };
 struct LayPad8 {
-  static constexpr bool PADDED = true;
+  static constexpr int SPLIT = 1;
+  __host__ __device__ static constexpr int slots(int M) { return M + M / 8 + 1; }
   __device__ __forceinline__ static int off(int i, int) { return i + (i >> 3); }
   __device__ __forceinline__ static int offc(int c, int) { return c + c / 8; }
 };
 __host__ __device__ constexpr int pad8(int i) { return i + (i >> 3); }
+// rows, swizzled: element i at i ^ h(i / 32) with h(b) = (b & 7) | ((b & 6) << 2),
+// a permutation inside every 32-element block.  For the radix-8 schedules it
+// gives 32 distinct bank pairs to each of: 32 consecutive elements, the
+// stride-8 scatter of a first radix-8 stage, and the scatter of a second one
+// (pad8 wraps the first of these across 35 slots, so three lanes collide).
+struct LaySwz32 {
+  static constexpr int SPLIT = 0;
+  __host__ __device__ static constexpr int slots(int M) { return 32 * (M / 32 + 1); }
+  __device__ __forceinline__ static int off(int i, int) {
+    const int b = i >> 5;
+    return i ^ ((b & 7) | ((b & 6) << 2));
+  }
+  __device__ __forceinline__ static int offc(int c, int) { return c; }
+};
 // column tiles (TX columns side by side): row idx of the tile padded by one
 // row per eight, so that a first stage writing rows j R + m from lanes of
 // consecutive j spreads over the LDS banks instead of hitting one
 struct LayColPad8 {
-  static constexpr bool PADDED = true;
+  static constexpr int SPLIT = 1;
   __device__ __forceinline__ static int off(int i, int ls) { return (i + (i >> 3)) * ls; }
   __device__ __forceinline__ static int offc(int c, int ls) { return (c + c / 8) * ls; }
 };
@@ -354,7 +369,7 @@ struct Stockham {
     constexpr bool EXACT = (L / R) % TQ == 0;
     if (act) {
       // ---- gather inputs
-      constexpr bool SPLIT_G = !Lay::PADDED || (L / R) % 8 == 0;
+      constexpr bool SPLIT_G = Lay::SPLIT == 2 || (Lay::SPLIT == 1 && (L / R) % 8 == 0);
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
         const int j = q + TQ * b;
@@ -385,7 +400,7 @@ struct Stockham {
       }
     }
     if constexpr (!LAST) {
-      constexpr bool SPLIT_W = !Lay::PADDED || NS % 8 == 0 || (NS == 1 && R % 8 == 0);
+      constexpr bool SPLIT_W = Lay::SPLIT == 2 || (Lay::SPLIT == 1 && (NS % 8 == 0 || (NS == 1 && R % 8 == 0)));
       __syncthreads();  // all reads of the previous LDS contents are done
 #pragma unroll
       for (int b = 0; b < NB; ++b) {

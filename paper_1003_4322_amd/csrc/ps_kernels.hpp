@@ -563,10 +563,10 @@ __host__ __device__ constexpr int row_slots(int M) { return pad8(M) + 1; }
 // rows of LDS (and thread groups) per grid row of the fused product pass
 __host__ __device__ constexpr int xprod_slots(bool mhd, bool els) { return els ? 9 : mhd ? 12 : 6; }
 
-template <typename T>
+template <typename T, class Lay = LayPad8>
 __device__ __forceinline__ C2<T> c2r_pre(const C2<T>* buf, int k, int M, const C2<T>* __restrict__ tw) {
   // branch-free: at k = 0 the pair is (Re X[0], Re X[M]) (M - k = M there)
-  C2<T> xk = buf[pad8(k)], xm = conj(buf[pad8(M - k)]);
+  C2<T> xk = buf[Lay::off(k, 1)], xm = conj(buf[Lay::off(M - k, 1)]);
   xk.y = k == 0 ? T(0) : xk.y;
   xm.y = k == 0 ? T(0) : xm.y;
   return (xk + xm) + mul_i(cmulc(xk - xm, tw[k]));  // conj(tw[k]) = e^{+2 pi i k/N}
@@ -585,10 +585,10 @@ __device__ __forceinline__ C2<T> c2r_pre_g(const C2<T>* src, int k, int M, int k
   return (xk + xm) + mul_i(cmulc(xk - xm, tw[k]));
 }
 
-template <typename T>
+template <typename T, class Lay = LayPad8>
 __device__ __forceinline__ C2<T> r2c_post(const C2<T>* buf, int k, int M, const C2<T>* __restrict__ tw) {
-  const C2<T> zk = buf[pad8(k == M ? 0 : k)];
-  const C2<T> zm = conj(buf[pad8(k == 0 ? 0 : M - k)]);
+  const C2<T> zk = buf[Lay::off(k == M ? 0 : k, 1)];
+  const C2<T> zm = conj(buf[Lay::off(k == 0 ? 0 : M - k, 1)]);
   const C2<T> e = T(0.5) * (zk + zm);
   const C2<T> o = T(0.5) * mul_mi(zk - zm);
   return e + cmul(o, tw[k]);
@@ -679,13 +679,13 @@ __global__ __launch_bounds__(G* TQ) void k_x_r2c(XArgs<T> a) {
 //
 // ELS (MHD, Elsasser form): inputs z+ (fields 0-2) and z- (3-5); outputs the
 // nine products T_ij = z+_i z-_j as field 3 i + j.
-template <typename T, int M, int TQ, int RB, class RL, bool MHD, bool ELS = false>
+template <typename T, int M, int TQ, int RB, class RL, bool MHD, bool ELS = false, class RLay = LayPad8>
 __global__ __launch_bounds__(xprod_slots(MHD, ELS) * RB * TQ) void k_x_prod(XArgs<T> a) {
   constexpr int FIN = ELS ? 6 : MHD ? 12 : 6, FOUT = ELS ? 9 : MHD ? 6 : 3;
   constexpr int G = xprod_slots(MHD, ELS) * RB, NT = G * TQ;
   using EI = Stockham<T, M, TQ, INV, RL>;
   using EF = Stockham<T, M, TQ, FWD, RL>;
-  constexpr int LP = row_slots(M);
+  constexpr int LP = RLay::slots(M);
   // rows of every field, then twiddles: the M + 1 factors e^{-2 pi i k/N} of
   // the half-length pre- and post-processing followed by the transforms' M - 1
   // factors in the bank-friendly staged order, or (when that would not fit in
@@ -711,7 +711,7 @@ __global__ __launch_bounds__(xprod_slots(MHD, ELS) * RB * TQ) void k_x_prod(XArg
   const bool in_act = f < FIN;
   const C2<T>* src = a.in + boxi * a.in_bs + (in_act ? f : 0) * a.in_fs + rloc * a.in_pitch;
   if (!ELS && in_act) {
-    for (int k = q; k <= M; k += TQ) buf[pad8(k)] = rok && k <= a.kmax ? src[k] : zero2<T>();
+    for (int k = q; k <= M; k += TQ) buf[RLay::off(k, 1)] = rok && k <= a.kmax ? src[k] : zero2<T>();
   }
   __syncthreads();
   // ---- inverse real FFTs, physical values back into the same slot.  ELS: the
@@ -719,17 +719,17 @@ __global__ __launch_bounds__(xprod_slots(MHD, ELS) * RB * TQ) void k_x_prod(XArg
   {
     C2<T> v[EI::SLOTS];
     if constexpr (ELS)
-      EI::template run_tw<LayPad8>(
+      EI::template run_tw<RLay>(
           v, buf, 1, q, twf,
           [&](int, int k) { return rok ? c2r_pre_g(src, k, M, a.kmax, twl) : zero2<T>(); }, in_act);
     else
-      EI::template run_tw<LayPad8>(v, buf, 1, q, twf, [&](int, int k) { return c2r_pre(buf, k, M, twl); },
+      EI::template run_tw<RLay>(v, buf, 1, q, twf, [&](int, int k) { return c2r_pre<T, RLay>(buf, k, M, twl); },
                                    in_act);
     __syncthreads();
     if (in_act) {
 #pragma unroll
       for (int s = 0; s < EI::LAST_NB * EI::RL_; ++s)
-        if (EI::last_valid(q, s)) buf[pad8(EI::last_index(q, s))] = v[s];
+        if (EI::last_valid(q, s)) buf[RLay::off(EI::last_index(q, s), 1)] = v[s];
     }
   }
   __syncthreads();
@@ -737,7 +737,7 @@ __global__ __launch_bounds__(xprod_slots(MHD, ELS) * RB * TQ) void k_x_prod(XArg
   // in the first stage of the forward transforms instead (below).
   for (int i = tid; !ELS && i < RB * M; i += NT) {
     const int r = i / M, n = i % M;
-    auto at = [&](int ff) -> C2<T>& { return smem[(ff * RB + r) * LP + pad8(n)]; };
+    auto at = [&](int ff) -> C2<T>& { return smem[(ff * RB + r) * LP + RLay::off(n, 1)]; };
     const C2<T> u0 = at(0), u1 = at(1), u2 = at(2);
     const C2<T> w0 = at(3), w1 = at(4), w2 = at(5);
     auto cx = [](C2<T> a1, C2<T> a2, C2<T> b1, C2<T> b2) {  // a1 b2 - a2 b1 per point
@@ -769,27 +769,27 @@ __global__ __launch_bounds__(xprod_slots(MHD, ELS) * RB * TQ) void k_x_prod(XArg
       // first stage's barrier, so overwriting the input slots after it is safe
       const C2<T>* ra = smem + ((f / 3) * RB + rb) * LP;
       const C2<T>* rm = smem + ((3 + f % 3) * RB + rb) * LP;
-      EF::template run_tw<LayPad8>(
+      EF::template run_tw<RLay>(
           v, buf, 1, q, twf,
           [&](int, int n) {
-            const C2<T> x = ra[pad8(n)], y = rm[pad8(n)];
+            const C2<T> x = ra[RLay::off(n, 1)], y = rm[RLay::off(n, 1)];
             return C2<T>{x.x * y.x, x.y * y.y};
           },
           active);
     } else {
-      EF::template run_tw<LayPad8>(v, buf, 1, q, twf, [&](int, int n) { return buf[pad8(n)]; }, active);
+      EF::template run_tw<RLay>(v, buf, 1, q, twf, [&](int, int n) { return buf[RLay::off(n, 1)]; }, active);
     }
     __syncthreads();
     if (active) {
 #pragma unroll
       for (int s = 0; s < EF::LAST_NB * EF::RL_; ++s)
-        if (EF::last_valid(q, s)) buf[pad8(EF::last_index(q, s))] = v[s];
+        if (EF::last_valid(q, s)) buf[RLay::off(EF::last_index(q, s), 1)] = v[s];
     }
   }
   __syncthreads();
   if (active && rok) {
     C2<T>* dst = a.out + boxi * a.out_bs + f * a.out_fs + rloc * a.out_pitch;
-    for (int k = q; k <= M && k <= a.kmax; k += TQ) dst[k] = r2c_post(buf, k, M, twl);
+    for (int k = q; k <= M && k <= a.kmax; k += TQ) dst[k] = r2c_post<T, RLay>(buf, k, M, twl);
   }
 }
 

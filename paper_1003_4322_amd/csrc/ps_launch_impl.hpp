@@ -240,7 +240,8 @@ hipError_t x_prod_v(bool mhd, bool els, XArgs<T> a, hipStream_t s) {
     constexpr bool M_ = decltype(mhd_c)::value, E_ = decltype(els_c)::value;
     constexpr int RB = decltype(rb_c)::value;
     const long grid = (a.rows * a.nb + RB - 1) / RB;
-    k_x_prod<T, N / 2, LC::TQ, RB, typename LC::RL, M_, E_>
+    using RLay = std::conditional_t<v.swz, LaySwz32, LayPad8>;
+    k_x_prod<T, N / 2, LC::TQ, RB, typename LC::RL, M_, E_, RLay>
         <<<dim3((unsigned)grid), dim3(xprod_slots(M_, E_) * RB * LC::TQ), 0, s>>>(a);
     return hipGetLastError();
   };
