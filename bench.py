@@ -16,7 +16,6 @@ the library's algorithmic byte counts give the achieved GB/s per pass.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import math
 import os
@@ -44,13 +43,9 @@ def log(*a):
 
 
 def src_hash() -> str:
-    h = hashlib.sha256()
-    d = os.path.join(ROOT, "paper_1003_4322_amd", "csrc")
-    for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".hpp", ".cpp")):
-            h.update(f.encode())
-            h.update(open(os.path.join(d, f), "rb").read())
-    return h.hexdigest()[:16]
+    """Hash of the device-side sources the traffic counters belong to."""
+    from paper_1003_4322_amd.profsum import src_hash as h
+    return h()
 
 
 def initial_state(w, dtype_c, device):

@@ -171,7 +171,12 @@ ps_status ps_energy_spectrum(ps_plan p, const void *fhat, int nfields, double *s
  * takes N+- = -i P(k) k_j F[z-+_j z+-_i] from the nine products z+_i z-_j
  * (fifteen real transforms per evaluation instead of eighteen; the default);
  * the two agree up to rounding when z+- are solenoidal, as every state the
- * step produces is.  Setting a variant drops a cached graph. */
+ * step produces is.  Kind "pipe" v: the inverse y pass, the product pass and
+ * the forward y pass of each right-hand side run as 2^v slabs of z-planes
+ * spread over helper streams (each plane's chain is independent of the
+ * others'), so that one slab's memory-bound y passes overlap another's
+ * compute-bound product pass; 0 = one slab on the plan's stream.  Setting a
+ * variant drops a cached graph. */
 ps_status ps_plan_set_variant(ps_plan p, const char *kind, int variant);
 int ps_plan_get_variant(ps_plan p, const char *kind);
 int ps_plan_variant_count(ps_plan p, const char *kind);

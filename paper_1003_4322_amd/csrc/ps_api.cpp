@@ -98,6 +98,10 @@ struct ps_plan_s {
   std::vector<void*> dbufs;             // device lists behind dtiles
   hipStream_t stream = nullptr;
   hipStream_t cap = nullptr;  // private stream used only for graph capture
+  // z-slab pipeline of the y / x / y passes: helper streams and fork/join events
+  static constexpr int NAUX = 3;
+  hipStream_t aux[NAUX] = {};
+  hipEvent_t ev_fork = nullptr, ev_join[NAUX] = {};
   void* ws = nullptr;
   size_t ws_bytes = 0, ws_need = 0;
   size_t real_total = 0, cplx_total = 0;
@@ -118,7 +122,9 @@ namespace {
 
 size_t csize(const ps_plan_s* p) { return p->dtype == PS_F32 ? 8 : 16; }
 
-const char* const KINDS[] = {"y", "z", "z_curl", "z_epi", "x_prod", "batch", "prune", "form"};
+const char* const KINDS[] = {"y", "z", "z_curl", "z_epi", "x_prod", "batch", "prune", "form", "pipe"};
+// "pipe" variant v: the y / x / y passes run as 2^v z-slabs over the helper streams
+constexpr int NPIPE = 4;
 
 int var_of(const ps_plan_s* p, const char* kind) {
   auto it = p->var.find(kind);
@@ -225,18 +231,21 @@ struct Seq {
   }
   double cs() const { return (double)sizeof(C); }
 
-  // strided pass in place on the first nfl fields of every box, line = z
-  ps_status ypass(C* x, long pitch, long bs, int nfl, int dir, int prune = 0) {
+  // strided pass in place on the first nfl fields of every box, line = z;
+  // nz >= 0: only the z-planes [z0, z0 + nz)
+  ps_status ypass(C* x, long pitch, long bs, int nfl, int dir, int prune = 0, int z0 = 0, int nz = -1) {
+    if (nz < 0) nz = b.N;
     ps::StridedArgs<T> a{};
     a.prune = prune;
-    a.in = x; a.out = x; a.tw = tw();
+    a.out = x + (long)z0 * b.N * pitch; a.in = a.out; a.tw = tw();
     a.in_fs = a.out_fs = (long)b.N * b.N * pitch;
     a.in_ls = a.out_ls = (long)b.N * pitch;
     a.in_es = a.out_es = pitch;
     a.in_bs = a.out_bs = bs;
-    a.ncols = (int)b.H; a.nlines = b.N; a.nf = nfl; a.nb = nb;
+    a.ncols = (int)b.H; a.nlines = nz; a.nf = nfl; a.nb = nb;
     const double full = (double)b.N * b.N * b.kx_keep, disk = (double)b.N * b.n_disk;
-    const double bytes = prune == 0 ? 2.0 * nfl * nb * b.nc * cs() : (double)nfl * nb * (full + disk) * cs();
+    const double frac = (double)nz / b.N;
+    const double bytes = frac * (prune == 0 ? 2.0 * nfl * nb * b.nc * cs() : (double)nfl * nb * (full + disk) * cs());
     const int v = var_of(p, "y");
     return enqueue(p, s, dir == ps::FWD ? "y_fwd" : "y_inv", bytes,
                    [&](hipStream_t st) { return ps::launch_strided<T>(b.N, dir, v, a, st); });
@@ -302,16 +311,17 @@ struct Seq {
     return enqueue(p, s, "z_curl", bytes,
                    [&](hipStream_t q) { return ps::launch_z_curl<T>(b.N, mhd, els(mhd), v, ca, b.dt, q); });
   }
-  ps_status pass_xprod(bool mhd) {
+  ps_status pass_xprod(bool mhd, int z0 = 0, int nz = -1) {
+    if (nz < 0) nz = b.N;
     const int nphys = this->nphys(mhd), nprod = this->nprod(mhd);
     ps::XArgs<T> xa{};
-    xa.in = work(); xa.out = work(); xa.tw = tw();
+    xa.out = work() + (long)z0 * b.N * b.P; xa.in = xa.out; xa.tw = tw();
     xa.in_pitch = xa.out_pitch = b.P; xa.in_fs = xa.out_fs = b.ncp;
     xa.in_bs = xa.out_bs = wk_bs();
-    xa.rows = (long)b.N * b.N; xa.nf = nphys; xa.nb = nb;
+    xa.rows = (long)nz * b.N; xa.nf = nphys; xa.nb = nb;
     xa.kmax = p->prune ? (int)b.kx_keep - 1 : b.N / 2;
     const int v = var_of(p, "x_prod");
-    const double per = p->prune ? (double)b.N * b.N * b.kx_keep : (double)b.nc;
+    const double per = (double)nz / b.N * (p->prune ? (double)b.N * b.N * b.kx_keep : (double)b.nc);
     return enqueue(p, s, "x_prod", (double)(nphys + nprod) * nb * per * cs(),
                    [&](hipStream_t q) { return ps::launch_x_prod<T>(b.N, mhd, els(mhd), v, xa, q); });
   }
@@ -338,13 +348,39 @@ struct Seq {
   }
 
   // nonlinear right-hand side, epilogue mode 0/1/2 (see k_z_epi)
+  // inverse y, products, forward y on the z-planes [z0, z0 + nz): every plane's
+  // chain is independent of the others' (only the z passes couple planes)
+  ps_status yxy(bool mhd, int z0, int nz) {
+    ps_status st = ypass(work(), b.P, wk_bs(), nphys(mhd), ps::INV, p->prune ? 1 : 0, z0, nz);
+    if (!st) st = pass_xprod(mhd, z0, nz);
+    if (!st) st = ypass(work(), b.P, wk_bs(), nprod(mhd), ps::FWD, p->prune ? 2 : 0, z0, nz);
+    return st;
+  }
+
   ps_status rhs(const C* src, bool mhd, int mode, C* out, const C* st0, const C* st1, T h, T nua, T nub) {
-    const int nphys = this->nphys(mhd), nprod = this->nprod(mhd);
     ps_status st = pass_zcurl(src, mhd);
     if (st) return st;
-    if ((st = ypass(work(), b.P, wk_bs(), nphys, ps::INV, p->prune ? 1 : 0))) return st;
-    if ((st = pass_xprod(mhd))) return st;
-    if ((st = ypass(work(), b.P, wk_bs(), nprod, ps::FWD, p->prune ? 2 : 0))) return st;
+    const int slabs = std::min(1 << var_of(p, "pipe"), b.N);
+    if (slabs <= 1) {
+      if ((st = yxy(mhd, 0, b.N))) return st;
+    } else {
+      // fork the slabs over the helper streams (their memory-bound y passes
+      // overlap other slabs' compute-bound product pass), then join
+      const int k = std::min(slabs, ps_plan_s::NAUX);
+      hipError_t e = hipEventRecord(p->ev_fork, s);
+      for (int i = 0; i < k && e == hipSuccess; ++i) e = hipStreamWaitEvent(p->aux[i], p->ev_fork, 0);
+      if (e != hipSuccess) return hip_fail(e, "slab fork");
+      for (int i = 0; i < slabs; ++i) {
+        Seq<T> q{p, b, b0, nb, p->aux[i % k]};
+        const int z0 = (int)((long)i * b.N / slabs), z1 = (int)((long)(i + 1) * b.N / slabs);
+        if ((st = q.yxy(mhd, z0, z1 - z0))) return st;
+      }
+      for (int i = 0; i < k && e == hipSuccess; ++i) {
+        e = hipEventRecord(p->ev_join[i], p->aux[i]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, p->ev_join[i], 0);
+      }
+      if (e != hipSuccess) return hip_fail(e, "slab join");
+    }
     return pass_zepi(mhd, mode, out, st0, st1, h, nua, nub);
   }
 
@@ -356,6 +392,8 @@ struct Seq {
     if (!strcmp(kind, "x_prod")) return pass_xprod(mhd);
     // as in the step's first stage (mode 1: pruned like the step, z* <- state)
     if (!strcmp(kind, "z_epi")) return pass_zepi(mhd, 1, zstar(), state, nullptr, T(0), T(0), T(0));
+    // the whole right-hand side as in the first stage (slab pipeline)
+    if (!strcmp(kind, "pipe")) return rhs(state, mhd, 1, zstar(), state, nullptr, T(0), T(0), T(0));
     return fail(PS_ERR_ARG, std::string("no tuning launch for kind ") + kind);
   }
 
@@ -420,6 +458,11 @@ void free_plan(ps_plan p) {
   }
   if (p->gexec) hipGraphExecDestroy(p->gexec);
   if (p->cap) hipStreamDestroy(p->cap);
+  for (auto& a : p->aux)
+    if (a) hipStreamDestroy(a);
+  if (p->ev_fork) hipEventDestroy(p->ev_fork);
+  for (auto& e : p->ev_join)
+    if (e) hipEventDestroy(e);
   for (auto& kv : p->tables) hipFree(kv.second);
   for (void* d : p->dbufs) hipFree(d);
   delete p;
@@ -627,6 +670,11 @@ ps_status ps_plan_create_batch(ps_plan* out, int nbox, const int* Ns, int nfield
       p->var["y"] = dtype == PS_F32 ? 2 : 0;
     }
     e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
+    for (int i = 0; i < ps_plan_s::NAUX && e == hipSuccess; ++i)
+      e = hipStreamCreateWithFlags(&p->aux[i], hipStreamNonBlocking);  // default priority
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming);
+    for (int i = 0; i < ps_plan_s::NAUX && e == hipSuccess; ++i)
+      e = hipEventCreateWithFlags(&p->ev_join[i], hipEventDisableTiming);
     if (e != hipSuccess) {
       free_plan(p);
       return hip_fail(e, "hipStreamCreate");
@@ -895,6 +943,7 @@ int ps_plan_variant_count(ps_plan p, const char* kind) {
   if (!p || !kind) return PS_ERR_ARG;
   if (!strcmp(kind, "batch") || !strcmp(kind, "prune")) return 2;
   if (!strcmp(kind, "form")) return p->nfields == 6 ? 2 : 1;
+  if (!strcmp(kind, "pipe")) return NPIPE;
   int n = 1;
   for (auto& b : p->boxes) n = std::max(n, ps::variant_count(kind, b.N, p->nfields == 6));
   return n;
@@ -924,8 +973,8 @@ ps_status ps_plan_autotune(ps_plan p, const void* state, ps_model m, int reps) {
       if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return fail(PS_ERR_HIP, "hipEventCreate failed");
       ps_status out = PS_OK;
-      for (const char* kind : {"z_curl", "y", "x_prod", "z_epi"}) {
-        const int n = ps::variant_count(kind, b.N, mhd);
+      for (const char* kind : {"z_curl", "y", "x_prod", "z_epi", "pipe"}) {
+        const int n = !strcmp(kind, "pipe") ? NPIPE : ps::variant_count(kind, b.N, mhd);
         if (n <= 1) continue;
         int best = 0;
         float best_ms = 1e30f;

@@ -49,10 +49,12 @@ def kind_of(name: str) -> str:
 
 
 def src_hash() -> str:
+    """Hash of the device-side sources (kernels, their configurations and
+    launchers); host-only code (ps_api.cpp) does not change a kernel's traffic."""
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_1003_4322_amd", "csrc")
     for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".hpp", ".cpp")):
+        if f.endswith((".hip", ".hpp")):
             h.update(f.encode())
             h.update(open(os.path.join(d, f), "rb").read())
     return h.hexdigest()[:16]

@@ -312,3 +312,23 @@ def test_box_abc_closed_form(B, dt):
     assert rel_l2(host(d), want) < (1e-13 if dt == "f64" else 2e-6)
     with pytest.raises(B.PsError):
         p.set_box(0.0, 1.0, 1.0)
+
+
+# ---------------------------------------------------------------- slab pipeline
+@pytest.mark.parametrize("graphs", [True, False])
+@pytest.mark.parametrize("pipe", [1, 2, 3])
+def test_rk2_pipe(B, ref, pipe, graphs):
+    """The y / x / y passes split into 2^pipe z-slabs over helper streams
+    (captured into the step's graph or launched directly) give the same step."""
+    say("rk2 pipe", pipe, graphs)
+    for model, N, nf in ((NS, 32, 3), (MHD, 24, 6)):
+        z0 = synth.random_ns(N, 7, 2.0) if model == NS else synth.random_mhd(N, 8, 9, 2.0)
+        p = B.Plan(N, nf, "f64")
+        p.set_graphs(graphs)
+        p.set_variant("prune", 1)
+        p.set_variant("pipe", pipe)
+        s = to_dev(z0, "f64")
+        pm = B.PS_NS if model == NS else B.PS_MHD
+        p.rk2_step(s, pm, 0.02, 0.01, 2e-3, 3)
+        want = ref.rk2_step(z0, model, 0.02, 0.01, 2e-3, 3)
+        assert rel_l2_w(host(s), want) < 3 * TOL_STEP["f64"], (model, rel_l2_w(host(s), want))

@@ -60,7 +60,7 @@ def test_fft_variants(B, ref, fft_case, kind, dt):
 
 @pytest.mark.parametrize("prune", [0, 1])
 @pytest.mark.parametrize("dt", ["f32", "f64"])
-@pytest.mark.parametrize("kind", ["y", "z_curl", "x_prod", "z_epi"])
+@pytest.mark.parametrize("kind", ["y", "z_curl", "x_prod", "z_epi", "pipe"])
 def test_nonlinear_ns_variants(B, ns_case, kind, dt, prune):
     u, want = ns_case[dt]
     p = B.Plan(N, 3, dt)
@@ -76,7 +76,7 @@ def test_nonlinear_ns_variants(B, ns_case, kind, dt, prune):
 @pytest.mark.parametrize("form", [0, 1])
 @pytest.mark.parametrize("prune", [0, 1])
 @pytest.mark.parametrize("dt", ["f32", "f64"])
-@pytest.mark.parametrize("kind", ["y", "z_curl", "x_prod", "z_epi"])
+@pytest.mark.parametrize("kind", ["y", "z_curl", "x_prod", "z_epi", "pipe"])
 def test_nonlinear_mhd_variants(B, mhd_case, kind, dt, prune, form):
     z, want = mhd_case[dt]
     p = B.Plan(N, 6, dt)
