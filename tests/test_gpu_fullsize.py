@@ -77,7 +77,8 @@ def test_mhd512_nonlinear_sampled(B, ref, dt, form):
 
 
 @pytest.mark.parametrize("case", [("mhd", 512, "f64", 0), ("mhd", 512, "f32", 0), ("mhd", 512, "f64", 1),
-                                  ("mhd", 512, "f32", 1), ("ns", 1024, "f32", 0), ("ns", 1024, "f64", 0)])
+                                  ("mhd", 512, "f32", 1), ("ns", 1024, "f32", 0), ("ns", 1024, "f64", 0),
+                                  ("mhd", 1024, "f32", 1)])
 def test_rk2_embedding(B, ref, case):
     model, N, dt, form = case
     say("embedding", model, N, dt, form)
