@@ -19,10 +19,15 @@
 // replaces the paper's cache-blocked local transpose of Sec. 3).
 //
 // Fusion (each is one kernel, data touch HBM once per pass):
-//   inverse z pass + spectral curl prologue       (state -> u, w [, b, j])
-//   x pass: inverse real FFTs + cross products + forward real FFTs
-//   forward z pass + 1/N^3 + dealias + projection (+ induction curl)
+//   inverse z pass + spectral curl prologue       (state -> u, w [, b, j]);
+//                  MHD in the Elsasser form: z+- transformed as they are
+//   x pass: inverse real FFTs + products (u x w [+ j x b, u x b], or the nine
+//                  z+_i z-_j) + forward real FFTs
+//   forward z pass + 1/N^3 + dealias + projection (+ induction curl, or the
+//                  divergence of the Elsasser products) + Coriolis term
 //                  + explicit midpoint RK2 stage update
+// Pruned launches skip every pencil and mode the 2/3 rule makes zero; box
+// lengths enter through the per-axis factors 2 pi / L of the wavenumbers.
 #pragma once
 #include <type_traits>
 

@@ -1,4 +1,4 @@
-"""Every kernel variant (tile width, reload, occupancy hint, radix-16
+"""Every kernel variant (tile width, split and direct forms, occupancy hint, radix-16
 schedule, rows per workgroup) against the FP64 oracle at 256^3, the smallest
 size with variants.  Same tolerances as the main parity suite."""
 import numpy as np
