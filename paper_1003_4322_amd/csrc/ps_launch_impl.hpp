@@ -247,17 +247,23 @@ hipError_t x_prod_v(bool mhd, bool els, XArgs<T> a, hipStream_t s) {
   };
   using t_ = std::true_type;
   using f_ = std::false_type;
+  // short rows (few threads per transform): enough rows per workgroup for
+  // about 192 threads, so that small boxes still fill whole waves
+  constexpr auto want = [](int slots, int rb) {
+    const int w = 192 / (slots * LC::TQ);
+    return w > rb ? w : rb;
+  };
   if (mhd && els) {
     if constexpr (X::fits(9, 1))
-      return go(t_{}, t_{}, std::integral_constant<int, X::rb(9, v.rb_mhd)>{});
+      return go(t_{}, t_{}, std::integral_constant<int, X::rb(9, want(9, v.rb_mhd))>{});
     return hipErrorInvalidValue;
   }
   if (mhd) {
     if constexpr (X::MHD_OK)
-      return go(t_{}, f_{}, std::integral_constant<int, X::rb(12, v.rb_mhd)>{});
+      return go(t_{}, f_{}, std::integral_constant<int, X::rb(12, want(12, v.rb_mhd))>{});
     return hipErrorInvalidValue;
   }
-  return go(f_{}, f_{}, std::integral_constant<int, X::rb(6, v.rb_ns)>{});
+  return go(f_{}, f_{}, std::integral_constant<int, X::rb(6, want(6, v.rb_ns))>{});
 }
 
 template <typename T, int N>
