@@ -175,8 +175,9 @@ ps_status ps_energy_spectrum(ps_plan p, const void *fhat, int nfields, double *s
  * the forward y pass of each right-hand side run as 2^v slabs of z-planes
  * spread over helper streams (each plane's chain is independent of the
  * others'), so that one slab's memory-bound y passes overlap another's
- * compute-bound product pass; 0 = one slab on the plan's stream.  Setting a
- * variant drops a cached graph. */
+ * compute-bound product pass; 0 = one slab on the plan's stream (default;
+ * ps_plan_autotune leaves this kind as set).  Setting a variant drops a
+ * cached graph. */
 ps_status ps_plan_set_variant(ps_plan p, const char *kind, int variant);
 int ps_plan_get_variant(ps_plan p, const char *kind);
 int ps_plan_variant_count(ps_plan p, const char *kind);
