@@ -126,8 +126,8 @@ ps_status ps_nonlinear_mhd(ps_plan p, const void *zhat, void *nhat);
 ps_status ps_rk2_step(ps_plan p, void *state, ps_model m, double nu, double eta, double dt,
                       int nsteps);
 
-/* Frame rotation for ps_rk2_step (Sec. 5: the code integrates the equations
- * "including rotation"; the paper gives no formula).  In a frame rotating at
+/* Frame rotation for ps_rk2_step (Sec. 5 lists rotating flows among what the
+ * code integrates; the paper gives no formula).  In a frame rotating at
  * angular velocity Omega = (ox, oy, oz) the momentum equation gains the
  * Coriolis acceleration -2 Omega x u (the centrifugal part is a gradient and
  * goes into the pressure), projected like every other term; F above gains

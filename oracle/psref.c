@@ -648,8 +648,9 @@ int psref_nonlinear_at(int N, int model, const double *fhat, int nk, const int *
 }
 
 /* ------------------------------------------------------------------------ */
-/* Time advance.  The paper's "main time-advance loop" does not name its     */
-/* integrator; the explicit midpoint second-order Runge-Kutta method is used:*/
+/* Time advance.  The paper times a time-advance loop (Sec. 4) without      */
+/* naming its integrator; the explicit midpoint second-order Runge-Kutta    */
+/* method is used:                                                           */
 /*   z* = z^n + (dt/2) F(z^n),   z^{n+1} = z^n + dt F(z*)                    */
 /* F(u) = N(u) - nu |k|^2 u (NS);  for MHD in Elsasser variables             */
 /* F(z+-) = N+-(z) - (nu+eta)/2 |k|^2 z+- - (nu-eta)/2 |k|^2 z-+.            */
