@@ -664,7 +664,7 @@ ps_status ps_plan_create_batch(ps_plan* out, int nbox, const int* Ns, int nfield
     if (any_var) {
       p->var["z_curl"] = 0;
       p->var["z_epi"] = nfields == 6 ? 5 : 2;  // MHD (Elsasser): z+ and z- in two workgroups
-      p->var["x_prod"] = dtype == PS_F32 ? 4 : 2;
+      p->var["x_prod"] = dtype == PS_F32 ? 4 : 7;
       p->var["y"] = dtype == PS_F32 ? 2 : 0;
     }
     e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);

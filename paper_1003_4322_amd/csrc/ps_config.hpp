@@ -56,6 +56,21 @@ PS_ALT(768, 48, 16, 16, 3)
 PS_ALT(1024, 64, 16, 8, 8)
 #undef PS_ALT
 
+// Wide schedules: a last radix of 4 over twice the threads (four values per
+// thread at the end, whole waves for nine product rows of M = 256); product
+// pass variants only.
+template <int L>
+struct LenWide : LenCfg<L> {};
+#define PS_WIDE(L_, TQ_, ...)                    \
+  template <>                                    \
+  struct LenWide<L_> {                           \
+    using RL = Radices<__VA_ARGS__>;             \
+    static constexpr int TQ = TQ_;               \
+  };
+PS_WIDE(256, 64, 4, 4, 4, 4)
+PS_WIDE(512, 128, 8, 4, 4, 4)
+#undef PS_WIDE
+
 #undef PS_LEN
 
 // grid sizes with a compiled configuration
@@ -108,7 +123,7 @@ struct ZV {
 };
 struct XV {
   int rb_ns, rb_mhd;  // rows per workgroup (reduced while the LDS tile would not fit)
-  bool alt;           // radix-16 schedule
+  int sched;          // 0 LenCfg, 1 radix-16 (LenAlt), 2 wide (LenWide)
   bool swz;           // rows in LDS swizzled (LaySwz32) instead of padded (LayPad8)
 };
 constexpr ZV ZCURL_V[] = {{1, 1, 1, false, false}, {1, 2, 1, false, false}, {1, 2, 2, false, false},
@@ -116,8 +131,8 @@ constexpr ZV ZCURL_V[] = {{1, 1, 1, false, false}, {1, 2, 1, false, false}, {1, 
 constexpr ZV ZEPI_V[] = {{0, 1, 1, false}, {1, 1, 1, false}, {1, 1, 2, false}, {1, 1, 1, true},
                          {2, 1, 1, false}, {1, 2, 1, false}, {1, 2, 2, false}, {2, 2, 1, false}};
 constexpr ZV STR_V[] = {{0, 1, 1, false}, {1, 1, 1, false}, {0, 1, 1, true}, {1, 1, 1, true}};
-constexpr XV XPROD_V[] = {{2, 1, false, false}, {4, 2, false, false}, {4, 2, true, false},
-                          {2, 1, true, false},  {2, 1, false, true},  {4, 2, false, true}};
+constexpr XV XPROD_V[] = {{2, 1, 0, false}, {4, 2, 0, false}, {4, 2, 1, false}, {2, 1, 1, false},
+                          {2, 1, 0, true},  {4, 2, 0, true},  {1, 1, 2, true},  {1, 1, 2, false}};
 constexpr int NZCURL = sizeof(ZCURL_V) / sizeof(ZV);
 // waves per SIMD that minb workgroups of `threads` threads occupy (4 SIMDs per CU)
 constexpr int waves_per_simd(int minb, int threads) {

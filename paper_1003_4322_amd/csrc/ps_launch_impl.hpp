@@ -234,7 +234,7 @@ hipError_t x_r2c_n(XArgs<T> a, hipStream_t s) {
 template <typename T, int N, int I>
 hipError_t x_prod_v(bool mhd, bool els, XArgs<T> a, hipStream_t s) {
   constexpr XV v = XPROD_V[I];
-  using LC = Sched<N / 2, v.alt>;
+  using LC = std::conditional_t<v.sched == 2, LenWide<N / 2>, Sched<N / 2, v.sched == 1>>;
   using X = XCfg<T, N / 2, LC::TQ>;
   auto go = [&](auto mhd_c, auto els_c, auto rb_c) {
     constexpr bool M_ = decltype(mhd_c)::value, E_ = decltype(els_c)::value;
