@@ -107,6 +107,12 @@ struct XCfg {
     return r;
   }
   static constexpr bool MHD_OK = fits(12, 1);
+  // launch limits alone: 1024 threads and the 160 KB of LDS a gfx950
+  // workgroup may hold (rows that overflow 64 KB cost occupancy, not
+  // correctness)
+  static constexpr bool launchable(int f) {
+    return (f * SLOTS + 2 * M) * 2 * (int)sizeof(T) <= 163840 && f * TQ <= 1024;
+  }
 };
 
 // Kernel variant tables.  Strided-pass variants: tile shift, z_curl split and

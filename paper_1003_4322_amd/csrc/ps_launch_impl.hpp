@@ -253,17 +253,27 @@ hipError_t x_prod_v(bool mhd, bool els, XArgs<T> a, hipStream_t s) {
     const int w = 192 / (slots * LC::TQ);
     return w > rb ? w : rb;
   };
+  // a variant whose configuration does not fit this size (threads or LDS)
+  // runs as variant 0, so that every variant index is valid at every size
   if (mhd && els) {
     if constexpr (X::fits(9, 1))
       return go(t_{}, t_{}, std::integral_constant<int, X::rb(9, want(9, v.rb_mhd))>{});
+    else if constexpr (I != 0)
+      return x_prod_v<T, N, 0>(mhd, els, a, s);
     return hipErrorInvalidValue;
   }
   if (mhd) {
     if constexpr (X::MHD_OK)
       return go(t_{}, f_{}, std::integral_constant<int, X::rb(12, want(12, v.rb_mhd))>{});
+    else if constexpr (I != 0)
+      return x_prod_v<T, N, 0>(mhd, els, a, s);
     return hipErrorInvalidValue;
   }
-  return go(f_{}, f_{}, std::integral_constant<int, X::rb(6, want(6, v.rb_ns))>{});
+  if constexpr (X::launchable(6))
+    return go(f_{}, f_{}, std::integral_constant<int, X::rb(6, want(6, v.rb_ns))>{});
+  else if constexpr (I != 0)
+    return x_prod_v<T, N, 0>(mhd, els, a, s);
+  return hipErrorInvalidValue;
 }
 
 template <typename T, int N>
