@@ -168,8 +168,10 @@ ps_status ps_energy_spectrum(ps_plan p, const void *fhat, int nfields, double *s
  * ps_rk2_step (ps_nonlinear_* still writes zeros there).  Kind "form" (MHD
  * plans only): 0 = the rotational form of Sec. 2 (products u x w + j x b and
  * u x b of the primitive fields), 1 = the Elsasser divergence form, which
- * takes N+- = -i P(k) k_j F[z-+_j z+-_i] from the nine products z+_i z-_j
- * (fifteen real transforms per evaluation instead of eighteen; the default);
+ * takes N+- = -i P(k) k_j F[z-+_j z+-_i] from the products z+_i z-_j less
+ * their isotropic part delta_ij z+_2 z-_2, a gradient that P(k) removes (eight
+ * products, so fourteen real transforms per evaluation instead of eighteen;
+ * the default);
  * the two agree up to rounding when z+- are solenoidal, as every state the
  * step produces is.  Kind "pipe" v: the inverse y pass, the product pass and
  * the forward y pass of each right-hand side run as 2^v slabs of z-planes

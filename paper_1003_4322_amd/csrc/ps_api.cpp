@@ -295,7 +295,7 @@ struct Seq {
   // fields of each stage: state, physical inputs of the products, products
   bool els(bool mhd) const { return mhd && p->els; }
   int nphys(bool mhd) const { return mhd ? (p->els ? 6 : 12) : 6; }
-  int nprod(bool mhd) const { return mhd ? (p->els ? 9 : 6) : 3; }
+  int nprod(bool mhd) const { return mhd ? (p->els ? 8 : 6) : 3; }
 
   ps_status pass_zcurl(const C* src, bool mhd) {
     const int nin = mhd ? 6 : 3, nphys = this->nphys(mhd);
@@ -664,7 +664,7 @@ ps_status ps_plan_create_batch(ps_plan* out, int nbox, const int* Ns, int nfield
     if (any_var) {
       p->var["z_curl"] = 0;
       p->var["z_epi"] = nfields == 6 ? 5 : 2;  // MHD (Elsasser): z+ and z- in two workgroups
-      p->var["x_prod"] = dtype == PS_F32 ? 4 : 7;
+      p->var["x_prod"] = dtype == PS_F32 ? (nfields == 6 ? 5 : 4) : 7;
       p->var["y"] = dtype == PS_F32 ? 2 : 0;
     }
     e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);

@@ -57,7 +57,7 @@ PS_ALT(1024, 64, 16, 8, 8)
 #undef PS_ALT
 
 // Wide schedules: a last radix of 4 over twice the threads (four values per
-// thread at the end, whole waves for nine product rows of M = 256); product
+// thread at the end, whole waves for any number of rows at M = 256); product
 // pass variants only.
 template <int L>
 struct LenWide : LenCfg<L> {};

@@ -21,8 +21,8 @@
 // Fusion (each is one kernel, data touch HBM once per pass):
 //   inverse z pass + spectral curl prologue       (state -> u, w [, b, j]);
 //                  MHD in the Elsasser form: z+- transformed as they are
-//   x pass: inverse real FFTs + products (u x w [+ j x b, u x b], or the nine
-//                  z+_i z-_j) + forward real FFTs
+//   x pass: inverse real FFTs + products (u x w [+ j x b, u x b], or the
+//                  eight z+_i z-_j less the isotropic part) + forward real FFTs
 //   forward z pass + 1/N^3 + dealias + projection (+ induction curl, or the
 //                  divergence of the Elsasser products) + Coriolis term
 //                  + explicit midpoint RK2 stage update
@@ -342,12 +342,14 @@ struct ZEpiArgs {
 };
 
 //
-// ELS (MHD, Elsasser form): in = the nine products T_ij = z+_i z-_j (field
-// 3 i + j) transformed along x and y; with a_i = sum_j k_j T^_ij and
-// c_i = sum_j k_j T^_ji (derivative wavenumbers),
+// ELS (MHD, Elsasser form): in = the products T_ij = z+_i z-_j less
+// delta_ij z+_2 z-_2 (field 3 i + j for the eight pairs other than (2, 2),
+// whose entry is zero) transformed along x and y; with a_i = sum_j k_j T^_ij
+// and c_i = sum_j k_j T^_ji (derivative wavenumbers),
 //   N+ = -i D(k) P(k) a / N^3,  N- = -i D(k) P(k) c / N^3,
 // the divergence form of -(z-+ . grad) z+-, equal to the form above for
-// solenoidal z+-.  a and c are accumulated field by field.
+// solenoidal z+- (the isotropic part left out adds a gradient to a and c,
+// which P(k) removes).  a and c are accumulated field by field.
 template <typename T, int L, int TQ, int TX, class RL, bool MHD, int MINW = 1, bool ELS = false, int SPLIT = 1>
 __global__ __launch_bounds__(TX* TQ, MINW) void k_z_epi(ZEpiArgs<T> a) {
   using E = Stockham<T, L, TQ, FWD, RL>;
@@ -400,7 +402,7 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_z_epi(ZEpiArgs<T> a) {
       for (int s = 0; s < NO; ++s) r[f][s] = zero2<T>();
     if constexpr (SPLIT == 1) {
       // the loop over i stays rolled (a_i gathers in acc and moves to its
-      // place after each row) so that the nine transforms' loads are not
+      // place after each row) so that the eight transforms' loads are not
       // stretched across each other
 #pragma unroll 1
       for (int i3 = 0; i3 < 3; ++i3) {
@@ -409,6 +411,7 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_z_epi(ZEpiArgs<T> a) {
         for (int s = 0; s < NO; ++s) acc[s] = zero2<T>();
 #pragma unroll
         for (int j3 = 0; j3 < 3; ++j3) {
+          if (j3 == 2 && i3 == 2) break;  // T_22 is zero (uniform over the workgroup)
           C2<T> v[E::SLOTS];
           E::template run_tw<typename CT::Lay>(v, smem + c, TX, q, tw, ld_of(3 * i3 + j3));
 #pragma unroll
@@ -430,7 +433,7 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_z_epi(ZEpiArgs<T> a) {
     } else {
       // part 0: a_i = sum_j k_j T_ij;  part 1: c_j = sum_i k_i T_ij
 #pragma unroll 1
-      for (int f = 0; f < 9; ++f) {
+      for (int f = 0; f < 8; ++f) {  // (2, 2) is zero
         const int i3 = f / 3, j3 = f % 3;
         const int t = part == 0 ? i3 : j3, m = part == 0 ? j3 : i3;
         C2<T> v[E::SLOTS];
@@ -566,7 +569,7 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_z_epi(ZEpiArgs<T> a) {
 // hold M+1 values.
 __host__ __device__ constexpr int row_slots(int M) { return pad8(M) + 1; }
 // rows of LDS (and thread groups) per grid row of the fused product pass
-__host__ __device__ constexpr int xprod_slots(bool mhd, bool els) { return els ? 9 : mhd ? 12 : 6; }
+__host__ __device__ constexpr int xprod_slots(bool mhd, bool els) { return els ? 8 : mhd ? 12 : 6; }
 
 template <typename T, class Lay = LayPad8>
 __device__ __forceinline__ C2<T> c2r_pre(const C2<T>* buf, int k, int M, const C2<T>* __restrict__ tw) {
@@ -683,10 +686,14 @@ __global__ __launch_bounds__(G* TQ) void k_x_r2c(XArgs<T> a) {
 // MHD: in [u0..2 w0..2 b0..2 j0..2]       out [u x w + j x b, u x b]
 //
 // ELS (MHD, Elsasser form): inputs z+ (fields 0-2) and z- (3-5); outputs the
-// nine products T_ij = z+_i z-_j as field 3 i + j.
+// eight fields of the stress T_ij = z+_i z-_j less its isotropic part
+// delta_ij T_22, as field 3 i + j: T_00 - T_22, T_01, T_02, T_10,
+// T_11 - T_22, T_12, T_20, T_21 (T_22 - T_22 = 0 is not stored).  The part
+// removed contributes the gradient -i k T^_22 to both N+ and N-, which the
+// projection P(k) annihilates.
 template <typename T, int M, int TQ, int RB, class RL, bool MHD, bool ELS = false, class RLay = LayPad8>
 __global__ __launch_bounds__(xprod_slots(MHD, ELS) * RB * TQ) void k_x_prod(XArgs<T> a) {
-  constexpr int FIN = ELS ? 6 : MHD ? 12 : 6, FOUT = ELS ? 9 : MHD ? 6 : 3;
+  constexpr int FIN = ELS ? 6 : MHD ? 12 : 6, FOUT = ELS ? 8 : MHD ? 6 : 3;
   constexpr int G = xprod_slots(MHD, ELS) * RB, NT = G * TQ;
   using EI = Stockham<T, M, TQ, INV, RL>;
   using EF = Stockham<T, M, TQ, FWD, RL>;
@@ -770,15 +777,24 @@ __global__ __launch_bounds__(xprod_slots(MHD, ELS) * RB * TQ) void k_x_prod(XArg
   {
     C2<T> v[EF::SLOTS];
     if constexpr (ELS) {
-      // T_ij = z+_i z-_j, i = f / 3, j = f % 3; every read happens before the
-      // first stage's barrier, so overwriting the input slots after it is safe
+      // T_ij = z+_i z-_j, i = f / 3, j = f % 3, less z+_2 z-_2 on the
+      // diagonal (f = 0, 4); every read happens before the first stage's
+      // barrier, so overwriting the input slots after it is safe
       const C2<T>* ra = smem + ((f / 3) * RB + rb) * LP;
       const C2<T>* rm = smem + ((3 + f % 3) * RB + rb) * LP;
+      const C2<T>* ra2 = smem + (2 * RB + rb) * LP;
+      const C2<T>* rm2 = smem + (5 * RB + rb) * LP;
+      const bool diag = f % 4 == 0;
       EF::template run_tw<RLay>(
           v, buf, 1, q, twf,
           [&](int, int n) {
             const C2<T> x = ra[RLay::off(n, 1)], y = rm[RLay::off(n, 1)];
-            return C2<T>{x.x * y.x, x.y * y.y};
+            C2<T> t{x.x * y.x, x.y * y.y};
+            if (diag) {
+              const C2<T> x2 = ra2[RLay::off(n, 1)], y2 = rm2[RLay::off(n, 1)];
+              t = C2<T>{t.x - x2.x * y2.x, t.y - x2.y * y2.y};
+            }
+            return t;
           },
           active);
     } else {

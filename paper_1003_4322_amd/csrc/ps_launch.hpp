@@ -32,7 +32,8 @@ template <typename T>
 int z_epi_tx(int N, int var);
 
 // els: MHD in the Elsasser (divergence) form -- z_curl transforms z+- without
-// a curl, x_prod forms the nine products z+_i z-_j, z_epi takes their divergence
+// a curl, x_prod forms the products z+_i z-_j (less z+_2 z-_2 on the diagonal,
+// eight fields), z_epi takes their divergence
 template <typename T>
 hipError_t launch_z_curl(int N, bool mhd, bool els, int var, ZCurlArgs<T> a, const DiskTiles* dt,
                          hipStream_t s);

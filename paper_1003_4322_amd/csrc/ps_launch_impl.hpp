@@ -256,8 +256,8 @@ hipError_t x_prod_v(bool mhd, bool els, XArgs<T> a, hipStream_t s) {
   // a variant whose configuration does not fit this size (threads or LDS)
   // runs as variant 0, so that every variant index is valid at every size
   if (mhd && els) {
-    if constexpr (X::fits(9, 1))
-      return go(t_{}, t_{}, std::integral_constant<int, X::rb(9, want(9, v.rb_mhd))>{});
+    if constexpr (X::fits(8, 1))
+      return go(t_{}, t_{}, std::integral_constant<int, X::rb(8, want(8, v.rb_mhd))>{});
     else if constexpr (I != 0)
       return x_prod_v<T, N, 0>(mhd, els, a, s);
     return hipErrorInvalidValue;

@@ -48,15 +48,24 @@ def kind_of(name: str) -> str:
     return "other"
 
 
+def _code_only(text: str) -> str:
+    """Source text without comments and with whitespace runs collapsed, so that
+    editing a comment does not count as changing a kernel."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def src_hash() -> str:
-    """Hash of the device-side sources (kernels, their configurations and
-    launchers); host-only code (ps_api.cpp) does not change a kernel's traffic."""
+    """Hash of the device-side code (kernels, their configurations and
+    launchers; comments excluded); host-only code (ps_api.cpp) does not change
+    a kernel's traffic."""
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_1003_4322_amd", "csrc")
     for f in sorted(os.listdir(d)):
         if f.endswith((".hip", ".hpp")):
             h.update(f.encode())
-            h.update(open(os.path.join(d, f), "rb").read())
+            h.update(_code_only(open(os.path.join(d, f), encoding="utf-8").read()).encode())
     return h.hexdigest()[:16]
 
 
