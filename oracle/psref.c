@@ -33,11 +33,30 @@ typedef double complex cplx;
 static const double TWO_PI = 6.28318530717958647692528676655900577;
 
 /* ------------------------------------------------------------------------ */
-/* Index conventions (Sec. 2, Fig. 1: real N^3 cube, half spectrum           */
-/* (N/2+1) x N x N after the real-to-complex transform).                     */
+/* Index conventions (Sec. 2, Fig. 1: a real nx x ny x nz grid, and its half */
+/* spectrum (nx/2+1) x ny x nz after the real-to-complex transform; the     */
+/* paper's cube is nx = ny = nz = N).                                        */
 /* ------------------------------------------------------------------------ */
 
-/* signed wavenumber of storage index i along ky or kz */
+typedef struct {
+  long nx, ny, nz;
+  long H;   /* nx/2 + 1 kx values        */
+  long nc;  /* nz ny H modes per field   */
+  long n3;  /* nz ny nx points per field */
+} grid;
+
+static grid grid_of(int nx, int ny, int nz) {
+  grid g;
+  g.nx = nx;
+  g.ny = ny;
+  g.nz = nz;
+  g.H = nx / 2 + 1;
+  g.nc = (long)nz * ny * g.H;
+  g.n3 = (long)nz * ny * nx;
+  return g;
+}
+
+/* signed wavenumber of storage index i along ky or kz (axis length N) */
 static long wav(long i, long N) { return (i < N / 2) ? i : i - N; }
 
 /* derivative wavenumber: odd derivatives of the Nyquist mode are zero */
@@ -46,7 +65,7 @@ static long dwav(long i, long N) {
   return (2 * i == N) ? 0 : wav(i, N);
 }
 
-/* kx storage index -> wavenumber (kx = 0..N/2) */
+/* kx storage index -> wavenumber (kx = 0..nx/2) */
 static long wavx(long i) { return i; }
 static long dwavx(long i, long N) {
   if (MUT(9)) return i;
@@ -69,10 +88,19 @@ int psref_set_box(double Lx, double Ly, double Lz) {
   return 0;
 }
 
-/* 2/3-rule dealiasing, spherical truncation: keep 9 |k|^2 < N^2 */
-static int dealias_keep(long k2, long N) {
-  if (MUT(3)) return 9 * k2 <= N * N;
-  return 9 * k2 < N * N;
+/* 2/3-rule dealiasing as a truncation on the index n: keep
+ *   (3 nx' / nx)^2 + (3 ny' / ny)^2 + (3 nz' / nz)^2 < 1,
+ * the sphere 9 |n|^2 < N^2 of the cube, stretched with the grid (each axis
+ * then keeps |n_a| < N_a / 3, the per-axis 2/3 rule).  Evaluated exactly in
+ * integers after multiplying by (nx ny nz)^2 (128-bit: up to 2^76). */
+static int dealias_keep(const grid *g, long ix, long iy, long iz) {
+  typedef __int128 i128;
+  const i128 X = g->nx, Y = MUT(17) ? g->nx : g->ny, Z = MUT(17) ? g->nx : g->nz;
+  const i128 lhs = 9 * ((i128)ix * ix * Y * Y * Z * Z + (i128)iy * iy * X * X * Z * Z +
+                        (i128)iz * iz * X * X * Y * Y);
+  const i128 rhs = X * X * Y * Y * Z * Z;
+  if (MUT(3)) return lhs <= rhs;
+  return lhs < rhs;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -141,91 +169,115 @@ static void line_fft(const line_plan *pl, const cplx *in, cplx *out, int inverse
   free(t);
 }
 
+/* one line plan per axis */
+typedef struct {
+  line_plan x, y, z;
+} plans;
+
+static int plans_init(plans *p, const grid *g) {
+  p->x.w = p->y.w = p->z.w = NULL;
+  if (line_plan_init(&p->x, (int)g->nx) || line_plan_init(&p->y, (int)g->ny) ||
+      line_plan_init(&p->z, (int)g->nz)) {
+    free(p->x.w);
+    free(p->y.w);
+    free(p->z.w);
+    return -3;
+  }
+  return 0;
+}
+
+static void plans_free(plans *p) {
+  line_plan_free(&p->x);
+  line_plan_free(&p->y);
+  line_plan_free(&p->z);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Three-dimensional real transforms (Sec. 2, Fig. 1): transforms along x,   */
 /* then y, then z for the forward direction; the reverse for the inverse.    */
 /* ------------------------------------------------------------------------ */
 
 static int size_ok(int N) { return N >= 2 && N <= 4096 && (N % 2) == 0; }
+static int grid_ok(int nx, int ny, int nz) { return size_ok(nx) && size_ok(ny) && size_ok(nz); }
 
-/* complex transforms along y then z (or z then y) of one half-spectrum field */
-static void pass_y(const line_plan *pl, int N, cplx *X, int inverse) {
-  const long H = N / 2 + 1;
+/* complex transforms along y (or z) of one half-spectrum field */
+static void pass_y(const line_plan *pl, const grid *g, cplx *X, int inverse) {
+  const long H = g->H, ny = g->ny;
 #pragma omp parallel
   {
-    cplx *a = (cplx *)malloc(sizeof(cplx) * (size_t)N);
-    cplx *b = (cplx *)malloc(sizeof(cplx) * (size_t)N);
+    cplx *a = (cplx *)malloc(sizeof(cplx) * (size_t)ny);
+    cplx *b = (cplx *)malloc(sizeof(cplx) * (size_t)ny);
 #pragma omp for schedule(static)
-    for (long zk = 0; zk < (long)N * H; ++zk) {
+    for (long zk = 0; zk < g->nz * H; ++zk) {
       long z = zk / H, kx = zk % H;
-      for (long y = 0; y < N; ++y) a[y] = X[(z * N + y) * H + kx];
+      for (long y = 0; y < ny; ++y) a[y] = X[(z * ny + y) * H + kx];
       line_fft(pl, a, b, inverse);
-      for (long y = 0; y < N; ++y) X[(z * N + y) * H + kx] = b[y];
+      for (long y = 0; y < ny; ++y) X[(z * ny + y) * H + kx] = b[y];
     }
     free(a);
     free(b);
   }
 }
 
-static void pass_z(const line_plan *pl, int N, cplx *X, int inverse) {
-  const long H = N / 2 + 1;
+static void pass_z(const line_plan *pl, const grid *g, cplx *X, int inverse) {
+  const long H = g->H, ny = g->ny, nz = g->nz;
 #pragma omp parallel
   {
-    cplx *a = (cplx *)malloc(sizeof(cplx) * (size_t)N);
-    cplx *b = (cplx *)malloc(sizeof(cplx) * (size_t)N);
+    cplx *a = (cplx *)malloc(sizeof(cplx) * (size_t)nz);
+    cplx *b = (cplx *)malloc(sizeof(cplx) * (size_t)nz);
 #pragma omp for schedule(static)
-    for (long yk = 0; yk < (long)N * H; ++yk) {
+    for (long yk = 0; yk < ny * H; ++yk) {
       long ky = yk / H, kx = yk % H;
-      for (long z = 0; z < N; ++z) a[z] = X[(z * N + ky) * H + kx];
+      for (long z = 0; z < nz; ++z) a[z] = X[(z * ny + ky) * H + kx];
       line_fft(pl, a, b, inverse);
-      for (long z = 0; z < N; ++z) X[(z * N + ky) * H + kx] = b[z];
+      for (long z = 0; z < nz; ++z) X[(z * ny + ky) * H + kx] = b[z];
     }
     free(a);
     free(b);
   }
 }
 
-static void r2c_field(const line_plan *pl, int N, const double *u, cplx *X) {
-  const long H = N / 2 + 1;
+static void r2c_field(const plans *pl, const grid *g, const double *u, cplx *X) {
+  const long H = g->H, nx = g->nx;
 #pragma omp parallel
   {
-    cplx *a = (cplx *)malloc(sizeof(cplx) * (size_t)N);
-    cplx *b = (cplx *)malloc(sizeof(cplx) * (size_t)N);
+    cplx *a = (cplx *)malloc(sizeof(cplx) * (size_t)nx);
+    cplx *b = (cplx *)malloc(sizeof(cplx) * (size_t)nx);
 #pragma omp for schedule(static)
-    for (long row = 0; row < (long)N * N; ++row) {
-      for (long x = 0; x < N; ++x) a[x] = u[row * N + x];
-      line_fft(pl, a, b, 0);
+    for (long row = 0; row < g->ny * g->nz; ++row) {
+      for (long x = 0; x < nx; ++x) a[x] = u[row * nx + x];
+      line_fft(&pl->x, a, b, 0);
       for (long kx = 0; kx < H; ++kx) X[row * H + kx] = b[kx];
     }
     free(a);
     free(b);
   }
-  pass_y(pl, N, X, 0);
-  pass_z(pl, N, X, 0);
+  pass_y(&pl->y, g, X, 0);
+  pass_z(&pl->z, g, X, 0);
 }
 
 /* Y is overwritten (used as the z/y-transformed intermediate) */
-static void c2r_field_inplace(const line_plan *pl, int N, cplx *Y, double *u) {
-  const long H = N / 2 + 1;
-  pass_z(pl, N, Y, 1);
-  pass_y(pl, N, Y, 1);
+static void c2r_field_inplace(const plans *pl, const grid *g, cplx *Y, double *u) {
+  const long H = g->H, nx = g->nx;
+  pass_z(&pl->z, g, Y, 1);
+  pass_y(&pl->y, g, Y, 1);
 #pragma omp parallel
   {
-    cplx *a = (cplx *)malloc(sizeof(cplx) * (size_t)N);
-    cplx *b = (cplx *)malloc(sizeof(cplx) * (size_t)N);
+    cplx *a = (cplx *)malloc(sizeof(cplx) * (size_t)nx);
+    cplx *b = (cplx *)malloc(sizeof(cplx) * (size_t)nx);
 #pragma omp for schedule(static)
-    for (long row = 0; row < (long)N * N; ++row) {
+    for (long row = 0; row < g->ny * g->nz; ++row) {
       const cplx *y = Y + row * H;
       /* Hermitian extension of the kx line; the imaginary parts of the
-       * kx = 0 and kx = N/2 bins are dropped */
+       * kx = 0 and kx = nx/2 bins are dropped */
       a[0] = creal(y[0]);
-      for (long k = 1; k < N / 2; ++k) {
+      for (long k = 1; k < nx / 2; ++k) {
         a[k] = y[k];
-        a[N - k] = conj(y[k]);
+        a[nx - k] = conj(y[k]);
       }
-      a[N / 2] = creal(y[N / 2]);
-      line_fft(pl, a, b, 1);
-      for (long x = 0; x < N; ++x) u[row * N + x] = creal(b[x]);
+      a[nx / 2] = creal(y[nx / 2]);
+      line_fft(&pl->x, a, b, 1);
+      for (long x = 0; x < nx; ++x) u[row * nx + x] = creal(b[x]);
     }
     free(a);
     free(b);
@@ -242,56 +294,58 @@ int psref_set_threads(int n) {
 #endif
 }
 
-int psref_fft_r2c(int N, int nf, const double *in, double *out) {
+int psref_fft_r2c(int nx, int ny, int nz, int nf, const double *in, double *out) {
   if (!in || !out || nf < 1) return -1;
-  if (!size_ok(N)) return -2;
-  line_plan pl;
-  if (line_plan_init(&pl, N)) return -3;
-  const long n3 = (long)N * N * N, nc = (long)N * N * (N / 2 + 1);
+  if (!grid_ok(nx, ny, nz)) return -2;
+  const grid g = grid_of(nx, ny, nz);
+  plans pl;
+  if (plans_init(&pl, &g)) return -3;
   for (int f = 0; f < nf; ++f)
-    r2c_field(&pl, N, in + f * n3, (cplx *)out + f * nc);
-  line_plan_free(&pl);
+    r2c_field(&pl, &g, in + f * g.n3, (cplx *)out + f * g.nc);
+  plans_free(&pl);
   return 0;
 }
 
-int psref_fft_c2r(int N, int nf, const double *in, double *out) {
+int psref_fft_c2r(int nx, int ny, int nz, int nf, const double *in, double *out) {
   if (!in || !out || nf < 1) return -1;
-  if (!size_ok(N)) return -2;
-  const long n3 = (long)N * N * N, nc = (long)N * N * (N / 2 + 1);
-  cplx *Y = (cplx *)malloc(sizeof(cplx) * (size_t)nc);
+  if (!grid_ok(nx, ny, nz)) return -2;
+  const grid g = grid_of(nx, ny, nz);
+  cplx *Y = (cplx *)malloc(sizeof(cplx) * (size_t)g.nc);
   if (!Y) return -3;
-  line_plan pl;
-  if (line_plan_init(&pl, N)) { free(Y); return -3; }
+  plans pl;
+  if (plans_init(&pl, &g)) { free(Y); return -3; }
   for (int f = 0; f < nf; ++f) {
-    memcpy(Y, (const cplx *)in + f * nc, sizeof(cplx) * (size_t)nc);
-    c2r_field_inplace(&pl, N, Y, out + f * n3);
+    memcpy(Y, (const cplx *)in + f * g.nc, sizeof(cplx) * (size_t)g.nc);
+    c2r_field_inplace(&pl, &g, Y, out + f * g.n3);
   }
-  line_plan_free(&pl);
+  plans_free(&pl);
   free(Y);
   return 0;
 }
 
-int psref_dft_at(int N, const double *in, int nk, const int *kx, const int *ky,
+int psref_dft_at(int nx, int ny, int nz, const double *in, int nk, const int *kx, const int *ky,
                  const int *kz, double *out) {
   if (!in || !out || nk < 0 || (nk > 0 && (!kx || !ky || !kz))) return -1;
-  if (!size_ok(N)) return -2;
+  if (!grid_ok(nx, ny, nz)) return -2;
   for (int i = 0; i < nk; ++i)
-    if (kx[i] < 0 || kx[i] > N / 2 || ky[i] < 0 || ky[i] >= N || kz[i] < 0 || kz[i] >= N)
+    if (kx[i] < 0 || kx[i] > nx / 2 || ky[i] < 0 || ky[i] >= ny || kz[i] < 0 || kz[i] >= nz)
       return -1;
-  line_plan pl;
-  if (line_plan_init(&pl, N)) return -3;
+  const grid g = grid_of(nx, ny, nz);
+  plans pl;
+  if (plans_init(&pl, &g)) return -3;
   for (int i = 0; i < nk; ++i) {
     cplx s = 0;
-    for (long z = 0; z < N; ++z)
-      for (long y = 0; y < N; ++y)
-        for (long x = 0; x < N; ++x) {
-          long e = ((long)kx[i] * x + (long)ky[i] * y + (long)kz[i] * z) % N;
-          s += in[(z * N + y) * N + x] * pl.w[e];
+    for (long z = 0; z < nz; ++z)
+      for (long y = 0; y < ny; ++y)
+        for (long x = 0; x < nx; ++x) {
+          cplx w = pl.x.w[((long)kx[i] * x) % nx] * pl.y.w[((long)ky[i] * y) % ny] *
+                   pl.z.w[((long)kz[i] * z) % nz];
+          s += in[(z * ny + y) * nx + x] * w;
         }
     out[2 * i] = creal(s);
     out[2 * i + 1] = cimag(s);
   }
-  line_plan_free(&pl);
+  plans_free(&pl);
   return 0;
 }
 
@@ -301,15 +355,15 @@ int psref_dft_at(int N, const double *in, int nk, const int *kx, const int *ky,
 /* ------------------------------------------------------------------------ */
 
 /* w = i k_d x u for one 3-vector field set of nc modes each */
-static void curl_fields(int N, const cplx *u, cplx *w) {
-  const long H = N / 2 + 1, nc = (long)N * N * H;
+static void curl_fields(const grid *g, const cplx *u, cplx *w) {
+  const long H = g->H, nc = g->nc, ny = g->ny;
 #pragma omp parallel for schedule(static)
-  for (long kz = 0; kz < N; ++kz)
-    for (long ky = 0; ky < N; ++ky)
+  for (long kz = 0; kz < g->nz; ++kz)
+    for (long ky = 0; ky < ny; ++ky)
       for (long kx = 0; kx < H; ++kx) {
-        long m = (kz * N + ky) * H + kx;
+        long m = (kz * ny + ky) * H + kx;
         const double *sc = MUT(16) ? (const double[3]){1, 1, 1} : g_s;
-        double ax = sc[0] * dwavx(kx, N), ay = sc[1] * dwav(ky, N), az = sc[2] * dwav(kz, N);
+        double ax = sc[0] * dwavx(kx, g->nx), ay = sc[1] * dwav(ky, ny), az = sc[2] * dwav(kz, g->nz);
         cplx ux = u[m], uy = u[nc + m], uz = u[2 * nc + m];
         w[m] = I * (ay * uz - az * uy);
         w[nc + m] = I * (az * ux - ax * uz);
@@ -318,25 +372,26 @@ static void curl_fields(int N, const cplx *u, cplx *w) {
       }
 }
 
-int psref_curl(int N, const double *uhat, double *what) {
+int psref_curl(int nx, int ny, int nz, const double *uhat, double *what) {
   if (!uhat || !what) return -1;
-  if (!size_ok(N)) return -2;
-  curl_fields(N, (const cplx *)uhat, (cplx *)what);
+  if (!grid_ok(nx, ny, nz)) return -2;
+  const grid g = grid_of(nx, ny, nz);
+  curl_fields(&g, (const cplx *)uhat, (cplx *)what);
   return 0;
 }
 
-/* v <- D(k) P(k) v / N^3 for a 3-vector field set (P(0) v := 0) */
-static void dealias_project(int N, cplx *v) {
-  const long H = N / 2 + 1, nc = (long)N * N * H;
-  const double inv = 1.0 / ((double)N * N * N);
+/* v <- D(k) P(k) v / (nx ny nz) for a 3-vector field set (P(0) v := 0) */
+static void dealias_project(const grid *g, cplx *v) {
+  const long H = g->H, nc = g->nc, ny = g->ny;
+  const double inv = 1.0 / (double)g->n3;
 #pragma omp parallel for schedule(static)
-  for (long kz = 0; kz < N; ++kz)
-    for (long ky = 0; ky < N; ++ky)
+  for (long kz = 0; kz < g->nz; ++kz)
+    for (long ky = 0; ky < ny; ++ky)
       for (long kx = 0; kx < H; ++kx) {
-        long m = (kz * N + ky) * H + kx;
-        long ix = wavx(kx), iy = wav(ky, N), iz = wav(kz, N);
+        long m = (kz * ny + ky) * H + kx;
+        long ix = wavx(kx), iy = wav(ky, ny), iz = wav(kz, g->nz);
         long k2 = ix * ix + iy * iy + iz * iz;
-        if (k2 == 0 || !dealias_keep(k2, N)) {
+        if (k2 == 0 || !dealias_keep(g, ix, iy, iz)) {
           v[m] = v[nc + m] = v[2 * nc + m] = 0;
           continue;
         }
@@ -365,46 +420,40 @@ static void cross_real(long n3, const double *a, const double *b, double *n) {
 }
 
 /* c2r of a 3-field spectral set (input preserved) */
-static int c2r3(const line_plan *pl, int N, const cplx *in, double *out, cplx *tmp) {
-  const long n3 = (long)N * N * N, nc = (long)N * N * (N / 2 + 1);
+static int c2r3(const plans *pl, const grid *g, const cplx *in, double *out, cplx *tmp) {
   for (int f = 0; f < 3; ++f) {
-    memcpy(tmp, in + f * nc, sizeof(cplx) * (size_t)nc);
-    c2r_field_inplace(pl, N, tmp, out + f * n3);
+    memcpy(tmp, in + f * g->nc, sizeof(cplx) * (size_t)g->nc);
+    c2r_field_inplace(pl, g, tmp, out + f * g->n3);
   }
   return 0;
 }
 
-static void r2c3(const line_plan *pl, int N, const double *in, cplx *out) {
-  const long n3 = (long)N * N * N, nc = (long)N * N * (N / 2 + 1);
-  for (int f = 0; f < 3; ++f) r2c_field(pl, N, in + f * n3, out + f * nc);
+static void r2c3(const plans *pl, const grid *g, const double *in, cplx *out) {
+  for (int f = 0; f < 3; ++f) r2c_field(pl, g, in + f * g->n3, out + f * g->nc);
 }
 
-int psref_nonlinear_ns(int N, const double *uhat_, double *nhat_) {
-  if (!uhat_ || !nhat_) return -1;
-  if (!size_ok(N)) return -2;
-  const long n3 = (long)N * N * N, nc = (long)N * N * (N / 2 + 1);
-  const cplx *uhat = (const cplx *)uhat_;
-  cplx *nhat = (cplx *)nhat_;
+static int nonlinear_ns(const grid *g, const cplx *uhat, cplx *nhat) {
+  const long n3 = g->n3, nc = g->nc;
   cplx *what = (cplx *)malloc(sizeof(cplx) * 3 * (size_t)nc);
   cplx *tmp = (cplx *)malloc(sizeof(cplx) * (size_t)nc);
   double *u = (double *)malloc(sizeof(double) * 3 * (size_t)n3);
   double *w = (double *)malloc(sizeof(double) * 3 * (size_t)n3);
-  line_plan pl;
+  plans pl;
   int rc = 0;
-  if (!what || !tmp || !u || !w || line_plan_init(&pl, N)) {
+  if (!what || !tmp || !u || !w || plans_init(&pl, g)) {
     rc = -3;
     goto done;
   }
-  curl_fields(N, uhat, what);               /* w^ = i k x u^            */
-  c2r3(&pl, N, uhat, u, tmp);               /* u(x)                      */
-  c2r3(&pl, N, what, w, tmp);               /* w(x)                      */
+  curl_fields(g, uhat, what);               /* w^ = i k x u^            */
+  c2r3(&pl, g, uhat, u, tmp);               /* u(x)                      */
+  c2r3(&pl, g, what, w, tmp);               /* w(x)                      */
   if (MUT(10))
     cross_real(n3, w, u, u);                /* planted: operands swapped */
   else
     cross_real(n3, u, w, u);                /* u x w, written over u     */
-  r2c3(&pl, N, u, nhat);                    /* F[u x w]                  */
-  dealias_project(N, nhat);                 /* D P (.) / N^3             */
-  line_plan_free(&pl);
+  r2c3(&pl, g, u, nhat);                    /* F[u x w]                  */
+  dealias_project(g, nhat);                 /* D P (.) / (nx ny nz)      */
+  plans_free(&pl);
 done:
   free(what);
   free(tmp);
@@ -413,12 +462,17 @@ done:
   return rc;
 }
 
-int psref_nonlinear_mhd(int N, const double *zhat_, double *nhat_) {
-  if (!zhat_ || !nhat_) return -1;
-  if (!size_ok(N)) return -2;
-  const long H = N / 2 + 1, n3 = (long)N * N * N, nc = (long)N * N * H;
-  const cplx *zp = (const cplx *)zhat_, *zm = zp + 3 * nc;
-  cplx *np_ = (cplx *)nhat_, *nm = np_ + 3 * nc;
+int psref_nonlinear_ns(int nx, int ny, int nz, const double *uhat, double *nhat) {
+  if (!uhat || !nhat) return -1;
+  if (!grid_ok(nx, ny, nz)) return -2;
+  const grid g = grid_of(nx, ny, nz);
+  return nonlinear_ns(&g, (const cplx *)uhat, (cplx *)nhat);
+}
+
+static int nonlinear_mhd(const grid *g, const cplx *zp, cplx *np_) {
+  const long H = g->H, n3 = g->n3, nc = g->nc, ny = g->ny;
+  const cplx *zm = zp + 3 * nc;
+  cplx *nm = np_ + 3 * nc;
   cplx *uh = (cplx *)malloc(sizeof(cplx) * 3 * (size_t)nc);
   cplx *bh = (cplx *)malloc(sizeof(cplx) * 3 * (size_t)nc);
   cplx *sh = (cplx *)malloc(sizeof(cplx) * 3 * (size_t)nc);
@@ -427,9 +481,9 @@ int psref_nonlinear_mhd(int N, const double *zhat_, double *nhat_) {
   double *b = (double *)malloc(sizeof(double) * 3 * (size_t)n3);
   double *w = (double *)malloc(sizeof(double) * 3 * (size_t)n3);
   double *j = (double *)malloc(sizeof(double) * 3 * (size_t)n3);
-  line_plan pl;
+  plans pl;
   int rc = 0;
-  if (!uh || !bh || !sh || !tmp || !u || !b || !w || !j || line_plan_init(&pl, N)) {
+  if (!uh || !bh || !sh || !tmp || !u || !b || !w || !j || plans_init(&pl, g)) {
     rc = -3;
     goto done;
   }
@@ -438,31 +492,30 @@ int psref_nonlinear_mhd(int N, const double *zhat_, double *nhat_) {
     uh[m] = 0.5 * (zp[m] + zm[m]);
     bh[m] = 0.5 * (zp[m] - zm[m]);
   }
-  c2r3(&pl, N, uh, u, tmp);
-  c2r3(&pl, N, bh, b, tmp);
-  curl_fields(N, uh, sh);                   /* w^ = i k x u^ */
-  c2r3(&pl, N, sh, w, tmp);
-  curl_fields(N, bh, sh);                   /* j^ = i k x b^ */
-  c2r3(&pl, N, sh, j, tmp);
+  c2r3(&pl, g, uh, u, tmp);
+  c2r3(&pl, g, bh, b, tmp);
+  curl_fields(g, uh, sh);                   /* w^ = i k x u^ */
+  c2r3(&pl, g, sh, w, tmp);
+  curl_fields(g, bh, sh);                   /* j^ = i k x b^ */
+  c2r3(&pl, g, sh, j, tmp);
   /* Lorentz + advection part: u x w + j x b  (into w), induction e = u x b (into u) */
   cross_real(n3, u, w, w);
   cross_real(n3, j, b, j);
   for (long i = 0; i < 3 * n3; ++i) w[i] += j[i];
   cross_real(n3, u, b, u);
-  r2c3(&pl, N, w, uh);                      /* F[u x w + j x b] */
-  r2c3(&pl, N, u, bh);                      /* F[u x b]         */
-  dealias_project(N, uh);                   /* D P (.) / N^3    */
-  curl_fields(N, bh, sh);                   /* i k x F[u x b]   */
+  r2c3(&pl, g, w, uh);                      /* F[u x w + j x b] */
+  r2c3(&pl, g, u, bh);                      /* F[u x b]         */
+  dealias_project(g, uh);                   /* D P (.) / (nx ny nz) */
+  curl_fields(g, bh, sh);                   /* i k x F[u x b]   */
   {
-    const double inv = 1.0 / ((double)N * N * N);
+    const double inv = 1.0 / (double)n3;
 #pragma omp parallel for schedule(static)
-    for (long kz = 0; kz < N; ++kz)
-      for (long ky = 0; ky < N; ++ky)
+    for (long kz = 0; kz < g->nz; ++kz)
+      for (long ky = 0; ky < ny; ++ky)
         for (long kx = 0; kx < H; ++kx) {
-          long m = (kz * N + ky) * H + kx;
-          long ix = wavx(kx), iy = wav(ky, N), iz = wav(kz, N);
-          long k2 = ix * ix + iy * iy + iz * iz;
-          double d = dealias_keep(k2, N) ? inv : 0.0;
+          long m = (kz * ny + ky) * H + kx;
+          long ix = wavx(kx), iy = wav(ky, ny), iz = wav(kz, g->nz);
+          double d = dealias_keep(g, ix, iy, iz) ? inv : 0.0;
           double sg = MUT(7) ? -1.0 : 1.0;
           for (int c = 0; c < 3; ++c) {
             cplx a = uh[c * nc + m], e = d * sh[c * nc + m];
@@ -471,7 +524,7 @@ int psref_nonlinear_mhd(int N, const double *zhat_, double *nhat_) {
           }
         }
   }
-  line_plan_free(&pl);
+  plans_free(&pl);
 done:
   free(uh);
   free(bh);
@@ -484,6 +537,13 @@ done:
   return rc;
 }
 
+int psref_nonlinear_mhd(int nx, int ny, int nz, const double *zhat, double *nhat) {
+  if (!zhat || !nhat) return -1;
+  if (!grid_ok(nx, ny, nz)) return -2;
+  const grid g = grid_of(nx, ny, nz);
+  return nonlinear_mhd(&g, (const cplx *)zhat, (cplx *)nhat);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Galerkin triad sum: the dealiased quadratic term as the convolution of    */
 /* Fourier coefficients, N(k) = D P sum_{p+q=k} u(p) x (i q x u(q)).  For a  */
@@ -492,64 +552,74 @@ done:
 /* ------------------------------------------------------------------------ */
 
 typedef struct {
-  long K;     /* cube half-width: |k_i| <= K */
-  long side;  /* 2K+1 */
-  cplx *v;    /* [f][kz][ky][kx] over the cube, full spectrum */
+  long K[3];     /* half-widths: |k_a| <= K[a] */
+  long side[3];  /* 2K+1 */
+  cplx *v;       /* [f][kz][ky][kx] over the box, full spectrum */
 } full_cube;
 
 /* effective full-spectrum coefficient seen by the inverse transform: the kx = 0
- * and kx = N/2 planes are used through their Hermitian part */
-static cplx eff_coef(int N, const cplx *F, long ix, long iy, long iz) {
-  const long H = N / 2 + 1;
+ * and kx = nx/2 planes are used through their Hermitian part */
+static cplx eff_coef(const grid *g, const cplx *F, long ix, long iy, long iz) {
+  const long H = g->H, ny = g->ny, nz = g->nz;
   long sx = ix < 0 ? -ix : ix;
   long syi, szi, myi, mzi;
   if (ix < 0) { iy = -iy; iz = -iz; }
-  syi = (iy % N + N) % N;
-  szi = (iz % N + N) % N;
-  myi = ((-iy) % N + N) % N;
-  mzi = ((-iz) % N + N) % N;
-  cplx a = F[(szi * N + syi) * H + sx];
-  if (sx == 0 || 2 * sx == N) {
-    cplx b = F[(mzi * N + myi) * H + sx];
+  syi = (iy % ny + ny) % ny;
+  szi = (iz % nz + nz) % nz;
+  myi = ((-iy) % ny + ny) % ny;
+  mzi = ((-iz) % nz + nz) % nz;
+  cplx a = F[(szi * ny + syi) * H + sx];
+  if (sx == 0 || 2 * sx == g->nx) {
+    cplx b = F[(mzi * ny + myi) * H + sx];
     a = 0.5 * (a + conj(b));
   }
   return ix < 0 ? conj(a) : a;
 }
 
-static int cube_build(int N, int nf, const cplx *F, full_cube *c) {
-  const long H = N / 2 + 1, nc = (long)N * N * H;
-  long K = 0;
+static size_t cube_index(const full_cube *c, int f, long ix, long iy, long iz) {
+  return (((size_t)f * c->side[2] + (iz + c->K[2])) * c->side[1] + (iy + c->K[1])) * c->side[0] +
+         (ix + c->K[0]);
+}
+
+static int cube_build(const grid *g, int nf, const cplx *F, full_cube *c) {
+  const long H = g->H, nc = g->nc, ny = g->ny, nz = g->nz;
+  long K[3] = {0, 0, 0};
   for (int f = 0; f < nf; ++f)
-    for (long kz = 0; kz < N; ++kz)
-      for (long ky = 0; ky < N; ++ky)
+    for (long kz = 0; kz < nz; ++kz)
+      for (long ky = 0; ky < ny; ++ky)
         for (long kx = 0; kx < H; ++kx) {
-          cplx a = F[f * nc + (kz * N + ky) * H + kx];
+          cplx a = F[f * nc + (kz * ny + ky) * H + kx];
           if (a != 0) {
-            long m = labs(wav(kz, N));
-            if (labs(wav(ky, N)) > m) m = labs(wav(ky, N));
-            if (kx > m) m = kx;
-            if (m > K) K = m;
+            if (kx > K[0]) K[0] = kx;
+            if (labs(wav(ky, ny)) > K[1]) K[1] = labs(wav(ky, ny));
+            if (labs(wav(kz, nz)) > K[2]) K[2] = labs(wav(kz, nz));
           }
         }
   /* content at Nyquist indices is outside the Galerkin set and ignored */
-  if (K > N / 2 - 1) K = N / 2 - 1;
-  c->K = K;
-  c->side = 2 * K + 1;
-  size_t n = (size_t)nf * c->side * c->side * c->side;
-  c->v = (cplx *)calloc(n, sizeof(cplx));
+  const long n[3] = {g->nx, ny, nz};
+  size_t cnt = (size_t)nf;
+  for (int a = 0; a < 3; ++a) {
+    if (K[a] > n[a] / 2 - 1) K[a] = n[a] / 2 - 1;
+    c->K[a] = K[a];
+    c->side[a] = 2 * K[a] + 1;
+    cnt *= (size_t)c->side[a];
+  }
+  c->v = (cplx *)calloc(cnt, sizeof(cplx));
   if (!c->v) return -3;
   for (int f = 0; f < nf; ++f)
-    for (long iz = -K; iz <= K; ++iz)
-      for (long iy = -K; iy <= K; ++iy)
-        for (long ix = -K; ix <= K; ++ix)
-          c->v[(((size_t)f * c->side + (iz + K)) * c->side + (iy + K)) * c->side + (ix + K)] =
-              eff_coef(N, F + f * nc, ix, iy, iz);
+    for (long iz = -K[2]; iz <= K[2]; ++iz)
+      for (long iy = -K[1]; iy <= K[1]; ++iy)
+        for (long ix = -K[0]; ix <= K[0]; ++ix)
+          c->v[cube_index(c, f, ix, iy, iz)] = eff_coef(g, F + f * nc, ix, iy, iz);
   return 0;
 }
 
+static int cube_has(const full_cube *c, long ix, long iy, long iz) {
+  return labs(ix) <= c->K[0] && labs(iy) <= c->K[1] && labs(iz) <= c->K[2];
+}
+
 static cplx cube_at(const full_cube *c, int f, long ix, long iy, long iz) {
-  if (ix < -c->K || ix > c->K || iy < -c->K || iy > c->K || iz < -c->K || iz > c->K) return 0;
-  return c->v[(((size_t)f * c->side + (iz + c->K)) * c->side + (iy + c->K)) * c->side + (ix + c->K)];
+  return cube_has(c, ix, iy, iz) ? c->v[cube_index(c, f, ix, iy, iz)] : 0;
 }
 
 static void cross_c(const cplx a[3], const cplx b[3], cplx o[3]) {
@@ -559,36 +629,37 @@ static void cross_c(const cplx a[3], const cplx b[3], cplx o[3]) {
 }
 
 /* i q x v with the derivative wavenumber (Nyquist components zero) */
-static void icurl_c(int N, long qx, long qy, long qz, const cplx v[3], cplx o[3]) {
-  double ax = (2 * labs(qx) == N) ? 0.0 : g_s[0] * qx;
-  double ay = (2 * labs(qy) == N) ? 0.0 : g_s[1] * qy;
-  double az = (2 * labs(qz) == N) ? 0.0 : g_s[2] * qz;
+static void icurl_c(const grid *g, long qx, long qy, long qz, const cplx v[3], cplx o[3]) {
+  double ax = (2 * labs(qx) == g->nx) ? 0.0 : g_s[0] * qx;
+  double ay = (2 * labs(qy) == g->ny) ? 0.0 : g_s[1] * qy;
+  double az = (2 * labs(qz) == g->nz) ? 0.0 : g_s[2] * qz;
   o[0] = I * (ay * v[2] - az * v[1]);
   o[1] = I * (az * v[0] - ax * v[2]);
   o[2] = I * (ax * v[1] - ay * v[0]);
 }
 
-int psref_nonlinear_at(int N, int model, const double *fhat, int nk, const int *kx,
-                       const int *ky, const int *kz, double *out) {
+int psref_nonlinear_at(int nx, int ny, int nz, int model, const double *fhat, int nk,
+                       const int *kx, const int *ky, const int *kz, double *out) {
   if (!fhat || !out || nk < 0 || (nk > 0 && (!kx || !ky || !kz))) return -1;
   if (model != 0 && model != 1) return -1;
-  if (!size_ok(N)) return -2;
+  if (!grid_ok(nx, ny, nz)) return -2;
   for (int i = 0; i < nk; ++i)
-    if (kx[i] < 0 || kx[i] > N / 2 || ky[i] < 0 || ky[i] >= N || kz[i] < 0 || kz[i] >= N)
+    if (kx[i] < 0 || kx[i] > nx / 2 || ky[i] < 0 || ky[i] >= ny || kz[i] < 0 || kz[i] >= nz)
       return -1;
+  const grid g = grid_of(nx, ny, nz);
   const int nf = model == 0 ? 3 : 6;
   full_cube c;
-  if (cube_build(N, nf, (const cplx *)fhat, &c)) return -3;
-  const long K = c.K;
+  if (cube_build(&g, nf, (const cplx *)fhat, &c)) return -3;
+  const long *K = c.K;
 #pragma omp parallel for schedule(dynamic, 1)
   for (int i = 0; i < nk; ++i) {
-    long ox = kx[i], oy = wav(ky[i], N), oz = wav(kz[i], N);
+    long ox = kx[i], oy = wav(ky[i], ny), oz = wav(kz[i], nz);
     cplx accL[3] = {0, 0, 0}, accE[3] = {0, 0, 0};
-    for (long pz = -K; pz <= K; ++pz)
-      for (long py = -K; py <= K; ++py)
-        for (long px = -K; px <= K; ++px) {
+    for (long pz = -K[2]; pz <= K[2]; ++pz)
+      for (long py = -K[1]; py <= K[1]; ++py)
+        for (long px = -K[0]; px <= K[0]; ++px) {
           long qx = ox - px, qy = oy - py, qz = oz - pz;
-          if (qx < -K || qx > K || qy < -K || qy > K || qz < -K || qz > K) continue;
+          if (!cube_has(&c, qx, qy, qz)) continue;
           if (model == 0) {
             cplx up[3], uq[3], wq[3], t[3];
             for (int f = 0; f < 3; ++f) {
@@ -596,7 +667,7 @@ int psref_nonlinear_at(int N, int model, const double *fhat, int nk, const int *
               uq[f] = cube_at(&c, f, qx, qy, qz);
             }
             if (up[0] == 0 && up[1] == 0 && up[2] == 0) continue;
-            icurl_c(N, qx, qy, qz, uq, wq);
+            icurl_c(&g, qx, qy, qz, uq, wq);
             cross_c(up, wq, t);
             for (int f = 0; f < 3; ++f) accL[f] += t[f];
           } else {
@@ -609,11 +680,11 @@ int psref_nonlinear_at(int N, int model, const double *fhat, int nk, const int *
               uq[f] = 0.5 * (zpq + zmq);
               bq[f] = 0.5 * (zpq - zmq);
             }
-            icurl_c(N, qx, qy, qz, uq, wq);  /* w(q) */
-            icurl_c(N, px, py, pz, bp, jp);  /* j(p) */
-            cross_c(up, wq, t1);             /* u(p) x w(q) */
-            cross_c(jp, bq, t2);             /* j(p) x b(q) */
-            cross_c(up, bq, t3);             /* u(p) x b(q) */
+            icurl_c(&g, qx, qy, qz, uq, wq);  /* w(q) */
+            icurl_c(&g, px, py, pz, bp, jp);  /* j(p) */
+            cross_c(up, wq, t1);              /* u(p) x w(q) */
+            cross_c(jp, bq, t2);              /* j(p) x b(q) */
+            cross_c(up, bq, t3);              /* u(p) x b(q) */
             for (int f = 0; f < 3; ++f) {
               accL[f] += t1[f] + t2[f];
               accE[f] += t3[f];
@@ -622,7 +693,7 @@ int psref_nonlinear_at(int N, int model, const double *fhat, int nk, const int *
         }
     long k2 = ox * ox + oy * oy + oz * oz;
     cplx res[6] = {0, 0, 0, 0, 0, 0};
-    if (k2 != 0 && dealias_keep(k2, N)) {
+    if (k2 != 0 && dealias_keep(&g, ox, oy, oz)) {
       double ax = g_s[0] * ox, ay = g_s[1] * oy, az = g_s[2] * oz;
       double q2 = ax * ax + ay * ay + az * az;
       cplx kv = ax * accL[0] + ay * accL[1] + az * accL[2];
@@ -631,7 +702,7 @@ int psref_nonlinear_at(int N, int model, const double *fhat, int nk, const int *
         for (int f = 0; f < 3; ++f) res[f] = pl_[f];
       } else {
         cplx ce[3];
-        icurl_c(N, ox, oy, oz, accE, ce);
+        icurl_c(&g, ox, oy, oz, accE, ce);
         for (int f = 0; f < 3; ++f) {
           res[f] = pl_[f] + ce[f];
           res[3 + f] = pl_[f] - ce[f];
@@ -663,15 +734,15 @@ int psref_nonlinear_at(int N, int model, const double *fhat, int nk, const int *
 /* ------------------------------------------------------------------------ */
 
 /* F -= P(k) (2 Omega x u) at every mode, u the velocity of state z */
-static void coriolis(int N, int model, const cplx *z, cplx *F, const double *om) {
-  const long H = N / 2 + 1, nc = (long)N * N * H;
+static void coriolis(const grid *g, int model, const cplx *z, cplx *F, const double *om) {
+  const long H = g->H, nc = g->nc, ny = g->ny;
   const double f = MUT(14) ? 1.0 : 2.0;
 #pragma omp parallel for schedule(static)
-  for (long kz = 0; kz < N; ++kz)
-    for (long ky = 0; ky < N; ++ky)
+  for (long kz = 0; kz < g->nz; ++kz)
+    for (long ky = 0; ky < ny; ++ky)
       for (long kx = 0; kx < H; ++kx) {
-        long m = (kz * N + ky) * H + kx;
-        long ix = wavx(kx), iy = wav(ky, N), iz = wav(kz, N);
+        long m = (kz * ny + ky) * H + kx;
+        long ix = wavx(kx), iy = wav(ky, ny), iz = wav(kz, g->nz);
         long k2 = ix * ix + iy * iy + iz * iz;
         if (k2 == 0) continue;
         cplx u[3];
@@ -691,19 +762,19 @@ static void coriolis(int N, int model, const cplx *z, cplx *F, const double *om)
       }
 }
 
-static int rhs(int N, int model, const cplx *z, cplx *F, double nu, double eta, const double *om) {
-  const long H = N / 2 + 1, nc = (long)N * N * H;
-  int rc = model == 0 ? psref_nonlinear_ns(N, (const double *)z, (double *)F)
-                      : psref_nonlinear_mhd(N, (const double *)z, (double *)F);
+static int rhs(const grid *g, int model, const cplx *z, cplx *F, double nu, double eta,
+               const double *om) {
+  const long H = g->H, nc = g->nc, ny = g->ny;
+  int rc = model == 0 ? nonlinear_ns(g, z, F) : nonlinear_mhd(g, z, F);
   if (rc) return rc;
   const double a = model == 0 ? nu : 0.5 * (nu + eta);
   const double b = model == 0 ? 0.0 : 0.5 * (nu - eta);
 #pragma omp parallel for schedule(static)
-  for (long kz = 0; kz < N; ++kz)
-    for (long ky = 0; ky < N; ++ky)
+  for (long kz = 0; kz < g->nz; ++kz)
+    for (long ky = 0; ky < ny; ++ky)
       for (long kx = 0; kx < H; ++kx) {
-        long m = (kz * N + ky) * H + kx;
-        long ix = wavx(kx), iy = wav(ky, N), iz = wav(kz, N);
+        long m = (kz * ny + ky) * H + kx;
+        long ix = wavx(kx), iy = wav(ky, ny), iz = wav(kz, g->nz);
         const double *sc = MUT(15) ? (const double[3]){1, 1, 1} : g_s;
         double k2 = sc[0] * sc[0] * ix * ix + sc[1] * sc[1] * iy * iy + sc[2] * sc[2] * iz * iz;
         if (model == 0) {
@@ -716,21 +787,22 @@ static int rhs(int N, int model, const cplx *z, cplx *F, double nu, double eta, 
           }
         }
       }
-  if (om && (om[0] != 0 || om[1] != 0 || om[2] != 0)) coriolis(N, model, z, F, om);
+  if (om && (om[0] != 0 || om[1] != 0 || om[2] != 0)) coriolis(g, model, z, F, om);
   return 0;
 }
 
-int psref_rk2_step(int N, int model, double *state_, double nu, double eta, double dt,
-                   int nsteps) {
-  return psref_rk2_step_rot(N, model, state_, nu, eta, dt, nsteps, NULL);
+int psref_rk2_step(int nx, int ny, int nz, int model, double *state, double nu, double eta,
+                   double dt, int nsteps) {
+  return psref_rk2_step_rot(nx, ny, nz, model, state, nu, eta, dt, nsteps, NULL);
 }
 
-int psref_rk2_step_rot(int N, int model, double *state_, double nu, double eta, double dt,
-                       int nsteps, const double *omega) {
+int psref_rk2_step_rot(int nx, int ny, int nz, int model, double *state_, double nu, double eta,
+                       double dt, int nsteps, const double *omega) {
   if (!state_ || nsteps < 0 || (model != 0 && model != 1)) return -1;
-  if (!size_ok(N)) return -2;
+  if (!grid_ok(nx, ny, nz)) return -2;
+  const grid g = grid_of(nx, ny, nz);
   const long nf = model == 0 ? 3 : 6;
-  const long n = nf * (long)N * N * (N / 2 + 1);
+  const long n = nf * g.nc;
   cplx *z = (cplx *)state_;
   cplx *zs = (cplx *)malloc(sizeof(cplx) * (size_t)n);
   cplx *F = (cplx *)malloc(sizeof(cplx) * (size_t)n);
@@ -740,10 +812,10 @@ int psref_rk2_step_rot(int N, int model, double *state_, double nu, double eta, 
     goto done;
   }
   for (int s = 0; s < nsteps; ++s) {
-    if ((rc = rhs(N, model, z, F, nu, eta, omega))) goto done;
+    if ((rc = rhs(&g, model, z, F, nu, eta, omega))) goto done;
 #pragma omp parallel for schedule(static)
     for (long m = 0; m < n; ++m) zs[m] = z[m] + (MUT(11) ? 1.0 : 0.5) * dt * F[m];
-    if ((rc = rhs(N, model, MUT(5) ? z : zs, F, nu, eta, omega))) goto done;
+    if ((rc = rhs(&g, model, MUT(5) ? z : zs, F, nu, eta, omega))) goto done;
 #pragma omp parallel for schedule(static)
     for (long m = 0; m < n; ++m) z[m] = z[m] + dt * F[m];
   }
@@ -782,30 +854,32 @@ static long shell_of(long k2) {
   return s;
 }
 
-int psref_num_shells(int N) {
-  if (!size_ok(N)) return -2;
-  long h = N / 2;
-  return (int)shell_of(3 * h * h) + 1;
+int psref_num_shells(int nx, int ny, int nz) {
+  if (!grid_ok(nx, ny, nz)) return -2;
+  long hx = nx / 2, hy = ny / 2, hz = nz / 2;
+  return (int)shell_of(hx * hx + hy * hy + hz * hz) + 1;
 }
 
-int psref_energy_spectrum(int N, int nf, const double *fhat_, double *spec, double *totals) {
+int psref_energy_spectrum(int nx, int ny, int nz, int nf, const double *fhat_, double *spec,
+                          double *totals) {
   if (!fhat_ || !spec || !totals || nf < 1) return -1;
-  if (!size_ok(N)) return -2;
-  const long H = N / 2 + 1, nc = (long)N * N * H;
-  const int ns = psref_num_shells(N);
+  if (!grid_ok(nx, ny, nz)) return -2;
+  const grid g = grid_of(nx, ny, nz);
+  const long H = g.H, nc = g.nc;
+  const int ns = psref_num_shells(nx, ny, nz);
   const cplx *F = (const cplx *)fhat_;
   nsum *es = (nsum *)calloc((size_t)ns, sizeof(nsum));
   if (!es) return -3;
   nsum Z = {0, 0};
   double maxdiv = 0;
-  for (long kz = 0; kz < N; ++kz)
-    for (long ky = 0; ky < N; ++ky)
+  for (long kz = 0; kz < nz; ++kz)
+    for (long ky = 0; ky < ny; ++ky)
       for (long kx = 0; kx < H; ++kx) {
-        long m = (kz * N + ky) * H + kx;
-        long ix = wavx(kx), iy = wav(ky, N), iz = wav(kz, N);
+        long m = (kz * ny + ky) * H + kx;
+        long ix = wavx(kx), iy = wav(ky, ny), iz = wav(kz, nz);
         long k2 = ix * ix + iy * iy + iz * iz;
-        double w = (kx == 0 || 2 * kx == N) ? 1.0 : 2.0;
-        if (MUT(4) && 2 * kx == N) w = 2.0;
+        double w = (kx == 0 || 2 * kx == nx) ? 1.0 : 2.0;
+        if (MUT(4) && 2 * kx == nx) w = 2.0;
         double e = 0;
         for (int f = 0; f < nf; ++f) {
           cplx a = F[f * nc + m];
@@ -816,7 +890,7 @@ int psref_energy_spectrum(int N, int nf, const double *fhat_, double *spec, doub
         nadd(&es[s], 0.5 * w * e);
         nadd(&Z, 0.5 * w * q2 * e);
         for (int f = 0; f + 2 < nf; f += 3) {
-          double ax = g_s[0] * dwavx(kx, N), ay = g_s[1] * dwav(ky, N), az = g_s[2] * dwav(kz, N);
+          double ax = g_s[0] * dwavx(kx, nx), ay = g_s[1] * dwav(ky, ny), az = g_s[2] * dwav(kz, nz);
           cplx d = ax * F[f * nc + m] + ay * F[(f + 1) * nc + m] + az * F[(f + 2) * nc + m];
           if (cabs(d) > maxdiv) maxdiv = cabs(d);
         }

@@ -14,16 +14,22 @@
  * (projection, dealiasing, the time integrator), the textbook reading is used
  * and stated at each function.
  *
- * Conventions (all arrays dense, C order):
- *   real fields      [f][z][y][x]            double,   x fastest, N^3 per field
+ * Conventions (all arrays dense, C order), on an nx x ny x nz grid (the
+ * paper's N^3 cube is nx = ny = nz = N):
+ *   real fields      [f][z][y][x]            double,   x fastest, nx ny nz per field
  *   spectral fields  [f][kz][ky][kx]         complex double (re,im interleaved),
- *                                            kx = 0..N/2 fastest, N*N*(N/2+1) per field
- *   ky, kz index i   -> wavenumber i for i < N/2, i - N otherwise (N/2 -> -N/2)
- *   derivative wavenumber (odd derivatives): 0 at the Nyquist index N/2
- *   grid points      x_j = 2*pi*j/N on [0, 2*pi)
+ *                                            kx = 0..nx/2 fastest, nz ny (nx/2+1) per field
+ *   ky, kz index i   -> wavenumber i for i < n/2, i - n otherwise (n/2 -> -n/2),
+ *                       n the axis length
+ *   derivative wavenumber (odd derivatives): 0 at the Nyquist index n/2
+ *   grid points      x_j = 2*pi*j/nx on [0, 2*pi) (likewise y, z)
+ *   dealiasing       keep (3 kx/nx)^2 + (3 ky/ny)^2 + (3 kz/nz)^2 < 1, the
+ *                    2/3-rule sphere 9|k|^2 < N^2 of the cube stretched with
+ *                    the grid
  *
  * All functions return 0 on success and a negative code on bad arguments
  * (-1 null pointer / bad enum, -2 unsupported size, -3 out of memory).
+ * Supported sizes: each of nx, ny, nz even, 2 <= n <= 4096.
  */
 #ifndef PSREF_H
 #define PSREF_H
@@ -37,48 +43,48 @@ extern "C" {
 int psref_set_threads(int n);
 
 /* Unnormalised forward 3D transform X(k) = sum_x u(x) exp(-i k.x) of nf real
- * fields, stored for kx = 0..N/2.  N even, 2 <= N <= 4096. */
-int psref_fft_r2c(int N, int nf, const double *in, double *out);
+ * fields, stored for kx = 0..nx/2. */
+int psref_fft_r2c(int nx, int ny, int nz, int nf, const double *in, double *out);
 
 /* Unnormalised inverse 3D transform of nf half spectra, in pass order:
  * inverse complex transforms along z then y on every kx plane, then
- * u(x) = Re Y_0 + 2 sum_{0<kx<N/2} Re(Y_kx e^{i kx x}) + Re Y_{N/2} (-1)^x.
- * The imaginary parts of the kx = 0 and kx = N/2 bins are ignored. */
-int psref_fft_c2r(int N, int nf, const double *in, double *out);
+ * u(x) = Re Y_0 + 2 sum_{0<kx<nx/2} Re(Y_kx e^{i kx x}) + Re Y_{nx/2} (-1)^x.
+ * The imaginary parts of the kx = 0 and kx = nx/2 bins are ignored. */
+int psref_fft_c2r(int nx, int ny, int nz, int nf, const double *in, double *out);
 
-/* Direct O(N^3)-per-bin sum of the forward transform at nk selected bins
- * (kx[i], ky[i], kz[i] are storage indices). out: nk complex values. */
-int psref_dft_at(int N, const double *in, int nk, const int *kx, const int *ky,
-                 const int *kz, double *out);
+/* Direct sum of the forward transform at nk selected bins (kx[i], ky[i],
+ * kz[i] are storage indices). out: nk complex values. */
+int psref_dft_at(int nx, int ny, int nz, const double *in, int nk, const int *kx,
+                 const int *ky, const int *kz, double *out);
 
 /* Spectral curl  w = i k_d x u  of one 3-component spectral vector. */
-int psref_curl(int N, const double *uhat, double *what);
+int psref_curl(int nx, int ny, int nz, const double *uhat, double *what);
 
 /* Dealiased, projected nonlinear term of incompressible Navier-Stokes in
- * rotational form, nhat = D P F[u x w] / N^3 (3 fields in, 3 out). */
-int psref_nonlinear_ns(int N, const double *uhat, double *nhat);
+ * rotational form, nhat = D P F[u x w] / (nx ny nz) (3 fields in, 3 out). */
+int psref_nonlinear_ns(int nx, int ny, int nz, const double *uhat, double *nhat);
 
 /* MHD nonlinear terms for the Elsasser state (z+ = u + b, z- = u - b):
- * N+- = D [ P F[u x w + j x b] +- i k_d x F[u x b] ] / N^3
+ * N+- = D [ P F[u x w + j x b] +- i k_d x F[u x b] ] / (nx ny nz)
  * (6 fields in: z+ then z-; 6 out: N+ then N-). */
-int psref_nonlinear_mhd(int N, const double *zhat, double *nhat);
+int psref_nonlinear_mhd(int nx, int ny, int nz, const double *zhat, double *nhat);
 
 /* Galerkin (direct triad sum) value of the same nonlinear terms at nk
  * selected storage indices.  model 0 = NS (uhat: 3 fields), 1 = MHD (6).
  * out: nk x (3 or 6) complex values, component-major per mode. */
-int psref_nonlinear_at(int N, int model, const double *fhat, int nk,
+int psref_nonlinear_at(int nx, int ny, int nz, int model, const double *fhat, int nk,
                        const int *kx, const int *ky, const int *kz, double *out);
 
 /* Explicit midpoint RK2 steps, in place.  model 0 = NS (3 fields, viscosity
  * nu), 1 = MHD Elsasser (6 fields, viscosity nu, resistivity eta). */
-int psref_rk2_step(int N, int model, double *state, double nu, double eta,
+int psref_rk2_step(int nx, int ny, int nz, int model, double *state, double nu, double eta,
                    double dt, int nsteps);
 
 /* The same in a frame rotating at omega[3] (NULL or all zero: no rotation):
  * the momentum equation gains -P(k) (2 Omega x u) at every k != 0 (for MHD
  * with u = (z+ + z-)/2, added to both Elsasser fields). */
-int psref_rk2_step_rot(int N, int model, double *state, double nu, double eta,
-                       double dt, int nsteps, const double *omega);
+int psref_rk2_step_rot(int nx, int ny, int nz, int model, double *state, double nu,
+                       double eta, double dt, int nsteps, const double *omega);
 
 /* Box lengths (default 2 pi each): physical wavenumbers k = (2 pi / L) n in
  * every derivative, in the projector and in |k|^2 of the viscous term and
@@ -86,15 +92,15 @@ int psref_rk2_step_rot(int N, int model, double *state, double nu, double eta,
  * Process-wide setting.  Returns -1 for non-positive or non-finite L. */
 int psref_set_box(double Lx, double Ly, double Lz);
 
-/* Number of spectral shells: s(3 (N/2)^2) + 1. */
-int psref_num_shells(int N);
+/* Number of spectral shells: s((nx/2)^2 + (ny/2)^2 + (nz/2)^2) + 1. */
+int psref_num_shells(int nx, int ny, int nz);
 
 /* Shell energy spectrum E(s) = 1/2 sum_{shell(k)=s} w |f(k)|^2 over nf
- * fields, w = 1 on the kx = 0 and kx = N/2 planes, 2 elsewhere, and the
+ * fields, w = 1 on the kx = 0 and kx = nx/2 planes, 2 elsewhere, and the
  * totals [E, Z, maxdiv] with Z = 1/2 sum w |k|^2 |f|^2 and maxdiv the largest
  * |k_d . f| over consecutive component triples (0 if nf is not a multiple of
- * 3).  shell(k) = round(|k|) evaluated exactly in integers. */
-int psref_energy_spectrum(int N, int nf, const double *fhat, double *spec,
+ * 3).  shell(k) = round(|k|) of the index, evaluated exactly in integers. */
+int psref_energy_spectrum(int nx, int ny, int nz, int nf, const double *fhat, double *spec,
                           double *totals);
 
 #ifdef __cplusplus

@@ -6,8 +6,8 @@ CPU-baseline leg of the benchmark may import this module.  The product path
 
 The arithmetic lives in ``psref.c`` (plain C, FP64); this module only builds
 and loads that library and marshals numpy arrays.  Every array is C-contiguous:
-real fields ``float64[nf, N, N, N]`` ([f][z][y][x]) and half spectra
-``complex128[nf, N, N, N//2+1]`` ([f][kz][ky][kx]).
+real fields ``float64[nf, nz, ny, nx]`` ([f][z][y][x]) and half spectra
+``complex128[nf, nz, ny, nx//2+1]`` ([f][kz][ky][kx]); the cube is nx = ny = nz.
 """
 from __future__ import annotations
 
@@ -39,7 +39,9 @@ def build(mutant: int = 0, out: Optional[str] = None, openmp: bool = True) -> st
 
 
 class Oracle:
-    """ctypes wrapper around one build of the oracle library."""
+    """ctypes wrapper around one build of the oracle library.  Grid sizes are
+    taken from the array shapes: real fields ``[nf, nz, ny, nx]``, half
+    spectra ``[nf, nz, ny, nx//2+1]`` (nx even)."""
 
     def __init__(self, path: Optional[str] = None):
         path = path or LIB
@@ -50,23 +52,22 @@ class Oracle:
         self.lib = ctypes.CDLL(path)
         dp = ctypes.POINTER(ctypes.c_double)
         ip = ctypes.POINTER(ctypes.c_int)
+        i = ctypes.c_int
+        d = ctypes.c_double
         L = self.lib
-        L.psref_set_threads.argtypes = [ctypes.c_int]
-        L.psref_fft_r2c.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp]
-        L.psref_fft_c2r.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp]
-        L.psref_dft_at.argtypes = [ctypes.c_int, dp, ctypes.c_int, ip, ip, ip, dp]
-        L.psref_curl.argtypes = [ctypes.c_int, dp, dp]
-        L.psref_nonlinear_ns.argtypes = [ctypes.c_int, dp, dp]
-        L.psref_nonlinear_mhd.argtypes = [ctypes.c_int, dp, dp]
-        L.psref_nonlinear_at.argtypes = [ctypes.c_int, ctypes.c_int, dp, ctypes.c_int, ip, ip,
-                                         ip, dp]
-        L.psref_rk2_step.argtypes = [ctypes.c_int, ctypes.c_int, dp, ctypes.c_double,
-                                     ctypes.c_double, ctypes.c_double, ctypes.c_int]
-        L.psref_rk2_step_rot.argtypes = [ctypes.c_int, ctypes.c_int, dp, ctypes.c_double,
-                                         ctypes.c_double, ctypes.c_double, ctypes.c_int, dp]
-        L.psref_set_box.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double]
-        L.psref_num_shells.argtypes = [ctypes.c_int]
-        L.psref_energy_spectrum.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp]
+        L.psref_set_threads.argtypes = [i]
+        L.psref_fft_r2c.argtypes = [i, i, i, i, dp, dp]
+        L.psref_fft_c2r.argtypes = [i, i, i, i, dp, dp]
+        L.psref_dft_at.argtypes = [i, i, i, dp, i, ip, ip, ip, dp]
+        L.psref_curl.argtypes = [i, i, i, dp, dp]
+        L.psref_nonlinear_ns.argtypes = [i, i, i, dp, dp]
+        L.psref_nonlinear_mhd.argtypes = [i, i, i, dp, dp]
+        L.psref_nonlinear_at.argtypes = [i, i, i, i, dp, i, ip, ip, ip, dp]
+        L.psref_rk2_step.argtypes = [i, i, i, i, dp, d, d, d, i]
+        L.psref_rk2_step_rot.argtypes = [i, i, i, i, dp, d, d, d, i, dp]
+        L.psref_set_box.argtypes = [d, d, d]
+        L.psref_num_shells.argtypes = [i, i, i]
+        L.psref_energy_spectrum.argtypes = [i, i, i, i, dp, dp, dp]
 
     # -- helpers -----------------------------------------------------------
     @staticmethod
@@ -80,13 +81,15 @@ class Oracle:
         return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
 
     @staticmethod
-    def _spec(a, N: int, nf: Optional[int] = None) -> np.ndarray:
+    def _spec(a, nf: Optional[int] = None):
+        """(array [nf, nz, ny, H], (nx, ny, nz)) with nx = 2 (H - 1)."""
         a = np.ascontiguousarray(a, dtype=np.complex128)
         if a.ndim == 3:
             a = a[None]
-        if a.shape[1:] != (N, N, N // 2 + 1) or (nf is not None and a.shape[0] != nf):
-            raise ValueError(f"bad spectral shape {a.shape} for N={N}")
-        return a
+        if a.ndim != 4 or a.shape[-1] < 2 or (nf is not None and a.shape[0] != nf):
+            raise ValueError(f"bad spectral shape {a.shape}")
+        nz, ny, H = a.shape[1:]
+        return a, (2 * (H - 1), ny, nz)
 
     @staticmethod
     def _check(rc: int, what: str):
@@ -102,58 +105,53 @@ class Oracle:
         squeeze = u.ndim == 3
         if squeeze:
             u = u[None]
-        nf, N = u.shape[0], u.shape[1]
-        out = np.empty((nf, N, N, N // 2 + 1), np.complex128)
-        self._check(self.lib.psref_fft_r2c(N, nf, self._p(u), self._p(out)), "fft_r2c")
+        nf, nz, ny, nx = u.shape
+        out = np.empty((nf, nz, ny, nx // 2 + 1), np.complex128)
+        self._check(self.lib.psref_fft_r2c(nx, ny, nz, nf, self._p(u), self._p(out)), "fft_r2c")
         return out[0] if squeeze else out
 
     def fft_c2r(self, X: np.ndarray) -> np.ndarray:
         squeeze = X.ndim == 3
-        N = X.shape[-2]
-        X = self._spec(X, N)
+        X, (nx, ny, nz) = self._spec(X)
         nf = X.shape[0]
-        out = np.empty((nf, N, N, N), np.float64)
-        self._check(self.lib.psref_fft_c2r(N, nf, self._p(X), self._p(out)), "fft_c2r")
+        out = np.empty((nf, nz, ny, nx), np.float64)
+        self._check(self.lib.psref_fft_c2r(nx, ny, nz, nf, self._p(X), self._p(out)), "fft_c2r")
         return out[0] if squeeze else out
 
     def dft_at(self, u: np.ndarray, kx, ky, kz) -> np.ndarray:
         u = np.ascontiguousarray(u, dtype=np.float64)
-        N = u.shape[-1]
+        nz, ny, nx = u.shape[-3:]
         kx, ky, kz = (np.ascontiguousarray(k, dtype=np.int32) for k in (kx, ky, kz))
         out = np.empty(len(kx), np.complex128)
-        self._check(self.lib.psref_dft_at(N, self._p(u), len(kx), self._ip(kx), self._ip(ky),
-                                          self._ip(kz), self._p(out)), "dft_at")
+        self._check(self.lib.psref_dft_at(nx, ny, nz, self._p(u), len(kx), self._ip(kx),
+                                          self._ip(ky), self._ip(kz), self._p(out)), "dft_at")
         return out
 
     def curl(self, uhat: np.ndarray) -> np.ndarray:
-        N = uhat.shape[-2]
-        uhat = self._spec(uhat, N, 3)
+        uhat, n = self._spec(uhat, 3)
         out = np.empty_like(uhat)
-        self._check(self.lib.psref_curl(N, self._p(uhat), self._p(out)), "curl")
+        self._check(self.lib.psref_curl(*n, self._p(uhat), self._p(out)), "curl")
         return out
 
     def nonlinear_ns(self, uhat: np.ndarray) -> np.ndarray:
-        N = uhat.shape[-2]
-        uhat = self._spec(uhat, N, 3)
+        uhat, n = self._spec(uhat, 3)
         out = np.empty_like(uhat)
-        self._check(self.lib.psref_nonlinear_ns(N, self._p(uhat), self._p(out)), "nonlinear_ns")
+        self._check(self.lib.psref_nonlinear_ns(*n, self._p(uhat), self._p(out)), "nonlinear_ns")
         return out
 
     def nonlinear_mhd(self, zhat: np.ndarray) -> np.ndarray:
-        N = zhat.shape[-2]
-        zhat = self._spec(zhat, N, 6)
+        zhat, n = self._spec(zhat, 6)
         out = np.empty_like(zhat)
-        self._check(self.lib.psref_nonlinear_mhd(N, self._p(zhat), self._p(out)),
+        self._check(self.lib.psref_nonlinear_mhd(*n, self._p(zhat), self._p(out)),
                     "nonlinear_mhd")
         return out
 
     def nonlinear_at(self, fhat: np.ndarray, model: int, kx, ky, kz) -> np.ndarray:
-        N = fhat.shape[-2]
         nf = 3 if model == NS else 6
-        fhat = self._spec(fhat, N, nf)
+        fhat, n = self._spec(fhat, nf)
         kx, ky, kz = (np.ascontiguousarray(k, dtype=np.int32) for k in (kx, ky, kz))
         out = np.empty((len(kx), nf), np.complex128)
-        self._check(self.lib.psref_nonlinear_at(N, model, self._p(fhat), len(kx), self._ip(kx),
+        self._check(self.lib.psref_nonlinear_at(*n, model, self._p(fhat), len(kx), self._ip(kx),
                                                 self._ip(ky), self._ip(kz), self._p(out)),
                     "nonlinear_at")
         return out
@@ -162,15 +160,15 @@ class Oracle:
                  nsteps: int = 1, omega=None) -> np.ndarray:
         """Returns a new array (the argument is not modified).  omega: the
         frame's rotation vector (Coriolis term), or None."""
-        N = state.shape[-2]
         nf = 3 if model == NS else 6
-        z = self._spec(state, N, nf).copy()
+        z, n = self._spec(state, nf)
+        z = z.copy()
         if omega is None:
-            rc = self.lib.psref_rk2_step(N, model, self._p(z), float(nu), float(eta), float(dt),
+            rc = self.lib.psref_rk2_step(*n, model, self._p(z), float(nu), float(eta), float(dt),
                                          int(nsteps))
         else:
             om = np.ascontiguousarray(omega, dtype=np.float64).reshape(3)
-            rc = self.lib.psref_rk2_step_rot(N, model, self._p(z), float(nu), float(eta),
+            rc = self.lib.psref_rk2_step_rot(*n, model, self._p(z), float(nu), float(eta),
                                              float(dt), int(nsteps), self._p(om))
         self._check(rc, "rk2_step")
         return z
@@ -179,16 +177,17 @@ class Oracle:
         """Box lengths for every later call (process-wide; default 2 pi)."""
         self._check(self.lib.psref_set_box(float(Lx), float(Ly), float(Lz)), "set_box")
 
-    def num_shells(self, N: int) -> int:
-        return int(self.lib.psref_num_shells(N))
+    def num_shells(self, nx: int, ny: Optional[int] = None, nz: Optional[int] = None) -> int:
+        ny = nx if ny is None else ny
+        nz = nx if nz is None else nz
+        return int(self.lib.psref_num_shells(nx, ny, nz))
 
     def energy_spectrum(self, fhat: np.ndarray):
-        N = fhat.shape[-2]
-        fhat = self._spec(fhat, N)
+        fhat, n = self._spec(fhat)
         nf = fhat.shape[0]
-        spec = np.empty(self.num_shells(N), np.float64)
+        spec = np.empty(self.num_shells(*n), np.float64)
         tot = np.empty(3, np.float64)
-        self._check(self.lib.psref_energy_spectrum(N, nf, self._p(fhat), self._p(spec),
+        self._check(self.lib.psref_energy_spectrum(*n, nf, self._p(fhat), self._p(spec),
                                                    self._p(tot)), "energy_spectrum")
         return spec, tot
 

@@ -89,6 +89,17 @@ class SparseField:
         out[:, kk[:, None], kk[None, :], : K + 1] = self.values.astype(dtype)
         return out
 
+    def dense_xyz(self, nx: int, ny: int, nz: int, dtype=np.complex128) -> np.ndarray:
+        """The same modes scattered into an nx x ny x nz grid's half spectrum
+        [c][kz][ky][kx] (each axis long enough to hold them)."""
+        K = self.K
+        if 2 * K >= min(nx, ny, nz) or K > nx // 2:
+            raise ValueError("grid too small for the field's modes")
+        out = np.zeros((self.values.shape[0], nz, ny, nx // 2 + 1), dtype=dtype)
+        kr = np.arange(-K, K + 1)
+        out[:, (kr % nz)[:, None], (kr % ny)[None, :], : K + 1] = self.values.astype(dtype)
+        return out
+
     def index_arrays(self):
         """(iz, iy, ix) storage indices of the cube, for scattering elsewhere."""
         K, N = self.K, self.N

@@ -15,6 +15,7 @@ it; each pin names the passage whose mathematics it checks.
 from __future__ import annotations
 
 import math
+from fractions import Fraction
 
 import numpy as np
 
@@ -60,29 +61,34 @@ def _random_half(rng, nf, N):
 # ---------------------------------------------------------------------------
 
 def brute_r2c(u: np.ndarray) -> np.ndarray:
-    """X(k) = sum_x u(x) exp(-i k.x), literally: every k against every x."""
-    N = u.shape[-1]
-    H = N // 2 + 1
-    kz, ky, kx = np.meshgrid(np.arange(N), np.arange(N), np.arange(H), indexing="ij")
-    z, y, x = np.meshgrid(np.arange(N), np.arange(N), np.arange(N), indexing="ij")
-    e = (np.outer(kx.ravel(), x.ravel()) + np.outer(ky.ravel(), y.ravel())
-         + np.outer(kz.ravel(), z.ravel())) % N
-    ph = np.exp(-1j * TWO_PI * e / N)
-    return (ph @ u.ravel()).reshape(N, N, H)
+    """X(k) = sum_x u(x) exp(-i k.x), literally: every k against every x
+    (u is [nz, ny, nx]; the phase of each axis is taken modulo its length)."""
+    nz, ny, nx = u.shape
+    H = nx // 2 + 1
+    kz, ky, kx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(H), indexing="ij")
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    ph = (np.outer(kx.ravel(), x.ravel()) % nx / nx + np.outer(ky.ravel(), y.ravel()) % ny / ny
+          + np.outer(kz.ravel(), z.ravel()) % nz / nz)
+    return (np.exp(-1j * TWO_PI * ph) @ u.ravel()).reshape(nz, ny, H)
 
 
 def brute_c2r(X: np.ndarray) -> np.ndarray:
     """The inverse in pass order: inverse sums along z and y on every kx plane,
-    then u = Re Y_0 + 2 sum_{0<k<N/2} Re(Y_k e^{ikx}) + Re Y_{N/2} (-1)^x."""
-    N = X.shape[0]
-    j = np.arange(N)
-    Einv = np.exp(1j * TWO_PI * (np.outer(j, j) % N) / N)  # [x, k]
-    Y = np.einsum("zc,cbk->zbk", Einv, X)   # along kz
-    Y = np.einsum("yb,zbk->zyk", Einv, Y)   # along ky
-    u = np.real(Y[..., 0])[..., None] * np.ones(N)
-    for k in range(1, N // 2):
-        u = u + 2.0 * np.real(Y[..., k][..., None] * np.exp(1j * TWO_PI * k * j / N))
-    u = u + np.real(Y[..., N // 2])[..., None] * ((-1.0) ** j)
+    then u = Re Y_0 + 2 sum_{0<k<nx/2} Re(Y_k e^{ikx}) + Re Y_{nx/2} (-1)^x."""
+    nz, ny, H = X.shape
+    nx = 2 * (H - 1)
+
+    def einv(n):  # [x, k]
+        j = np.arange(n)
+        return np.exp(1j * TWO_PI * (np.outer(j, j) % n) / n)
+
+    Y = np.einsum("zc,cbk->zbk", einv(nz), X)   # along kz
+    Y = np.einsum("yb,zbk->zyk", einv(ny), Y)   # along ky
+    j = np.arange(nx)
+    u = np.real(Y[..., 0])[..., None] * np.ones(nx)
+    for k in range(1, nx // 2):
+        u = u + 2.0 * np.real(Y[..., k][..., None] * np.exp(1j * TWO_PI * k * j / nx))
+    u = u + np.real(Y[..., nx // 2])[..., None] * ((-1.0) ** j)
     return u
 
 
@@ -191,17 +197,18 @@ def pin_curl_nyquist(o):
 # ---------------------------------------------------------------------------
 
 def _effective_full(F: np.ndarray):
-    """All modes of the full spectrum with |k_i| < N/2 as seen by the inverse
+    """All modes of the full spectrum with |k_a| < n_a/2 as seen by the inverse
     transform (Hermitian part of the kx = 0 plane): returns (K [M,3], V [nf,M])."""
-    nf, N = F.shape[0], F.shape[1]
+    nf, nz, ny, H = F.shape
+    nx = 2 * (H - 1)
     ks, vals = [], []
-    for kz in range(-(N // 2) + 1, N // 2):
-        for ky in range(-(N // 2) + 1, N // 2):
-            for kx in range(-(N // 2) + 1, N // 2):
+    for kz in range(-(nz // 2) + 1, nz // 2):
+        for ky in range(-(ny // 2) + 1, ny // 2):
+            for kx in range(-(nx // 2) + 1, nx // 2):
                 sx, sy, sz = (kx, ky, kz) if kx >= 0 else (-kx, -ky, -kz)
-                a = F[:, sz % N, sy % N, sx]
+                a = F[:, sz % nz, sy % ny, sx]
                 if sx == 0:
-                    a = 0.5 * (a + np.conj(F[:, (-sz) % N, (-sy) % N, 0]))
+                    a = 0.5 * (a + np.conj(F[:, (-sz) % nz, (-sy) % ny, 0]))
                 if kx < 0:
                     a = np.conj(a)
                 if np.any(a != 0):
@@ -210,14 +217,25 @@ def _effective_full(F: np.ndarray):
     return np.array(ks, dtype=np.int64).reshape(-1, 3), np.array(vals).T.reshape(nf, -1)
 
 
-def _kept_outputs(N):
+def _in_ellipsoid(n, k) -> bool:
+    """The 2/3 rule on grid n = (nx, ny, nz): (3 kx/nx)^2 + (3 ky/ny)^2 +
+    (3 kz/nz)^2 < 1 in exact rational arithmetic (the sphere 9|k|^2 < N^2 of
+    the cube)."""
+    return sum(Fraction(3 * int(k[a]), n[a]) ** 2 for a in range(3)) < 1
+
+
+def _signed(i, n):
+    return i if i < n // 2 else i - n
+
+
+def _kept_outputs(n):
+    nx, ny, nz = n
     out = []
-    for kz in range(N):
-        for ky in range(N):
-            for kx in range(N // 2 + 1):
-                k = np.array([kx, ky if ky < N // 2 else ky - N, kz if kz < N // 2 else kz - N])
-                k2 = int(k @ k)
-                if k2 > 0 and 9 * k2 < N * N:
+    for kz in range(nz):
+        for ky in range(ny):
+            for kx in range(nx // 2 + 1):
+                k = np.array([kx, _signed(ky, ny), _signed(kz, nz)])
+                if int(k @ k) > 0 and _in_ellipsoid(n, k):
                     out.append(((kz, ky, kx), k))
     return out
 
@@ -225,7 +243,7 @@ def _kept_outputs(N):
 def brute_triads(F: np.ndarray, model: int) -> np.ndarray:
     """Dealiased, projected quadratic term as a literal sum over triads
     p + q = k of Fourier coefficients (Galerkin convolution)."""
-    N = F.shape[1]
+    n = (2 * (F.shape[3] - 1), F.shape[2], F.shape[1])
     K, V = _effective_full(F)
     index = {tuple(k): i for i, k in enumerate(K)}
     out = np.zeros(F.shape, np.complex128)
@@ -243,7 +261,7 @@ def brute_triads(F: np.ndarray, model: int) -> np.ndarray:
         return np.stack([a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2],
                          a[0] * b[1] - a[1] * b[0]])
 
-    for (sz, sy, sx), k in _kept_outputs(N):
+    for (sz, sy, sx), k in _kept_outputs(n):
         q = k[None, :] - K
         qi = np.array([index.get(tuple(x), -1) for x in q])
         m = qi >= 0
@@ -574,6 +592,136 @@ def pin_box_inertial_wave(o):
         assert _rel(got, U * _rk2_factor(lam, dt) ** 2) < 1e-13, _rel(got, U * _rk2_factor(lam, dt) ** 2)
     finally:
         o.set_box()
+
+
+# ---------------------------------------------------------------------------
+# Grids whose axis lengths differ (Sec. 5: domains of non-unit aspect ratio;
+# the grid (nx, ny, nz) replaces the cube N^3 in every definition)
+# ---------------------------------------------------------------------------
+
+def _random_grid_half(rng, nf, n):
+    nx, ny, nz = n
+    s = (nf, nz, ny, nx // 2 + 1)
+    return rng.standard_normal(s) + 1j * rng.standard_normal(s)
+
+
+def pin_grid_fft_brute(o):
+    """Literal DFT sums on grids with three different axis lengths."""
+    rng = np.random.default_rng(51)
+    for nx, ny, nz in ((6, 4, 8), (8, 12, 6)):
+        u = rng.standard_normal((nz, ny, nx))
+        assert _rel(o.fft_r2c(u), brute_r2c(u)) < 1e-13, (nx, ny, nz)
+        X = _random_grid_half(rng, 1, (nx, ny, nz))[0]
+        assert _rel(o.fft_c2r(X), brute_c2r(X)) < 1e-13, (nx, ny, nz)
+        kx = np.array([0, 1, nx // 2, 2]); ky = np.array([0, ny - 1, 2, ny // 2])
+        kz = np.array([nz - 1, 0, 3, nz // 2])
+        assert np.abs(o.dft_at(u, kx, ky, kz) - brute_r2c(u)[kz, ky, kx]).max() < 1e-12
+
+
+def pin_grid_fft_numpy(o):
+    """numpy's rfftn/irfftn on grids with different axis lengths."""
+    rng = np.random.default_rng(52)
+    for nz, ny, nx in ((12, 16, 24), (24, 8, 18)):
+        u = rng.standard_normal((2, nz, ny, nx))
+        assert _rel(o.fft_r2c(u), np.fft.rfftn(u, axes=(1, 2, 3))) < 1e-13
+        X = _random_grid_half(rng, 2, (nx, ny, nz))
+        ref = np.fft.irfftn(X, s=(nz, ny, nx), axes=(1, 2, 3)) * (nx * ny * nz)
+        assert _rel(o.fft_c2r(X), ref) < 1e-13
+
+
+def _random_in_ellipsoid(rng, nf, n):
+    """Random half spectrum, zero outside the 2/3-rule ellipsoid of grid n (an
+    input with no aliases reaching a kept mode)."""
+    F = _random_grid_half(rng, nf, n)
+    nx, ny, nz = n
+    for kz in range(nz):
+        for ky in range(ny):
+            for kx in range(nx // 2 + 1):
+                if not _in_ellipsoid(n, (kx, _signed(ky, ny), _signed(kz, nz))):
+                    F[:, kz, ky, kx] = 0
+    return F
+
+
+def pin_grid_triad_brute(o):
+    """The dealiased, projected nonlinear terms (NS and MHD) on grids with
+    different axis lengths equal the literal triad sum with the stretched
+    2/3-rule mask, and the oracle's triad-sum entry agrees."""
+    rng = np.random.default_rng(53)
+    for n in ((12, 8, 16), (16, 12, 10)):
+        u = _random_in_ellipsoid(rng, 3, n)
+        ref = brute_triads(u, NS)
+        assert _rel(o.nonlinear_ns(u), ref) < 1e-13, n
+        z = _random_in_ellipsoid(rng, 6, n)
+        ref = brute_triads(z, MHD)
+        assert _rel(o.nonlinear_mhd(z), ref) < 1e-13, n
+        kz = np.array([1, 0, n[2] - 2, 3]); ky = np.array([1, 1, n[1] - 1, 0])
+        kx = np.array([0, 2, 1, 1])
+        got = o.nonlinear_at(z, MHD, kx, ky, kz)
+        assert np.abs(got.T - ref[:, kz, ky, kx]).max() < 1e-13 * np.abs(ref).max()
+
+
+def _low(F, K):
+    """Coefficients of a half spectrum on the cube |k_a| <= K, and the norm of
+    everything outside it."""
+    nz, ny = F.shape[1], F.shape[2]
+    kr = np.arange(-K, K + 1)
+    iz, iy = (kr % nz)[:, None], (kr % ny)[None, :]
+    low = F[:, iz, iy, : K + 1]
+    rest = F.copy()
+    rest[:, iz, iy, : K + 1] = 0
+    return low, float(np.linalg.norm(rest.ravel()))
+
+
+def pin_grid_embedding(o):
+    """A field with modes |k| <= 2 evolves identically on any grid that keeps
+    every mode it reaches: one RK2 step (support |k| <= 8) on 32^3 and on
+    grids with different axis lengths, NS and MHD, rotating, in a box."""
+    K, nu, dt = 8, 0.01, 0.02
+    om = np.array([0.4, -0.3, 0.9])
+    u = synth.band_limited(32, 61, 2)
+    b = synth.band_limited(32, 62, 2)
+    zsp = synth.SparseField(32, 2, np.concatenate([(u.values + b.values), (u.values - b.values)]))
+    o.set_box(2 * math.pi, 3 * math.pi, 4 * math.pi)
+    try:
+        ref_ns = o.rk2_step(u.dense(), NS, nu, 0.0, dt, 1, omega=om)
+        ref_mhd = o.rk2_step(zsp.dense(), MHD, nu, 0.5 * nu, dt, 1, omega=om)
+        ref_nl = o.nonlinear_mhd(zsp.dense())
+        for n in ((32, 48, 64), (64, 32, 48)):
+            for got, ref in ((o.rk2_step(u.dense_xyz(*n), NS, nu, 0.0, dt, 1, omega=om), ref_ns),
+                             (o.rk2_step(zsp.dense_xyz(*n), MHD, nu, 0.5 * nu, dt, 1, omega=om),
+                              ref_mhd),
+                             (o.nonlinear_mhd(zsp.dense_xyz(*n)), ref_nl)):
+                gl, grest = _low(got, K)
+                rl, rrest = _low(ref, K)
+                scale = np.linalg.norm(rl.ravel())
+                assert grest < 1e-13 * scale and rrest < 1e-13 * scale, n
+                assert _rel(gl, rl) < 1e-13, (n, _rel(gl, rl))
+    finally:
+        o.set_box()
+
+
+def pin_grid_spectrum_brute(o):
+    """Shell energies on a grid with different axis lengths by a plain loop:
+    weight 1 on the kx = 0 and kx = nx/2 planes, shells round(|k|) of the
+    index."""
+    nx, ny, nz = 8, 6, 10
+    rng = np.random.default_rng(54)
+    F = _random_grid_half(rng, 3, (nx, ny, nz))
+    ns = o.num_shells(nx, ny, nz)
+    spec = np.zeros(ns)
+    for kz in range(nz):
+        for ky in range(ny):
+            for kx in range(nx // 2 + 1):
+                k2 = kx ** 2 + _signed(ky, ny) ** 2 + _signed(kz, nz) ** 2
+                s = 0
+                while not (4 * k2 < (2 * s + 1) ** 2):
+                    s += 1
+                w = 1.0 if kx in (0, nx // 2) else 2.0
+                spec[s] += 0.5 * w * sum(abs(F[c, kz, ky, kx]) ** 2 for c in range(3))
+    got, tot = o.energy_spectrum(F)
+    assert ns == int(math.floor(math.sqrt((nx // 2) ** 2 + (ny // 2) ** 2 + (nz // 2) ** 2) + 0.5)) + 1
+    assert _rel(got, spec) < 1e-14
+    assert abs(tot[0] - spec.sum()) < 1e-13 * spec.sum()
 
 
 ALL_PINS = [v for k, v in sorted(globals().items()) if k.startswith("pin_")]

@@ -27,6 +27,7 @@ MUTANTS = {
     14: "rotation: Omega x u instead of 2 Omega x u",
     15: "box: viscous term with the index |n|^2",
     16: "box: curl without the factors 2 pi / L",
+    17: "grid: dealiasing sphere of nx on every axis",
 }
 
 
