@@ -75,6 +75,19 @@ ps_status ps_plan_create(ps_plan *out, int N, int nfields, ps_dtype dtype);
 ps_status ps_plan_create_batch(ps_plan *out, int nbox, const int *N, int nfields,
                                ps_dtype dtype);
 
+/* Plan for one box of nx x ny x nz points (Sec. 5 says the method applies to
+ * domains whose aspect ratio is not unity; each length one of the sizes
+ * above).  Real fields are [f][z][y][x] (nx fastest), half spectra
+ * [f][kz][ky][kx <= nx/2]; the transforms are unnormalised and the nonlinear
+ * terms carry 1/(nx ny nz).  The 2/3 rule keeps the modes with
+ * (3 kx/nx)^2 + (3 ky/ny)^2 + (3 kz/nz)^2 < 1 (the sphere 9|k|^2 < N^2 below
+ * when the lengths agree), the shells are round(|k|) of the index, and
+ * ps_num_shells gives s((nx/2)^2 + (ny/2)^2 + (nz/2)^2) + 1 of them.  MHD
+ * needs an nx that ps_plan_create would accept for MHD.  Everything below
+ * applies with N read per axis. */
+ps_status ps_plan_create_grid(ps_plan *out, int nx, int ny, int nz, int nfields,
+                              ps_dtype dtype);
+
 /* Releases the plan (not the caller's buffers).  NULL is a no-op. */
 ps_status ps_plan_destroy(ps_plan p);
 

@@ -27,6 +27,7 @@ _vp, _sz, _i, _d = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_doub
 _SIGS = [
     ("ps_plan_create", _i, [ctypes.POINTER(_vp), _i, _i, _i]),
     ("ps_plan_create_batch", _i, [ctypes.POINTER(_vp), _i, ctypes.POINTER(_i), _i, _i]),
+    ("ps_plan_create_grid", _i, [ctypes.POINTER(_vp), _i, _i, _i, _i, _i]),
     ("ps_plan_destroy", _i, [_vp]),
     ("ps_plan_set_stream", _i, [_vp, _vp]),
     ("ps_plan_workspace_bytes", _sz, [_vp]),
@@ -103,19 +104,31 @@ def dtype_code(dtype: Union[str, torch.dtype, int]) -> int:
 
 
 class Plan:
-    """A plan for one N^3 box (``N`` an int) or an ensemble (``N`` a list)."""
+    """A plan for one N^3 box (``N`` an int), an ensemble (``N`` a list) or
+    one nx x ny x nz box (``grid=(nx, ny, nz)``, ``N`` ignored)."""
 
-    def __init__(self, N: Union[int, Sequence[int]], nfields: int = 3, dtype="f32",
-                 device: Union[int, str, torch.device, None] = None, workspace: bool = True):
+    def __init__(self, N: Union[int, Sequence[int], None] = None, nfields: int = 3, dtype="f32",
+                 device: Union[int, str, torch.device, None] = None, workspace: bool = True,
+                 grid: Optional[Sequence[int]] = None):
         self.dtype = dtype_code(dtype)
         self.nfields = int(nfields)
-        self.sizes = [int(N)] if isinstance(N, int) else [int(n) for n in N]
+        if grid is not None:
+            self.dims = [tuple(int(n) for n in grid)]
+            if len(self.dims[0]) != 3:
+                raise ValueError("grid must be (nx, ny, nz)")
+        else:
+            sizes = [int(N)] if isinstance(N, int) else [int(n) for n in N]
+            self.dims = [(n, n, n) for n in sizes]
+        self.sizes = [d[0] for d in self.dims]
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None \
             else torch.device(device)
         L = lib()
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
-            if len(self.sizes) == 1:
+            if grid is not None:
+                _check(L.ps_plan_create_grid(ctypes.byref(h), *self.dims[0], self.nfields,
+                                             self.dtype), "ps_plan_create_grid")
+            elif len(self.sizes) == 1:
                 _check(L.ps_plan_create(ctypes.byref(h), self.sizes[0], self.nfields, self.dtype),
                        "ps_plan_create")
             else:
@@ -175,20 +188,20 @@ class Plan:
         return _RDT[self.dtype]
 
     def spectral_shape(self, nf: Optional[int] = None):
-        assert len(self.sizes) == 1, "ensembles use flat buffers"
-        N = self.sizes[0]
-        return (nf or self.nfields, N, N, N // 2 + 1)
+        assert len(self.dims) == 1, "ensembles use flat buffers"
+        nx, ny, nz = self.dims[0]
+        return (nf or self.nfields, nz, ny, nx // 2 + 1)
 
     def real_shape(self):
-        assert len(self.sizes) == 1, "ensembles use flat buffers"
-        N = self.sizes[0]
-        return (self.nfields, N, N, N)
+        assert len(self.dims) == 1, "ensembles use flat buffers"
+        nx, ny, nz = self.dims[0]
+        return (self.nfields, nz, ny, nx)
 
     def n_complex(self) -> int:
-        return sum(self.nfields * n * n * (n // 2 + 1) for n in self.sizes)
+        return sum(self.nfields * nz * ny * (nx // 2 + 1) for nx, ny, nz in self.dims)
 
     def n_real(self) -> int:
-        return sum(self.nfields * n ** 3 for n in self.sizes)
+        return sum(self.nfields * nx * ny * nz for nx, ny, nz in self.dims)
 
     def _need(self, t: torch.Tensor, kind: str, name: str, numel: Optional[int] = None):
         want = self.complex_dtype if kind == "c" else self.real_dtype

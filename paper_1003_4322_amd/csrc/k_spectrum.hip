@@ -29,7 +29,7 @@ int variant_count(const char* kind, int N, bool mhd) {
 
 // Second stage: per-shell sums over planes in plane order, then the totals in
 // shell order, all Neumaier-compensated (one workgroup).
-__global__ __launch_bounds__(1024) void k_spec_final(const double* part, const double* pmax, int N,
+__global__ __launch_bounds__(1024) void k_spec_final(const double* part, const double* pmax, int nplanes,
                                                      int nshell, double* spec, double* totals) {
   __shared__ double zs[1024];
   __shared__ double es[1024];
@@ -38,7 +38,7 @@ __global__ __launch_bounds__(1024) void k_spec_final(const double* part, const d
     const int s = s0 + threadIdx.x;
     if (s < nshell) {
       NSum E{0, 0}, Z{0, 0};
-      for (int p = 0; p < N; ++p) {
+      for (int p = 0; p < nplanes; ++p) {
         nadd(E, part[((long)p * nshell + s) * 2]);
         nadd(Z, part[((long)p * nshell + s) * 2 + 1]);
       }
@@ -58,7 +58,7 @@ __global__ __launch_bounds__(1024) void k_spec_final(const double* part, const d
   }
   if (threadIdx.x == 0) {
     double mx = 0;
-    for (int p = 0; p < N; ++p) mx = fmax(mx, pmax[p]);
+    for (int p = 0; p < nplanes; ++p) mx = fmax(mx, pmax[p]);
     totals[0] = Et.s + Et.c;
     totals[1] = Zt.s + Zt.c;
     totals[2] = mx;
@@ -68,10 +68,10 @@ __global__ __launch_bounds__(1024) void k_spec_final(const double* part, const d
 
 template <typename T>
 hipError_t launch_spectrum(SpecArgs<T> a, double* spec, double* totals, hipStream_t s) {
-  k_spec_planes<T><<<dim3(a.N), dim3(256), 0, s>>>(a);
+  k_spec_planes<T><<<dim3(a.nz), dim3(256), 0, s>>>(a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  k_spec_final<<<dim3(1), dim3(1024), 0, s>>>(a.part, a.pmax, a.N, a.nshell, spec, totals);
+  k_spec_final<<<dim3(1), dim3(1024), 0, s>>>(a.part, a.pmax, a.nz, a.nshell, spec, totals);
   return hipGetLastError();
 }
 

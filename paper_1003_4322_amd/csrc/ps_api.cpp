@@ -35,28 +35,41 @@ ps_status fail(ps_status s, const std::string& msg) {
 }
 
 struct Box {
-  int N = 0;
+  int nx = 0, ny = 0, nz = 0;
   size_t real_off = 0, cplx_off = 0;  // element offsets in user field sets
   int nshell = 0;
   int cls = 0, idx = 0;  // class and index within it
 };
 
-// a run of consecutive boxes of equal size
+// a run of consecutive boxes of equal grid
 struct Class {
-  int N = 0, first = 0, nb = 0;
+  int nx = 0, ny = 0, nz = 0, first = 0, nb = 0;
+  ps::Grid g{};   // axis lengths and the 2/3 rule
   long H = 0, P = 0;
-  long nc = 0;    // N*N*H   valid complex values per field
-  long ncp = 0;   // N*N*P   pitched complex values per field
-  long n3 = 0;    // N^3
+  long nc = 0;    // nz*ny*H   valid complex values per field
+  long ncp = 0;   // nz*ny*P   pitched complex values per field
+  long n3 = 0;    // nx*ny*nz
   int nshell = 0;
-  // counts inside the 2/3 sphere (half storage): modes, (kx, ky) columns, kx values
+  // counts inside the 2/3 rule (half storage): modes, (kx, ky) columns, kx values
   long n_sphere = 0, n_disk = 0, kx_keep = 0;
   size_t real_off = 0, cplx_off = 0;   // of the first box
   size_t ws_off = 0;                   // byte offset of the class workspace
   size_t zs_box = 0, work_box = 0, spec_box = 0;  // bytes per box
-  void* tw = nullptr;  // device twiddle table (length N), owned by the plan
+  // device twiddle tables of lengths nx, ny and nz, owned by the plan
+  void* twx = nullptr;
+  void* twy = nullptr;
+  void* twz = nullptr;
   const ps::DiskTiles* dt = nullptr;  // z-pass disk tile lists, owned by the plan
+  bool same_grid(int x, int y, int z) const { return nx == x && ny == y && nz == z; }
 };
+
+// length of the axis a pass kind transforms ("z_curl", "z_epi", "z": z;
+// "y": y; "x_prod": x)
+int axis_len(const Class& c, const char* kind) {
+  if (!strcmp(kind, "y")) return c.ny;
+  if (!strcmp(kind, "x_prod")) return c.nx;
+  return c.nz;
+}
 
 struct TimingRec {
   int kind;
@@ -94,7 +107,7 @@ struct ps_plan_s {
   double omega[3] = {0, 0, 0};  // frame rotation (Coriolis term of the step)
   double bs[3] = {1, 1, 1};     // box factors 2 pi / L per axis (x, y, z)
   std::map<int, void*> tables;
-  std::map<int, ps::DiskTiles> dtiles;  // per grid size: z-pass tiles meeting the 2/3 disk
+  std::map<long, ps::DiskTiles> dtiles;  // per grid: z-pass tiles meeting the 2/3 disk
   std::vector<void*> dbufs;             // device lists behind dtiles
   hipStream_t stream = nullptr;
   hipStream_t cap = nullptr;  // private stream used only for graph capture
@@ -220,7 +233,9 @@ struct Seq {
   int b0, nb;  // boxes [b0, b0 + nb) of the class
   hipStream_t s;
   using C = ps::C2<T>;
-  const C* tw() const { return (const C*)b.tw; }
+  const C* twx() const { return (const C*)b.twx; }
+  const C* twy() const { return (const C*)b.twy; }
+  const C* twz() const { return (const C*)b.twz; }
   int nf() const { return p->nfields; }
   long st_bs() const { return nf() * b.nc; }      // state / zstar box stride
   long wk_bs() const { return 2 * nf() * b.ncp; }  // work box stride
@@ -234,44 +249,46 @@ struct Seq {
   // strided pass in place on the first nfl fields of every box, line = z;
   // nz >= 0: only the z-planes [z0, z0 + nz)
   ps_status ypass(C* x, long pitch, long bs, int nfl, int dir, int prune = 0, int z0 = 0, int nz = -1) {
-    if (nz < 0) nz = b.N;
+    if (nz < 0) nz = b.nz;
     ps::StridedArgs<T> a{};
     a.prune = prune;
-    a.out = x + (long)z0 * b.N * pitch; a.in = a.out; a.tw = tw();
-    a.in_fs = a.out_fs = (long)b.N * b.N * pitch;
-    a.in_ls = a.out_ls = (long)b.N * pitch;
+    a.g = b.g;
+    a.out = x + (long)z0 * b.ny * pitch; a.in = a.out; a.tw = twy();
+    a.in_fs = a.out_fs = (long)b.nz * b.ny * pitch;
+    a.in_ls = a.out_ls = (long)b.ny * pitch;
     a.in_es = a.out_es = pitch;
     a.in_bs = a.out_bs = bs;
     a.ncols = (int)b.H; a.nlines = nz; a.nf = nfl; a.nb = nb;
-    const double full = (double)b.N * b.N * b.kx_keep, disk = (double)b.N * b.n_disk;
-    const double frac = (double)nz / b.N;
+    const double full = (double)b.nz * b.ny * b.kx_keep, disk = (double)b.nz * b.n_disk;
+    const double frac = (double)nz / b.nz;
     const double bytes = frac * (prune == 0 ? 2.0 * nfl * nb * b.nc * cs() : (double)nfl * nb * (full + disk) * cs());
     const int v = var_of(p, "y");
     return enqueue(p, s, dir == ps::FWD ? "y_fwd" : "y_inv", bytes,
-                   [&](hipStream_t st) { return ps::launch_strided<T>(b.N, dir, v, a, st); });
+                   [&](hipStream_t st) { return ps::launch_strided<T>(b.ny, dir, v, a, st); });
   }
   ps_status zpass(const C* in, long in_pitch, long in_bs, C* out, long out_pitch, long out_bs, int dir) {
     ps::StridedArgs<T> a{};
-    a.in = in; a.out = out; a.tw = tw();
-    a.in_fs = (long)b.N * b.N * in_pitch; a.out_fs = (long)b.N * b.N * out_pitch;
+    a.g = b.g;
+    a.in = in; a.out = out; a.tw = twz();
+    a.in_fs = (long)b.nz * b.ny * in_pitch; a.out_fs = (long)b.nz * b.ny * out_pitch;
     a.in_ls = in_pitch; a.out_ls = out_pitch;
-    a.in_es = (long)b.N * in_pitch; a.out_es = (long)b.N * out_pitch;
+    a.in_es = (long)b.ny * in_pitch; a.out_es = (long)b.ny * out_pitch;
     a.in_bs = in_bs; a.out_bs = out_bs;
-    a.ncols = (int)b.H; a.nlines = b.N; a.nf = nf(); a.nb = nb;
+    a.ncols = (int)b.H; a.nlines = b.ny; a.nf = nf(); a.nb = nb;
     const double bytes = 2.0 * nf() * nb * b.nc * cs();
     const int v = var_of(p, "z");
     return enqueue(p, s, dir == ps::FWD ? "z_fwd" : "z_inv", bytes,
-                   [&](hipStream_t st) { return ps::launch_strided<T>(b.N, dir, v, a, st); });
+                   [&](hipStream_t st) { return ps::launch_strided<T>(b.nz, dir, v, a, st); });
   }
 
   ps_status r2c(const T* real_in, C* out) {
     ps::XArgs<T> a{};
-    a.in = (const C*)real_in; a.out = out; a.tw = tw();
-    a.in_pitch = b.N / 2; a.in_fs = (long)b.N * b.N * (b.N / 2); a.in_bs = nf() * a.in_fs;
+    a.in = (const C*)real_in; a.out = out; a.tw = twx();
+    a.in_pitch = b.nx / 2; a.in_fs = (long)b.nz * b.ny * (b.nx / 2); a.in_bs = nf() * a.in_fs;
     a.out_pitch = b.H; a.out_fs = b.nc; a.out_bs = st_bs();
-    a.rows = (long)b.N * b.N; a.nf = nf(); a.nb = nb;
+    a.rows = (long)b.ny * b.nz; a.nf = nf(); a.nb = nb;
     const double bytes = nf() * nb * (b.n3 * (double)sizeof(T) + b.nc * cs());
-    ps_status st = enqueue(p, s, "x_r2c", bytes, [&](hipStream_t q) { return ps::launch_x_r2c<T>(b.N, a, q); });
+    ps_status st = enqueue(p, s, "x_r2c", bytes, [&](hipStream_t q) { return ps::launch_x_r2c<T>(b.nx, a, q); });
     if (st) return st;
     if ((st = ypass(out, b.H, st_bs(), nf(), ps::FWD))) return st;
     return zpass(out, b.H, st_bs(), out, b.H, st_bs(), ps::FWD);
@@ -283,12 +300,12 @@ struct Seq {
     if (st) return st;
     if ((st = ypass(w, b.P, wk_bs(), nf(), ps::INV))) return st;
     ps::XArgs<T> a{};
-    a.in = w; a.out = (C*)real_out; a.tw = tw();
+    a.in = w; a.out = (C*)real_out; a.tw = twx();
     a.in_pitch = b.P; a.in_fs = b.ncp; a.in_bs = wk_bs();
-    a.out_pitch = b.N / 2; a.out_fs = (long)b.N * b.N * (b.N / 2); a.out_bs = nf() * a.out_fs;
-    a.rows = (long)b.N * b.N; a.nf = nf(); a.nb = nb;
+    a.out_pitch = b.nx / 2; a.out_fs = (long)b.nz * b.ny * (b.nx / 2); a.out_bs = nf() * a.out_fs;
+    a.rows = (long)b.ny * b.nz; a.nf = nf(); a.nb = nb;
     const double bytes = nf() * nb * (b.n3 * (double)sizeof(T) + b.nc * cs());
-    return enqueue(p, s, "x_c2r", bytes, [&](hipStream_t q) { return ps::launch_x_c2r<T>(b.N, a, q); });
+    return enqueue(p, s, "x_c2r", bytes, [&](hipStream_t q) { return ps::launch_x_c2r<T>(b.nx, a, q); });
   }
 
   // the five passes of one right-hand side evaluation
@@ -300,39 +317,39 @@ struct Seq {
   ps_status pass_zcurl(const C* src, bool mhd) {
     const int nin = mhd ? 6 : 3, nphys = this->nphys(mhd);
     ps::ZCurlArgs<T> ca{};
-    ca.in = src; ca.out = work(); ca.tw = tw();
-    ca.in_fs = b.nc; ca.in_pitch = b.H; ca.out_fs = b.ncp; ca.out_pitch = b.P; ca.N = b.N;
+    ca.in = src; ca.out = work(); ca.tw = twz();
+    ca.in_fs = b.nc; ca.in_pitch = b.H; ca.out_fs = b.ncp; ca.out_pitch = b.P; ca.g = b.g;
     ca.in_bs = st_bs(); ca.out_bs = wk_bs(); ca.nb = nb;
     ca.prune = p->prune;
     ca.sx = (T)p->bs[0]; ca.sy = (T)p->bs[1]; ca.sz = (T)p->bs[2];
     const int v = var_of(p, "z_curl");
-    const double bytes = p->prune ? ((double)nin * b.n_sphere + (double)nphys * b.n_disk * b.N) * nb * cs()
+    const double bytes = p->prune ? ((double)nin * b.n_sphere + (double)nphys * b.n_disk * b.nz) * nb * cs()
                                   : (double)(nin + nphys) * nb * b.nc * cs();
     return enqueue(p, s, "z_curl", bytes,
-                   [&](hipStream_t q) { return ps::launch_z_curl<T>(b.N, mhd, els(mhd), v, ca, b.dt, q); });
+                   [&](hipStream_t q) { return ps::launch_z_curl<T>(b.nz, mhd, els(mhd), v, ca, b.dt, q); });
   }
   ps_status pass_xprod(bool mhd, int z0 = 0, int nz = -1) {
-    if (nz < 0) nz = b.N;
+    if (nz < 0) nz = b.nz;
     const int nphys = this->nphys(mhd), nprod = this->nprod(mhd);
     ps::XArgs<T> xa{};
-    xa.out = work() + (long)z0 * b.N * b.P; xa.in = xa.out; xa.tw = tw();
+    xa.out = work() + (long)z0 * b.ny * b.P; xa.in = xa.out; xa.tw = twx();
     xa.in_pitch = xa.out_pitch = b.P; xa.in_fs = xa.out_fs = b.ncp;
     xa.in_bs = xa.out_bs = wk_bs();
-    xa.rows = (long)nz * b.N; xa.nf = nphys; xa.nb = nb;
-    xa.kmax = p->prune ? (int)b.kx_keep - 1 : b.N / 2;
+    xa.rows = (long)nz * b.ny; xa.nf = nphys; xa.nb = nb;
+    xa.kmax = p->prune ? (int)b.kx_keep - 1 : b.nx / 2;
     const int v = var_of(p, "x_prod");
-    const double per = (double)nz / b.N * (p->prune ? (double)b.N * b.N * b.kx_keep : (double)b.nc);
+    const double per = (double)nz / b.nz * (p->prune ? (double)b.nz * b.ny * b.kx_keep : (double)b.nc);
     return enqueue(p, s, "x_prod", (double)(nphys + nprod) * nb * per * cs(),
-                   [&](hipStream_t q) { return ps::launch_x_prod<T>(b.N, mhd, els(mhd), v, xa, q); });
+                   [&](hipStream_t q) { return ps::launch_x_prod<T>(b.nx, mhd, els(mhd), v, xa, q); });
   }
   ps_status pass_zepi(bool mhd, int mode, C* out, const C* st0, const C* st1, T h, T nua, T nub) {
     const int nprod = this->nprod(mhd), nst = mhd ? 6 : 3;
     ps::ZEpiArgs<T> ea{};
-    ea.in = work(); ea.out = out; ea.st0 = st0; ea.st1 = st1; ea.tw = tw();
+    ea.in = work(); ea.out = out; ea.st0 = st0; ea.st1 = st1; ea.tw = twz();
     ea.in_fs = b.ncp; ea.in_pitch = b.P; ea.out_fs = b.nc; ea.out_pitch = b.H;
     ea.in_bs = wk_bs(); ea.out_bs = st_bs(); ea.nb = nb;
-    ea.scale = (T)(1.0 / ((double)b.N * b.N * b.N));
-    ea.h = h; ea.nua = nua; ea.nub = nub; ea.N = b.N; ea.mode = mode;
+    ea.scale = (T)(1.0 / (double)b.n3);
+    ea.h = h; ea.nua = nua; ea.nub = nub; ea.g = b.g; ea.mode = mode;
     ea.rot = mode != 0 && (p->omega[0] != 0 || p->omega[1] != 0 || p->omega[2] != 0);
     ea.w2x = (T)(2 * p->omega[0]); ea.w2y = (T)(2 * p->omega[1]); ea.w2z = (T)(2 * p->omega[2]);
     ea.prune = p->prune;
@@ -341,10 +358,10 @@ struct Seq {
     const int v = var_of(p, "z_epi");
     double bytes = (double)(nprod + nst + nrw * nst) * nb * b.nc * cs();
     if (p->prune)
-      bytes = ((double)nprod * b.n_disk * b.N +
+      bytes = ((double)nprod * b.n_disk * b.nz +
                (mode == 0 ? (double)nst * b.nc : (double)(1 + nrw) * nst * b.n_sphere)) * nb * cs();
     return enqueue(p, s, "z_epi", bytes,
-                   [&](hipStream_t q) { return ps::launch_z_epi<T>(b.N, mhd, els(mhd), v, ea, b.dt, q); });
+                   [&](hipStream_t q) { return ps::launch_z_epi<T>(b.nz, mhd, els(mhd), v, ea, b.dt, q); });
   }
 
   // nonlinear right-hand side, epilogue mode 0/1/2 (see k_z_epi)
@@ -360,9 +377,9 @@ struct Seq {
   ps_status rhs(const C* src, bool mhd, int mode, C* out, const C* st0, const C* st1, T h, T nua, T nub) {
     ps_status st = pass_zcurl(src, mhd);
     if (st) return st;
-    const int slabs = std::min(1 << var_of(p, "pipe"), b.N);
+    const int slabs = std::min(1 << var_of(p, "pipe"), b.nz);
     if (slabs <= 1) {
-      if ((st = yxy(mhd, 0, b.N))) return st;
+      if ((st = yxy(mhd, 0, b.nz))) return st;
     } else {
       // fork the slabs over the helper streams (their memory-bound y passes
       // overlap other slabs' compute-bound product pass), then join
@@ -372,7 +389,7 @@ struct Seq {
       if (e != hipSuccess) return hip_fail(e, "slab fork");
       for (int i = 0; i < slabs; ++i) {
         Seq<T> q{p, b, b0, nb, p->aux[i % k]};
-        const int z0 = (int)((long)i * b.N / slabs), z1 = (int)((long)(i + 1) * b.N / slabs);
+        const int z0 = (int)((long)i * b.nz / slabs), z1 = (int)((long)(i + 1) * b.nz / slabs);
         if ((st = q.yxy(mhd, z0, z1 - z0))) return st;
       }
       for (int i = 0; i < k && e == hipSuccess; ++i) {
@@ -405,8 +422,8 @@ struct Seq {
 
   ps_status spectrum(int i, const C* f, int nfl, double* spec, double* totals) {
     ps::SpecArgs<T> a{};
-    a.f = f; a.part = spec_part(i); a.pmax = a.part + (long)b.N * b.nshell * 2;
-    a.fs = b.nc; a.pitch = b.H; a.N = b.N; a.nf = nfl; a.nshell = b.nshell;
+    a.f = f; a.part = spec_part(i); a.pmax = a.part + (long)b.nz * b.nshell * 2;
+    a.fs = b.nc; a.pitch = b.H; a.nx = b.nx; a.ny = b.ny; a.nz = b.nz; a.nf = nfl; a.nshell = b.nshell;
     a.sx = p->bs[0]; a.sy = p->bs[1]; a.sz = p->bs[2];
     return enqueue(p, s, "spectrum", nfl * b.nc * cs(),
                    [&](hipStream_t q) { return ps::launch_spectrum<T>(a, spec, totals, q); });
@@ -466,33 +483,36 @@ void free_plan(ps_plan p) {
   delete p;
 }
 
-// For every tile width a z-pass variant of size N can use, the list of tiles
-// (tile | ky << 16, ky-major, tile fastest) whose first column lies inside the
-// disk 9 (kx^2 + ky^2) < N^2; the kernels skip exactly the other tiles.
+// For every tile width a z-pass variant of the class's z length can use, the
+// list of tiles (tile | ky << 16, ky-major, tile fastest) whose first column
+// lies inside the disk Grid::disk(kx, ky); the kernels skip exactly the other
+// tiles.
 template <typename T>
-ps_status upload_disk_tiles(ps_plan p, int N) {
-  if (p->dtiles.count(N)) return PS_OK;
-  ps::DiskTiles& dt = p->dtiles[N];
+ps_status upload_disk_tiles(ps_plan p, const Class& c) {
+  const long key = ((long)c.nx << 22) | ((long)c.ny << 11) | c.nz;
+  if (p->dtiles.count(key)) return PS_OK;
+  ps::DiskTiles& dt = p->dtiles[key];
   const bool mhd = p->nfields == 6;
   std::set<int> widths;
-  for (int v = 0; v < ps::variant_count("z_curl", N, mhd); ++v) widths.insert(ps::z_curl_tx<T>(N, v));
-  for (int v = 0; v < ps::variant_count("z_epi", N, mhd); ++v) widths.insert(ps::z_epi_tx<T>(N, v));
-  const long H = N / 2 + 1;
+  for (int v = 0; v < ps::variant_count("z_curl", c.nz, mhd); ++v) widths.insert(ps::z_curl_tx<T>(c.nz, v));
+  for (int v = 0; v < ps::variant_count("z_epi", c.nz, mhd); ++v) widths.insert(ps::z_epi_tx<T>(c.nz, v));
   for (int tx : widths) {
     if (tx < 1 || tx > ps::DiskTiles::MAXTX) return fail(PS_ERR_STATE, "z-pass tile width out of range");
     std::vector<int> list;
-    const long ntile = (H + tx - 1) / tx;
-    for (long ky = 0; ky < N; ++ky) {
-      const long kyw = ky < N / 2 ? ky : ky - N;
+    const long ntile = (c.H + tx - 1) / tx;
+    for (long ky = 0; ky < c.ny; ++ky) {
+      const int kyw = (int)(ky < c.ny / 2 ? ky : ky - c.ny);
       for (long t = 0; t < ntile; ++t)
-        if (9 * (t * tx * t * tx + kyw * kyw) < (long)N * N) list.push_back((int)(t | ky << 16));
+        if (c.g.disk((int)(t * tx), kyw)) list.push_back((int)(t | ky << 16));
     }
     void* d = nullptr;
-    hipError_t e = hipMalloc(&d, list.size() * sizeof(int));
+    hipError_t e = hipMalloc(&d, std::max<size_t>(list.size(), 1) * sizeof(int));
     if (e != hipSuccess) return fail(PS_ERR_NOMEM, std::string("disk tile list: ") + hipGetErrorString(e));
     p->dbufs.push_back(d);
-    e = hipMemcpy(d, list.data(), list.size() * sizeof(int), hipMemcpyHostToDevice);
-    if (e != hipSuccess) return hip_fail(e, "disk tile upload");
+    if (!list.empty()) {
+      e = hipMemcpy(d, list.data(), list.size() * sizeof(int), hipMemcpyHostToDevice);
+      if (e != hipSuccess) return hip_fail(e, "disk tile upload");
+    }
     dt.list[tx] = (const int*)d;
     dt.count[tx] = (int)list.size();
   }
@@ -569,17 +589,21 @@ const char* ps_status_string(ps_status s) {
 
 const char* ps_last_error(void) { return g_last_error.c_str(); }
 
-ps_status ps_plan_create_batch(ps_plan* out, int nbox, const int* Ns, int nfields, ps_dtype dtype) {
+}  // extern "C"
+
+namespace {
+
+// boxes of grids dims[3 i .. 3 i + 2] = (nx, ny, nz)
+ps_status create_plan(ps_plan* out, int nbox, const int* dims, int nfields, ps_dtype dtype) {
   return guarded([&]() -> ps_status {
     if (!out) return fail(PS_ERR_ARG, "out is NULL");
     *out = nullptr;
-    if (nbox < 1 || !Ns) return fail(PS_ERR_ARG, "need nbox >= 1 and a size array");
     if (nfields != 3 && nfields != 6) return fail(PS_ERR_SIZE, "nfields must be 3 (NS) or 6 (MHD)");
     if (dtype != PS_F32 && dtype != PS_F64) return fail(PS_ERR_ARG, "dtype must be PS_F32 or PS_F64");
-    for (int i = 0; i < nbox; ++i)
-      if (!ps::size_supported(Ns[i])) {
+    for (int i = 0; i < 3 * nbox; ++i)
+      if (!ps::size_supported(dims[i])) {
         char buf[128];
-        snprintf(buf, sizeof buf, "unsupported N = %d (box %d)", Ns[i], i);
+        snprintf(buf, sizeof buf, "unsupported axis length %d (box %d)", dims[i], i / 3);
         return fail(PS_ERR_SIZE, buf);
       }
     ps_plan p = new ps_plan_s();
@@ -594,41 +618,48 @@ ps_status ps_plan_create_batch(ps_plan* out, int nbox, const int* Ns, int nfield
     size_t roff = 0, coff = 0;
     for (int i = 0; i < nbox; ++i) {
       Box b;
-      b.N = Ns[i];
+      b.nx = dims[3 * i];
+      b.ny = dims[3 * i + 1];
+      b.nz = dims[3 * i + 2];
       b.real_off = roff;
       b.cplx_off = coff;
-      roff += (size_t)nfields * b.N * b.N * b.N;
-      coff += (size_t)nfields * b.N * b.N * (b.N / 2 + 1);
-      b.nshell = (int)shell_of(3L * (b.N / 2) * (b.N / 2)) + 1;
-      if (p->classes.empty() || p->classes.back().N != b.N) {
+      roff += (size_t)nfields * b.nx * b.ny * b.nz;
+      coff += (size_t)nfields * b.nz * b.ny * (b.nx / 2 + 1);
+      {
+        const long hx = b.nx / 2, hy = b.ny / 2, hz = b.nz / 2;
+        b.nshell = (int)shell_of(hx * hx + hy * hy + hz * hz) + 1;
+      }
+      if (p->classes.empty() || !p->classes.back().same_grid(b.nx, b.ny, b.nz)) {
         Class c;
-        c.N = b.N;
+        c.nx = b.nx;
+        c.ny = b.ny;
+        c.nz = b.nz;
+        c.g = ps::make_grid(c.nx, c.ny, c.nz);
         c.first = i;
         c.nb = 0;
-        c.H = c.N / 2 + 1;
+        c.H = c.nx / 2 + 1;
         const long align = 128 / (long)cs;
         c.P = (c.H + align - 1) / align * align;
-        c.nc = (long)c.N * c.N * c.H;
-        c.ncp = (long)c.N * c.N * c.P;
-        c.n3 = (long)c.N * c.N * c.N;
+        c.nc = (long)c.nz * c.ny * c.H;
+        c.ncp = (long)c.nz * c.ny * c.P;
+        c.n3 = (long)c.nx * c.ny * c.nz;
         c.nshell = b.nshell;
         {
-          const long N = c.N, N2 = N * N;
-          auto w = [N](long i) { return i < N / 2 ? i : i - N; };
+          auto w = [](long i, long n) { return (int)(i < n / 2 ? i : i - n); };
           for (long kx = 0; kx < c.H; ++kx)
-            for (long ky = 0; ky < N; ++ky) {
-              const long p2 = kx * kx + w(ky) * w(ky);
-              if (9 * p2 >= N2) continue;
+            for (long ky = 0; ky < c.ny; ++ky) {
+              if (!c.g.disk((int)kx, w(ky, c.ny))) continue;
               ++c.n_disk;
-              for (long kz = 0; kz < N; ++kz) c.n_sphere += 9 * (p2 + w(kz) * w(kz)) < N2;
+              const int pp = c.g.perp((int)kx, w(ky, c.ny));
+              for (long kz = 0; kz < c.nz; ++kz) c.n_sphere += c.g.keep_p(pp, w(kz, c.nz));
             }
-          c.kx_keep = (N - 1) / 3 + 1;
+          while (c.kx_keep < c.H && c.g.disk((int)c.kx_keep, 0)) ++c.kx_keep;
         }
         c.real_off = b.real_off;
         c.cplx_off = b.cplx_off;
         c.zs_box = (size_t)nfields * c.nc * cs;
         c.work_box = (size_t)2 * nfields * c.ncp * cs;
-        c.spec_box = align256(((size_t)c.N * c.nshell * 2 + c.N) * sizeof(double));
+        c.spec_box = align256(((size_t)c.nz * c.nshell * 2 + c.nz) * sizeof(double));
         p->classes.push_back(c);
       }
       b.cls = (int)p->classes.size() - 1;
@@ -644,29 +675,33 @@ ps_status ps_plan_create_batch(ps_plan* out, int nbox, const int* Ns, int nfield
     p->real_total = roff;
     p->cplx_total = coff;
     for (auto& c : p->classes) {
-      ps_status st = dtype == PS_F32 ? upload_table<float>(p, c.N) : upload_table<double>(p, c.N);
-      if (!st) st = dtype == PS_F32 ? upload_disk_tiles<float>(p, c.N) : upload_disk_tiles<double>(p, c.N);
+      ps_status st = PS_OK;
+      for (int n : {c.nx, c.ny, c.nz})
+        if (!st) st = dtype == PS_F32 ? upload_table<float>(p, n) : upload_table<double>(p, n);
+      if (!st) st = dtype == PS_F32 ? upload_disk_tiles<float>(p, c) : upload_disk_tiles<double>(p, c);
       if (st) {
         free_plan(p);
         return st;
       }
-      c.tw = p->tables[c.N];
-      c.dt = &p->dtiles[c.N];
+      c.twx = p->tables[c.nx];
+      c.twy = p->tables[c.ny];
+      c.twz = p->tables[c.nz];
+      c.dt = &p->dtiles[((long)c.nx << 22) | ((long)c.ny << 11) | c.nz];
     }
-    // measured defaults at 512^3 (the autotuner refines them per workload)
-    bool any_var = false;
-    for (auto& b : p->boxes) any_var |= ps::variant_count("z_curl", b.N, nfields == 6) > 1;
     // MHD: the Elsasser divergence form (fewer transforms, same result)
     if (nfields == 6) {
       p->var["form"] = 1;
       p->els = true;
     }
-    if (any_var) {
-      p->var["z_curl"] = 0;
-      p->var["z_epi"] = nfields == 6 ? 5 : 2;  // MHD (Elsasser): z+ and z- in two workgroups
-      p->var["x_prod"] = dtype == PS_F32 ? (nfields == 6 ? 5 : 4) : 7;
-      p->var["y"] = dtype == PS_F32 ? 2 : 0;
-    }
+    // measured defaults at 512^3 (the autotuner refines them per workload),
+    // set where some box's pass has variants
+    const std::pair<const char*, int> defaults[] = {
+        {"z_curl", 0},
+        {"z_epi", nfields == 6 ? 5 : 2},  // MHD (Elsasser): z+ and z- in two workgroups
+        {"x_prod", dtype == PS_F32 ? (nfields == 6 ? 5 : 4) : 7},
+        {"y", dtype == PS_F32 ? 2 : 0}};
+    for (auto& d : defaults)
+      if (ps_plan_variant_count(p, d.first) > d.second) p->var[d.first] = d.second;
     e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
     for (int i = 0; i < ps_plan_s::NAUX && e == hipSuccess; ++i)
       e = hipStreamCreateWithFlags(&p->aux[i], hipStreamNonBlocking);  // default priority
@@ -682,8 +717,28 @@ ps_status ps_plan_create_batch(ps_plan* out, int nbox, const int* Ns, int nfield
   });
 }
 
+}  // namespace
+
+extern "C" {
+
+ps_status ps_plan_create_batch(ps_plan* out, int nbox, const int* Ns, int nfields, ps_dtype dtype) {
+  return guarded([&]() -> ps_status {
+    if (!out) return fail(PS_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (nbox < 1 || !Ns) return fail(PS_ERR_ARG, "need nbox >= 1 and a size array");
+    std::vector<int> dims(3 * (size_t)nbox);
+    for (int i = 0; i < nbox; ++i) dims[3 * i] = dims[3 * i + 1] = dims[3 * i + 2] = Ns[i];
+    return create_plan(out, nbox, dims.data(), nfields, dtype);
+  });
+}
+
 ps_status ps_plan_create(ps_plan* out, int N, int nfields, ps_dtype dtype) {
   return ps_plan_create_batch(out, 1, &N, nfields, dtype);
+}
+
+ps_status ps_plan_create_grid(ps_plan* out, int nx, int ny, int nz, int nfields, ps_dtype dtype) {
+  const int dims[3] = {nx, ny, nz};
+  return create_plan(out, 1, dims, nfields, dtype);
 }
 
 ps_status ps_plan_destroy(ps_plan p) {
@@ -776,7 +831,7 @@ static ps_status nonlinear(ps_plan p, const void* in, void* out, bool mhd) {
     return by_type(p, [&](auto* tag) -> ps_status {
       using T = std::remove_pointer_t<decltype(tag)>;
       for (auto& c : p->classes)
-        if (mhd && !ps::mhd_supported<T>(c.N)) return fail(PS_ERR_SIZE, "MHD not supported at this N and dtype");
+        if (mhd && !ps::mhd_supported<T>(c.nx)) return fail(PS_ERR_SIZE, "MHD not supported at this nx and dtype");
       return for_each_launch<T>(p, p->stream, [&](Seq<T>& q, int bi) {
         const Box& b = p->boxes[bi];
         ps::C2<T>* o = (ps::C2<T>*)out + b.cplx_off;
@@ -805,7 +860,7 @@ ps_status ps_rk2_step(ps_plan p, void* state, ps_model m, double nu, double eta,
     return by_type(p, [&](auto* tag) -> ps_status {
       using T = std::remove_pointer_t<decltype(tag)>;
       for (auto& c : p->classes)
-        if (mhd && !ps::mhd_supported<T>(c.N)) return fail(PS_ERR_SIZE, "MHD not supported at this N and dtype");
+        if (mhd && !ps::mhd_supported<T>(c.nx)) return fail(PS_ERR_SIZE, "MHD not supported at this nx and dtype");
       auto one_step = [&](hipStream_t s) -> ps_status {
         return for_each_launch<T>(p, s, [&](Seq<T>& q, int bi) {
           return q.rk2((ps::C2<T>*)state + p->boxes[bi].cplx_off, mhd, nu, eta, dt);
@@ -943,7 +998,7 @@ int ps_plan_variant_count(ps_plan p, const char* kind) {
   if (!strcmp(kind, "form")) return p->nfields == 6 ? 2 : 1;
   if (!strcmp(kind, "pipe")) return NPIPE;
   int n = 1;
-  for (auto& b : p->boxes) n = std::max(n, ps::variant_count(kind, b.N, p->nfields == 6));
+  for (auto& c : p->classes) n = std::max(n, ps::variant_count(kind, axis_len(c, kind), p->nfields == 6));
   return n;
 }
 
@@ -963,7 +1018,7 @@ ps_status ps_plan_autotune(ps_plan p, const void* state, ps_model m, int reps) {
       using T = std::remove_pointer_t<decltype(tag)>;
       size_t ci = 0;
       for (size_t i = 1; i < p->classes.size(); ++i)
-        if (p->classes[i].N > p->classes[ci].N) ci = i;
+        if (p->classes[i].n3 > p->classes[ci].n3) ci = i;
       const Class& b = p->classes[ci];
       Seq<T> q{p, b, 0, b.nb, p->stream};
       const auto* st = (const ps::C2<T>*)state + b.cplx_off;
@@ -974,7 +1029,7 @@ ps_status ps_plan_autotune(ps_plan p, const void* state, ps_model m, int reps) {
       // (the slab pipeline is left as set: its effect here is within 2 %, and
       // its concurrent launches would blur the per-pass timings)
       for (const char* kind : {"z_curl", "y", "x_prod", "z_epi"}) {
-        const int n = ps::variant_count(kind, b.N, mhd);
+        const int n = ps::variant_count(kind, axis_len(b, kind), mhd);
         if (n <= 1) continue;
         int best = 0;
         float best_ms = 1e30f;

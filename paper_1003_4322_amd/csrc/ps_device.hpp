@@ -449,4 +449,43 @@ __device__ __forceinline__ int wav(int i, int N) { return i < N / 2 ? i : i - N;
 __device__ __forceinline__ int dwav(int i, int N) { return 2 * i == N ? 0 : wav(i, N); }
 __device__ __forceinline__ int dwavx(int i, int N) { return 2 * i == N ? 0 : i; }
 
+// A box's grid: axis lengths and the 2/3 rule on it.  A mode is kept when
+// (3 kx/nx)^2 + (3 ky/ny)^2 + (3 kz/nz)^2 < 1 (the sphere 9|k|^2 < N^2 of the
+// cube, stretched with the grid), tested in integers as
+// 9 (kx^2 wx + ky^2 wy + kz^2 wz) < lim with w_a = (M / n_a)^2, lim = M^2,
+// M = lcm(nx, ny, nz).  Every term stays below 6.75 M^2 < 2^31 for M <= 3072,
+// the largest lcm of the supported lengths.
+struct Grid {
+  int nx, ny, nz;
+  int wx, wy, wz, lim;
+  // (kx, ky) pencil inside the disk the z passes keep
+  __host__ __device__ bool disk(int kx, int ky) const { return 9 * (kx * kx * wx + ky * ky * wy) < lim; }
+  // weighted |k_perp|^2 of a pencil, and the full test from it
+  __host__ __device__ int perp(int kx, int ky) const { return kx * kx * wx + ky * ky * wy; }
+  __host__ __device__ bool keep_p(int perp2, int kz) const { return 9 * (perp2 + kz * kz * wz) < lim; }
+  __host__ __device__ bool keep(int kx, int ky, int kz) const { return keep_p(perp(kx, ky), kz); }
+};
+
+inline Grid make_grid(int nx, int ny, int nz) {
+  auto gcd = [](int a, int b) {
+    while (b) {
+      const int t = a % b;
+      a = b;
+      b = t;
+    }
+    return a;
+  };
+  int M = nx / gcd(nx, ny) * ny;
+  M = M / gcd(M, nz) * nz;
+  Grid g;
+  g.nx = nx;
+  g.ny = ny;
+  g.nz = nz;
+  g.wx = (M / nx) * (M / nx);
+  g.wy = (M / ny) * (M / ny);
+  g.wz = (M / nz) * (M / nz);
+  g.lim = M * M;
+  return g;
+}
+
 }  // namespace ps

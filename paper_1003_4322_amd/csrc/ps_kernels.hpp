@@ -23,7 +23,7 @@
 //                  MHD in the Elsasser form: z+- transformed as they are
 //   x pass: inverse real FFTs + products (u x w [+ j x b, u x b], or the
 //                  eight z+_i z-_j less the isotropic part) + forward real FFTs
-//   forward z pass + 1/N^3 + dealias + projection (+ induction curl, or the
+//   forward z pass + 1/(nx ny nz) + dealias + projection (+ induction curl, or the
 //                  divergence of the Elsasser products) + Coriolis term
 //                  + explicit midpoint RK2 stage update
 // Pruned launches skip every pencil and mode the 2/3 rule makes zero; box
@@ -74,11 +74,12 @@ struct StridedArgs {
   long out_fs, out_ls, out_es;
   long in_bs, out_bs;  // box strides (ensembles of equal-size boxes)
   int ncols, ntile, nlines, nf, nb;
-  // dealias-sphere pruning of a y pass (columns kx, elements ky):
-  // 0 none; 1 input zero outside the disk 9(kx^2+ky^2) < N^2 (inverse pass);
-  // 2 only outputs inside the disk are needed (forward pass).  Tiles with
-  // every kx >= N/3 are skipped.
+  // dealias pruning of a y pass (columns kx, elements ky): 0 none; 1 input
+  // zero outside the disk g.disk(kx, ky) (inverse pass); 2 only outputs
+  // inside the disk are needed (forward pass).  Tiles whose every kx lies
+  // beyond the 2/3 rule are skipped.
   int prune;
+  Grid g;
 };
 
 template <typename T, int L, int TQ, int TX, int DIR, class RL, int MINW = 1>
@@ -94,13 +95,9 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_strided(StridedArgs<T> a) {
   blk /= a.nlines;
   const int f = blk % a.nf, box = blk / a.nf;
   const int col = tile * TX + c;
-  constexpr int N = L;
-  if (a.prune && 9 * (tile * TX) * (tile * TX) >= N * N) return;  // whole tile outside
-  const bool ok = col < a.ncols && (!a.prune || 9 * col * col < N * N);
-  auto in_disk = [&](int idx) {
-    const int k = wav(idx, N);
-    return 9 * (col * col + k * k) < N * N;
-  };
+  if (a.prune && !a.g.disk(tile * TX, 0)) return;  // whole tile outside
+  const bool ok = col < a.ncols && (!a.prune || a.g.disk(col, 0));
+  auto in_disk = [&](int idx) { return a.g.disk(col, wav(idx, L)); };
   const C2<T>* in = a.in + box * a.in_bs + f * a.in_fs + line * a.in_ls + col;
   C2<T>* out = a.out + box * a.out_bs + f * a.out_fs + line * a.out_ls + col;
   C2<T> v[E::SLOTS];
@@ -130,7 +127,8 @@ struct ZCurlArgs {
   long in_fs, in_pitch;   // field stride, kx pitch of the input (line = ky)
   long out_fs, out_pitch;
   long in_bs, out_bs;     // box strides
-  int N, ntile, nb;
+  Grid g;                 // the box's grid (the transform runs along z, length nz)
+  int ntile, nb;
   int prune;  // 1: state zero outside the 2/3 sphere; only disk columns are produced
   // pruned launches: the ntl tiles (tile | ky << 16) that meet the disk, so
   // that no workgroup is spent on, and no XCD is left idle by, empty tiles
@@ -143,12 +141,12 @@ struct ZCurlArgs {
 struct ZTile {
   int tile, ky, box;
 };
-__device__ __forceinline__ ZTile z_tile(int blk, int ntile, int N, const int* tiles, int ntl) {
+__device__ __forceinline__ ZTile z_tile(int blk, int ntile, int ny, const int* tiles, int ntl) {
   if (tiles) {
     const int e = tiles[blk % ntl];
     return {e & 0xffff, e >> 16, blk / ntl};
   }
-  return {blk % ntile, (blk / ntile) % N, blk / (ntile * N)};
+  return {blk % ntile, (blk / ntile) % ny, blk / (ntile * ny)};
 }
 
 // Output groups: 0 u, 1 w = curl u (NS and MHD), 2 b, 3 j = curl b (MHD).
@@ -177,18 +175,18 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_z_curl(ZCurlArgs<T> a) {
   const int tid = threadIdx.x, c = tid % TX, q = tid / TX;
   const int blk0 = xcd_remap(blockIdx.x, gridDim.x);
   const int part = blk0 % SPLIT, blk = blk0 / SPLIT;
-  const int N = L;
-  const ZTile zt = z_tile(blk, a.ntile, N, a.prune ? a.tiles : nullptr, a.ntl);
+  const Grid& g = a.g;
+  const ZTile zt = z_tile(blk, a.ntile, g.ny, a.prune ? a.tiles : nullptr, a.ntl);
   const int tile = zt.tile, ky = zt.ky, box = zt.box;
   const int col = tile * TX + c;
-  const int kyw = wav(ky, N);
-  if (a.prune && 9 * ((tile * TX) * (tile * TX) + kyw * kyw) >= N * N) return;  // tile outside the disk
-  const bool ok = col < N / 2 + 1 && (!a.prune || 9 * (col * col + kyw * kyw) < N * N);
-  const long in_es = (long)N * a.in_pitch, out_es = (long)N * a.out_pitch;
+  const int kyw = wav(ky, g.ny);
+  if (a.prune && !g.disk(tile * TX, kyw)) return;  // tile outside the disk
+  const bool ok = col < g.nx / 2 + 1 && (!a.prune || g.disk(col, kyw));
+  const long in_es = (long)g.ny * a.in_pitch, out_es = (long)g.ny * a.out_pitch;
   const C2<T>* in = a.in + box * a.in_bs + ky * a.in_pitch + col;
   C2<T>* out = a.out + box * a.out_bs + ky * a.out_pitch + col;
-  const T kx = a.sx * (T)dwavx(col, N), kyd = a.sy * (T)dwav(ky, N);
-  const int kperp2 = col * col + kyw * kyw;
+  const T kx = a.sx * (T)dwavx(col, g.nx), kyd = a.sy * (T)dwav(ky, g.ny);
+  const int kperp2 = g.perp(col, kyw);
   if constexpr (TWL) {
     fill_staged<T, L>(smem + CT::ROWS * TX, a.tw, 1, tid, TX * TQ, RL{});
     __syncthreads();
@@ -200,10 +198,7 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_z_curl(ZCurlArgs<T> a) {
       return TwTable<T>{a.tw, 1};
   }();
   // element kz of the column is stored (nonzero) input
-  auto live = [&](int kzi) {
-    const int kzw = wav(kzi, N);
-    return ok && (!a.prune || 9 * (kperp2 + kzw * kzw) < N * N);
-  };
+  auto live = [&](int kzi) { return ok && (!a.prune || g.keep_p(kperp2, wav(kzi, L))); };
   // component f of u (sign +1) or b (sign -1) at kz row offset off
   auto base_at = [&](int f, long off, T sign) -> C2<T> {
     if constexpr (MHD)
@@ -215,7 +210,7 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_z_curl(ZCurlArgs<T> a) {
   // a getter g(f) of the base's components at wavenumber index kzi
   auto field_of = [&](int grp, int comp, int kzi, auto g) -> C2<T> {
     if ((grp & 1) == 0) return g(comp);
-    const T kz = a.sz * (T)dwav(kzi, N);
+    const T kz = a.sz * (T)dwav(kzi, L);
     C2<T> r;
     if (comp == 0)
       r = kyd * g(2) - kz * g(1);
@@ -259,7 +254,7 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_z_curl(ZCurlArgs<T> a) {
         if (!live(kzi)) return zero2<T>();
         const long off = (long)kzi * in_es;
         if (!curl) return base_at(comp, off, sign);
-        const T kz = a.sz * (T)dwav(kzi, N);
+        const T kz = a.sz * (T)dwav(kzi, L);
         const T ka = comp == 1 ? kz : kA, kb = comp == 0 ? kz : kB;
         return mul_i(ka * base_at(ca, off, sign) - kb * base_at(cb, off, sign));
       });
@@ -311,7 +306,8 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_z_curl(ZCurlArgs<T> a) {
 // ---------------------------------------------------------------------------
 // Forward z pass with the nonlinear-term epilogue.
 // in: products transformed along x and y (NS: u x w; MHD: u x w + j x b, u x b)
-// N^ = D(k) P(k) F[n] / N^3;  MHD: N+- = D(k) [P(k) F[nL] +- i k_d x F[e]] / N^3
+// N^ = D(k) P(k) F[n] / n3;  MHD: N+- = D(k) [P(k) F[nL] +- i k_d x F[e]] / n3
+// (n3 = nx ny nz, D the 2/3 rule of the grid)
 // mode 0: out = N^
 // mode 1: out (= z*) = z^n + h (N^ - V(z^n))          h = dt/2
 // mode 2: st0 (= z^n, in place) = z^n + h (N^ - V(z*)), h = dt; z* = st1
@@ -330,7 +326,8 @@ struct ZEpiArgs {
   long out_fs, out_pitch;  // out, st0 and st1 share this layout
   long in_bs, out_bs;      // box strides
   T scale, h, nua, nub;
-  int N, ntile, mode, nb;
+  Grid g;  // the box's grid (the transform runs along z, length nz)
+  int ntile, mode, nb;
   int prune;  // 1: only modes inside the 2/3 sphere are read or updated (mode 0 still writes zeros)
   const int* tiles;  // as in ZCurlArgs; used by pruned launches with mode != 0
   int ntl;
@@ -346,7 +343,7 @@ struct ZEpiArgs {
 // delta_ij z+_2 z-_2 (field 3 i + j for the eight pairs other than (2, 2),
 // whose entry is zero) transformed along x and y; with a_i = sum_j k_j T^_ij
 // and c_i = sum_j k_j T^_ji (derivative wavenumbers),
-//   N+ = -i D(k) P(k) a / N^3,  N- = -i D(k) P(k) c / N^3,
+//   N+ = -i D(k) P(k) a / n3,  N- = -i D(k) P(k) c / n3,
 // the divergence form of -(z-+ . grad) z+-, equal to the form above for
 // solenoidal z+- (the isotropic part left out adds a gradient to a and c,
 // which P(k) removes).  a and c are accumulated field by field.
@@ -364,15 +361,15 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_z_epi(ZEpiArgs<T> a) {
   const int tid = threadIdx.x, c = tid % TX, q = tid / TX;
   const int blk0 = xcd_remap(blockIdx.x, gridDim.x);
   const int part = blk0 % SPLIT, blk = blk0 / SPLIT;  // part 0: z+ (a), part 1: z- (c)
-  const int N = L;
-  const ZTile zt = z_tile(blk, a.ntile, N, a.prune && a.mode != 0 ? a.tiles : nullptr, a.ntl);
+  const Grid& g = a.g;
+  const ZTile zt = z_tile(blk, a.ntile, g.ny, a.prune && a.mode != 0 ? a.tiles : nullptr, a.ntl);
   const int tile = zt.tile, ky = zt.ky, box = zt.box;
   const int col = tile * TX + c;
-  const int kyw0 = wav(ky, N);
-  if (a.prune && a.mode != 0 && 9 * ((tile * TX) * (tile * TX) + kyw0 * kyw0) >= N * N) return;
-  const bool ok = col < N / 2 + 1;
-  const bool disk = !a.prune || 9 * (col * col + kyw0 * kyw0) < N * N;
-  const long in_es = (long)N * a.in_pitch, out_es = (long)N * a.out_pitch;
+  const int kyw0 = wav(ky, g.ny);
+  if (a.prune && a.mode != 0 && !g.disk(tile * TX, kyw0)) return;
+  const bool ok = col < g.nx / 2 + 1;
+  const bool disk = !a.prune || g.disk(col, kyw0);
+  const long in_es = (long)g.ny * a.in_pitch, out_es = (long)g.ny * a.out_pitch;
   const C2<T>* in = a.in + box * a.in_bs + ky * a.in_pitch + col;
   if constexpr (TWL) {
     fill_staged<T, L>(smem + CT::ROWS * TX, a.tw, 1, tid, TX * TQ, RL{});
@@ -395,7 +392,7 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_z_epi(ZEpiArgs<T> a) {
   constexpr int NR = ELS ? 3 * (2 / SPLIT) : NF;
   C2<T> r[NR][NO];
   if constexpr (ELS) {
-    const T kxd0 = a.sx * (T)dwavx(col, N), kyd0 = a.sy * (T)dwav(ky, N);
+    const T kxd0 = a.sx * (T)dwavx(col, g.nx), kyd0 = a.sy * (T)dwav(ky, g.ny);
 #pragma unroll
     for (int f = 0; f < NR; ++f)
 #pragma unroll
@@ -416,7 +413,7 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_z_epi(ZEpiArgs<T> a) {
           E::template run_tw<typename CT::Lay>(v, smem + c, TX, q, tw, ld_of(3 * i3 + j3));
 #pragma unroll
           for (int s = 0; s < NO; ++s) {
-            const T kzd0 = a.sz * (T)dwav(E::last_index(q, s), N);
+            const T kzd0 = a.sz * (T)dwav(E::last_index(q, s), L);
             const T kj = j3 == 0 ? kxd0 : j3 == 1 ? kyd0 : kzd0;
             const T ki = i3 == 0 ? kxd0 : i3 == 1 ? kyd0 : kzd0;
             acc[s] = acc[s] + kj * v[s];
@@ -440,7 +437,7 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_z_epi(ZEpiArgs<T> a) {
         E::template run_tw<typename CT::Lay>(v, smem + c, TX, q, tw, ld_of(f));
 #pragma unroll
         for (int s = 0; s < NO; ++s) {
-          const T kzd0 = a.sz * (T)dwav(E::last_index(q, s), N);
+          const T kzd0 = a.sz * (T)dwav(E::last_index(q, s), L);
           const T km = m == 0 ? kxd0 : m == 1 ? kyd0 : kzd0;
           r[0][s] = r[0][s] + (t == 0 ? km : T(0)) * v[s];
           r[1][s] = r[1][s] + (t == 1 ? km : T(0)) * v[s];
@@ -460,15 +457,16 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_z_epi(ZEpiArgs<T> a) {
   if (!ok) return;  // no barrier follows
 
   const long base = box * a.out_bs + ky * a.out_pitch + col;
-  const int ikx = col, iky = wav(ky, N);
-  const T kxd = a.sx * (T)dwavx(col, N), kyd = a.sy * (T)dwav(ky, N);
+  const int ikx = col, iky = wav(ky, g.ny);
+  const int kperp2 = g.perp(ikx, iky);
+  const T kxd = a.sx * (T)dwavx(col, g.nx), kyd = a.sy * (T)dwav(ky, g.ny);
 #pragma unroll
   for (int s = 0; s < NO; ++s) {
     if (!E::last_valid(q, s)) continue;
     const int kzi = E::last_index(q, s);
-    const int ikz = wav(kzi, N);
+    const int ikz = wav(kzi, L);
     const long k2i = (long)ikx * ikx + (long)iky * iky + (long)ikz * ikz;
-    const bool sphere = 9 * k2i < (long)N * N;
+    const bool sphere = g.keep_p(kperp2, ikz);
     if (a.prune && !sphere && a.mode != 0) continue;  // stays zero
     const bool keep = k2i > 0 && sphere;
     // physical wavenumber (projector, |k|^2); keep / sphere use the index
@@ -495,7 +493,7 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_z_epi(ZEpiArgs<T> a) {
       n2 = n2 - (kz * ik2) * kn;
       if constexpr (MHD) {
         const C2<T> e0 = a.scale * r[3][s], e1 = a.scale * r[4][s], e2 = a.scale * r[5][s];
-        const T kzd = a.sz * (T)dwav(kzi, N);
+        const T kzd = a.sz * (T)dwav(kzi, L);
         const C2<T> c0 = mul_i(kyd * e2 - kzd * e1);
         const C2<T> c1 = mul_i(kzd * e0 - kxd * e2);
         const C2<T> c2 = mul_i(kxd * e1 - kyd * e0);
@@ -609,7 +607,7 @@ struct XArgs {
   const C2<T>* tw;   // length N
   long in_fs, in_pitch, out_fs, out_pitch;  // per-row pitch in complex elements
   long in_bs, out_bs;  // box strides
-  long rows;         // rows per field (N*N)
+  long rows;         // rows per field (ny nz)
   int nf, nb;
   int kmax;  // fused passes: coefficients kx > kmax are zero on input and not needed on output
 };
@@ -844,18 +842,18 @@ __device__ __forceinline__ long isqrt_floor(long n) {  // n >= 0
 template <typename T>
 struct SpecArgs {
   const C2<T>* f;
-  double* part;     // [N][nshell][2] (E, Z) per plane
-  double* pmax;     // [N] max |k_d . f| per plane
+  double* part;     // [nz][nshell][2] (E, Z) per plane
+  double* pmax;     // [nz] max |k_d . f| per plane
   long fs, pitch;   // field stride, kx pitch
-  int N, nf, nshell;
+  int nx, ny, nz, nf, nshell;
   double sx, sy, sz;  // box factors 2 pi / L (enstrophy and divergence; shells stay on the index)
 };
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_spec_planes(SpecArgs<T> a) {
-  const int kz = blockIdx.x, N = a.N, H = N / 2 + 1;
-  const long izw = wav(kz, N);
-  const double kzd = a.sz * dwav(kz, N);
+  const int kz = blockIdx.x, NX = a.nx, NY = a.ny, H = NX / 2 + 1;
+  const long izw = wav(kz, a.nz);
+  const double kzd = a.sz * dwav(kz, a.nz);
   const double qz2 = a.sz * a.sz * (double)(izw * izw);
   __shared__ double red[256];
   double mx = 0;
@@ -863,8 +861,8 @@ __global__ __launch_bounds__(256) void k_spec_planes(SpecArgs<T> a) {
     NSum E{0, 0}, Z{0, 0};
     const long lo2 = (long)(2 * s - 1) * (2 * s - 1);  // shell s: lo2 <= 4|k|^2 < hi2
     const long hi2 = (long)(2 * s + 1) * (2 * s + 1);
-    for (int ky = 0; ky < N; ++ky) {
-      const long iyw = wav(ky, N);
+    for (int ky = 0; ky < NY; ++ky) {
+      const long iyw = wav(ky, NY);
       const long A4 = 4 * (iyw * iyw + izw * izw);
       if (A4 >= hi2) continue;
       long kx0 = 0;
@@ -876,8 +874,8 @@ __global__ __launch_bounds__(256) void k_spec_planes(SpecArgs<T> a) {
       }
       long kx1 = isqrt_floor(hi2 - A4 - 1) / 2;  // largest kx with 4 kx^2 < hi2 - A4
       if (kx1 > H - 1) kx1 = H - 1;
-      const C2<T>* row = a.f + (long)kz * N * a.pitch + (long)ky * a.pitch;
-      const double kyd = a.sy * dwav(ky, N);
+      const C2<T>* row = a.f + (long)kz * NY * a.pitch + (long)ky * a.pitch;
+      const double kyd = a.sy * dwav(ky, NY);
       const double qyz2 = a.sy * a.sy * (double)(iyw * iyw) + qz2;
       for (long kx = kx0; kx <= kx1; ++kx) {
         double e = 0;
@@ -885,11 +883,11 @@ __global__ __launch_bounds__(256) void k_spec_planes(SpecArgs<T> a) {
           const C2<T> v = row[ff * a.fs + kx];
           e += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
         }
-        const double w = (kx == 0 || 2 * kx == N) ? 0.5 : 1.0;  // (1/2) * weight
+        const double w = (kx == 0 || 2 * kx == NX) ? 0.5 : 1.0;  // (1/2) * weight
         const double q2 = a.sx * a.sx * (double)(kx * kx) + qyz2;  // physical |k|^2
         nadd(E, w * e);
         nadd(Z, w * q2 * e);
-        const double kxd = a.sx * dwavx((int)kx, N);
+        const double kxd = a.sx * dwavx((int)kx, NX);
         for (int ff = 0; ff + 2 < a.nf; ff += 3) {
           const C2<T> v0 = row[ff * a.fs + kx], v1 = row[(ff + 1) * a.fs + kx], v2 = row[(ff + 2) * a.fs + kx];
           const double dx = kxd * v0.x + kyd * v1.x + kzd * v2.x;

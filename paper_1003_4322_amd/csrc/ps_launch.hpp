@@ -1,5 +1,6 @@
 // ps_launch.hpp -- host-side launchers of the gfx950 kernels (internal).
-// Each launcher picks the compiled configuration for the grid size N and the
+// Each launcher picks the compiled configuration for the length N of the axis
+// its pass transforms (z passes: nz, y passes: ny, x passes: nx) and the
 // requested variant, fills in the tile counts and enqueues one kernel.
 #pragma once
 
@@ -18,8 +19,9 @@ int variant_count(const char* kind, int N, bool mhd);
 
 template <typename T>
 hipError_t launch_strided(int N, int dir, int var, StridedArgs<T> a, hipStream_t s);
-// Tiles of a z pass that meet the dealiasing disk 9 (kx^2 + ky^2) < N^2,
-// one device list per tile width (entries tile | ky << 16, ky-major).
+// Tiles of a z pass whose first column meets the dealiasing disk
+// Grid::disk(kx, ky), one device list per tile width (entries
+// tile | ky << 16, ky-major).
 struct DiskTiles {
   static constexpr int MAXTX = 16;
   const int* list[MAXTX + 1] = {};

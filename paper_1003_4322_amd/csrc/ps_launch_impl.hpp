@@ -30,9 +30,9 @@ hipError_t strided_v(int dir, StridedArgs<T> a, hipStream_t s) {
   constexpr int TX = StridedTX<T, N, LC::TQ, v.sh>::value;
   a.ntile = cdiv(a.ncols, TX);
   // pruned passes: launch only the tiles whose first column kx = tile TX
-  // satisfies 9 kx^2 < N^2 (the kernel skips the others)
+  // is kept by the 2/3 rule (the kernel skips the others)
   if (a.prune)
-    while (a.ntile > 0 && 9L * ((a.ntile - 1) * TX) * ((a.ntile - 1) * TX) >= (long)N * N) --a.ntile;
+    while (a.ntile > 0 && !a.g.disk((a.ntile - 1) * TX, 0)) --a.ntile;
   const long grid = (long)a.ntile * a.nlines * a.nf * a.nb;
   if (grid <= 0) return hipSuccess;
   if (dir == FWD)
@@ -77,7 +77,7 @@ constexpr int zepi_tx_of() {
 
 // grid of a z pass: every tile, or only those in the disk list
 template <int TX>
-long z_grid(int N, int ntile, int nb, bool listed, const DiskTiles* dt, const int*& tiles, int& ntl) {
+long z_grid(int ny, int ntile, int nb, bool listed, const DiskTiles* dt, const int*& tiles, int& ntl) {
   static_assert(TX <= DiskTiles::MAXTX, "disk tile lists cover widths up to 16");
   if (listed && dt && dt->list[TX]) {
     tiles = dt->list[TX];
@@ -86,7 +86,7 @@ long z_grid(int N, int ntile, int nb, bool listed, const DiskTiles* dt, const in
   }
   tiles = nullptr;
   ntl = 0;
-  return (long)ntile * N * nb;
+  return (long)ntile * ny * nb;
 }
 
 template <typename T, int N, int I, bool MHD, bool ELS = false>
@@ -95,8 +95,9 @@ hipError_t z_curl_v(ZCurlArgs<T> a, const DiskTiles* dt, hipStream_t s) {
   using LC = Sched<N, v.alt>;
   constexpr int TX = StridedTX<T, N, LC::TQ, v.sh>::value;
   constexpr int SPLIT = (MHD && !ELS) ? v.split : (v.split > 2 ? 2 : v.split);
-  a.ntile = cdiv(N / 2 + 1, TX);
-  const long grid = z_grid<TX>(N, a.ntile, a.nb, a.prune != 0, dt, a.tiles, a.ntl) * SPLIT;
+  if (a.g.nz != N) return hipErrorInvalidValue;
+  a.ntile = cdiv(a.g.nx / 2 + 1, TX);
+  const long grid = z_grid<TX>(a.g.ny, a.ntile, a.nb, a.prune != 0, dt, a.tiles, a.ntl) * SPLIT;
   k_z_curl<T, N, LC::TQ, TX, typename LC::RL, MHD, SPLIT, v.direct, waves_per_simd(v.minb, TX * LC::TQ), ELS>
       <<<dim3((unsigned)grid), dim3(TX * LC::TQ), 0, s>>>(a);
   return hipGetLastError();
@@ -157,8 +158,9 @@ hipError_t z_epi_v(ZEpiArgs<T> a, const DiskTiles* dt, hipStream_t s) {
   using LC = Sched<N, v.alt>;
   constexpr int TX = StridedTX<T, N, LC::TQ, v.sh>::value;
   constexpr int SPLIT = ELS && v.split >= 2 ? 2 : 1;
-  a.ntile = cdiv(N / 2 + 1, TX);
-  const long grid = z_grid<TX>(N, a.ntile, a.nb, a.prune && a.mode != 0, dt, a.tiles, a.ntl) * SPLIT;
+  if (a.g.nz != N) return hipErrorInvalidValue;
+  a.ntile = cdiv(a.g.nx / 2 + 1, TX);
+  const long grid = z_grid<TX>(a.g.ny, a.ntile, a.nb, a.prune && a.mode != 0, dt, a.tiles, a.ntl) * SPLIT;
   k_z_epi<T, N, LC::TQ, TX, typename LC::RL, MHD, waves_per_simd(v.minb, TX * LC::TQ), ELS, SPLIT>
       <<<dim3((unsigned)grid), dim3(TX * LC::TQ), 0, s>>>(a);
   return hipGetLastError();

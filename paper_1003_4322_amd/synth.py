@@ -177,6 +177,52 @@ def random_solenoidal(N: int, seed: int, k0: float, energy: float = 0.5) -> Spar
     return SparseField(N, K, v)
 
 
+def random_grid(nx: int, ny: int, nz: int, seed: int, k0: float, energy: float = 0.5,
+                dtype=np.complex128) -> np.ndarray:
+    """Dense random-phase, divergence-free, zero-mean field [3][kz][ky][kx] on
+    an nx x ny x nz grid, filling the kept region (3kx/nx)^2 + (3ky/ny)^2 +
+    (3kz/nz)^2 < 1 with amplitudes |k| exp(-(|k|/k0)^2) (|k| of the index) and
+    total energy 1/2 <|u|^2> = ``energy``.
+
+    Steps as in random_solenoidal: complex Gaussian a(k) from (seed, storage
+    index, component); v = k x a; the kx = 0 plane replaced by its Hermitian
+    part; k = 0 and modes outside the kept region zeroed; then scaled.
+    """
+    H = nx // 2 + 1
+    kz = np.where(np.arange(nz) < nz // 2, np.arange(nz), np.arange(nz) - nz)
+    ky = np.where(np.arange(ny) < ny // 2, np.arange(ny), np.arange(ny) - ny)
+    KZ, KY, KX = np.meshgrid(kz, ky, np.arange(H), indexing="ij")
+    m = (np.arange(nz)[:, None, None] * ny + np.arange(ny)[None, :, None]) * H + np.arange(H)
+    a = np.empty((3,) + KZ.shape, np.complex128)
+    for c in range(3):
+        ctr = (m.astype(np.uint64) * np.uint64(3) + np.uint64(c)) * np.uint64(2)
+        re, im = box_muller(uniform53(seed, ctr), uniform53(seed, ctr + np.uint64(1)))
+        a[c] = re + 1j * im
+    fx, fy, fz = KX.astype(np.float64), KY.astype(np.float64), KZ.astype(np.float64)
+    v = np.empty_like(a)
+    v[0] = fy * a[2] - fz * a[1]
+    v[1] = fz * a[0] - fx * a[2]
+    v[2] = fx * a[1] - fy * a[0]
+    # Hermitian part of the kx = 0 plane: v(0, ky, kz) = conj(v(0, -ky, -kz))
+    iy, iz = (-np.arange(ny)) % ny, (-np.arange(nz)) % nz
+    p0 = v[:, :, :, 0]
+    v[:, :, :, 0] = 0.5 * (p0 + np.conj(p0[:, iz[:, None], iy[None, :]]))
+    # kept region in exact integers: 9 (kx^2 (ny nz)^2 + ...) < (nx ny nz)^2,
+    # below 2^63 for axis lengths up to 1024
+    X, Y, Z = np.int64(nx), np.int64(ny), np.int64(nz)
+    KX64, KY64, KZ64 = KX.astype(np.int64), KY.astype(np.int64), KZ.astype(np.int64)
+    q = 9 * (KX64 ** 2 * (Y * Z) ** 2 + KY64 ** 2 * (X * Z) ** 2 + KZ64 ** 2 * (X * Y) ** 2)
+    k2 = KX * KX + KY * KY + KZ * KZ
+    keep = (q < (X * Y * Z) ** 2) & (k2 > 0)
+    kk = np.sqrt(k2.astype(np.float64))
+    v *= keep * np.exp(-(kk / k0) ** 2)
+    w = np.where(KX == 0, 1.0, 2.0)
+    w[..., -1] = 1.0
+    e = 0.5 * np.sum(w * np.sum(np.abs(v) ** 2, axis=0))
+    v *= math.sqrt(energy / e)
+    return v.astype(dtype)
+
+
 def target_spectrum(N: int, k0: float, energy: float = 0.5) -> np.ndarray:
     """Shell energies the generator aims at, for shells 0..s(3 (N/2)^2)."""
     s_sphere = int(shell_index(np.array([(N * N - 1) // 9]))[0])

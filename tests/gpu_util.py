@@ -49,8 +49,9 @@ def rel_l2(a: np.ndarray, b: np.ndarray) -> float:
 
 def rel_l2_w(a: np.ndarray, b: np.ndarray) -> float:
     """Hermitian-weighted relative L2 over half spectra (= physical-space L2)."""
-    N = a.shape[-2]
-    w = hweights(N)
+    w = np.full(a.shape[-1], 2.0)  # kx = 0 and kx = nx/2 count once
+    w[0] = 1.0
+    w[-1] = 1.0
     num = np.sum(w * np.abs(a - b) ** 2)
     den = np.sum(w * np.abs(b) ** 2)
     return float(np.sqrt(num / (den if den > 0 else 1.0)))

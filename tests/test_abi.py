@@ -51,12 +51,20 @@ def test_create_rejects_bad_arguments_before_hip(L):
     assert L.ps_plan_create(ctypes.byref(h), 32, 4, 0) == -2      # nfields
     assert h.value is None                                          # *out cleared
     assert L.ps_plan_create(ctypes.byref(h), 30, 3, 0) == -2      # not 2^a 3^b in the table
-    assert b"unsupported N = 30" in L.ps_last_error()
+    assert b"unsupported axis length 30" in L.ps_last_error()
     assert L.ps_plan_create(ctypes.byref(h), 2048, 3, 0) == -2    # too large
     assert L.ps_plan_create(ctypes.byref(h), 32, 3, 7) == -1      # dtype
     arr = (ctypes.c_int * 2)(64, 100)
     assert L.ps_plan_create_batch(ctypes.byref(h), 2, arr, 3, 0) == -2
     assert L.ps_plan_create_batch(ctypes.byref(h), 0, arr, 3, 0) == -1
+    # grids with different axis lengths: each length is checked
+    assert L.ps_plan_create_grid(None, 32, 48, 64, 3, 0) == -1
+    assert L.ps_plan_create_grid(ctypes.byref(h), 32, 40, 64, 3, 0) == -2
+    assert b"unsupported axis length 40" in L.ps_last_error()
+    assert L.ps_plan_create_grid(ctypes.byref(h), 32, 48, 2048, 3, 0) == -2
+    assert L.ps_plan_create_grid(ctypes.byref(h), 32, 48, 64, 4, 0) == -2
+    assert L.ps_plan_create_grid(ctypes.byref(h), 32, 48, 64, 3, 9) == -1
+    assert h.value is None
 
 
 def test_null_plan_calls(L):

@@ -1,0 +1,207 @@
+"""Grids with different axis lengths (nx, ny, nz) against the FP64 oracle:
+transforms, nonlinear terms (NS; MHD in both forms), RK2 steps with rotation
+in a stretched box, the shell spectrum, pruned and not; and, at sizes where
+every pass has kernel variants, exact embedding of a band-limited field after
+autotuning.  Tolerances as in the cubic parity tests.
+"""
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import CDT, DEV, host, rel_l2, rel_l2_w, rounded, say, to_dev
+from oracle.psref import MHD, NS
+from paper_1003_4322_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL_FFT = {"f64": 1e-13, "f32": 2e-6}
+TOL_NL = {"f64": 1e-12, "f32": 2e-5}
+TOL_STEP = {"f64": 1e-12, "f32": 2e-6}
+
+# (nx, ny, nz): every pair of axes differs, several tiles and ragged tails
+GRIDS_FFT = [(16, 24, 32), (48, 32, 12), (8, 64, 24), (96, 16, 48)]
+GRIDS_NL = [(32, 48, 64), (64, 24, 48), (48, 96, 32)]
+OMEGA = (1.5, -2.0, 3.0)
+BOX = (2 * np.pi, 3 * np.pi, 5 * np.pi)
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_1003_4322_amd import binding
+    binding.lib()
+    return binding
+
+
+def grid_mhd(n, s1, s2, k0):
+    u = synth.random_grid(*n, s1, k0)
+    b = synth.random_grid(*n, s2, k0)
+    return np.concatenate([u + b, u - b])
+
+
+def box_solenoidal(z, L):
+    """Remove the divergence of each 3-vector group in the box's metric."""
+    nz, ny, H = z.shape[1:]
+    kz = np.fft.fftfreq(nz, 1.0 / nz)[:, None, None]
+    ky = np.fft.fftfreq(ny, 1.0 / ny)[None, :, None]
+    kx = np.arange(H)[None, None, :]
+    k = [2 * np.pi / L[0] * kx, 2 * np.pi / L[1] * ky, 2 * np.pi / L[2] * kz]
+    k2 = k[0] ** 2 + k[1] ** 2 + k[2] ** 2
+    k2[0, 0, 0] = 1.0
+    out = z.copy()
+    for g in range(0, z.shape[0], 3):
+        kv = sum(k[c] * z[g + c] for c in range(3))
+        for c in range(3):
+            out[g + c] = z[g + c] - k[c] * kv / k2
+    return out
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("n", GRIDS_FFT, ids=lambda n: "x".join(map(str, n)))
+def test_grid_fft(B, ref, n, dt):
+    say("grid fft", n, dt)
+    nx, ny, nz = n
+    rng = np.random.default_rng(nx * 10000 + ny * 100 + nz)
+    u = rounded(rng.standard_normal((3, nz, ny, nx)), dt)
+    p = B.Plan(nfields=3, dtype=dt, grid=n)
+    assert p.spectral_shape() == (3, nz, ny, nx // 2 + 1)
+    got = host(p.fft_r2c(to_dev(u, dt, "r")))
+    want = ref.fft_r2c(u)
+    assert rel_l2(got, want) < TOL_FFT[dt], rel_l2(got, want)
+    s = (3, nz, ny, nx // 2 + 1)
+    X = rounded(rng.standard_normal(s) + 1j * rng.standard_normal(s), dt)  # not Hermitian
+    got = host(p.fft_c2r(to_dev(X, dt)))
+    want = ref.fft_c2r(X)
+    assert rel_l2(got, want) < TOL_FFT[dt], rel_l2(got, want)
+
+
+@pytest.mark.parametrize("prune", [0, 1])
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("n", GRIDS_NL, ids=lambda n: "x".join(map(str, n)))
+def test_grid_nonlinear_ns(B, ref, n, dt, prune):
+    say("grid nonlinear ns", n, dt, prune)
+    u = rounded(synth.random_grid(*n, 7, 6.0), dt)
+    p = B.Plan(nfields=3, dtype=dt, grid=n)
+    p.set_variant("prune", prune)
+    out = torch.full(u.shape, 1e30, dtype=CDT[dt], device=DEV)
+    got = host(p.nonlinear_ns(to_dev(u, dt), out))
+    want = ref.nonlinear_ns(u)
+    assert rel_l2_w(got, want) < TOL_NL[dt], rel_l2_w(got, want)
+
+
+@pytest.mark.parametrize("form", [0, 1])
+@pytest.mark.parametrize("prune", [0, 1])
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("n", GRIDS_NL, ids=lambda n: "x".join(map(str, n)))
+def test_grid_nonlinear_mhd(B, ref, n, dt, prune, form):
+    say("grid nonlinear mhd", n, dt, prune, form)
+    z = rounded(grid_mhd(n, 8, 9, 6.0), dt)
+    p = B.Plan(nfields=6, dtype=dt, grid=n)
+    p.set_variant("prune", prune)
+    p.set_variant("form", form)
+    out = torch.full(z.shape, 1e30, dtype=CDT[dt], device=DEV)
+    got = host(p.nonlinear_mhd(to_dev(z, dt), out))
+    want = ref.nonlinear_mhd(z)
+    assert rel_l2_w(got, want) < TOL_NL[dt], rel_l2_w(got, want)
+
+
+@pytest.fixture
+def boxed(ref):
+    ref.set_box(*BOX)
+    yield ref
+    ref.set_box()
+
+
+@pytest.mark.parametrize("model,form", [("ns", 0), ("mhd", 0), ("mhd", 1)])
+@pytest.mark.parametrize("prune", [0, 1])
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_grid_rk2_rotation_box(B, boxed, dt, prune, model, form):
+    """Two RK2 steps (graph replay) rotating, in a stretched box."""
+    n = (48, 32, 64)
+    say("grid rk2", n, model, dt, prune, form)
+    if model == "ns":
+        z0, nf, pm, m, eta = synth.random_grid(*n, 11, 5.0), 3, B.PS_NS, NS, 0.0
+    else:
+        z0, nf, pm, m, eta = grid_mhd(n, 12, 13, 5.0), 6, B.PS_MHD, MHD, 0.01
+    z0 = rounded(box_solenoidal(z0, BOX), dt)
+    p = B.Plan(nfields=nf, dtype=dt, grid=n)
+    p.set_variant("prune", prune)
+    if model == "mhd":
+        p.set_variant("form", form)
+    p.set_box(*BOX)
+    p.set_rotation(*OMEGA)
+    s = to_dev(z0, dt)
+    p.rk2_step(s, pm, 0.02, eta, 4e-3, 2)
+    want = boxed.rk2_step(z0, m, 0.02, eta, 4e-3, 2, omega=OMEGA)
+    assert rel_l2_w(host(s), want) < 3 * TOL_STEP[dt], rel_l2_w(host(s), want)
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_grid_spectrum(B, boxed, dt):
+    n = (32, 24, 48)
+    say("grid spectrum", n, dt)
+    u = rounded(synth.random_grid(*n, 14, 5.0), dt)
+    p = B.Plan(nfields=3, dtype=dt, grid=n)
+    p.set_box(*BOX)
+    assert p.nshells[0] == boxed.num_shells(*n)
+    spec, tot = p.energy_spectrum(to_dev(u, dt))
+    ws, wt = boxed.energy_spectrum(u)
+    spec, tot = host(spec), host(tot)
+    assert np.abs(spec - ws).max() <= 1e-12 * ws.max()
+    assert abs(tot[0] - wt[0]) <= 1e-12 * wt[0] and abs(tot[1] - wt[1]) <= 1e-12 * wt[1]
+    assert abs(tot[2] - wt[2]) <= 1e-10 * wt[2]
+
+
+def scatter(sf, n, cdt):
+    """SparseField modes |k| <= K into an nx x ny x nz half spectrum on the GPU."""
+    nx, ny, nz = n
+    K = sf.K
+    st = torch.zeros((sf.values.shape[0], nz, ny, nx // 2 + 1), dtype=cdt, device=DEV)
+    kr = np.arange(-K, K + 1)
+    vals = torch.from_numpy(np.ascontiguousarray(sf.values)).to(DEV, cdt)
+    fi = torch.arange(sf.values.shape[0], device=DEV).view(-1, 1, 1, 1)
+    st.index_put_((fi, torch.as_tensor(kr % nz, device=DEV).view(1, -1, 1, 1),
+                   torch.as_tensor(kr % ny, device=DEV).view(1, 1, -1, 1),
+                   torch.arange(K + 1, device=DEV).view(1, 1, 1, -1)), vals)
+    return st
+
+
+@pytest.mark.parametrize("case", [("mhd", (256, 512, 384), "f32", 1), ("mhd", (512, 256, 256), "f64", 1),
+                                  ("ns", (384, 256, 512), "f32", 0), ("mhd", (256, 384, 512), "f32", 0)],
+                         ids=lambda c: f"{c[0]}-{'x'.join(map(str, c[1]))}-{c[2]}-form{c[3]}")
+def test_grid_embedding_autotuned(B, ref, case):
+    """A field with modes |k| <= 4 takes one RK2 step (support |k| <= 16)
+    identically on a 64^3 grid (oracle) and on a large grid whose every pass
+    has kernel variants, in the autotuned configuration."""
+    model, n, dt, form = case
+    say("grid embedding", model, n, dt, form)
+    cdt = CDT[dt]
+    K, n0 = 4, 64
+    if model == "mhd":
+        u, b = synth.band_limited(n0, 31, K), synth.band_limited(n0, 32, K)
+        small = synth.SparseField(n0, K, np.concatenate([(u + b).values, (u - b).values]))
+        nf, pm, m, nu, eta = 6, B.PS_MHD, MHD, 5e-4, 5e-4
+    else:
+        small = synth.band_limited(n0, 33, K)
+        nf, pm, m, nu, eta = 3, B.PS_NS, NS, 2e-4, 0.0
+    vals = rounded(small.values, dt)
+    small = synth.SparseField(n0, K, vals)
+    want_full = ref.rk2_step(small.dense(), m, nu, eta, 2e-3, 1, omega=OMEGA)
+    z = scatter(small, n, cdt)
+    p = B.Plan(nfields=nf, dtype=dt, grid=n)
+    p.set_variant("prune", 1)
+    if model == "mhd":
+        p.set_variant("form", form)
+    p.set_rotation(*OMEGA)
+    say("autotune", p.autotune(z, pm, 2))
+    p.rk2_step(z, pm, nu, eta, 2e-3, 1)
+    Kc = 4 * K
+    kr = np.arange(-Kc, Kc + 1)
+    nx, ny, nz = n
+    got = host(z[:, kr % nz][:, :, kr % ny][..., :Kc + 1])
+    want = want_full[:, kr % n0][:, :, kr % n0][..., :Kc + 1]
+    tol = 2e-6 if dt == "f32" else 1e-12
+    assert rel_l2(got, want) < tol, rel_l2(got, want)
+    tot = float(z.abs().double().pow(2).sum().item())
+    inside = float(np.sum(np.abs(got) ** 2))
+    assert tot - inside <= tol * tol * tot + 1e-15 * tot, (tot, inside)
+    del z, p
