@@ -214,6 +214,57 @@ def ensemble_run(steps: int = 100, warmup: int = 5):
 PRUNE = 1
 
 
+def grid_run(ms_cube: float, steps: int = 10):
+    """MHD (Elsasser form) on a 512 x 512 x 1024 grid in a (2 pi, 2 pi, 4 pi)
+    box rotating about z, FP32, autotuned: steps/s, the passes, and the time
+    per grid point relative to the 512^3 headline step (1.0 = the same)."""
+    import numpy as np
+    import torch
+
+    from paper_1003_4322_amd import binding, synth
+
+    n = (512, 512, 1024)
+    w = WORKLOADS["mhd512"]
+    dev = torch.device("cuda:0")
+    sf = synth.mhd_sparse(512, w["seeds"][0], w["seeds"][1], w["k0"])
+    nx, ny, nz = n
+    K = sf.K
+    st = torch.zeros((6, nz, ny, nx // 2 + 1), dtype=torch.complex64, device=dev)
+    kr = np.arange(-K, K + 1)
+    st.index_put_((torch.arange(6, device=dev).view(-1, 1, 1, 1),
+                   torch.as_tensor(kr % nz, device=dev).view(1, -1, 1, 1),
+                   torch.as_tensor(kr % ny, device=dev).view(1, 1, -1, 1),
+                   torch.arange(K + 1, device=dev).view(1, 1, 1, -1)),
+                  torch.from_numpy(np.ascontiguousarray(sf.values)).to(dev, torch.complex64))
+    plan = binding.Plan(nfields=6, dtype="f32", device=dev, grid=n)
+    plan.set_variant("prune", PRUNE)
+    plan.set_box(2 * np.pi, 2 * np.pi, 4 * np.pi)
+    plan.set_rotation(0.0, 0.0, 2.0)
+    tuned = plan.autotune(st, binding.PS_MHD, 2)
+    plan.rk2_step(st, binding.PS_MHD, w["nu"], w["eta"], w["dt"], 2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.rk2_step(st, binding.PS_MHD, w["nu"], w["eta"], w["dt"], steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    plan.set_timing(True)
+    plan.timing_reset()
+    plan.rk2_step(st, binding.PS_MHD, w["nu"], w["eta"], w["dt"], 2)
+    torch.cuda.synchronize()
+    passes = pass_table(plan.timings())
+    plan.set_timing(False)
+    ms = el * 1e3 / steps
+    out = {"grid": list(n), "box": "(2 pi, 2 pi, 4 pi)", "omega": [0.0, 0.0, 2.0], "dtype": "f32",
+           "steps": steps, "steps_per_s": round(1e3 / ms, 3), "ms_per_step": round(ms, 3),
+           "time_per_point_vs_512^3": round(ms / (2.0 * ms_cube), 3),
+           "variants": tuned, "passes": passes,
+           "energy_after": float(plan.energy_spectrum(st)[1][0].item())}
+    plan.close()
+    del st
+    torch.cuda.empty_cache()
+    return out
+
+
 def precision_pair(wname: str, steps: int, warmup: int = 2, spectra_every: int = 0):
     """FP32 and FP64 forms of a workload from the same FP32-representable
     initial state: steps/s of each and the FP32-vs-FP64 distance; optional
@@ -373,7 +424,7 @@ def main():
     ap.add_argument("--no-prune", action="store_true",
                     help="transform every pencil (no dealias-sphere pruning)")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the 256^3, 1024^3, ensemble and 32^3 workloads")
+                    help="skip the 256^3, 1024^3, ensemble, 32^3 and 512x512x1024 workloads")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: the hot path keeps the whole box on one device "
@@ -413,6 +464,8 @@ def main():
         extras["ensemble"] = ensemble_run()
         log("extra: NS 32^3 FP64 latency")
         extras["ns32"] = precision_pair("ns32", 200)
+        log("extra: MHD 512 x 512 x 1024 FP32, rotating, (2 pi, 2 pi, 4 pi) box")
+        extras["mhd_grid"] = grid_run(ms)
 
     cpu = None
     if not args.no_cpu:
