@@ -698,7 +698,7 @@ ps_status create_plan(ps_plan* out, int nbox, const int* dims, int nfields, ps_d
     const std::pair<const char*, int> defaults[] = {
         {"z_curl", 0},
         {"z_epi", nfields == 6 ? 5 : 2},  // MHD (Elsasser): z+ and z- in two workgroups
-        {"x_prod", dtype == PS_F32 ? (nfields == 6 ? 5 : 4) : 7},
+        {"x_prod", dtype == PS_F32 ? (nfields == 6 ? 8 : 4) : 7},
         {"y", dtype == PS_F32 ? 2 : 0}};
     for (auto& d : defaults)
       if (ps_plan_variant_count(p, d.first) > d.second) p->var[d.first] = d.second;

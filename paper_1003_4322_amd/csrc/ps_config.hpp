@@ -98,15 +98,16 @@ struct XCfg {
   // LDS slots per row: the larger of the padded and swizzled layouts
   static constexpr int SLOTS = (M + M / 8 + 1) > 32 * (M / 32 + 1) ? (M + M / 8 + 1) : 32 * (M / 32 + 1);
   static constexpr int G = (256 / TQ) < 1 ? 1 : 256 / TQ;  // plain passes: rows per workgroup
-  static constexpr bool fits(int f, int rb) {
-    return (f * rb * SLOTS + 2 * M) * 2 * (int)sizeof(T) <= 65536 && f * rb * TQ <= 1024;
+  // lim: LDS bytes per workgroup (64 KB; 80 KB for two workgroups per CU)
+  static constexpr bool fits(int f, int rb, int lim = 65536) {
+    return (f * rb * SLOTS + 2 * M) * 2 * (int)sizeof(T) <= lim && f * rb * TQ <= 1024;
   }
-  static constexpr int rb(int f, int want) {
+  static constexpr int rb(int f, int want, int lim = 65536) {
     int r = want < 1 ? 1 : want;
-    while (r > 1 && !fits(f, r)) r >>= 1;
+    while (r > 1 && !fits(f, r, lim)) r >>= 1;
     return r;
   }
-  static constexpr bool MHD_OK = fits(12, 1);
+  static constexpr bool MHD_OK = fits(12, 1, 65536);
   // launch limits alone: 1024 threads and the 160 KB of LDS a gfx950
   // workgroup may hold (rows that overflow 64 KB cost occupancy, not
   // correctness)
@@ -131,6 +132,7 @@ struct XV {
   int rb_ns, rb_mhd;  // rows per workgroup (reduced while the LDS tile would not fit)
   int sched;          // 0 LenCfg, 1 radix-16 (LenAlt), 2 wide (LenWide)
   bool swz;           // rows in LDS swizzled (LaySwz32) instead of padded (LayPad8)
+  bool big = false;   // up to 80 KB of LDS per workgroup (two per CU) instead of 64 KB
 };
 constexpr ZV ZCURL_V[] = {{1, 1, 1, false, false}, {1, 2, 1, false, false}, {1, 2, 2, false, false},
                           {1, 2, 1, true, false},  {1, 1, 1, false, true}};
@@ -138,7 +140,8 @@ constexpr ZV ZEPI_V[] = {{0, 1, 1, false}, {1, 1, 1, false}, {1, 1, 2, false}, {
                          {2, 1, 1, false}, {1, 2, 1, false}, {1, 2, 2, false}, {2, 2, 1, false}};
 constexpr ZV STR_V[] = {{0, 1, 1, false}, {1, 1, 1, false}, {0, 1, 1, true}, {1, 1, 1, true}};
 constexpr XV XPROD_V[] = {{2, 1, 0, false}, {4, 2, 0, false}, {4, 2, 1, false}, {2, 1, 1, false},
-                          {2, 1, 0, true},  {4, 2, 0, true},  {1, 1, 2, true},  {1, 1, 2, false}};
+                          {2, 1, 0, true},  {4, 2, 0, true},  {1, 1, 2, true},  {1, 1, 2, false},
+                          {8, 4, 0, true, true}, {8, 4, 0, false, true}, {4, 2, 2, true, true}};
 constexpr int NZCURL = sizeof(ZCURL_V) / sizeof(ZV);
 // waves per SIMD that minb workgroups of `threads` threads occupy (4 SIMDs per CU)
 constexpr int waves_per_simd(int minb, int threads) {

@@ -689,7 +689,8 @@ __global__ __launch_bounds__(G* TQ) void k_x_r2c(XArgs<T> a) {
 // T_11 - T_22, T_12, T_20, T_21 (T_22 - T_22 = 0 is not stored).  The part
 // removed contributes the gradient -i k T^_22 to both N+ and N-, which the
 // projection P(k) annihilates.
-template <typename T, int M, int TQ, int RB, class RL, bool MHD, bool ELS = false, class RLay = LayPad8>
+template <typename T, int M, int TQ, int RB, class RL, bool MHD, bool ELS = false, class RLay = LayPad8,
+          int LDSLIM = 65536>
 __global__ __launch_bounds__(xprod_slots(MHD, ELS) * RB * TQ) void k_x_prod(XArgs<T> a) {
   constexpr int FIN = ELS ? 6 : MHD ? 12 : 6, FOUT = ELS ? 8 : MHD ? 6 : 3;
   constexpr int G = xprod_slots(MHD, ELS) * RB, NT = G * TQ;
@@ -699,8 +700,8 @@ __global__ __launch_bounds__(xprod_slots(MHD, ELS) * RB * TQ) void k_x_prod(XArg
   // rows of every field, then twiddles: the M + 1 factors e^{-2 pi i k/N} of
   // the half-length pre- and post-processing followed by the transforms' M - 1
   // factors in the bank-friendly staged order, or (when that would not fit in
-  // 64 KB) the plain table of length N = 2M, which serves both
-  constexpr bool STAGED = (G * LP + 2 * M) * (int)sizeof(C2<T>) <= 65536;
+  // LDSLIM bytes) the plain table of length N = 2M, which serves both
+  constexpr bool STAGED = (G * LP + 2 * M) * (int)sizeof(C2<T>) <= LDSLIM;
   __shared__ C2<T> smem[G * LP + 2 * M];
   C2<T>* twl = smem + G * LP;
   const int tid = threadIdx.x, g = tid / TQ, q = tid % TQ;

@@ -238,12 +238,13 @@ hipError_t x_prod_v(bool mhd, bool els, XArgs<T> a, hipStream_t s) {
   constexpr XV v = XPROD_V[I];
   using LC = std::conditional_t<v.sched == 2, LenWide<N / 2>, Sched<N / 2, v.sched == 1>>;
   using X = XCfg<T, N / 2, LC::TQ>;
+  constexpr int LIM = v.big ? 81920 : 65536;  // LDS bytes per workgroup
   auto go = [&](auto mhd_c, auto els_c, auto rb_c) {
     constexpr bool M_ = decltype(mhd_c)::value, E_ = decltype(els_c)::value;
     constexpr int RB = decltype(rb_c)::value;
     const long grid = (a.rows * a.nb + RB - 1) / RB;
     using RLay = std::conditional_t<v.swz, LaySwz32, LayPad8>;
-    k_x_prod<T, N / 2, LC::TQ, RB, typename LC::RL, M_, E_, RLay>
+    k_x_prod<T, N / 2, LC::TQ, RB, typename LC::RL, M_, E_, RLay, LIM>
         <<<dim3((unsigned)grid), dim3(xprod_slots(M_, E_) * RB * LC::TQ), 0, s>>>(a);
     return hipGetLastError();
   };
@@ -259,20 +260,20 @@ hipError_t x_prod_v(bool mhd, bool els, XArgs<T> a, hipStream_t s) {
   // runs as variant 0, so that every variant index is valid at every size
   if (mhd && els) {
     if constexpr (X::fits(8, 1))
-      return go(t_{}, t_{}, std::integral_constant<int, X::rb(8, want(8, v.rb_mhd))>{});
+      return go(t_{}, t_{}, std::integral_constant<int, X::rb(8, want(8, v.rb_mhd), LIM)>{});
     else if constexpr (I != 0)
       return x_prod_v<T, N, 0>(mhd, els, a, s);
     return hipErrorInvalidValue;
   }
   if (mhd) {
     if constexpr (X::MHD_OK)
-      return go(t_{}, f_{}, std::integral_constant<int, X::rb(12, want(12, v.rb_mhd))>{});
+      return go(t_{}, f_{}, std::integral_constant<int, X::rb(12, want(12, v.rb_mhd), LIM)>{});
     else if constexpr (I != 0)
       return x_prod_v<T, N, 0>(mhd, els, a, s);
     return hipErrorInvalidValue;
   }
   if constexpr (X::launchable(6))
-    return go(f_{}, f_{}, std::integral_constant<int, X::rb(6, want(6, v.rb_ns))>{});
+    return go(f_{}, f_{}, std::integral_constant<int, X::rb(6, want(6, v.rb_ns), LIM)>{});
   else if constexpr (I != 0)
     return x_prod_v<T, N, 0>(mhd, els, a, s);
   return hipErrorInvalidValue;
