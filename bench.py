@@ -27,6 +27,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "RK2 steps/s + FFT GB/s (%HBM peak) at 512^3, FP32 vs FP64 at stated L2 err"
 HBM_PEAK_GBS = 8000.0
+ALU_PEAK_TFS = 78.6  # FP32 vector without packed instructions: 256 CUs x 4 SIMDs x 16 lanes x 2 x 2.4 GHz
 
 WORKLOADS = {
     # name: (N, model, nu, eta, dt, seeds, k0)
@@ -369,6 +370,18 @@ def run_primary(args, w, model, nf, N, dev):
     roofline = {"bound": "hbm", "kernel": dom, "achieved": d["GB/s"], "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(d["GB/s"] / HBM_PEAK_GBS, 4),
                 "traffic": traffic}
+    if dom == "x_prod":
+        # the same launch against the vector ALU: real transforms of length N
+        # per grid row (inverse inputs + forward products), 2.5 N log2 N flops
+        # each, over N^2 rows; FP32 without packed instructions peaks at
+        # 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz = 78.6 TFLOP/s
+        form = (tuned32 or {}).get("form", plan32.variant("form"))
+        nt = 9 if nf == 3 else (14 if form == 1 else 18)
+        flops = nt * N * N * 2.5 * N * math.log2(N)
+        tf = flops / (d["avg_ms"] * 1e-3) / 1e12
+        roofline["alu_view"] = {"bound": "alu", "achieved": round(tf, 2), "peak": ALU_PEAK_TFS,
+                                "unit": "TFLOP/s", "frac": round(tf / ALU_PEAK_TFS, 4),
+                                "flops_per_launch": flops}
 
     fp64 = None
     if not args.no_fp64:

@@ -178,15 +178,17 @@ ps_status ps_energy_spectrum(ps_plan p, const void *fhat, int nfields, double *s
  * and modes outside the sphere 9|k|^2 < N^2 are neither read nor transformed);
  * valid when the input is zero outside that sphere (a dealiased state stays
  * dealiased under the step), and modes outside it are then left untouched by
- * ps_rk2_step (ps_nonlinear_* still writes zeros there).  Kind "form" (MHD
- * plans only): 0 = the rotational form of Sec. 2 (products u x w + j x b and
- * u x b of the primitive fields), 1 = the Elsasser divergence form, which
- * takes N+- = -i P(k) k_j F[z-+_j z+-_i] from the products z+_i z-_j less
- * their isotropic part delta_ij z+_2 z-_2, a gradient that P(k) removes (eight
- * products, so fourteen real transforms per evaluation instead of eighteen;
- * the default);
- * the two agree up to rounding when z+- are solenoidal, as every state the
- * step produces is.  Kind "pipe" v: the inverse y pass, the product pass and
+ * ps_rk2_step (ps_nonlinear_* still writes zeros there).  Kind "form":
+ * 0 = the rotational form of Sec. 2 (NS: u x w; MHD: u x w + j x b and u x b
+ * of the primitive fields), 1 = the divergence form.  MHD (Elsasser
+ * variables): N+- = -i P(k) k_j F[z-+_j z+-_i] from the products z+_i z-_j
+ * less their isotropic part delta_ij z+_2 z-_2, a gradient that P(k) removes
+ * (eight products, so fourteen real transforms per evaluation instead of
+ * eighteen; the MHD default).  NS: N = -i P(k) k_j F[u_i u_j] from the five
+ * products of the symmetric u_i u_j less delta_ij u_2 u_2 (eight real
+ * transforms instead of nine, and no curl; the FP32 NS default).  Each form agrees with the
+ * rotational one up to rounding when the state is solenoidal, as every state
+ * the step produces is.  Kind "pipe" v: the inverse y pass, the product pass and
  * the forward y pass of each right-hand side run as 2^v slabs of z-planes
  * spread over helper streams (each plane's chain is independent of the
  * others'), so that one slab's memory-bound y passes overlap another's

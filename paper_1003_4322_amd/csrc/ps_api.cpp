@@ -310,9 +310,9 @@ struct Seq {
 
   // the five passes of one right-hand side evaluation
   // fields of each stage: state, physical inputs of the products, products
-  bool els(bool mhd) const { return mhd && p->els; }
-  int nphys(bool mhd) const { return mhd ? (p->els ? 6 : 12) : 6; }
-  int nprod(bool mhd) const { return mhd ? (p->els ? 8 : 6) : 3; }
+  bool els(bool) const { return p->els; }
+  int nphys(bool mhd) const { return p->els ? (mhd ? 6 : 3) : (mhd ? 12 : 6); }
+  int nprod(bool mhd) const { return p->els ? (mhd ? 8 : 5) : (mhd ? 6 : 3); }
 
   ps_status pass_zcurl(const C* src, bool mhd) {
     const int nin = mhd ? 6 : 3, nphys = this->nphys(mhd);
@@ -688,8 +688,9 @@ ps_status create_plan(ps_plan* out, int nbox, const int* dims, int nfields, ps_d
       c.twz = p->tables[c.nz];
       c.dt = &p->dtiles[((long)c.nx << 22) | ((long)c.ny << 11) | c.nz];
     }
-    // MHD: the Elsasser divergence form (fewer transforms, same result)
-    if (nfields == 6) {
+    // the divergence form (fewer transforms, same result): MHD always; NS in
+    // FP32 (in FP64 its product pass is the slower one at 1024^3)
+    if (nfields == 6 || dtype == PS_F32) {
       p->var["form"] = 1;
       p->els = true;
     }
@@ -995,7 +996,7 @@ int ps_plan_get_variant(ps_plan p, const char* kind) {
 int ps_plan_variant_count(ps_plan p, const char* kind) {
   if (!p || !kind) return PS_ERR_ARG;
   if (!strcmp(kind, "batch") || !strcmp(kind, "prune")) return 2;
-  if (!strcmp(kind, "form")) return p->nfields == 6 ? 2 : 1;
+  if (!strcmp(kind, "form")) return 2;
   if (!strcmp(kind, "pipe")) return NPIPE;
   int n = 1;
   for (auto& c : p->classes) n = std::max(n, ps::variant_count(kind, axis_len(c, kind), p->nfields == 6));

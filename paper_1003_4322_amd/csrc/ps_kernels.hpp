@@ -158,8 +158,9 @@ __device__ __forceinline__ ZTile z_tile(int blk, int ntile, int ny, const int* t
 // keeps register use, and so occupancy, near that of a plain FFT.  The
 // transforms' twiddles are staged in LDS (TwStaged) when that costs no occupancy.
 //
-// ELS (MHD, Elsasser form): no curl is needed; the six fields z+, z- are
-// transformed as they are, SPLIT workgroups sharing them (SPLIT 1 or 2).
+// ELS (divergence form): no curl is needed; the state's fields (MHD: z+, z-;
+// NS: u) are transformed as they are, SPLIT workgroups sharing them (MHD:
+// SPLIT 1 or 2; NS: 1).
 template <typename T, int L, int TQ, int TX, class RL, bool MHD, int SPLIT, bool DIRECT, int MINW = 1,
           bool ELS = false>
 __global__ __launch_bounds__(TX* TQ, MINW) void k_z_curl(ZCurlArgs<T> a) {
@@ -168,7 +169,7 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_z_curl(ZCurlArgs<T> a) {
   using Lay = typename CT::Lay;
   constexpr int NS_ = E::FIRST_SLOTS;
   constexpr int NG = MHD ? 4 : 2;
-  static_assert(NG % SPLIT == 0 && (!ELS || (MHD && SPLIT <= 2)), "split must divide the output groups");
+  static_assert(NG % SPLIT == 0 && (!ELS || (MHD ? SPLIT <= 2 : SPLIT == 1)), "split must divide the output groups");
   constexpr int GPP = NG / SPLIT;
   constexpr bool TWL = CT::TW_FITS;
   __shared__ C2<T> smem[CT::ROWS * TX + (TWL ? L : 0)];
@@ -228,7 +229,7 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_z_curl(ZCurlArgs<T> a) {
   };
 
   if constexpr (ELS) {
-    constexpr int PER = 6 / SPLIT;
+    constexpr int PER = (MHD ? 6 : 3) / SPLIT;
 #pragma unroll 1
     for (int fo = part * PER; fo < (part + 1) * PER; ++fo) {
       C2<T> v[E::SLOTS];
@@ -350,8 +351,7 @@ struct ZEpiArgs {
 template <typename T, int L, int TQ, int TX, class RL, bool MHD, int MINW = 1, bool ELS = false, int SPLIT = 1>
 __global__ __launch_bounds__(TX* TQ, MINW) void k_z_epi(ZEpiArgs<T> a) {
   using E = Stockham<T, L, TQ, FWD, RL>;
-  static_assert(!ELS || MHD, "the Elsasser form is MHD only");
-  static_assert(SPLIT == 1 || (ELS && SPLIT == 2), "only the Elsasser form splits z+ from z-");
+  static_assert(SPLIT == 1 || (ELS && MHD && SPLIT == 2), "only the Elsasser form splits z+ from z-");
   constexpr int NF = MHD ? 6 : 3;       // state fields
   constexpr int NOUT = NF / SPLIT;      // state fields this workgroup updates
   constexpr int NO = E::LAST_NB * E::RL_;
@@ -389,9 +389,36 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_z_epi(ZEpiArgs<T> a) {
   // NS / rotational MHD: r[f] = transformed input field f.
   // Elsasser: r[0..2] = a (unsplit or part 0), r[3..5] = c (unsplit); with
   // SPLIT = 2, part 1 keeps c in r[0..2].
-  constexpr int NR = ELS ? 3 * (2 / SPLIT) : NF;
+  constexpr int NR = ELS ? (MHD ? 3 * (2 / SPLIT) : 3) : NF;
   C2<T> r[NR][NO];
-  if constexpr (ELS) {
+  if constexpr (ELS && !MHD) {
+    // NS divergence form: the five products S_00 - S_22, S_11 - S_22, S_01,
+    // S_02, S_12 of S_ij = u_i u_j (symmetric, less its isotropic part);
+    // r = a, a_i = sum_j k_j S_ij
+    const T kxd0 = a.sx * (T)dwavx(col, g.nx), kyd0 = a.sy * (T)dwav(ky, g.ny);
+#pragma unroll
+    for (int f = 0; f < 3; ++f)
+#pragma unroll
+      for (int s = 0; s < NO; ++s) r[f][s] = zero2<T>();
+#pragma unroll 1
+    for (int f = 0; f < 5; ++f) {
+      // (i, j) of product f; the diagonal ones (f < 2) feed a_i only
+      const int i3 = f < 2 ? f : f == 4 ? 1 : 0;
+      const int j3 = f < 2 ? f : f == 2 ? 1 : 2;
+      C2<T> v[E::SLOTS];
+      E::template run_tw<typename CT::Lay>(v, smem + c, TX, q, tw, ld_of(f));
+#pragma unroll
+      for (int s = 0; s < NO; ++s) {
+        const T kzd0 = a.sz * (T)dwav(E::last_index(q, s), L);
+        const T kj = j3 == 0 ? kxd0 : j3 == 1 ? kyd0 : kzd0;
+        const T ki = i3 == 0 ? kxd0 : i3 == 1 ? kyd0 : kzd0;
+        const bool off = f >= 2;
+        r[0][s] = r[0][s] + ((i3 == 0 ? kj : T(0)) + (off && j3 == 0 ? ki : T(0))) * v[s];
+        r[1][s] = r[1][s] + ((i3 == 1 ? kj : T(0)) + (off && j3 == 1 ? ki : T(0))) * v[s];
+        r[2][s] = r[2][s] + ((i3 == 2 ? kj : T(0)) + (off && j3 == 2 ? ki : T(0))) * v[s];
+      }
+    }
+  } else if constexpr (ELS) {
     const T kxd0 = a.sx * (T)dwavx(col, g.nx), kyd0 = a.sy * (T)dwav(ky, g.ny);
 #pragma unroll
     for (int f = 0; f < NR; ++f)
@@ -567,7 +594,7 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_z_epi(ZEpiArgs<T> a) {
 // hold M+1 values.
 __host__ __device__ constexpr int row_slots(int M) { return pad8(M) + 1; }
 // rows of LDS (and thread groups) per grid row of the fused product pass
-__host__ __device__ constexpr int xprod_slots(bool mhd, bool els) { return els ? 8 : mhd ? 12 : 6; }
+__host__ __device__ constexpr int xprod_slots(bool mhd, bool els) { return els ? (mhd ? 8 : 5) : mhd ? 12 : 6; }
 
 template <typename T, class Lay = LayPad8>
 __device__ __forceinline__ C2<T> c2r_pre(const C2<T>* buf, int k, int M, const C2<T>* __restrict__ tw) {
@@ -683,7 +710,11 @@ __global__ __launch_bounds__(G* TQ) void k_x_r2c(XArgs<T> a) {
 // NS : in [u0 u1 u2 w0 w1 w2]             out [u x w]
 // MHD: in [u0..2 w0..2 b0..2 j0..2]       out [u x w + j x b, u x b]
 //
-// ELS (MHD, Elsasser form): inputs z+ (fields 0-2) and z- (3-5); outputs the
+// ELS, NS (divergence form): input u (fields 0-2); outputs the five fields of
+// S_ij = u_i u_j less its isotropic part delta_ij S_22: S_00 - S_22,
+// S_11 - S_22, S_01, S_02, S_12 (symmetric; the gradient removed is again
+// annihilated by P(k)).
+// ELS, MHD (Elsasser form): inputs z+ (fields 0-2) and z- (3-5); outputs the
 // eight fields of the stress T_ij = z+_i z-_j less its isotropic part
 // delta_ij T_22, as field 3 i + j: T_00 - T_22, T_01, T_02, T_10,
 // T_11 - T_22, T_12, T_20, T_21 (T_22 - T_22 = 0 is not stored).  The part
@@ -692,7 +723,7 @@ __global__ __launch_bounds__(G* TQ) void k_x_r2c(XArgs<T> a) {
 template <typename T, int M, int TQ, int RB, class RL, bool MHD, bool ELS = false, class RLay = LayPad8,
           int LDSLIM = 65536>
 __global__ __launch_bounds__(xprod_slots(MHD, ELS) * RB * TQ) void k_x_prod(XArgs<T> a) {
-  constexpr int FIN = ELS ? 6 : MHD ? 12 : 6, FOUT = ELS ? 8 : MHD ? 6 : 3;
+  constexpr int FIN = ELS ? (MHD ? 6 : 3) : MHD ? 12 : 6, FOUT = ELS ? (MHD ? 8 : 5) : MHD ? 6 : 3;
   constexpr int G = xprod_slots(MHD, ELS) * RB, NT = G * TQ;
   using EI = Stockham<T, M, TQ, INV, RL>;
   using EF = Stockham<T, M, TQ, FWD, RL>;
@@ -776,14 +807,18 @@ __global__ __launch_bounds__(xprod_slots(MHD, ELS) * RB * TQ) void k_x_prod(XArg
   {
     C2<T> v[EF::SLOTS];
     if constexpr (ELS) {
-      // T_ij = z+_i z-_j, i = f / 3, j = f % 3, less z+_2 z-_2 on the
-      // diagonal (f = 0, 4); every read happens before the first stage's
-      // barrier, so overwriting the input slots after it is safe
-      const C2<T>* ra = smem + ((f / 3) * RB + rb) * LP;
-      const C2<T>* rm = smem + ((3 + f % 3) * RB + rb) * LP;
+      // MHD: T_ij = z+_i z-_j, i = f / 3, j = f % 3, less z+_2 z-_2 on the
+      // diagonal (f = 0, 4).  NS: S_ij = u_i u_j for (i, j) = (0, 0), (1, 1),
+      // (0, 1), (0, 2), (1, 2), less u_2 u_2 on the diagonal (f = 0, 1).
+      // Every read happens before the first stage's barrier, so overwriting
+      // the input slots after it is safe.
+      const int fi = MHD ? f / 3 : (f < 2 ? f : f == 4 ? 1 : 0);
+      const int fj = MHD ? 3 + f % 3 : (f < 2 ? f : f == 2 ? 1 : 2);
+      const C2<T>* ra = smem + (fi * RB + rb) * LP;
+      const C2<T>* rm = smem + (fj * RB + rb) * LP;
       const C2<T>* ra2 = smem + (2 * RB + rb) * LP;
-      const C2<T>* rm2 = smem + (5 * RB + rb) * LP;
-      const bool diag = f % 4 == 0;
+      const C2<T>* rm2 = smem + ((MHD ? 5 : 2) * RB + rb) * LP;
+      const bool diag = MHD ? f % 4 == 0 : f < 2;
       EF::template run_tw<RLay>(
           v, buf, 1, q, twf,
           [&](int, int n) {

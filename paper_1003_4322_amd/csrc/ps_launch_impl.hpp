@@ -94,7 +94,7 @@ hipError_t z_curl_v(ZCurlArgs<T> a, const DiskTiles* dt, hipStream_t s) {
   constexpr ZV v = ZCURL_V[I];
   using LC = Sched<N, v.alt>;
   constexpr int TX = StridedTX<T, N, LC::TQ, v.sh>::value;
-  constexpr int SPLIT = (MHD && !ELS) ? v.split : (v.split > 2 ? 2 : v.split);
+  constexpr int SPLIT = (MHD && !ELS) ? v.split : !MHD && ELS ? 1 : (v.split > 2 ? 2 : v.split);
   if (a.g.nz != N) return hipErrorInvalidValue;
   a.ntile = cdiv(a.g.nx / 2 + 1, TX);
   const long grid = z_grid<TX>(a.g.ny, a.ntile, a.nb, a.prune != 0, dt, a.tiles, a.ntl) * SPLIT;
@@ -105,7 +105,7 @@ hipError_t z_curl_v(ZCurlArgs<T> a, const DiskTiles* dt, hipStream_t s) {
 
 template <typename T, int N, int I>
 hipError_t z_curl_m(bool mhd, bool els, ZCurlArgs<T> a, const DiskTiles* dt, hipStream_t s) {
-  if (mhd && els) return z_curl_v<T, N, I, true, true>(a, dt, s);
+  if (els) return mhd ? z_curl_v<T, N, I, true, true>(a, dt, s) : z_curl_v<T, N, I, false, true>(a, dt, s);
   return mhd ? z_curl_v<T, N, I, true>(a, dt, s) : z_curl_v<T, N, I, false>(a, dt, s);
 }
 
@@ -157,7 +157,7 @@ hipError_t z_epi_v(ZEpiArgs<T> a, const DiskTiles* dt, hipStream_t s) {
   constexpr ZV v = ZEPI_V[I];
   using LC = Sched<N, v.alt>;
   constexpr int TX = StridedTX<T, N, LC::TQ, v.sh>::value;
-  constexpr int SPLIT = ELS && v.split >= 2 ? 2 : 1;
+  constexpr int SPLIT = ELS && MHD && v.split >= 2 ? 2 : 1;
   if (a.g.nz != N) return hipErrorInvalidValue;
   a.ntile = cdiv(a.g.nx / 2 + 1, TX);
   const long grid = z_grid<TX>(a.g.ny, a.ntile, a.nb, a.prune && a.mode != 0, dt, a.tiles, a.ntl) * SPLIT;
@@ -168,7 +168,7 @@ hipError_t z_epi_v(ZEpiArgs<T> a, const DiskTiles* dt, hipStream_t s) {
 
 template <typename T, int N, int I>
 hipError_t z_epi_m(bool mhd, bool els, ZEpiArgs<T> a, const DiskTiles* dt, hipStream_t s) {
-  if (mhd && els) return z_epi_v<T, N, I, true, true>(a, dt, s);
+  if (els) return mhd ? z_epi_v<T, N, I, true, true>(a, dt, s) : z_epi_v<T, N, I, false, true>(a, dt, s);
   return mhd ? z_epi_v<T, N, I, true>(a, dt, s) : z_epi_v<T, N, I, false>(a, dt, s);
 }
 
@@ -268,6 +268,13 @@ hipError_t x_prod_v(bool mhd, bool els, XArgs<T> a, hipStream_t s) {
   if (mhd) {
     if constexpr (X::MHD_OK)
       return go(t_{}, f_{}, std::integral_constant<int, X::rb(12, want(12, v.rb_mhd), LIM)>{});
+    else if constexpr (I != 0)
+      return x_prod_v<T, N, 0>(mhd, els, a, s);
+    return hipErrorInvalidValue;
+  }
+  if (els) {
+    if constexpr (X::launchable(5))
+      return go(f_{}, t_{}, std::integral_constant<int, X::rb(5, want(5, v.rb_ns), LIM)>{});
     else if constexpr (I != 0)
       return x_prod_v<T, N, 0>(mhd, els, a, s);
     return hipErrorInvalidValue;

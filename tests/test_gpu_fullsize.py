@@ -78,7 +78,7 @@ def test_mhd512_nonlinear_sampled(B, ref, dt, form):
 
 @pytest.mark.parametrize("case", [("mhd", 512, "f64", 0), ("mhd", 512, "f32", 0), ("mhd", 512, "f64", 1),
                                   ("mhd", 512, "f32", 1), ("ns", 1024, "f32", 0), ("ns", 1024, "f64", 0),
-                                  ("mhd", 1024, "f32", 1)])
+                                  ("mhd", 1024, "f32", 1), ("ns", 1024, "f32", 1)])
 def test_rk2_embedding(B, ref, case):
     model, N, dt, form = case
     say("embedding", model, N, dt, form)
@@ -99,8 +99,7 @@ def test_rk2_embedding(B, ref, case):
     z = sparse_to_dev(big, cdt)
     p = B.Plan(N, nf, dt)
     p.set_variant("prune", 1)
-    if model == "mhd":
-        p.set_variant("form", form)
+    p.set_variant("form", form)
     say("autotune", p.autotune(z, pm, 2))
     p.rk2_step(z, pm, nu, eta, dtime, steps)
     Kc = 4 * K  # support after two steps

@@ -74,14 +74,16 @@ def test_grid_fft(B, ref, n, dt):
     assert rel_l2(got, want) < TOL_FFT[dt], rel_l2(got, want)
 
 
+@pytest.mark.parametrize("form", [0, 1])
 @pytest.mark.parametrize("prune", [0, 1])
 @pytest.mark.parametrize("dt", ["f64", "f32"])
 @pytest.mark.parametrize("n", GRIDS_NL, ids=lambda n: "x".join(map(str, n)))
-def test_grid_nonlinear_ns(B, ref, n, dt, prune):
-    say("grid nonlinear ns", n, dt, prune)
+def test_grid_nonlinear_ns(B, ref, n, dt, prune, form):
+    say("grid nonlinear ns", n, dt, prune, form)
     u = rounded(synth.random_grid(*n, 7, 6.0), dt)
     p = B.Plan(nfields=3, dtype=dt, grid=n)
     p.set_variant("prune", prune)
+    p.set_variant("form", form)
     out = torch.full(u.shape, 1e30, dtype=CDT[dt], device=DEV)
     got = host(p.nonlinear_ns(to_dev(u, dt), out))
     want = ref.nonlinear_ns(u)
@@ -111,7 +113,7 @@ def boxed(ref):
     ref.set_box()
 
 
-@pytest.mark.parametrize("model,form", [("ns", 0), ("mhd", 0), ("mhd", 1)])
+@pytest.mark.parametrize("model,form", [("ns", 0), ("ns", 1), ("mhd", 0), ("mhd", 1)])
 @pytest.mark.parametrize("prune", [0, 1])
 @pytest.mark.parametrize("dt", ["f64", "f32"])
 def test_grid_rk2_rotation_box(B, boxed, dt, prune, model, form):
@@ -125,8 +127,7 @@ def test_grid_rk2_rotation_box(B, boxed, dt, prune, model, form):
     z0 = rounded(box_solenoidal(z0, BOX), dt)
     p = B.Plan(nfields=nf, dtype=dt, grid=n)
     p.set_variant("prune", prune)
-    if model == "mhd":
-        p.set_variant("form", form)
+    p.set_variant("form", form)
     p.set_box(*BOX)
     p.set_rotation(*OMEGA)
     s = to_dev(z0, dt)
@@ -166,7 +167,8 @@ def scatter(sf, n, cdt):
 
 
 @pytest.mark.parametrize("case", [("mhd", (256, 512, 384), "f32", 1), ("mhd", (512, 256, 256), "f64", 1),
-                                  ("ns", (384, 256, 512), "f32", 0), ("mhd", (256, 384, 512), "f32", 0)],
+                                  ("ns", (384, 256, 512), "f32", 0), ("mhd", (256, 384, 512), "f32", 0),
+                                  ("ns", (512, 384, 256), "f64", 1)],
                          ids=lambda c: f"{c[0]}-{'x'.join(map(str, c[1]))}-{c[2]}-form{c[3]}")
 def test_grid_embedding_autotuned(B, ref, case):
     """A field with modes |k| <= 4 takes one RK2 step (support |k| <= 16)
@@ -189,8 +191,7 @@ def test_grid_embedding_autotuned(B, ref, case):
     z = scatter(small, n, cdt)
     p = B.Plan(nfields=nf, dtype=dt, grid=n)
     p.set_variant("prune", 1)
-    if model == "mhd":
-        p.set_variant("form", form)
+    p.set_variant("form", form)
     p.set_rotation(*OMEGA)
     say("autotune", p.autotune(z, pm, 2))
     p.rk2_step(z, pm, nu, eta, 2e-3, 1)

@@ -60,14 +60,18 @@ def test_fft_c2r(B, ref, N, dt):
     assert np.array_equal(host(xd), X)  # input preserved
 
 
+@pytest.mark.parametrize("form", [0, 1])
 @pytest.mark.parametrize("prune", [0, 1])
 @pytest.mark.parametrize("dt", ["f64", "f32"])
 @pytest.mark.parametrize("N", [8, 16, 24, 32, 48, 64])
-def test_nonlinear_ns(B, ref, N, dt, prune):
-    say("nonlinear_ns", N, dt, prune)
+def test_nonlinear_ns(B, ref, N, dt, prune, form):
+    """form 1 (divergence form, products u_i u_j) against the oracle's
+    rotational form: equal up to rounding for solenoidal inputs."""
+    say("nonlinear_ns", N, dt, prune, form)
     u = rounded(synth.random_ns(N, 1000 + N, 2.0 if N < 32 else 3.0), dt)
     p = B.Plan(N, 3, dt)
     p.set_variant("prune", prune)
+    p.set_variant("form", form)
     out = torch.full(u.shape, 1e30, dtype=CDT[dt], device=DEV)
     got = host(p.nonlinear_ns(to_dev(u, dt), out))
     want = ref.nonlinear_ns(u)
@@ -92,14 +96,16 @@ def test_nonlinear_mhd(B, ref, N, dt, prune, form):
     assert rel_l2_w(got, want) < TOL_NL[dt], rel_l2_w(got, want)
 
 
+@pytest.mark.parametrize("form", [0, 1])
 @pytest.mark.parametrize("prune", [0, 1])
 @pytest.mark.parametrize("dt", ["f64", "f32"])
-def test_rk2_ns_32_one_step(B, ref, dt, prune):
+def test_rk2_ns_32_one_step(B, ref, dt, prune, form):
     """NS 32^3, nu = 0.02, dt = 1e-3, seed 1, k0 = 2, E = 0.5: one RK2 step."""
-    say("rk2 ns 32", dt, prune)
+    say("rk2 ns 32", dt, prune, form)
     u0 = rounded(synth.random_ns(32, 1, 2.0), dt)
     p = B.Plan(32, 3, dt)
     p.set_variant("prune", prune)
+    p.set_variant("form", form)
     s = to_dev(u0, dt)
     p.rk2_step(s, B.PS_NS, 0.02, 0.0, 1e-3, 1)
     got = host(s)
@@ -147,15 +153,17 @@ def test_spectrum(B, ref, N, dt):
 OMEGA = (1.5, -2.0, 3.0)
 
 
+@pytest.mark.parametrize("form", [0, 1])
 @pytest.mark.parametrize("prune", [0, 1])
 @pytest.mark.parametrize("dt", ["f64", "f32"])
-def test_rk2_ns_rotation(B, ref, dt, prune):
+def test_rk2_ns_rotation(B, ref, dt, prune, form):
     """Rotating frame: two RK2 steps of NS 32^3 with a Coriolis term strong
     enough to matter (|2 Omega| dt ~ 0.04) against the oracle."""
-    say("rk2 ns rotation", dt, prune)
+    say("rk2 ns rotation", dt, prune, form)
     u0 = rounded(synth.random_ns(32, 1, 2.0), dt)
     p = B.Plan(32, 3, dt)
     p.set_variant("prune", prune)
+    p.set_variant("form", form)
     p.set_rotation(*OMEGA)
     s = to_dev(u0, dt)
     p.rk2_step(s, B.PS_NS, 0.02, 0.0, 5e-3, 2)
@@ -250,14 +258,16 @@ def boxed(ref):
     ref.set_box()
 
 
+@pytest.mark.parametrize("form", [0, 1])
 @pytest.mark.parametrize("prune", [0, 1])
 @pytest.mark.parametrize("dt", ["f64", "f32"])
-def test_box_nonlinear_ns(B, boxed, dt, prune):
-    say("box nonlinear ns", dt, prune)
+def test_box_nonlinear_ns(B, boxed, dt, prune, form):
+    say("box nonlinear ns", dt, prune, form)
     N = 24
-    u = rounded(synth.random_ns(N, 41, 2.0), dt)
+    u = rounded(box_solenoidal(synth.random_ns(N, 41, 2.0), BOX), dt)
     p = B.Plan(N, 3, dt)
     p.set_variant("prune", prune)
+    p.set_variant("form", form)
     p.set_box(*BOX)
     got = host(p.nonlinear_ns(to_dev(u, dt)))
     assert rel_l2_w(got, boxed.nonlinear_ns(u)) < TOL_NL[dt]

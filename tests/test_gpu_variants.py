@@ -58,16 +58,18 @@ def test_fft_variants(B, ref, fft_case, kind, dt):
         assert e1 < TOL_FFT[dt] and e2 < TOL_FFT[dt], (kind, v, e1, e2)
 
 
+@pytest.mark.parametrize("form", [0, 1])
 @pytest.mark.parametrize("prune", [0, 1])
 @pytest.mark.parametrize("dt", ["f32", "f64"])
 @pytest.mark.parametrize("kind", ["y", "z_curl", "x_prod", "z_epi", "pipe"])
-def test_nonlinear_ns_variants(B, ns_case, kind, dt, prune):
+def test_nonlinear_ns_variants(B, ns_case, kind, dt, prune, form):
     u, want = ns_case[dt]
     p = B.Plan(N, 3, dt)
     p.set_variant("prune", prune)
+    p.set_variant("form", form)
     ud = to_dev(u, dt)
     for v in range(p.variant_count(kind)):
-        say("ns variant", kind, v, dt, prune)
+        say("ns variant", kind, v, dt, prune, form)
         p.set_variant(kind, v)
         e = rel_l2_w(host(p.nonlinear_ns(ud)), want)
         assert e < TOL_NL[dt], (kind, v, e)
