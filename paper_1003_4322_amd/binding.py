@@ -117,6 +117,8 @@ class Plan:
             if len(self.dims[0]) != 3:
                 raise ValueError("grid must be (nx, ny, nz)")
         else:
+            if N is None:
+                raise ValueError("Plan needs N (an int or a list) or grid=(nx, ny, nz)")
             sizes = [int(N)] if isinstance(N, int) else [int(n) for n in N]
             self.dims = [(n, n, n) for n in sizes]
         self.sizes = [d[0] for d in self.dims]
