@@ -262,6 +262,9 @@ struct Seq {
     const double full = (double)b.nz * b.ny * b.kx_keep, disk = (double)b.nz * b.n_disk;
     const double frac = (double)nz / b.nz;
     const double bytes = frac * (prune == 0 ? 2.0 * nfl * nb * b.nc * cs() : (double)nfl * nb * (full + disk) * cs());
+    // streaming stores once the written columns (every ky of the kept kx)
+    // exceed the 256 MB last-level cache
+    a.nt = (double)nfl * nb * nz * b.ny * (prune ? b.kx_keep : b.H) * cs() > 268435456.0;
     const int v = var_of(p, "y");
     return enqueue(p, s, dir == ps::FWD ? "y_fwd" : "y_inv", bytes,
                    [&](hipStream_t st) { return ps::launch_strided<T>(b.ny, dir, v, a, st); });
@@ -337,6 +340,9 @@ struct Seq {
     xa.in_bs = xa.out_bs = wk_bs();
     xa.rows = (long)nz * b.ny; xa.nf = nphys; xa.nb = nb;
     xa.kmax = p->prune ? (int)b.kx_keep - 1 : b.nx / 2;
+    // streaming stores once the product rows written exceed the 256 MB
+    // last-level cache
+    xa.nt = (double)nprod * nb * nz * b.ny * (xa.kmax + 1) * cs() > 268435456.0;
     const int v = var_of(p, "x_prod");
     const double per = (double)nz / b.nz * (p->prune ? (double)b.nz * b.ny * b.kx_keep : (double)b.nc);
     return enqueue(p, s, "x_prod", (double)(nphys + nprod) * nb * per * cs(),

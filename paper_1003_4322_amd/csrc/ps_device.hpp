@@ -45,6 +45,14 @@ __device__ __forceinline__ C2<T> mul_i(C2<T> a) { return C2<T>{-a.y, a.x}; }
 // c ? x : y on values
 template <typename T>
 __device__ __forceinline__ C2<T> sel(bool c, C2<T> x, C2<T> y) { return c ? x : y; }
+// streaming store (non-temporal hint): for outputs far larger than the caches
+// that the next pass reads back from HBM anyway
+template <typename T>
+__device__ __forceinline__ void store_nt(C2<T>* p, C2<T> v) {
+  typedef T V2 __attribute__((ext_vector_type(2)));
+  V2 w = {v.x, v.y};
+  __builtin_nontemporal_store(w, reinterpret_cast<V2*>(p));
+}
 template <typename T>
 __device__ __forceinline__ C2<T> mul_mi(C2<T> a) { return C2<T>{a.y, -a.x}; }
 template <typename T>

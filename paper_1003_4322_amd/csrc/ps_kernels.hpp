@@ -80,6 +80,7 @@ struct StridedArgs {
   // beyond the 2/3 rule are skipped.
   int prune;
   Grid g;
+  int nt;  // inverse passes: streaming stores (set when the output far exceeds the caches)
 };
 
 template <typename T, int L, int TQ, int TX, int DIR, class RL, int MINW = 1>
@@ -108,7 +109,16 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_strided(StridedArgs<T> a) {
 #pragma unroll
   for (int s = 0; s < E::LAST_NB * E::RL_; ++s) {
     const int idx = E::last_index(q, s);
-    if (ok && E::last_valid(q, s) && (a.prune != 2 || in_disk(idx))) out[idx * a.out_es] = v[s];
+    if (ok && E::last_valid(q, s) && (a.prune != 2 || in_disk(idx))) {
+      // inverse passes write whole columns that only the next pass reads:
+      // streaming stores when they far exceed the caches (measured faster
+      // there; slower for the forward pass's scattered disk outputs and for
+      // outputs the last-level cache can hold)
+      if (DIR == INV && a.nt)
+        store_nt(out + idx * a.out_es, v[s]);
+      else
+        out[idx * a.out_es] = v[s];
+    }
   }
 }
 
@@ -637,6 +647,7 @@ struct XArgs {
   long rows;         // rows per field (ny nz)
   int nf, nb;
   int kmax;  // fused passes: coefficients kx > kmax are zero on input and not needed on output
+  int nt;    // fused pass: streaming stores for the output (set when it far exceeds the caches)
 };
 
 // plain inverse: complex rows (pitch in_pitch) -> real rows (N reals, pitch out_pitch complex = M)
@@ -844,7 +855,13 @@ __global__ __launch_bounds__(xprod_slots(MHD, ELS) * RB * TQ) void k_x_prod(XArg
   __syncthreads();
   if (active && rok) {
     C2<T>* dst = a.out + boxi * a.out_bs + f * a.out_fs + rloc * a.out_pitch;
-    for (int k = q; k <= M && k <= a.kmax; k += TQ) dst[k] = r2c_post<T, RLay>(buf, k, M, twl);
+    for (int k = q; k <= M && k <= a.kmax; k += TQ) {
+      const C2<T> x = r2c_post<T, RLay>(buf, k, M, twl);
+      if (a.nt)
+        store_nt(dst + k, x);
+      else
+        dst[k] = x;
+    }
   }
 }
 
