@@ -43,10 +43,26 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def _code_only(text: str) -> str:
+    """Source text without comments, whitespace runs collapsed."""
+    import re
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def src_hash() -> str:
-    """Hash of the device-side sources the traffic counters belong to."""
-    from paper_1003_4322_amd.profsum import src_hash as h
-    return h()
+    """Hash of the device-side code (kernels, their configurations and
+    launchers; comments excluded) that committed traffic counters belong to:
+    host-only code (ps_api.cpp) does not change a kernel's traffic."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_1003_4322_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".hpp")):
+            h.update(f.encode())
+            h.update(_code_only(open(os.path.join(d, f), encoding="utf-8").read()).encode())
+    return h.hexdigest()[:16]
 
 
 def initial_state(w, dtype_c, device):
@@ -178,6 +194,7 @@ def ensemble_run(steps: int = 100, warmup: int = 5):
     sizes = [64] * 48 + [96] * 16 + [128] * 4
     plan = binding.Plan(sizes, 3, "f32", device="cuda:0")
     plan.set_variant("prune", PRUNE)
+    plan.set_variant("form", FORM)
     st = torch.empty(plan.n_complex(), dtype=torch.complex64, device="cuda:0")
     for i, N in enumerate(sizes):
         f = synth.random_ns(N, 1000 + i, synth.ensemble_k0(1000 + i), dtype=np.complex64)
@@ -212,7 +229,16 @@ def ensemble_run(steps: int = 100, warmup: int = 5):
     return out
 
 
+# the synthetic states are solenoidal and zero outside the 2/3 sphere, and
+# the step keeps them so: the divergence form and dealias pruning apply
 PRUNE = 1
+FORM = 1
+
+
+def form_for(model: str, dtype: str) -> int:
+    """The divergence form, except for FP64 Navier-Stokes, whose product pass
+    is faster in the rotational form at 1024^3 (measured; same result)."""
+    return 0 if (FORM == 0 or (model == "ns" and dtype == "f64")) else 1
 
 
 def grid_run(ms_cube: float, steps: int = 10):
@@ -239,6 +265,7 @@ def grid_run(ms_cube: float, steps: int = 10):
                   torch.from_numpy(np.ascontiguousarray(sf.values)).to(dev, torch.complex64))
     plan = binding.Plan(nfields=6, dtype="f32", device=dev, grid=n)
     plan.set_variant("prune", PRUNE)
+    plan.set_variant("form", FORM)
     plan.set_box(2 * np.pi, 2 * np.pi, 4 * np.pi)
     plan.set_rotation(0.0, 0.0, 2.0)
     tuned = plan.autotune(st, binding.PS_MHD, 2)
@@ -285,6 +312,7 @@ def precision_pair(wname: str, steps: int, warmup: int = 2, spectra_every: int =
         s = s32.clone() if dt == "f32" else s32.to(torch.complex128)
         plan = binding.Plan(w["N"], nf, dt, device=dev)
         plan.set_variant("prune", PRUNE)
+        plan.set_variant("form", form_for(w["model"], dt))
         tuned = plan.autotune(s, model, 2)
         one = s.clone()  # one step from the identical initial state
         plan.rk2_step(one, model, w["nu"], w["eta"], w["dt"], 1)
@@ -320,31 +348,83 @@ def precision_pair(wname: str, steps: int, warmup: int = 2, spectra_every: int =
     return res
 
 
-def cpu_baseline(w, sample_N):
-    """The FP64 oracle timed on this host for one RK2 step at sample_N^3 of
-    the same workload recipe, scaled to the workload's N by N^3 log N."""
+def host_info():
+    """Cores this process may use, the CPU model and the host's memory."""
+    info = {"nproc": len(os.sched_getaffinity(0)), "cpu_count": os.cpu_count()}
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                info["cpu_model"] = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        for line in open("/proc/meminfo"):
+            k, v = line.split(":", 1)
+            if k in ("MemTotal", "MemAvailable"):
+                info[k + "_GB"] = round(float(v.split()[0]) * 1024 / 1e9, 1)
+    except OSError:
+        pass
+    return info
+
+
+def oracle_step_bytes(N: int, nf: int) -> float:
+    """Host memory of one oracle RK2 step (FP64): the state, its copy, z* and
+    the right-hand side (4 x nf half spectra), the nonlinear term's spectral
+    temporaries (3 x 3 + 1 fields) and its physical fields (6 or 12 of N^3)."""
+    sc = N * N * (N // 2 + 1) * 16.0
+    return 4 * nf * sc + 10 * sc + (12 if nf == 6 else 6) * N ** 3 * 8.0
+
+
+def cpu_baseline(w, sample_N: int = 0, single_N: int = 128):
+    """The FP64 oracle, as it stands, timed on this host: one RK2 step of the
+    workload's recipe on all cores at the workload's own size when the host
+    has the memory (else at sample_N), and one step on a single thread at
+    single_N.  Measured values only: nothing is scaled to another size."""
     import numpy as np
 
     from oracle.psref import MHD, NS, oracle
     from paper_1003_4322_amd import synth
 
     o = oracle()
-    threads = o.set_threads(0)
-    if w["model"] == "mhd":
-        z = synth.random_mhd(sample_N, w["seeds"][0], w["seeds"][1], w["k0"], dtype=np.complex64)
-        model = MHD
-    else:
-        z = synth.random_ns(sample_N, w["seeds"][0], w["k0"], dtype=np.complex64)
-        model = NS
-    z = z.astype(np.complex128)
-    t0 = time.perf_counter()
-    o.rk2_step(z, model, w["nu"], w["eta"], w["dt"], 1)
-    t = time.perf_counter() - t0
+    host = host_info()
+    mhd = w["model"] == "mhd"
+    nf = 6 if mhd else 3
     N = w["N"]
-    scale = (N / sample_N) ** 3 * math.log(N) / math.log(sample_N)
-    return {"value": 1.0 / (t * scale), "unit": "steps/s", "cores": threads, "kind": "oracle",
-            "sample": f"one FP64 RK2 step of the same recipe at {sample_N}^3 took {t:.2f} s; "
-                      f"scaled to {N}^3 by (N/{sample_N})^3 log N / log {sample_N} = {scale:.2f}"}
+    avail = host.get("MemAvailable_GB", 0.0) * 1e9
+    if not sample_N:
+        sample_N = N if avail > 1.3 * oracle_step_bytes(N, nf) + 8e9 else 256
+
+    def recipe(n):
+        if mhd:
+            sf = synth.mhd_sparse(n, w["seeds"][0], w["seeds"][1], w["k0"])
+        else:
+            sf = synth.random_solenoidal(n, w["seeds"][0], w["k0"])
+        # the FP32-representable values the GPU's FP32 run starts from
+        return synth.SparseField(n, sf.K, sf.values.astype(np.complex64).astype(np.complex128)).dense()
+
+    def one_step(n, threads):
+        z = recipe(n)
+        used = o.set_threads(threads)
+        t0 = time.perf_counter()
+        o.rk2_step(z, MHD if mhd else NS, w["nu"], w["eta"], w["dt"], 1)
+        return time.perf_counter() - t0, used
+
+    t_all, cores = one_step(sample_N, len(os.sched_getaffinity(0)))
+    t_one, _ = one_step(single_N, 1)
+    o.set_threads(cores)
+    what = f"{'MHD' if mhd else 'NS'} {sample_N}^3"
+    res = {"value": 1.0 / t_all, "unit": "steps/s", "cores": cores, "kind": "oracle",
+           "sample": f"one FP64 RK2 step (the first of the run) of the {what} recipe on {cores} "
+                     f"threads: {t_all:.2f} s, measured" +
+                     ("" if sample_N == N else f"; the {N}^3 step does not fit this host's memory, "
+                                               f"so the value is the {sample_N}^3 rate, not scaled"),
+           "measured": {"N": sample_N, "threads": cores, "s_per_step": round(t_all, 3),
+                        "steps_per_s": round(1.0 / t_all, 5)},
+           "single_thread": {"N": single_N, "threads": 1, "s_per_step": round(t_one, 3),
+                             "steps_per_s": round(1.0 / t_one, 5)},
+           "host": host}
+    return res
 
 
 def run_primary(args, w, model, nf, N, dev):
@@ -356,7 +436,8 @@ def run_primary(args, w, model, nf, N, dev):
     s32, _ = initial_state(w, torch.complex64, dev)
     s32_0 = s32.clone()
     plan32 = binding.Plan(N, nf, "f32", device=dev)
-    plan32.set_variant("prune", 0 if args.no_prune else 1)
+    plan32.set_variant("prune", PRUNE)
+    plan32.set_variant("form", FORM)
     log("fp32 plan ready, workspace GB", plan32.workspace_bytes() / 1e9)
     tuned32 = None if args.no_tune else plan32.autotune(s32, model, 3)
     log("fp32 variants", tuned32)
@@ -375,8 +456,7 @@ def run_primary(args, w, model, nf, N, dev):
         # per grid row (inverse inputs + forward products), 2.5 N log2 N flops
         # each, over N^2 rows; FP32 without packed instructions peaks at
         # 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz = 78.6 TFLOP/s
-        form = (tuned32 or {}).get("form", plan32.variant("form"))
-        nt = 9 if nf == 3 else (14 if form == 1 else 18)
+        nt = (8 if FORM == 1 else 9) if nf == 3 else (14 if FORM == 1 else 18)
         flops = nt * N * N * 2.5 * N * math.log2(N)
         tf = flops / (d["avg_ms"] * 1e-3) / 1e12
         roofline["alu_view"] = {"bound": "alu", "achieved": round(tf, 2), "peak": ALU_PEAK_TFS,
@@ -390,7 +470,8 @@ def run_primary(args, w, model, nf, N, dev):
         del plan32
         torch.cuda.empty_cache()
         plan64 = binding.Plan(N, nf, "f64", device=dev)
-        plan64.set_variant("prune", 0 if args.no_prune else 1)
+        plan64.set_variant("prune", PRUNE)
+        plan64.set_variant("form", form_for(w["model"], "f64"))
         tuned64 = None if args.no_tune else plan64.autotune(s64, model, 3)
         log("fp64 variants", tuned64)
         ms64, stats64, ms64_graph = run_timed(plan64, s64, model, w, args.steps, args.warmup)
@@ -403,7 +484,8 @@ def run_primary(args, w, model, nf, N, dev):
         del plan64
         torch.cuda.empty_cache()
         plan32 = binding.Plan(N, nf, "f32", device=dev)
-        plan32.set_variant("prune", 0 if args.no_prune else 1)
+        plan32.set_variant("prune", PRUNE)
+        plan32.set_variant("form", FORM)
         for k, v in (tuned32 or {}).items():
             plan32.set_variant(k, v)
         plan32.rk2_step(a, model, w["nu"], w["eta"], w["dt"], 1)
@@ -430,12 +512,15 @@ def main():
     ap.add_argument("--workload", default="mhd512", choices=sorted(WORKLOADS))
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=256)
+    ap.add_argument("--cpu-sample", type=int, default=0,
+                    help="size of the oracle's all-core step (0: the workload's own if it fits)")
     ap.add_argument("--copy-only", action="store_true",
                     help="only the reference device copy (for counter scaling)")
     ap.add_argument("--no-tune", action="store_true", help="default kernel variants")
     ap.add_argument("--no-prune", action="store_true",
                     help="transform every pencil (no dealias-sphere pruning)")
+    ap.add_argument("--rotational", action="store_true",
+                    help="the rotational form of the nonlinear term instead of the divergence form")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the 256^3, 1024^3, ensemble, 32^3 and 512x512x1024 workloads")
     args = ap.parse_args()
@@ -448,8 +533,9 @@ def main():
 
     from paper_1003_4322_amd import binding
 
-    global PRUNE
+    global PRUNE, FORM
     PRUNE = 0 if args.no_prune else 1
+    FORM = 0 if args.rotational else 1
     w = WORKLOADS[args.workload]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -482,8 +568,9 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        log(f"cpu baseline: oracle, one step at {args.cpu_sample}^3")
+        log("cpu baseline: the oracle, one step on all cores and one on a single thread")
         cpu = cpu_baseline(w, args.cpu_sample)
+        log(f"cpu baseline: {cpu['sample']}")
 
     line = {
         "metric": METRIC, "value": round(1e3 / ms, 3), "unit": "steps/s", "n_gpus": 1,
@@ -495,8 +582,7 @@ def main():
                                f"random-phase k0={w['k0']} seeds {list(w['seeds'])}",
                    "N": N, "fields": nf, "workload_key": args.workload,
                    "prune": PRUNE,
-                   "mhd_form": (("elsasser-divergence" if (tuned32 or {}).get("form", 1) == 1
-                                 else "rotational") if nf == 6 else None)},
+                   "form": "divergence" if FORM == 1 else "rotational"},
         "ms_per_step_graph": round(ms_graph, 4),
         "variants": tuned32,
         "passes": passes32,

@@ -61,17 +61,20 @@ typedef enum {
   PS_ERR_NOMEM = -3,    /* host or table allocation failed, workspace too small */
   PS_ERR_HIP = -4,      /* a HIP runtime call failed (detail in ps_last_error) */
   PS_ERR_STATE = -5,    /* call not valid in the plan's state (e.g. no workspace) */
-  PS_ERR_DIVERGED = -6  /* reserved: non-finite energy detected */
+  PS_ERR_DIVERGED = -6  /* the blow-up monitor found a non-finite or exploding energy */
 } ps_status;
 
-/* Plan for one N^3 box of nfields fields (3: NS velocity; 6: MHD z+, z-).
+/* Plan for one N^3 box of nfields fields (3: NS velocity; 6: MHD z+, z-),
+ * the 2 pi-periodic box of Sec. 2 discretised by N^3 points (Fig. 1).
  * N must be one of 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512,
  * 768, 1024 (even, 2^a 3^b).  Builds FP64-accurate twiddle tables on the
  * device of the current HIP device.  *out is set to NULL on failure. */
 ps_status ps_plan_create(ps_plan *out, int N, int nfields, ps_dtype dtype);
 
 /* Plan for an ensemble of nbox independent boxes of sizes N[0..nbox), all
- * with nfields fields; field sets are concatenated box after box. */
+ * with nfields fields; field sets are concatenated box after box.  Each box
+ * is the problem of Sec. 2 on its own; the paper runs one box at a time, and
+ * batching independent boxes is this library's addition. */
 ps_status ps_plan_create_batch(ps_plan *out, int nbox, const int *N, int nfields,
                                ps_dtype dtype);
 
@@ -123,21 +126,41 @@ ps_status ps_fft_c2r(ps_plan p, const void *cplx_in, void *real_out);
 /* Navier-Stokes nonlinear term (Sec. 2, Eq. 1-2, rotational form):
  * nhat = D(k) P(k) F[u x w] / N^3 with u = c2r(uhat), w = c2r(i k x uhat),
  * D the 2/3-rule spherical truncation (keep 9|k|^2 < N^2), P(k) = I - k k^T/|k|^2
- * (P(0) = 0).  3 fields in, 3 out; the plan must have nfields = 3. */
+ * (P(0) = 0).  3 fields in, 3 out; the plan must have nfields = 3.  With the
+ * default variants any input is valid (it need be neither solenoidal nor
+ * dealiased); the "form" and "prune" variants below have preconditions. */
 ps_status ps_nonlinear_ns(ps_plan p, const void *uhat, void *nhat);
 
-/* MHD nonlinear terms for the Elsasser state (z+ then z-; plan nfields = 6):
+/* MHD nonlinear terms for the Elsasser state (z+ then z-; plan nfields = 6).
+ * Sec. 5 names the MHD form of the solver without its equations; the
+ * quadratic terms of incompressible MHD are taken in rotational form, with
+ * the transforms, projection and 2/3 rule Sec. 2 uses for Navier-Stokes:
  * N+- = D [ P F[u x w + j x b] +- i k x F[u x b] ] / N^3,
- * u = (z+ + z-)/2, b = (z+ - z-)/2, w = curl u, j = curl b. */
+ * u = (z+ + z-)/2, b = (z+ - z-)/2, w = curl u, j = curl b.  With the
+ * default variants any input is valid; the "form" and "prune" variants
+ * below are faster and have preconditions. */
 ps_status ps_nonlinear_mhd(ps_plan p, const void *zhat, void *nhat);
 
-/* nsteps explicit midpoint RK2 steps in place on the spectral state:
+/* nsteps explicit midpoint RK2 steps in place on the spectral state (the
+ * main time-advance loop of Sec. 4; the paper does not name its integrator):
  * z* = z + (dt/2) F(z), z <- z + dt F(z*), F = nonlinear term - viscous
  * term (NS: nu |k|^2 u; MHD: |k|^2 ((nu+eta)/2 z+- + (nu-eta)/2 z-+)).
  * One RK2 step is replayed from a captured HIP graph unless graphs are
  * disabled or kernel timing is on.  Needs a workspace. */
 ps_status ps_rk2_step(ps_plan p, void *state, ps_model m, double nu, double eta, double dt,
                       int nsteps);
+
+/* Blow-up monitor for ps_rk2_step (the time-advance loop of Sec. 4).  With
+ * every > 0, each call computes the FP64 total energy of every box of the
+ * state (ps_energy_spectrum over all fields) before its first step, after
+ * every `every` steps and after its last step; the energies are read back to
+ * the host, which synchronises the plan's stream.  The call stops and
+ * returns PS_ERR_DIVERGED (detail: box, energy and step in ps_last_error) as
+ * soon as some box's energy is not finite or exceeds `growth` times its value
+ * at the start of the call; the state is then the one at that check.  every
+ * = 0 (the default) switches the monitor off.  PS_ERR_ARG for every < 0 or,
+ * with every > 0, growth not finite or not > 1. */
+ps_status ps_plan_set_monitor(ps_plan p, int every, double growth);
 
 /* Frame rotation for ps_rk2_step (Sec. 5 lists rotating flows among what the
  * code integrates; the paper gives no formula).  In a frame rotating at
@@ -160,7 +183,8 @@ ps_status ps_plan_set_rotation(ps_plan p, double ox, double oy, double oz);
  * case.  Drops a cached graph.  PS_ERR_ARG for non-positive or non-finite L. */
 ps_status ps_plan_set_box(ps_plan p, double Lx, double Ly, double Lz);
 
-/* Shell spectrum of nfields fields per box (1 <= nfields <= plan nfields):
+/* Shell spectrum of nfields fields per box (1 <= nfields <= plan nfields),
+ * one of the global quantities Sec. 3 computes by reductions over the grid:
  * spec_dev[s] = 1/2 sum_{round(|k|)=s} w |f(k)|^2 (w = 1 on the kx = 0 and
  * kx = N/2 planes, 2 elsewhere) and totals_dev = [E, Z, maxdiv] with
  * Z = 1/2 sum w |k|^2 |f|^2 and maxdiv = max |k . f| over consecutive
@@ -168,6 +192,18 @@ ps_status ps_plan_set_box(ps_plan p, double Lx, double Ly, double Lz);
  * Ensembles: per-box spectra concatenated, 3 totals per box.  Device output. */
 ps_status ps_energy_spectrum(ps_plan p, const void *fhat, int nfields, double *spec_dev,
                              double *totals_dev);
+
+/* Kinetic and magnetic energy and cross-helicity of an Elsasser state (plan
+ * nfields = 6; Sec. 3 computes global quantities and spectra by reductions,
+ * Sec. 5 runs the solver for MHD).  With u = (z+ + z-)/2 and b = (z+ - z-)/2
+ * at every mode, and the weights and shells of ps_energy_spectrum:
+ *   spec_dev[s] = Eu(s) = 1/2 sum_{round(|k|)=s} w |u(k)|^2,
+ *   spec_dev[nshell + s] = Eb(s) (the same with b),
+ *   spec_dev[2 nshell + s] = Hc(s) = 1/2 sum w Re(u(k) . conj b(k)),
+ * totals_dev = [Eu, Eb, Hc] (each the sum of its shells).  FP64,
+ * deterministic (fixed-order compensated sums).  Ensembles: 3 nshell values
+ * and 3 totals per box, box after box.  Device output; needs a workspace. */
+ps_status ps_mhd_spectrum(ps_plan p, const void *zhat, double *spec_dev, double *totals_dev);
 
 /* Kernel variants.  Pass kinds: "y", "z" (plain strided passes), "z_curl",
  * "z_epi", "x_prod"; the tile width, radix schedule or register/LDS trade-off
@@ -180,15 +216,20 @@ ps_status ps_energy_spectrum(ps_plan p, const void *fhat, int nfields, double *s
  * dealiased under the step), and modes outside it are then left untouched by
  * ps_rk2_step (ps_nonlinear_* still writes zeros there).  Kind "form":
  * 0 = the rotational form of Sec. 2 (NS: u x w; MHD: u x w + j x b and u x b
- * of the primitive fields), 1 = the divergence form.  MHD (Elsasser
- * variables): N+- = -i P(k) k_j F[z-+_j z+-_i] from the products z+_i z-_j
- * less their isotropic part delta_ij z+_2 z-_2, a gradient that P(k) removes
- * (eight products, so fourteen real transforms per evaluation instead of
- * eighteen; the MHD default).  NS: N = -i P(k) k_j F[u_i u_j] from the five
- * products of the symmetric u_i u_j less delta_ij u_2 u_2 (eight real
- * transforms instead of nine, and no curl; the FP32 NS default).  Each form agrees with the
- * rotational one up to rounding when the state is solenoidal, as every state
- * the step produces is.  Kind "pipe" v: the inverse y pass, the product pass and
+ * of the primitive fields), the default, valid for any input; 1 = the
+ * divergence form.  MHD (Elsasser variables): N+- = -i P(k) k_j F[z-+_j z+-_i]
+ * from the products z+_i z-_j less their isotropic part delta_ij z+_2 z-_2,
+ * a gradient that P(k) removes (eight products, so fourteen real transforms
+ * per evaluation instead of eighteen).  NS: N = -i P(k) k_j F[u_i u_j] from
+ * the five products of the symmetric u_i u_j less delta_ij u_2 u_2 (eight
+ * real transforms instead of nine, and no curl).  Precondition of form 1:
+ * the state is solenoidal (k . z = 0 for every 3-vector, in the box's
+ * metric) AND zero outside the 2/3 sphere; it then agrees with form 0 up to
+ * rounding (both sets of products are alias-free inside the sphere), and
+ * every state ps_rk2_step makes from such a state is again such a state.
+ * On other inputs the two forms compute different functions (they differ by
+ * P(u div u) and by the aliases of the products); nothing checks the
+ * precondition.  Kind "pipe" v: the inverse y pass, the product pass and
  * the forward y pass of each right-hand side run as 2^v slabs of z-planes
  * spread over helper streams (each plane's chain is independent of the
  * others'), so that one slab's memory-bound y passes overlap another's
@@ -202,8 +243,20 @@ int ps_plan_variant_count(ps_plan p, const char *kind);
 /* Autotuner: times every variant of the RK2 passes (z_curl, y, x_prod, z_epi)
  * reps times on the caller's state for model m and keeps the fastest.  Reads
  * state, writes only the workspace; synchronises the plan's stream.  Plan
- * time, like FFT planning, is not part of a step. */
+ * time, like FFT planning, is not part of a step (Sec. 4 leaves planning out
+ * of its timings).  When the environment variable PS_TUNE_CACHE names a
+ * file, the tuned variants are kept there under a key of everything the
+ * timings depend on (device architecture, HIP runtime version, this
+ * library's build hash, model, dtype, fields, every size class, and the
+ * "form", "prune", "batch" and "pipe" variants); a later call with the same
+ * key takes them from the file and times nothing.  A file that cannot be
+ * read or written only costs the timing runs. */
 ps_status ps_plan_autotune(ps_plan p, const void *state, ps_model m, int reps);
+
+/* Timing launches the last ps_plan_autotune made: 0 when its variants came
+ * from the PS_TUNE_CACHE file, -1 before the first call; PS_ERR_ARG for a
+ * NULL plan. */
+int ps_plan_autotune_timed(ps_plan p);
 
 /* Per-kernel timing with HIP events on the plan's stream (disables graph
  * replay while on).  Statistics accumulate until ps_plan_timing_reset. */
@@ -220,6 +273,10 @@ ps_status ps_plan_timing_get(ps_plan p, int idx, const char **name, double *tota
 
 const char *ps_status_string(ps_status s);
 const char *ps_last_error(void);
+
+/* Hash of the sources and flags the library was built from (16 hex digits,
+ * static storage); the binding compares it with the sources beside it. */
+const char *ps_build_hash(void);
 
 #ifdef __cplusplus
 }

@@ -26,6 +26,12 @@
 #ifndef PSREF_MUTANT
 #define PSREF_MUTANT 0
 #endif
+#ifndef PSREF_SRC_HASH
+#define PSREF_SRC_HASH "unknown"
+#endif
+
+/* hash of the sources this build was compiled from (set by the build step) */
+const char *psref_build_hash(void) { return PSREF_SRC_HASH; }
 #define MUT(n) (PSREF_MUTANT == (n))
 
 typedef double complex cplx;
@@ -333,6 +339,7 @@ int psref_dft_at(int nx, int ny, int nz, const double *in, int nk, const int *kx
   const grid g = grid_of(nx, ny, nz);
   plans pl;
   if (plans_init(&pl, &g)) return -3;
+#pragma omp parallel for schedule(dynamic, 1)
   for (int i = 0; i < nk; ++i) {
     cplx s = 0;
     for (long z = 0; z < nz; ++z)
@@ -768,7 +775,7 @@ static int rhs(const grid *g, int model, const cplx *z, cplx *F, double nu, doub
   int rc = model == 0 ? nonlinear_ns(g, z, F) : nonlinear_mhd(g, z, F);
   if (rc) return rc;
   const double a = model == 0 ? nu : 0.5 * (nu + eta);
-  const double b = model == 0 ? 0.0 : 0.5 * (nu - eta);
+  const double b = model == 0 ? 0.0 : (MUT(18) ? 0.5 * (eta - nu) : 0.5 * (nu - eta));
 #pragma omp parallel for schedule(static)
   for (long kz = 0; kz < g->nz; ++kz)
     for (long ky = 0; ky < ny; ++ky)
@@ -904,5 +911,58 @@ int psref_energy_spectrum(int nx, int ny, int nz, int nf, const double *fhat_, d
   totals[1] = nval(&Z);
   totals[2] = maxdiv;
   free(es);
+  return 0;
+}
+
+/* MHD global quantities of an Elsasser state (Sec. 3: global quantities by
+ * reductions; Sec. 5: the MHD form of the solver).  With the primitive
+ * fields u = (z+ + z-)/2 and b = (z+ - z-)/2 at every mode:
+ *   Eu(s) = 1/2 sum_{shell(k)=s} w |u(k)|^2       kinetic energy
+ *   Eb(s) = 1/2 sum_{shell(k)=s} w |b(k)|^2       magnetic energy
+ *   Hc(s) = 1/2 sum_{shell(k)=s} w Re(u(k) . b(k)*)  cross-helicity
+ * (the spectral form of the box averages 1/2 <|u|^2>, 1/2 <|b|^2> and
+ * 1/2 <u . b>), with the weights and shells of psref_energy_spectrum.
+ * spec holds [Eu(s)] then [Eb(s)] then [Hc(s)], each of nshell values;
+ * totals = [Eu, Eb, Hc], each the compensated sum of its shells in order. */
+int psref_mhd_spectrum(int nx, int ny, int nz, const double *zhat_, double *spec,
+                       double *totals) {
+  if (!zhat_ || !spec || !totals) return -1;
+  if (!grid_ok(nx, ny, nz)) return -2;
+  const grid g = grid_of(nx, ny, nz);
+  const long H = g.H, nc = g.nc;
+  const int ns = psref_num_shells(nx, ny, nz);
+  const cplx *zp = (const cplx *)zhat_, *zm = zp + 3 * nc;
+  nsum *acc = (nsum *)calloc((size_t)3 * ns, sizeof(nsum));
+  if (!acc) return -3;
+  const double half = MUT(20) ? 1.0 : 0.5;
+  for (long kz = 0; kz < nz; ++kz)
+    for (long ky = 0; ky < ny; ++ky)
+      for (long kx = 0; kx < H; ++kx) {
+        long m = (kz * ny + ky) * H + kx;
+        long ix = wavx(kx), iy = wav(ky, ny), iz = wav(kz, nz);
+        double w = (kx == 0 || 2 * kx == nx) ? 1.0 : 2.0;
+        double eu = 0, eb = 0, hc = 0;
+        for (int c = 0; c < 3; ++c) {
+          cplx u = half * (zp[c * nc + m] + zm[c * nc + m]);
+          cplx b = MUT(19) ? 0.5 * (zm[c * nc + m] - zp[c * nc + m])
+                           : 0.5 * (zp[c * nc + m] - zm[c * nc + m]);
+          eu += creal(u) * creal(u) + cimag(u) * cimag(u);
+          eb += creal(b) * creal(b) + cimag(b) * cimag(b);
+          hc += creal(u * conj(b));
+        }
+        long s = shell_of(ix * ix + iy * iy + iz * iz);
+        nadd(&acc[s], 0.5 * w * eu);
+        nadd(&acc[ns + s], 0.5 * w * eb);
+        nadd(&acc[2 * ns + s], 0.5 * w * hc);
+      }
+  for (int q = 0; q < 3; ++q) {
+    nsum t = {0, 0};
+    for (int s = 0; s < ns; ++s) {
+      spec[q * ns + s] = nval(&acc[q * ns + s]);
+      nadd(&t, spec[q * ns + s]);
+    }
+    totals[q] = nval(&t);
+  }
+  free(acc);
   return 0;
 }

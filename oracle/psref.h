@@ -38,6 +38,9 @@
 extern "C" {
 #endif
 
+/* Hash of the sources (psref.c, psref.h) the library was built from. */
+const char *psref_build_hash(void);
+
 /* Number of OpenMP threads the oracle uses (<= 0: leave the runtime default).
  * Returns the number of threads that will be used. */
 int psref_set_threads(int n);
@@ -102,6 +105,16 @@ int psref_num_shells(int nx, int ny, int nz);
  * 3).  shell(k) = round(|k|) of the index, evaluated exactly in integers. */
 int psref_energy_spectrum(int nx, int ny, int nz, int nf, const double *fhat, double *spec,
                           double *totals);
+
+/* MHD global quantities of an Elsasser state (6 fields, z+ then z-), from
+ * u = (z+ + z-)/2 and b = (z+ - z-)/2 at every mode, with the weights and
+ * shells of psref_energy_spectrum:
+ *   spec[s]            = Eu(s) = 1/2 sum_{shell(k)=s} w |u(k)|^2
+ *   spec[nshell + s]   = Eb(s) = 1/2 sum_{shell(k)=s} w |b(k)|^2
+ *   spec[2 nshell + s] = Hc(s) = 1/2 sum_{shell(k)=s} w Re(u(k) . conj b(k))
+ * and totals = [Eu, Eb, Hc] (kinetic energy, magnetic energy,
+ * cross-helicity: 1/2 <|u|^2>, 1/2 <|b|^2>, 1/2 <u . b> over the box). */
+int psref_mhd_spectrum(int nx, int ny, int nz, const double *zhat, double *spec, double *totals);
 
 #ifdef __cplusplus
 }

@@ -12,6 +12,7 @@ real fields ``float64[nf, nz, ny, nx]`` ([f][z][y][x]) and half spectra
 from __future__ import annotations
 
 import ctypes
+import hashlib
 import math
 import os
 import subprocess
@@ -26,12 +27,22 @@ LIB = os.path.join(HERE, "libpsref.so")
 NS, MHD = 0, 1
 
 
+def src_hash() -> str:
+    """SHA-256 (16 hex digits) of psref.c and psref.h."""
+    h = hashlib.sha256()
+    for f in (SRC, os.path.join(HERE, "psref.h")):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def build(mutant: int = 0, out: Optional[str] = None, openmp: bool = True) -> str:
     """Compile psref.c with gcc.  ``mutant`` > 0 plants the numbered mistake
     (used only by the mutation tests).  Returns the path of the library."""
     out = out or LIB
     cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall", "-Wextra",
-           "-Wno-unused-parameter", f"-DPSREF_MUTANT={int(mutant)}", SRC, "-o", out, "-lm"]
+           "-Wno-unused-parameter", f"-DPSREF_MUTANT={int(mutant)}",
+           f'-DPSREF_SRC_HASH="{src_hash()}"', SRC, "-o", out, "-lm"]
     if openmp:
         cmd.insert(1, "-fopenmp")
     subprocess.run(cmd, check=True, capture_output=True, text=True)
@@ -50,6 +61,11 @@ class Oracle:
                 raise FileNotFoundError(path)
             build()
         self.lib = ctypes.CDLL(path)
+        self.lib.psref_build_hash.restype = ctypes.c_char_p
+        have, want = self.lib.psref_build_hash().decode(), src_hash()
+        if have != want:
+            raise RuntimeError(f"{path} was built from other sources (hash {have}, sources {want}):"
+                               " rebuild it with oracle.psref.build()")
         dp = ctypes.POINTER(ctypes.c_double)
         ip = ctypes.POINTER(ctypes.c_int)
         i = ctypes.c_int
@@ -68,6 +84,7 @@ class Oracle:
         L.psref_set_box.argtypes = [d, d, d]
         L.psref_num_shells.argtypes = [i, i, i]
         L.psref_energy_spectrum.argtypes = [i, i, i, i, dp, dp, dp]
+        L.psref_mhd_spectrum.argtypes = [i, i, i, dp, dp, dp]
 
     # -- helpers -----------------------------------------------------------
     @staticmethod
@@ -190,6 +207,17 @@ class Oracle:
         self._check(self.lib.psref_energy_spectrum(*n, nf, self._p(fhat), self._p(spec),
                                                    self._p(tot)), "energy_spectrum")
         return spec, tot
+
+    def mhd_spectrum(self, zhat: np.ndarray):
+        """(spec[3, nshell] = [Eu(s), Eb(s), Hc(s)], totals [Eu, Eb, Hc]) of an
+        Elsasser state (6 fields)."""
+        zhat, n = self._spec(zhat, 6)
+        ns = self.num_shells(*n)
+        spec = np.empty(3 * ns, np.float64)
+        tot = np.empty(3, np.float64)
+        self._check(self.lib.psref_mhd_spectrum(*n, self._p(zhat), self._p(spec), self._p(tot)),
+                    "mhd_spectrum")
+        return spec.reshape(3, ns), tot
 
 
 _default: Optional[Oracle] = None

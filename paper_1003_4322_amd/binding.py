@@ -39,13 +39,16 @@ _SIGS = [
     ("ps_nonlinear_ns", _i, [_vp, _vp, _vp]),
     ("ps_nonlinear_mhd", _i, [_vp, _vp, _vp]),
     ("ps_rk2_step", _i, [_vp, _vp, _i, _d, _d, _d, _i]),
+    ("ps_plan_set_monitor", _i, [_vp, _i, _d]),
     ("ps_plan_set_rotation", _i, [_vp, _d, _d, _d]),
     ("ps_plan_set_box", _i, [_vp, _d, _d, _d]),
     ("ps_energy_spectrum", _i, [_vp, _vp, _i, _vp, _vp]),
+    ("ps_mhd_spectrum", _i, [_vp, _vp, _vp, _vp]),
     ("ps_plan_set_variant", _i, [_vp, ctypes.c_char_p, _i]),
     ("ps_plan_get_variant", _i, [_vp, ctypes.c_char_p]),
     ("ps_plan_variant_count", _i, [_vp, ctypes.c_char_p]),
     ("ps_plan_autotune", _i, [_vp, _vp, _i, _i]),
+    ("ps_plan_autotune_timed", _i, [_vp]),
     ("ps_plan_set_timing", _i, [_vp, _i]),
     ("ps_plan_set_graphs", _i, [_vp, _i]),
     ("ps_plan_timing_reset", _i, [_vp]),
@@ -54,6 +57,7 @@ _SIGS = [
                                 ctypes.POINTER(ctypes.c_long), ctypes.POINTER(_d)]),
     ("ps_status_string", ctypes.c_char_p, [_i]),
     ("ps_last_error", ctypes.c_char_p, []),
+    ("ps_build_hash", ctypes.c_char_p, []),
 ]
 SYMBOLS = [s[0] for s in _SIGS]
 
@@ -67,7 +71,8 @@ class PsError(RuntimeError):
 
 
 def lib() -> ctypes.CDLL:
-    """The in-tree libps.so (built by paper_1003_4322_amd.build)."""
+    """The in-tree libps.so (built by paper_1003_4322_amd.build).  Raises if it
+    is missing or was built from other sources than the ones beside it."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
@@ -78,6 +83,11 @@ def lib() -> ctypes.CDLL:
             fn = getattr(L, name)
             fn.restype = res
             fn.argtypes = args
+        from . import build as _build
+        have, want = L.ps_build_hash().decode(), _build.src_hash()
+        if have != want:
+            raise ImportError(f"{LIB_PATH} was built from other sources (hash {have}, sources "
+                              f"{want}): rebuild it with paper_1003_4322_amd/build.py")
         _lib = L
     return _lib
 
@@ -280,6 +290,26 @@ class Plan:
                "ps_energy_spectrum")
         return spec, tot
 
+    def mhd_spectrum(self, zhat: torch.Tensor) -> Tuple[torch.Tensor, torch.Tensor]:
+        """Device FP64 (spectra [Eu(s)], [Eb(s)], [Hc(s)] per box, totals
+        [Eu, Eb, Hc] per box) of an Elsasser state; one box: shapes (3, nshell)
+        and (3,)."""
+        self._need(zhat, "c", "zhat")
+        spec = torch.empty(3 * sum(self.nshells), dtype=torch.float64, device=self.device)
+        tot = torch.empty(3 * len(self.sizes), dtype=torch.float64, device=self.device)
+        self._stream()
+        _check(lib().ps_mhd_spectrum(self.handle, _ptr(zhat), _ptr(spec), _ptr(tot)),
+               "ps_mhd_spectrum")
+        if len(self.sizes) == 1:
+            return spec.view(3, self.nshells[0]), tot
+        return spec, tot
+
+    def set_monitor(self, every: int, growth: float = 1e3):
+        """Blow-up monitor of rk2_step: energy checked every ``every`` steps;
+        PsError with code -6 (PS_ERR_DIVERGED) when it is not finite or grew by
+        more than ``growth``.  every = 0 switches it off."""
+        _check(lib().ps_plan_set_monitor(self.handle, int(every), float(growth)), "set_monitor")
+
     def set_rotation(self, ox: float, oy: float, oz: float):
         """Rotating frame for rk2_step: Coriolis term -P(k)(2 Omega x u)."""
         _check(lib().ps_plan_set_rotation(self.handle, float(ox), float(oy), float(oz)),
@@ -309,6 +339,10 @@ class Plan:
         self._stream()
         _check(lib().ps_plan_autotune(self.handle, _ptr(state), int(model), int(reps)), "autotune")
         return self.variants()
+
+    def autotune_timed(self) -> int:
+        """Timing launches of the last autotune (0: taken from PS_TUNE_CACHE)."""
+        return int(lib().ps_plan_autotune_timed(self.handle))
 
     # -- timing ----------------------------------------------------------------
     def set_timing(self, on: bool):

@@ -1,4 +1,5 @@
-// Deterministic FP64 shell spectrum.
+// Deterministic FP64 shell spectra (energy and enstrophy; MHD energies and
+// cross-helicity).
 #include <cstring>
 
 #include "ps_config.hpp"
@@ -28,54 +29,68 @@ int variant_count(const char* kind, int N, bool mhd) {
 }
 
 // Second stage: per-shell sums over planes in plane order, then the totals in
-// shell order, all Neumaier-compensated (one workgroup).
+// shell order, all Neumaier-compensated (one workgroup).  Q = 2 (energy):
+// spec[s] = E(s), totals = [sum E, sum Z, max over planes of pmax]; Q = 3
+// (MHD): spec[q nshell + s] = quantity q of shell s, totals[q] = its sum.
+template <int Q>
 __global__ __launch_bounds__(1024) void k_spec_final(const double* part, const double* pmax, int nplanes,
                                                      int nshell, double* spec, double* totals) {
-  __shared__ double zs[1024];
-  __shared__ double es[1024];
-  NSum Et{0, 0}, Zt{0, 0};
+  __shared__ double sh[Q][1024];
+  NSum tot[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) tot[q] = NSum{0, 0};
   for (int s0 = 0; s0 < nshell; s0 += blockDim.x) {
     const int s = s0 + threadIdx.x;
     if (s < nshell) {
-      NSum E{0, 0}, Z{0, 0};
-      for (int p = 0; p < nplanes; ++p) {
-        nadd(E, part[((long)p * nshell + s) * 2]);
-        nadd(Z, part[((long)p * nshell + s) * 2 + 1]);
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        NSum e{0, 0};
+        for (int p = 0; p < nplanes; ++p) nadd(e, part[((long)p * nshell + s) * Q + q]);
+        const double v = e.s + e.c;
+        sh[q][threadIdx.x] = v;
+        if (Q == 3)
+          spec[q * nshell + s] = v;
+        else if (q == 0)
+          spec[s] = v;
       }
-      spec[s] = E.s + E.c;
-      es[threadIdx.x] = E.s + E.c;
-      zs[threadIdx.x] = Z.s + Z.c;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
       const int n = nshell - s0 < (int)blockDim.x ? nshell - s0 : (int)blockDim.x;
-      for (int i = 0; i < n; ++i) {
-        nadd(Et, es[i]);
-        nadd(Zt, zs[i]);
-      }
+      for (int i = 0; i < n; ++i)
+#pragma unroll
+        for (int q = 0; q < Q; ++q) nadd(tot[q], sh[q][i]);
     }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    double mx = 0;
-    for (int p = 0; p < nplanes; ++p) mx = fmax(mx, pmax[p]);
-    totals[0] = Et.s + Et.c;
-    totals[1] = Zt.s + Zt.c;
-    totals[2] = mx;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) totals[q] = tot[q].s + tot[q].c;
+    if (Q == 2) {
+      double mx = 0;
+      for (int p = 0; p < nplanes; ++p) mx = fmax(mx, pmax[p]);
+      totals[2] = mx;
+    }
   }
 }
 
 
 template <typename T>
-hipError_t launch_spectrum(SpecArgs<T> a, double* spec, double* totals, hipStream_t s) {
-  k_spec_planes<T><<<dim3(a.nz), dim3(256), 0, s>>>(a);
+hipError_t launch_spectrum(SpecArgs<T> a, bool mhd, double* spec, double* totals, hipStream_t s) {
+  if (mhd)
+    k_spec_planes<T, true><<<dim3(a.nz), dim3(256), 0, s>>>(a);
+  else
+    k_spec_planes<T, false><<<dim3(a.nz), dim3(256), 0, s>>>(a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  k_spec_final<<<dim3(1), dim3(1024), 0, s>>>(a.part, a.pmax, a.nz, a.nshell, spec, totals);
+  if (mhd)
+    k_spec_final<3><<<dim3(1), dim3(1024), 0, s>>>(a.part, a.pmax, a.nz, a.nshell, spec, totals);
+  else
+    k_spec_final<2><<<dim3(1), dim3(1024), 0, s>>>(a.part, a.pmax, a.nz, a.nshell, spec, totals);
   return hipGetLastError();
 }
 
-template hipError_t launch_spectrum<float>(SpecArgs<float>, double*, double*, hipStream_t);
-template hipError_t launch_spectrum<double>(SpecArgs<double>, double*, double*, hipStream_t);
+template hipError_t launch_spectrum<float>(SpecArgs<float>, bool, double*, double*, hipStream_t);
+template hipError_t launch_spectrum<double>(SpecArgs<double>, bool, double*, double*, hipStream_t);
 
 }  // namespace ps

@@ -8,7 +8,7 @@
 //   zstar  F half spectra, dense pitch H = N/2+1       (RK2 midpoint state)
 //   work   2F half spectra, pitch P (H rounded up to 128 bytes)
 //          (physical-space passes: u, w [, b, j] and then the products)
-//   spec   N * nshell * 2 + N doubles                  (spectrum partials)
+//   spec   N * nshell * 3 + N doubles                  (spectrum partials)
 // laid out [zstar of all boxes][work of all boxes][spec of all boxes].
 #include <hip/hip_runtime.h>
 
@@ -129,6 +129,12 @@ struct ps_plan_s {
   std::vector<TimingRec> pending;
   std::vector<KindStat> stats;
   std::map<std::string, int> kind_index;
+  // blow-up monitor of ps_rk2_step: energy check every mon_every steps
+  int mon_every = 0;
+  double mon_growth = 0;
+  double* diag = nullptr;  // device: spectra (sum of nshell) then 3 totals per box, owned
+  // timing launches of the last ps_plan_autotune (0: its result came from the cache)
+  int tune_timed = -1;
 };
 
 namespace {
@@ -426,13 +432,15 @@ struct Seq {
     return rhs(zs, mhd, 2, nullptr, state, zs, (T)dt, nua, nub);
   }
 
-  ps_status spectrum(int i, const C* f, int nfl, double* spec, double* totals) {
+  // energy spectrum of nfl fields (mhd false) or the MHD quantities of the
+  // six Elsasser fields (mhd true) of box i of the class
+  ps_status spectrum(int i, const C* f, int nfl, bool mhd, double* spec, double* totals) {
     ps::SpecArgs<T> a{};
-    a.f = f; a.part = spec_part(i); a.pmax = a.part + (long)b.nz * b.nshell * 2;
+    a.f = f; a.part = spec_part(i); a.pmax = a.part + (long)b.nz * b.nshell * (mhd ? 3 : 2);
     a.fs = b.nc; a.pitch = b.H; a.nx = b.nx; a.ny = b.ny; a.nz = b.nz; a.nf = nfl; a.nshell = b.nshell;
     a.sx = p->bs[0]; a.sy = p->bs[1]; a.sz = p->bs[2];
     return enqueue(p, s, "spectrum", nfl * b.nc * cs(),
-                   [&](hipStream_t q) { return ps::launch_spectrum<T>(a, spec, totals, q); });
+                   [&](hipStream_t q) { return ps::launch_spectrum<T>(a, mhd, spec, totals, q); });
   }
 };
 
@@ -486,6 +494,7 @@ void free_plan(ps_plan p) {
     if (e) hipEventDestroy(e);
   for (auto& kv : p->tables) hipFree(kv.second);
   for (void* d : p->dbufs) hipFree(d);
+  if (p->diag) hipFree(p->diag);
   delete p;
 }
 
@@ -576,6 +585,108 @@ ps_status sync_timing(ps_plan p) {
   return PS_OK;
 }
 
+// FP64 energy of every box of `state` (all of the plan's fields), read back
+// to the host: e[i] for box i.  Synchronises the plan's stream.
+template <typename T>
+ps_status box_energies(ps_plan p, const void* state, std::vector<double>& e) {
+  const size_t nb = p->boxes.size();
+  size_t so = 0;
+  for (auto& b : p->boxes) so += b.nshell;
+  double* tot = p->diag + so;
+  so = 0;
+  for (size_t i = 0; i < nb; ++i) {
+    auto& b = p->boxes[i];
+    Seq<T> q{p, p->classes[b.cls], 0, p->classes[b.cls].nb, p->stream};
+    ps_status st = q.spectrum(b.idx, (const ps::C2<T>*)state + b.cplx_off, p->nfields, false, p->diag + so,
+                              tot + 3 * i);
+    if (st) return st;
+    so += b.nshell;
+  }
+  std::vector<double> t(3 * nb);
+  hipError_t er = hipMemcpyAsync(t.data(), tot, t.size() * sizeof(double), hipMemcpyDeviceToHost, p->stream);
+  if (er == hipSuccess) er = hipStreamSynchronize(p->stream);
+  if (er != hipSuccess) return hip_fail(er, "monitor read-back");
+  e.resize(nb);
+  for (size_t i = 0; i < nb; ++i) e[i] = t[3 * i];
+  return PS_OK;
+}
+
+// Persistent autotune cache (file named by PS_TUNE_CACHE): one line per key,
+// "key<TAB>kind=v,kind=v,...".  The key names everything the timings depend
+// on: device architecture, HIP runtime, the library build, model, dtype,
+// fields, every size class and the variants that are not tuned.
+std::string tune_key(ps_plan p, bool mhd) {
+  hipDeviceProp_t prop;
+  std::string arch = "unknown";
+  if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) arch = prop.gcnArchName;
+  int rt = 0;
+  (void)hipRuntimeGetVersion(&rt);
+  char buf[160];
+  snprintf(buf, sizeof buf, "%s|hip%d|%s|%s|%s|nf%d", arch.c_str(), rt, ps_build_hash(), mhd ? "mhd" : "ns",
+           p->dtype == PS_F32 ? "f32" : "f64", p->nfields);
+  std::string k = buf;
+  for (auto& c : p->classes) {
+    snprintf(buf, sizeof buf, "|%dx%dx%d*%d", c.nx, c.ny, c.nz, c.nb);
+    k += buf;
+  }
+  for (const char* kind : {"form", "prune", "batch", "pipe"}) {
+    snprintf(buf, sizeof buf, "|%s=%d", kind, var_of(p, kind));
+    k += buf;
+  }
+  return k;
+}
+
+const char* const TUNED[] = {"z_curl", "y", "x_prod", "z_epi"};
+
+bool tune_cache_lookup(ps_plan p, const std::string& key) {
+  const char* path = getenv("PS_TUNE_CACHE");
+  if (!path || !*path) return false;
+  FILE* f = fopen(path, "r");
+  if (!f) return false;
+  std::map<std::string, int> found;
+  bool hit = false;
+  char line[4096];
+  while (fgets(line, sizeof line, f)) {
+    char* tab = strchr(line, '\t');
+    if (!tab || std::string(line, tab) != key) continue;
+    std::map<std::string, int> v;
+    bool ok = true;
+    for (char* tok = strtok(tab + 1, ",\n"); tok; tok = strtok(nullptr, ",\n")) {
+      char* eq = strchr(tok, '=');
+      if (!eq) { ok = false; break; }
+      const std::string kind(tok, eq);
+      const int val = atoi(eq + 1);
+      if (val < 0 || val >= ps_plan_variant_count(p, kind.c_str())) { ok = false; break; }
+      v[kind] = val;
+    }
+    for (const char* kind : TUNED) ok = ok && v.count(kind);
+    if (ok) {  // the last valid line for the key wins
+      found = v;
+      hit = true;
+    }
+  }
+  fclose(f);
+  if (hit)
+    for (auto& kv : found) p->var[kv.first] = kv.second;
+  return hit;
+}
+
+void tune_cache_store(ps_plan p, const std::string& key) {
+  const char* path = getenv("PS_TUNE_CACHE");
+  if (!path || !*path) return;
+  std::string line = key + "\t";
+  for (int i = 0; i < 4; ++i) {
+    char buf[64];
+    snprintf(buf, sizeof buf, "%s%s=%d", i ? "," : "", TUNED[i], var_of(p, TUNED[i]));
+    line += buf;
+  }
+  line += "\n";
+  FILE* f = fopen(path, "a");
+  if (!f) return;  // a cache that cannot be written only costs the next plan its timing runs
+  fwrite(line.data(), 1, line.size(), f);
+  fclose(f);
+}
+
 }  // namespace
 
 extern "C" {
@@ -594,6 +705,11 @@ const char* ps_status_string(ps_status s) {
 }
 
 const char* ps_last_error(void) { return g_last_error.c_str(); }
+
+#ifndef PS_SRC_HASH
+#define PS_SRC_HASH "unknown"
+#endif
+const char* ps_build_hash(void) { return PS_SRC_HASH; }
 
 }  // extern "C"
 
@@ -665,7 +781,7 @@ ps_status create_plan(ps_plan* out, int nbox, const int* dims, int nfields, ps_d
         c.cplx_off = b.cplx_off;
         c.zs_box = (size_t)nfields * c.nc * cs;
         c.work_box = (size_t)2 * nfields * c.ncp * cs;
-        c.spec_box = align256(((size_t)c.nz * c.nshell * 2 + c.nz) * sizeof(double));
+        c.spec_box = align256(((size_t)c.nz * c.nshell * 3 + c.nz) * sizeof(double));
         p->classes.push_back(c);
       }
       b.cls = (int)p->classes.size() - 1;
@@ -694,12 +810,9 @@ ps_status create_plan(ps_plan* out, int nbox, const int* dims, int nfields, ps_d
       c.twz = p->tables[c.nz];
       c.dt = &p->dtiles[((long)c.nx << 22) | ((long)c.ny << 11) | c.nz];
     }
-    // the divergence form (fewer transforms, same result): MHD always; NS in
-    // FP32 (in FP64 its product pass is the slower one at 1024^3)
-    if (nfields == 6 || dtype == PS_F32) {
-      p->var["form"] = 1;
-      p->els = true;
-    }
+    // the rotational form by default: valid for any input; the divergence
+    // form (fewer transforms) needs a solenoidal, truncated state and is set
+    // by the caller
     // measured defaults at 512^3 (the autotuner refines them per workload),
     // set where some box's pass has variants
     const std::pair<const char*, int> defaults[] = {
@@ -709,6 +822,16 @@ ps_status create_plan(ps_plan* out, int nbox, const int* dims, int nfields, ps_d
         {"y", dtype == PS_F32 ? 2 : 0}};
     for (auto& d : defaults)
       if (ps_plan_variant_count(p, d.first) > d.second) p->var[d.first] = d.second;
+    {
+      size_t nsh = 0;
+      for (auto& b : p->boxes) nsh += b.nshell;
+      e = hipMalloc(&p->diag, (nsh + 3 * p->boxes.size()) * sizeof(double));
+      if (e != hipSuccess) {
+        p->diag = nullptr;
+        free_plan(p);
+        return fail(PS_ERR_NOMEM, std::string("diagnostics buffer: ") + hipGetErrorString(e));
+      }
+    }
     e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
     for (int i = 0; i < ps_plan_s::NAUX && e == hipSuccess; ++i)
       e = hipStreamCreateWithFlags(&p->aux[i], hipStreamNonBlocking);  // default priority
@@ -873,9 +996,33 @@ ps_status ps_rk2_step(ps_plan p, void* state, ps_model m, double nu, double eta,
           return q.rk2((ps::C2<T>*)state + p->boxes[bi].cplx_off, mhd, nu, eta, dt);
         });
       };
+      // the blow-up monitor: energies at the start, then after every
+      // mon_every steps and after the last one
+      std::vector<double> e0, e1;
+      const int every = p->mon_every > 0 ? p->mon_every : nsteps;
+      if (p->mon_every > 0) {
+        if (ps_status st = box_energies<T>(p, state, e0)) return st;
+        for (size_t i = 0; i < e0.size(); ++i)
+          if (!std::isfinite(e0[i])) return fail(PS_ERR_DIVERGED, "initial energy is not finite");
+      }
+      auto check = [&](int done) -> ps_status {
+        if (p->mon_every <= 0) return PS_OK;
+        if (ps_status st = box_energies<T>(p, state, e1)) return st;
+        for (size_t i = 0; i < e1.size(); ++i)
+          if (!std::isfinite(e1[i]) || e1[i] > p->mon_growth * e0[i]) {
+            char buf[200];
+            snprintf(buf, sizeof buf, "box %zu: energy %.6g after %d of %d steps (%.6g at the start)", i, e1[i],
+                     done, nsteps, e0[i]);
+            return fail(PS_ERR_DIVERGED, buf);
+          }
+        return PS_OK;
+      };
       if (!p->graphs || p->timing) {
-        for (int i = 0; i < nsteps; ++i)
+        for (int i = 0; i < nsteps; ++i) {
           if (ps_status st = one_step(p->stream)) return st;
+          if ((i + 1) % every == 0 || i + 1 == nsteps)
+            if (ps_status st = check(i + 1)) return st;
+        }
         return PS_OK;
       }
       char key[256];
@@ -906,6 +1053,45 @@ ps_status ps_rk2_step(ps_plan p, void* state, ps_model m, double nu, double eta,
       for (int i = 0; i < nsteps; ++i) {
         hipError_t e = hipGraphLaunch(p->gexec, p->stream);
         if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+        if ((i + 1) % every == 0 || i + 1 == nsteps)
+          if (ps_status st = check(i + 1)) return st;
+      }
+      return PS_OK;
+    });
+  });
+}
+
+ps_status ps_plan_set_monitor(ps_plan p, int every, double growth) {
+  if (ps_status st = validate_plan(p)) return st;
+  if (every < 0) return fail(PS_ERR_ARG, "every < 0");
+  if (every > 0 && !(growth > 1.0 && std::isfinite(growth)))
+    return fail(PS_ERR_ARG, "growth must be finite and > 1");
+  p->mon_every = every;
+  p->mon_growth = growth;
+  return PS_OK;
+}
+
+ps_status ps_mhd_spectrum(ps_plan p, const void* zhat, double* spec_dev, double* totals_dev) {
+  return guarded([&]() -> ps_status {
+    if (ps_status st = validate_plan(p)) return st;
+    if (p->nfields != 6) return fail(PS_ERR_ARG, "MHD diagnostics need a plan with nfields = 6");
+    if (ps_status st = need_ws(p)) return st;
+    size_t nsh = 0;
+    for (auto& b : p->boxes) nsh += b.nshell;
+    if (ps_status st = check_dev(zhat, p->cplx_total * csize(p), "zhat")) return st;
+    if (ps_status st = check_dev(spec_dev, 3 * nsh * sizeof(double), "spec")) return st;
+    if (ps_status st = check_dev(totals_dev, 3 * p->boxes.size() * sizeof(double), "totals")) return st;
+    if (ps_status st = set_device(p)) return st;
+    return by_type(p, [&](auto* tag) -> ps_status {
+      using T = std::remove_pointer_t<decltype(tag)>;
+      size_t so = 0;
+      for (size_t i = 0; i < p->boxes.size(); ++i) {
+        auto& b = p->boxes[i];
+        Seq<T> q{p, p->classes[b.cls], 0, p->classes[b.cls].nb, p->stream};
+        ps_status st = q.spectrum(b.idx, (const ps::C2<T>*)zhat + b.cplx_off, 6, true, spec_dev + 3 * so,
+                                  totals_dev + 3 * i);
+        if (st) return st;
+        so += b.nshell;
       }
       return PS_OK;
     });
@@ -933,7 +1119,7 @@ ps_status ps_energy_spectrum(ps_plan p, const void* fhat, int nfields, double* s
       for (size_t i = 0; i < p->boxes.size(); ++i) {
         auto& b = p->boxes[i];
         Seq<T> q{p, p->classes[b.cls], 0, p->classes[b.cls].nb, p->stream};
-        ps_status st = q.spectrum(b.idx, (const ps::C2<T>*)fhat + b.cplx_off, nfields, spec_dev + so,
+        ps_status st = q.spectrum(b.idx, (const ps::C2<T>*)fhat + b.cplx_off, nfields, false, spec_dev + so,
                                   totals_dev + 3 * i);
         if (st) return st;
         so += b.nshell;
@@ -1019,6 +1205,17 @@ ps_status ps_plan_autotune(ps_plan p, const void* state, ps_model m, int reps) {
     if (ps_status st = need_ws(p)) return st;
     if (ps_status st = check_dev(state, p->cplx_total * csize(p), "state")) return st;
     if (ps_status st = set_device(p)) return st;
+    const std::string key = tune_key(p, mhd);
+    if (tune_cache_lookup(p, key)) {
+      p->tune_timed = 0;
+      if (p->gexec) {
+        hipGraphExecDestroy(p->gexec);
+        p->gexec = nullptr;
+        p->gkey.clear();
+      }
+      return PS_OK;
+    }
+    int timed = 0;
     const bool timing = p->timing;
     p->timing = false;
     ps_status res = by_type(p, [&](auto* tag) -> ps_status {
@@ -1044,7 +1241,7 @@ ps_status ps_plan_autotune(ps_plan p, const void* state, ps_model m, int reps) {
           p->var[kind] = v;
           if ((out = q.tune_launch(kind, st, mhd))) break;  // warm-up
           hipEventRecord(e0, p->stream);
-          for (int r = 0; r < reps && out == PS_OK; ++r) out = q.tune_launch(kind, st, mhd);
+          for (int r = 0; r < reps && out == PS_OK; ++r, ++timed) out = q.tune_launch(kind, st, mhd);
           hipEventRecord(e1, p->stream);
           hipError_t e = hipEventSynchronize(e1);
           float ms = 0;
@@ -1063,13 +1260,20 @@ ps_status ps_plan_autotune(ps_plan p, const void* state, ps_model m, int reps) {
       return out;
     });
     p->timing = timing;
+    p->tune_timed = timed;
     if (p->gexec) {
       hipGraphExecDestroy(p->gexec);
       p->gexec = nullptr;
       p->gkey.clear();
     }
+    if (res == PS_OK) tune_cache_store(p, key);
     return res;
   });
+}
+
+int ps_plan_autotune_timed(ps_plan p) {
+  if (!p) return PS_ERR_ARG;
+  return p->tune_timed;
 }
 
 ps_status ps_plan_set_timing(ps_plan p, int enable) {

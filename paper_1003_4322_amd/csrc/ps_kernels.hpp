@@ -866,12 +866,17 @@ __global__ __launch_bounds__(xprod_slots(MHD, ELS) * RB * TQ) void k_x_prod(XArg
 }
 
 // ---------------------------------------------------------------------------
-// Shell spectrum, deterministic.  Kernel 1: one workgroup per kz plane; the
+// Shell spectra, deterministic.  Kernel 1: one workgroup per kz plane; the
 // thread owning shell s visits, for every ky of the plane, the contiguous kx
-// run of modes with round(|k|) = s and accumulates E(s) and Z(s) with
+// run of modes with round(|k|) = s and accumulates Q quantities with
 // Neumaier compensation in a fixed order.  Kernel 2 sums the per-plane
 // partials over planes in order.  No atomics, so results are bitwise
 // reproducible.
+//   energy (Q = 2): E(s) = 1/2 sum w |f|^2 and Z(s) = 1/2 sum w |k|^2 |f|^2
+//                   over nf fields, plus max |k_d . f| per plane;
+//   MHD    (Q = 3): with u = (z+ + z-)/2, b = (z+ - z-)/2 (fields 0-2, 3-5):
+//                   Eu(s) = 1/2 sum w |u|^2, Eb(s) = 1/2 sum w |b|^2,
+//                   Hc(s) = 1/2 sum w Re(u . conj b).
 // ---------------------------------------------------------------------------
 struct NSum {
   double s, c;
@@ -895,15 +900,16 @@ __device__ __forceinline__ long isqrt_floor(long n) {  // n >= 0
 template <typename T>
 struct SpecArgs {
   const C2<T>* f;
-  double* part;     // [nz][nshell][2] (E, Z) per plane
-  double* pmax;     // [nz] max |k_d . f| per plane
+  double* part;     // [nz][nshell][Q] per plane
+  double* pmax;     // [nz] max |k_d . f| per plane (energy spectrum only)
   long fs, pitch;   // field stride, kx pitch
   int nx, ny, nz, nf, nshell;
   double sx, sy, sz;  // box factors 2 pi / L (enstrophy and divergence; shells stay on the index)
 };
 
-template <typename T>
+template <typename T, bool MHD>
 __global__ __launch_bounds__(256) void k_spec_planes(SpecArgs<T> a) {
+  constexpr int Q = MHD ? 3 : 2;
   const int kz = blockIdx.x, NX = a.nx, NY = a.ny, H = NX / 2 + 1;
   const long izw = wav(kz, a.nz);
   const double kzd = a.sz * dwav(kz, a.nz);
@@ -911,7 +917,9 @@ __global__ __launch_bounds__(256) void k_spec_planes(SpecArgs<T> a) {
   __shared__ double red[256];
   double mx = 0;
   for (int s = threadIdx.x; s < a.nshell; s += blockDim.x) {
-    NSum E{0, 0}, Z{0, 0};
+    NSum acc[Q];
+#pragma unroll
+    for (int qq = 0; qq < Q; ++qq) acc[qq] = NSum{0, 0};
     const long lo2 = (long)(2 * s - 1) * (2 * s - 1);  // shell s: lo2 <= 4|k|^2 < hi2
     const long hi2 = (long)(2 * s + 1) * (2 * s + 1);
     for (int ky = 0; ky < NY; ++ky) {
@@ -931,36 +939,54 @@ __global__ __launch_bounds__(256) void k_spec_planes(SpecArgs<T> a) {
       const double kyd = a.sy * dwav(ky, NY);
       const double qyz2 = a.sy * a.sy * (double)(iyw * iyw) + qz2;
       for (long kx = kx0; kx <= kx1; ++kx) {
-        double e = 0;
-        for (int ff = 0; ff < a.nf; ++ff) {
-          const C2<T> v = row[ff * a.fs + kx];
-          e += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
-        }
         const double w = (kx == 0 || 2 * kx == NX) ? 0.5 : 1.0;  // (1/2) * weight
-        const double q2 = a.sx * a.sx * (double)(kx * kx) + qyz2;  // physical |k|^2
-        nadd(E, w * e);
-        nadd(Z, w * q2 * e);
-        const double kxd = a.sx * dwavx((int)kx, NX);
-        for (int ff = 0; ff + 2 < a.nf; ff += 3) {
-          const C2<T> v0 = row[ff * a.fs + kx], v1 = row[(ff + 1) * a.fs + kx], v2 = row[(ff + 2) * a.fs + kx];
-          const double dx = kxd * v0.x + kyd * v1.x + kzd * v2.x;
-          const double dy = kxd * v0.y + kyd * v1.y + kzd * v2.y;
-          const double d = sqrt(dx * dx + dy * dy);
-          mx = d > mx ? d : mx;
+        if constexpr (MHD) {
+          double eu = 0, eb = 0, hc = 0;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const C2<T> zp = row[c * a.fs + kx], zm = row[(3 + c) * a.fs + kx];
+            const double ux = 0.5 * ((double)zp.x + (double)zm.x), uy = 0.5 * ((double)zp.y + (double)zm.y);
+            const double bx = 0.5 * ((double)zp.x - (double)zm.x), by = 0.5 * ((double)zp.y - (double)zm.y);
+            eu += ux * ux + uy * uy;
+            eb += bx * bx + by * by;
+            hc += ux * bx + uy * by;
+          }
+          nadd(acc[0], w * eu);
+          nadd(acc[1], w * eb);
+          nadd(acc[2], w * hc);
+        } else {
+          double e = 0;
+          for (int ff = 0; ff < a.nf; ++ff) {
+            const C2<T> v = row[ff * a.fs + kx];
+            e += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+          }
+          const double q2 = a.sx * a.sx * (double)(kx * kx) + qyz2;  // physical |k|^2
+          nadd(acc[0], w * e);
+          nadd(acc[1], w * q2 * e);
+          const double kxd = a.sx * dwavx((int)kx, NX);
+          for (int ff = 0; ff + 2 < a.nf; ff += 3) {
+            const C2<T> v0 = row[ff * a.fs + kx], v1 = row[(ff + 1) * a.fs + kx], v2 = row[(ff + 2) * a.fs + kx];
+            const double dx = kxd * v0.x + kyd * v1.x + kzd * v2.x;
+            const double dy = kxd * v0.y + kyd * v1.y + kzd * v2.y;
+            const double d = sqrt(dx * dx + dy * dy);
+            mx = d > mx ? d : mx;
+          }
         }
       }
     }
-    double* p = a.part + ((long)kz * a.nshell + s) * 2;
-    p[0] = E.s + E.c;
-    p[1] = Z.s + Z.c;
+    double* p = a.part + ((long)kz * a.nshell + s) * Q;
+#pragma unroll
+    for (int qq = 0; qq < Q; ++qq) p[qq] = acc[qq].s + acc[qq].c;
   }
-  red[threadIdx.x] = mx;
-  __syncthreads();
-  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+  if constexpr (!MHD) {
+    red[threadIdx.x] = mx;
     __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+      if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) a.pmax[kz] = red[0];
   }
-  if (threadIdx.x == 0) a.pmax[kz] = red[0];
 }
 
 }  // namespace ps

@@ -48,7 +48,8 @@ template <typename T>
 hipError_t launch_x_r2c(int N, XArgs<T> a, hipStream_t s);
 template <typename T>
 hipError_t launch_x_prod(int N, bool mhd, bool els, int var, XArgs<T> a, hipStream_t s);
+// mhd: Eu(s), Eb(s), Hc(s) of an Elsasser state instead of E(s) (and Z, maxdiv)
 template <typename T>
-hipError_t launch_spectrum(SpecArgs<T> a, double* spec, double* totals, hipStream_t s);
+hipError_t launch_spectrum(SpecArgs<T> a, bool mhd, double* spec, double* totals, hipStream_t s);
 
 }  // namespace ps

@@ -342,6 +342,61 @@ def band_limited(N: int, seed: int, kmax: int, energy: float = 0.5) -> SparseFie
     return SparseField(N, K, v)
 
 
+def _flat_group(N: int, seed: int, kz: int, kyr: np.ndarray, kxr: np.ndarray) -> np.ndarray:
+    """v = k x a / |k| at storage plane kz, rows ky in kyr (storage indices) and
+    columns kx in kxr: a complex Gaussian 3-vector a per mode from (seed,
+    storage index, component), so every mode has the same expected size."""
+    H = N // 2 + 1
+    KY, KX = np.meshgrid(kyr, kxr, indexing="ij")
+    m = (np.int64(kz) * N + KY) * H + KX
+    a = np.empty((3,) + KY.shape, np.complex128)
+    for c in range(3):
+        ctr = (m.astype(np.uint64) * np.uint64(3) + np.uint64(c)) * np.uint64(2)
+        re, im = box_muller(uniform53(seed, ctr), uniform53(seed, ctr + np.uint64(1)))
+        a[c] = re + 1j * im
+    wz = kz if kz < N // 2 else kz - N
+    ky = np.where(KY < N // 2, KY, KY - N).astype(np.float64)
+    kx = KX.astype(np.float64)
+    kn = np.sqrt(kx * kx + ky * ky + float(wz * wz))
+    kn[kn == 0] = 1.0
+    return np.stack([ky * a[2] - wz * a[1], wz * a[0] - kx * a[2], kx * a[1] - ky * a[0]]) / kn
+
+
+def flat_solenoidal(N: int, seed: int, groups: int = 1, energy: float = 0.5,
+                    dtype=np.complex128) -> np.ndarray:
+    """Dense field [3 groups][kz][ky][kx] of solenoidal 3-vectors whose modes
+    fill the kept sphere 9|k|^2 < N^2 (k != 0) with the same expected
+    amplitude at every |k| (a flat spectrum up to the 2/3 edge), zero outside;
+    the kx = 0 plane is replaced by its Hermitian part.  Group g uses seed + g
+    and is scaled to total energy ``energy``.  Only the planes |kz| < N/3 are
+    generated (the others are zero), one plane at a time."""
+    H = N // 2 + 1
+    K = (N - 1) // 3                      # |k_i| <= K inside the sphere
+    kr = np.concatenate([np.arange(0, K + 1), np.arange(N - K, N)])   # storage rows
+    kxr = np.arange(K + 1)
+    out = np.zeros((3 * groups, N, N, H), dtype=dtype)
+    wy = np.where(kr < N // 2, kr, kr - N)
+    for g in range(groups):
+        e = 0.0
+        for kz in kr:
+            wz = kz if kz < N // 2 else kz - N
+            v = _flat_group(N, seed + g, int(kz), kr, kxr)
+            # Hermitian part of the kx = 0 column: v(0, ky, kz) = conj v(0, -ky, -kz)
+            mz = (-int(kz)) % N
+            mrow = (-kr) % N
+            w0 = _flat_group(N, seed + g, mz, mrow, np.array([0]))[..., 0]
+            v[..., 0] = 0.5 * (v[..., 0] + np.conj(w0))
+            k2 = wy[:, None] ** 2 + kxr[None, :] ** 2 + wz * wz
+            keep = (9 * k2 < N * N) & (k2 > 0)
+            v *= keep
+            w = np.where(kxr == 0, 1.0, 2.0)[None, :]
+            e += 0.5 * float(np.sum(w * np.sum(np.abs(v) ** 2, axis=0)))
+            out[3 * g:3 * g + 3, kz, kr[:, None], kxr[None, :]] = v.astype(dtype)
+        out[3 * g:3 * g + 3] *= np.asarray(math.sqrt(energy / e), dtype=np.float64).astype(
+            out.real.dtype)
+    return out
+
+
 def embed(f: SparseField, N: int) -> SparseField:
     """The same low-wavenumber coefficients on a grid of size N."""
     assert f.K < N // 3 or f.K < N // 2

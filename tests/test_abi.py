@@ -81,3 +81,23 @@ def test_null_plan_calls(L):
     assert L.ps_plan_set_workspace(None, None, 0) == -1
     assert L.ps_plan_timing_count(None) == -1
     assert b"plan is NULL" in L.ps_last_error()
+
+
+def test_new_calls_reject_null_plan(L):
+    assert L.ps_plan_set_monitor(None, 1, 10.0) == -1
+    assert L.ps_mhd_spectrum(None, None, None, None) == -1
+    assert L.ps_plan_autotune_timed(None) == -1
+
+
+def test_library_is_built_from_these_sources(L):
+    from paper_1003_4322_amd import build
+    assert L.ps_build_hash().decode() == build.src_hash()
+
+
+def test_stale_library_is_refused(monkeypatch):
+    """A library whose embedded hash differs from the sources is not loaded."""
+    from paper_1003_4322_amd import binding, build
+    monkeypatch.setattr(build, "src_hash", lambda: "0000000000000000")
+    monkeypatch.setattr(binding, "_lib", None)
+    with pytest.raises(ImportError, match="built from other sources"):
+        binding.lib()

@@ -23,7 +23,7 @@ TOL_FFT = {"f64": 1e-13, "f32": 2e-6}
 TOL_NL = {"f64": 1e-12, "f32": 2e-5}
 TOL_STEP = {"f64": 1e-12, "f32": 2e-6}
 
-FFT_SIZES = [8, 12, 16, 24, 32, 48, 64, 96, 128]
+FFT_SIZES = [8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 384]
 
 
 @pytest.fixture(scope="module")

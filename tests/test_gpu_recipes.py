@@ -1,0 +1,107 @@
+"""Full-state one-step parity on the benchmark workloads' own recipes.
+
+* NS 256^3: random-phase k0 = 4, seed 2, nu = 1e-3, dt = 2e-3;
+* MHD (Elsasser) 256^3 with the 512^3 workload's recipe: u seed 3, b seed 4,
+  k0 = 3, E_u = E_b = 1/2, nu = eta = 5e-4, dt = 1e-3;
+* MHD 512^3 itself: the FP64 GPU step against the oracle (when the host has
+  the memory for the oracle's step), the FP32 step against both.
+
+Each runs on the default plan and on the benchmark's launch configuration
+(divergence form, dealias pruning, autotuned variants).  Tolerances: the
+method's bars, relative L2 over the state, 1e-12 (FP64) and 2e-6 (FP32, from
+the identical FP32-representable state).
+"""
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import DEV, rel_l2_w_dev, rounded, say, to_dev
+from oracle.psref import MHD, NS
+from paper_1003_4322_amd import synth
+
+pytestmark = pytest.mark.gpu
+TOL_STEP = {"f64": 1e-12, "f32": 2e-6}
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_1003_4322_amd import binding
+    binding.lib()
+    return binding
+
+
+def run_step(B, N, nf, dt, x, model, nu, eta, step, bench_config):
+    p = B.Plan(N, nf, dt)
+    s = to_dev(x, dt)
+    if bench_config:
+        p.set_variant("prune", 1)
+        p.set_variant("form", 1)
+        say("autotune", p.autotune(s, model, 2))
+    p.rk2_step(s, model, nu, eta, step, 1)
+    p.close()
+    return s
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("model", ["ns", "mhd"])
+def test_recipe_256_one_step(B, ref, model, dt):
+    N = 256
+    if model == "ns":
+        x = rounded(synth.random_ns(N, 2, 4.0), dt)
+        nf, pm, om, nu, eta, step = 3, B.PS_NS, NS, 1e-3, 0.0, 2e-3
+    else:
+        x = rounded(synth.random_mhd(N, 3, 4, 3.0), dt)
+        nf, pm, om, nu, eta, step = 6, B.PS_MHD, MHD, 5e-4, 5e-4, 1e-3
+    want = torch.from_numpy(ref.rk2_step(x, om, nu, eta, step, 1)).to(DEV)
+    for bench_config in (False, True):
+        say("recipe 256", model, dt, "bench config" if bench_config else "defaults")
+        got = run_step(B, N, nf, dt, x, pm, nu, eta, step, bench_config)
+        e = rel_l2_w_dev(got, want)
+        say(f"rel-L2 {e:.3e}")
+        assert e < TOL_STEP[dt], (bench_config, e)
+
+
+def mem_available() -> float:
+    with open("/proc/meminfo") as f:
+        for line in f:
+            if line.startswith("MemAvailable:"):
+                return float(line.split()[1]) * 1024
+    return 0.0
+
+
+@pytest.mark.slow
+def test_mhd512_recipe_step_vs_oracle(B, ref):
+    """The headline workload's first step in the benchmark's launch
+    configuration: FP64 GPU vs the oracle from the recipe's FP64 state
+    (<= 1e-12); FP32 GPU vs the oracle from the FP32-rounded state, and vs the
+    FP64 GPU step from that same state (the benchmark's FP32-vs-FP64 figure),
+    each <= 2e-6."""
+    need = 48e9
+    have = mem_available()
+    if have < need:
+        pytest.skip(f"host has {have / 1e9:.0f} GB available; the 512^3 MHD oracle step needs "
+                    f"about {need / 1e9:.0f} GB")
+    N = 512
+    sf = synth.mhd_sparse(N, 3, 4, 3.0)
+    bad = []
+    got32 = None
+    for dt in ("f64", "f32"):
+        say("mhd512 recipe: oracle step", dt)
+        x = rounded(sf.dense(), dt)
+        want = torch.from_numpy(ref.rk2_step(x, MHD, 5e-4, 5e-4, 1e-3, 1)).to(DEV)
+        say("mhd512 recipe: GPU step", dt)
+        got = run_step(B, N, 6, dt, x, B.PS_MHD, 5e-4, 5e-4, 1e-3, True)
+        e = rel_l2_w_dev(got, want)
+        say(dt, f"vs oracle {e:.3e}")
+        if not e < TOL_STEP[dt]:
+            bad.append((dt, e))
+        if dt == "f32":
+            got32 = got
+        del want
+    say("mhd512 recipe: FP64 GPU step from the FP32-rounded state")
+    got64 = run_step(B, N, 6, "f64", rounded(sf.dense(), "f32"), B.PS_MHD, 5e-4, 5e-4, 1e-3, True)
+    e = rel_l2_w_dev(got32, got64)
+    say(f"f32 vs f64 {e:.3e}")
+    if not e < TOL_STEP["f32"]:
+        bad.append(("f32 vs f64", e))
+    assert not bad, bad

@@ -28,6 +28,9 @@ MUTANTS = {
     15: "box: viscous term with the index |n|^2",
     16: "box: curl without the factors 2 pi / L",
     17: "grid: dealiasing sphere of nx on every axis",
+    18: "MHD: nu and eta swapped in the cross term of the resistive coupling",
+    19: "MHD diagnostics: b taken as (z- - z+)/2",
+    20: "MHD diagnostics: u = z+ + z- without the 1/2",
 }
 
 
