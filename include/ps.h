@@ -193,6 +193,19 @@ ps_status ps_plan_set_box(ps_plan p, double Lx, double Ly, double Lz);
 ps_status ps_energy_spectrum(ps_plan p, const void *fhat, int nfields, double *spec_dev,
                              double *totals_dev);
 
+/* ps_energy_spectrum for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same arguments and the same results, bit for bit, but the
+ * per-plane partials live in a device scratch array the library holds (16 MiB
+ * per device, enough for every supported grid; one box at a time), so the
+ * plan needs no workspace and the call allocates nothing.  Every call on a
+ * device shares that device's scratch: calls that overlap on one device (on
+ * different streams, or from different threads) race and must not be
+ * issued.  PS_ERR_SIZE if a box's partials (nz nshell 2 + nz doubles) exceed
+ * the scratch, PS_ERR_ARG as for ps_energy_spectrum. */
+ps_status ps_energy_spectrum_static(ps_plan p, const void *fhat, int nfields, double *spec_dev,
+                                    double *totals_dev);
+
 /* Kinetic and magnetic energy and cross-helicity of an Elsasser state (plan
  * nfields = 6; Sec. 3 computes global quantities and spectra by reductions,
  * Sec. 5 runs the solver for MHD).  With u = (z+ + z-)/2 and b = (z+ - z-)/2

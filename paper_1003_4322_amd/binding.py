@@ -43,6 +43,7 @@ _SIGS = [
     ("ps_plan_set_rotation", _i, [_vp, _d, _d, _d]),
     ("ps_plan_set_box", _i, [_vp, _d, _d, _d]),
     ("ps_energy_spectrum", _i, [_vp, _vp, _i, _vp, _vp]),
+    ("ps_energy_spectrum_static", _i, [_vp, _vp, _i, _vp, _vp]),
     ("ps_mhd_spectrum", _i, [_vp, _vp, _vp, _vp]),
     ("ps_plan_set_variant", _i, [_vp, ctypes.c_char_p, _i]),
     ("ps_plan_get_variant", _i, [_vp, ctypes.c_char_p]),
@@ -288,6 +289,21 @@ class Plan:
         self._stream()
         _check(lib().ps_energy_spectrum(self.handle, _ptr(fhat), nf, _ptr(spec), _ptr(tot)),
                "ps_energy_spectrum")
+        return spec, tot
+
+    def energy_spectrum_static(self, fhat: torch.Tensor, nfields: Optional[int] = None
+                               ) -> Tuple[torch.Tensor, torch.Tensor]:
+        """energy_spectrum through the allocation-free entry point (no
+        workspace needed; the partials live in the library's device scratch).
+        The output tensors are allocated here, by torch, not by the library."""
+        nf = nfields or self.nfields
+        if fhat.dtype != self.complex_dtype or fhat.device != self.device or not fhat.is_contiguous():
+            raise TypeError("fhat: contiguous complex tensor of the plan's dtype and device")
+        spec = torch.empty(sum(self.nshells), dtype=torch.float64, device=self.device)
+        tot = torch.empty(3 * len(self.sizes), dtype=torch.float64, device=self.device)
+        self._stream()
+        _check(lib().ps_energy_spectrum_static(self.handle, _ptr(fhat), nf, _ptr(spec), _ptr(tot)),
+               "ps_energy_spectrum_static")
         return spec, tot
 
     def mhd_spectrum(self, zhat: torch.Tensor) -> Tuple[torch.Tensor, torch.Tensor]:

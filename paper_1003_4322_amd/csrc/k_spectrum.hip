@@ -1,11 +1,38 @@
 // Deterministic FP64 shell spectra (energy and enstrophy; MHD energies and
 // cross-helicity).
 #include <cstring>
+#include <map>
+#include <mutex>
 
 #include "ps_config.hpp"
 #include "ps_launch.hpp"
 
 namespace ps {
+
+// Library-held scratch of the allocation-free spectrum entry point
+// (ps_energy_spectrum_static): the per-plane partials of one box at a time.
+// Each device the library runs on holds its own copy until the process
+// ends.  Host code never passes the array's name to a kernel (on the host it
+// is only a stand-in for the symbol): it uses the device address that
+// spectrum_scratch() looked up with the device current.
+static __device__ __align__(256) double scratch[SPEC_SCRATCH_BYTES / sizeof(double)];
+
+hipError_t spectrum_scratch(int device, double** ptr) {
+  static std::mutex mu;
+  static std::map<int, double*> addr;  // device -> address of its copy
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = addr.find(device);
+  if (it != addr.end()) {
+    *ptr = it->second;
+    return hipSuccess;
+  }
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));  // the current device's copy
+  if (e != hipSuccess) return e;
+  addr[device] = static_cast<double*>(p);
+  *ptr = static_cast<double*>(p);
+  return hipSuccess;
+}
 
 bool size_supported(int N) {
   switch (N) {

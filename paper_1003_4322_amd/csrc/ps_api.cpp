@@ -135,6 +135,8 @@ struct ps_plan_s {
   double* diag = nullptr;  // device: spectra (sum of nshell) then 3 totals per box, owned
   // timing launches of the last ps_plan_autotune (0: its result came from the cache)
   int tune_timed = -1;
+  // this device's copy of the library-held spectrum scratch
+  double* scratch = nullptr;
 };
 
 namespace {
@@ -832,6 +834,13 @@ ps_status create_plan(ps_plan* out, int nbox, const int* dims, int nfields, ps_d
         return fail(PS_ERR_NOMEM, std::string("diagnostics buffer: ") + hipGetErrorString(e));
       }
     }
+    // set-up of the allocation-free spectrum entry point: the address of
+    // this device's copy of its scratch (looked up once per device)
+    e = ps::spectrum_scratch(p->device, &p->scratch);
+    if (e != hipSuccess) {
+      free_plan(p);
+      return hip_fail(e, "hipGetSymbolAddress (spectrum scratch)");
+    }
     e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
     for (int i = 0; i < ps_plan_s::NAUX && e == hipSuccess; ++i)
       e = hipStreamCreateWithFlags(&p->aux[i], hipStreamNonBlocking);  // default priority
@@ -1069,6 +1078,54 @@ ps_status ps_plan_set_monitor(ps_plan p, int every, double growth) {
   p->mon_every = every;
   p->mon_growth = growth;
   return PS_OK;
+}
+
+ps_status ps_energy_spectrum_static(ps_plan p, const void* fhat, int nfields, double* spec_dev,
+                                    double* totals_dev) {
+  return guarded([&]() -> ps_status {
+    if (ps_status st = validate_plan(p)) return st;
+    if (nfields < 1 || nfields > p->nfields) return fail(PS_ERR_ARG, "nfields out of range");
+    if (!p->scratch) return fail(PS_ERR_STATE, "the library scratch of this device was not set up");
+    size_t nsh = 0;
+    for (auto& b : p->boxes) {
+      nsh += b.nshell;
+      const size_t need = ((size_t)b.nz * b.nshell * 2 + b.nz) * sizeof(double);
+      if (need > ps::SPEC_SCRATCH_BYTES) {
+        char buf[200];
+        snprintf(buf, sizeof buf, "box of %d x %d x %d needs %zu bytes of scratch; the library holds %zu",
+                 b.nx, b.ny, b.nz, need, ps::SPEC_SCRATCH_BYTES);
+        return fail(PS_ERR_SIZE, buf);
+      }
+    }
+    const Class& lc = p->classes.back();
+    if (ps_status st = check_dev(fhat, p->cplx_total * csize(p) - (size_t)(p->nfields - nfields) *
+                                           lc.nc * csize(p), "fhat"))
+      return st;
+    if (ps_status st = check_dev(spec_dev, nsh * sizeof(double), "spec")) return st;
+    if (ps_status st = check_dev(totals_dev, 3 * p->boxes.size() * sizeof(double), "totals")) return st;
+    if (ps_status st = set_device(p)) return st;
+    return by_type(p, [&](auto* tag) -> ps_status {
+      using T = std::remove_pointer_t<decltype(tag)>;
+      size_t so = 0;
+      for (size_t i = 0; i < p->boxes.size(); ++i) {
+        const Box& b = p->boxes[i];
+        const Class& c = p->classes[b.cls];
+        // boxes run one after another on the plan's stream, each reusing the
+        // scratch after the previous box's last kernel has read it; every
+        // entry is written before it is read, so nothing is cleared
+        ps::SpecArgs<T> a{};
+        a.f = (const ps::C2<T>*)fhat + b.cplx_off;
+        a.part = p->scratch;
+        a.pmax = a.part + (long)b.nz * b.nshell * 2;
+        a.fs = c.nc; a.pitch = c.H; a.nx = b.nx; a.ny = b.ny; a.nz = b.nz; a.nf = nfields; a.nshell = b.nshell;
+        a.sx = p->bs[0]; a.sy = p->bs[1]; a.sz = p->bs[2];
+        const hipError_t e = ps::launch_spectrum<T>(a, false, spec_dev + so, totals_dev + 3 * i, p->stream);
+        if (e != hipSuccess) return hip_fail(e, "spectrum (static scratch)");
+        so += b.nshell;
+      }
+      return PS_OK;
+    });
+  });
 }
 
 ps_status ps_mhd_spectrum(ps_plan p, const void* zhat, double* spec_dev, double* totals_dev) {

@@ -48,6 +48,14 @@ template <typename T>
 hipError_t launch_x_r2c(int N, XArgs<T> a, hipStream_t s);
 template <typename T>
 hipError_t launch_x_prod(int N, bool mhd, bool els, int var, XArgs<T> a, hipStream_t s);
+// Bytes of the library-held device scratch of ps_energy_spectrum_static:
+// the partials of one box, nz * nshell * 2 + nz doubles (14.6 MB at
+// 1024^3, the largest supported grid).
+constexpr size_t SPEC_SCRATCH_BYTES = size_t(16) << 20;
+// Device address of the current device's copy of that scratch (looked up
+// once per device; call with `device` current).
+hipError_t spectrum_scratch(int device, double** ptr);
+
 // mhd: Eu(s), Eb(s), Hc(s) of an Elsasser state instead of E(s) (and Z, maxdiv)
 template <typename T>
 hipError_t launch_spectrum(SpecArgs<T> a, bool mhd, double* spec, double* totals, hipStream_t s);
