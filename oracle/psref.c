@@ -662,7 +662,11 @@ int psref_nonlinear_at(int nx, int ny, int nz, int model, const double *fhat, in
   for (int i = 0; i < nk; ++i) {
     long ox = kx[i], oy = wav(ky[i], ny), oz = wav(kz[i], nz);
     cplx accL[3] = {0, 0, 0}, accE[3] = {0, 0, 0};
-    for (long pz = -K[2]; pz <= K[2]; ++pz)
+    /* the sum runs plane by plane in pz (each plane's terms summed on their
+     * own, then the plane sums added), so that its rounding stays near
+     * eps sqrt(terms per plane) even for the ~10^8 triads of a large grid */
+    for (long pz = -K[2]; pz <= K[2]; ++pz) {
+      cplx plL[3] = {0, 0, 0}, plE[3] = {0, 0, 0};
       for (long py = -K[1]; py <= K[1]; ++py)
         for (long px = -K[0]; px <= K[0]; ++px) {
           long qx = ox - px, qy = oy - py, qz = oz - pz;
@@ -676,7 +680,7 @@ int psref_nonlinear_at(int nx, int ny, int nz, int model, const double *fhat, in
             if (up[0] == 0 && up[1] == 0 && up[2] == 0) continue;
             icurl_c(&g, qx, qy, qz, uq, wq);
             cross_c(up, wq, t);
-            for (int f = 0; f < 3; ++f) accL[f] += t[f];
+            for (int f = 0; f < 3; ++f) plL[f] += t[f];
           } else {
             cplx up[3], bp[3], uq[3], bq[3], wq[3], jp[3], t1[3], t2[3], t3[3];
             for (int f = 0; f < 3; ++f) {
@@ -693,11 +697,16 @@ int psref_nonlinear_at(int nx, int ny, int nz, int model, const double *fhat, in
             cross_c(jp, bq, t2);              /* j(p) x b(q) */
             cross_c(up, bq, t3);              /* u(p) x b(q) */
             for (int f = 0; f < 3; ++f) {
-              accL[f] += t1[f] + t2[f];
-              accE[f] += t3[f];
+              plL[f] += t1[f] + t2[f];
+              plE[f] += t3[f];
             }
           }
         }
+      for (int f = 0; f < 3; ++f) {
+        accL[f] += plL[f];
+        accE[f] += plE[f];
+      }
+    }
     long k2 = ox * ox + oy * oy + oz * oz;
     cplx res[6] = {0, 0, 0, 0, 0, 0};
     if (k2 != 0 && dealias_keep(&g, ox, oy, oz)) {
