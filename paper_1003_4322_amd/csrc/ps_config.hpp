@@ -116,6 +116,30 @@ struct XCfg {
   }
 };
 
+// Packed x pass (k_x_prod_pk): W = max(ceil(FIN rb / 2), ceil(FOUT rb / 2))
+// complex transforms of length N, TQ threads each; LDS of W rows of `slots`
+// plus N staged twiddles.
+// lp: LDS slots per transform.
+template <typename T, int N, int TQ>
+struct XPkCfg {
+  static constexpr int w(int fin, int fout, int rb) {
+    const int a = (fin * rb + 1) / 2, b = (fout * rb + 1) / 2;
+    return a > b ? a : b;
+  }
+  static constexpr bool fits(int fin, int fout, int rb, int lp, int lim) {
+    return (w(fin, fout, rb) * lp + N) * 2 * (int)sizeof(T) <= lim && w(fin, fout, rb) * TQ <= 1024;
+  }
+  // an even number of grid rows, so that every transform pairs one field on
+  // two grid rows (two different fields, such as u and its curl, can differ
+  // in size by |k|, and the smaller would carry the larger one's rounding)
+  static constexpr int rb(int fin, int fout, int want, int lp, int lim) {
+    int r = 2;
+    while (2 * r <= want) r *= 2;  // a power of two, at least 2
+    while (r > 2 && !fits(fin, fout, r, lp, lim)) r >>= 1;
+    return r;
+  }
+};
+
 // Kernel variant tables.  Strided-pass variants: tile shift, z_curl split and
 // direct gather, minimum workgroups per CU asked of the register allocator,
 // alternate (radix-16) schedule.  Product-pass variants: rows per workgroup,
@@ -133,6 +157,8 @@ struct XV {
   int sched;          // 0 LenCfg, 1 radix-16 (LenAlt), 2 wide (LenWide)
   bool swz;           // rows in LDS swizzled (LaySwz32) instead of padded (LayPad8)
   bool big = false;   // up to 80 KB of LDS per workgroup (two per CU) instead of 64 KB
+  bool pk = false;    // packed form (k_x_prod_pk): two real rows per complex transform of length N
+  bool ex = false;    // packed form: per-exchange LDS layouts (LayEx) and rows in natural order
 };
 constexpr ZV ZCURL_V[] = {{1, 1, 1, false, false}, {1, 2, 1, false, false}, {1, 2, 2, false, false},
                           {1, 2, 1, true, false},  {1, 1, 1, false, true}};
@@ -141,7 +167,12 @@ constexpr ZV ZEPI_V[] = {{0, 1, 1, false}, {1, 1, 1, false}, {1, 1, 2, false}, {
 constexpr ZV STR_V[] = {{0, 1, 1, false}, {1, 1, 1, false}, {0, 1, 1, true}, {1, 1, 1, true}};
 constexpr XV XPROD_V[] = {{2, 1, 0, false}, {4, 2, 0, false}, {4, 2, 1, false}, {2, 1, 1, false},
                           {2, 1, 0, true},  {4, 2, 0, true},  {1, 1, 2, true},  {1, 1, 2, false},
-                          {8, 4, 0, true, true}, {8, 4, 0, false, true}, {4, 2, 2, true, true}};
+                          {8, 4, 0, true, true}, {8, 4, 0, false, true}, {4, 2, 2, true, true},
+                          // packed form
+                          {2, 2, 0, false, false, true, true}, {4, 4, 0, false, true, true, true},
+                          {2, 2, 0, true, false, true}, {4, 4, 0, true, true, true},
+                          {2, 2, 1, false, false, true, true}, {4, 4, 1, false, true, true, true},
+                          {8, 8, 0, false, true, true, true}};
 constexpr int NZCURL = sizeof(ZCURL_V) / sizeof(ZV);
 // waves per SIMD that minb workgroups of `threads` threads occupy (4 SIMDs per CU)
 constexpr int waves_per_simd(int minb, int threads) {

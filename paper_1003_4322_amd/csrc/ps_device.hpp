@@ -263,6 +263,24 @@ struct LayColPad8 {
   __device__ __forceinline__ static int offc(int c, int ls) { return (c + c / 8) * ls; }
 };
 
+// Per-exchange layout: the buffer a stage of span NS and radix R writes (and
+// the next stage reads) keeps element i at i + P floor(i / B), P = NS and
+// B = max(NS R, 32) while NS < 32, plain otherwise.  Over any 32 consecutive
+// threads the stage's writes (base (j / NS) NS R + j % NS, plus m NS) and the
+// next stage's reads (j + m L / R') fall in distinct 8-byte bank pairs, and
+// every access of a thread is its base plus a constant: offc(c) when
+// c % B == 0 (reads at stride L / R'), m NS when B % (NS R) == 0 (writes).
+template <int NS, int R>
+struct LayEx {
+  static constexpr int P = NS < 32 ? NS : 0;
+  static constexpr int B = NS * R > 32 ? NS * R : 32;
+  __host__ __device__ static constexpr int off(int i) { return P ? i + P * (i / B) : i; }
+  __host__ __device__ static constexpr int offc(int c) { return P ? c + P * (c / B) : c; }
+  static constexpr bool read_splits(int c) { return P == 0 || c % B == 0; }
+  static constexpr bool write_splits = P == 0 || B % (NS * R) == 0;
+  __host__ __device__ static constexpr int slots(int L) { return off(L - 1) + 1; }
+};
+
 // ---------------------------------------------------------------------------
 // Stockham autosort FFT of length L done by TQ cooperating threads.
 //
@@ -433,6 +451,91 @@ struct Stockham {
     stage<NS, R, NS == 1, sizeof...(Rest) == 0, Lay>(v, lds, ls, q, tw, ld, act);
     if constexpr (sizeof...(Rest) > 0) chain<NS * R, Lay>(v, lds, ls, q, tw, ld, act, Radices<Rest...>{});
   }
+
+  // ---- the same with a layout of its own per exchange (LayEx): stage
+  // (NS, R) gathers through the layout of the exchange before it (LR) and
+  // writes through LayEx<NS, R>.  One transform per buffer, unit stride.
+  template <int NS, int R, bool FIRST, bool LAST, class LR, class TW, class Ld>
+  __device__ __forceinline__ static void stage_ex(C2<T> (&v)[SLOTS], C2<T>* lds, int q, const TW& tw, Ld& ld,
+                                                  bool act) {
+    using LW = LayEx<NS, R>;
+    constexpr int NB = cdiv(L / R, TQ);
+    constexpr bool EXACT = (L / R) % TQ == 0;
+    if (act) {
+      constexpr bool SPLIT_G = FIRST || LR::read_splits(L / R);
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int j = q + TQ * b;
+        const bool ok = EXACT || j < L / R;
+        if constexpr (FIRST) {
+#pragma unroll
+          for (int m = 0; m < R; ++m) v[b * R + m] = ok ? ld(b * R + m, j + m * (L / R)) : zero2<T>();
+        } else {
+          const int ja = LR::off(j);
+#pragma unroll
+          for (int m = 0; m < R; ++m) {
+            const int o = SPLIT_G ? ja + LR::offc(m * (L / R)) : LR::off(j + m * (L / R));
+            v[b * R + m] = ok ? lds[o] : zero2<T>();
+          }
+        }
+      }
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int j = q + TQ * b;
+        C2<T>* a = &v[b * R];
+        if constexpr (NS > 1) {
+          const int k = j % NS;
+#pragma unroll
+          for (int m = 1; m < R; ++m) a[m] = tw_apply<DIR>(a[m], tw.template get<L, NS, R>(m, k));
+        }
+        dft<R, DIR>(a);
+      }
+    }
+    if constexpr (!LAST) {
+      __syncthreads();  // all reads of the previous LDS contents are done
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int j = q + TQ * b;
+        if (act && (EXACT || j < L / R)) {
+          const int base = (j / NS) * NS * R + (j % NS);
+          const int ba = LW::off(base);
+#pragma unroll
+          for (int m = 0; m < R; ++m) lds[LW::write_splits ? ba + m * NS : LW::off(base + m * NS)] = v[b * R + m];
+        }
+      }
+      __syncthreads();  // writes visible before the next stage gathers
+    }
+  }
+  template <int NS, class LR, class TW, class Ld, int R, int... Rest>
+  __device__ __forceinline__ static void chain_ex(C2<T> (&v)[SLOTS], C2<T>* lds, int q, const TW& tw, Ld& ld,
+                                                  bool act, Radices<R, Rest...>) {
+    stage_ex<NS, R, NS == 1, sizeof...(Rest) == 0, LR>(v, lds, q, tw, ld, act);
+    if constexpr (sizeof...(Rest) > 0) chain_ex<NS * R, LayEx<NS, R>>(v, lds, q, tw, ld, act, Radices<Rest...>{});
+  }
+  template <class TW, class Ld>
+  __device__ __forceinline__ static void run_ex(C2<T> (&v)[SLOTS], C2<T>* lds, int q, const TW& tw, Ld ld,
+                                                bool act = true) {
+    chain_ex<1, LayEx<1, 1>>(v, lds, q, tw, ld, act, RL{});
+  }
+  // LDS slots of one transform's buffer under run_ex (the exchanges, and the
+  // natural-order copy callers keep after the last stage)
+  template <class RR>
+  struct ExSlots;
+  template <int... Rs>
+  struct ExSlots<Radices<Rs...>> {
+    static constexpr int value = [] {
+      int rs[] = {Rs...};
+      int m = L, ns = 1;
+      for (int r : rs) {
+        const int p = ns < 32 ? ns : 0, b = ns * r > 32 ? ns * r : 32;
+        const int sl = (p ? (L - 1) + p * ((L - 1) / b) : L - 1) + 1;
+        m = sl > m ? sl : m;
+        ns *= r;
+      }
+      return m;
+    }();
+  };
+  static constexpr int EX_SLOTS = ExSlots<RL>::value;
 
   // tw: table of exp(-2 pi i e / (L * twmul)), e < L * twmul.
   template <class Lay = LayStride, class Ld>

@@ -866,6 +866,198 @@ __global__ __launch_bounds__(xprod_slots(MHD, ELS) * RB * TQ) void k_x_prod(XArg
 }
 
 // ---------------------------------------------------------------------------
+// Fused x pass, packed form: two real rows per complex transform of the full
+// length N (z = x + i y), instead of one half-length transform with twiddled
+// pre- and post-processing per real row.
+//   inverse: for k = 0..N-1, Z[k] = X[k] + i Y[k] from the stored half spectra
+//            (X[N-k] = conj X[k] above N/2; only the real parts of the k = 0
+//            and k = N/2 bins, the pass-order convention), z = inverse DFT_N(Z);
+//            then x = Re z and y = Im z are the two physical rows;
+//   forward: z = p + i q for two product rows p, q, Z = DFT_N(z);
+//            P[k] = (Z[k] + conj Z[N-k]) / 2, Q[k] = -i (Z[k] - conj Z[N-k]) / 2.
+// Real rows are numbered r = f RB + rb (field f, grid row rb of the
+// workgroup, RB even); transform c carries real rows 2c and 2c + 1, one field
+// on two grid rows.  Transforms of
+// the inverse phase leave the physical rows in their LDS slots; the forward
+// phase forms each product from them in its first stage (ProdTerms) and
+// reuses the slots after the first stage's barrier.
+// ---------------------------------------------------------------------------
+// Products of the fused pass as sums of at most four terms s * f_a * f_b of
+// physical input fields (field numbering as k_x_prod's inputs and outputs).
+struct PTerm {
+  int a, b, s;  // s = 0: unused slot
+};
+struct ProdDef {
+  PTerm t[4];
+};
+__host__ __device__ constexpr ProdDef prod_def(bool mhd, bool els, int fo) {
+  if (els && mhd) {  // T_ij = z+_i z-_j (fields 0-2, 3-5), less z+_2 z-_2 on the diagonal
+    const int i = fo / 3, j = fo % 3;
+    if (i == j) return ProdDef{{{i, 3 + j, 1}, {2, 5, -1}, {0, 0, 0}, {0, 0, 0}}};
+    return ProdDef{{{i, 3 + j, 1}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}}};
+  }
+  if (els) {  // S_00 - S_22, S_11 - S_22, S_01, S_02, S_12 of S = u u
+    if (fo == 0) return ProdDef{{{0, 0, 1}, {2, 2, -1}, {0, 0, 0}, {0, 0, 0}}};
+    if (fo == 1) return ProdDef{{{1, 1, 1}, {2, 2, -1}, {0, 0, 0}, {0, 0, 0}}};
+    if (fo == 2) return ProdDef{{{0, 1, 1}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}}};
+    if (fo == 3) return ProdDef{{{0, 2, 1}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}}};
+    return ProdDef{{{1, 2, 1}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}}};
+  }
+  // rotational: inputs u (0-2), w (3-5) [, b (6-8), j (9-11)];
+  // component c of a x b is a_{c+1} b_{c+2} - a_{c+2} b_{c+1}
+  const int c = fo % 3, c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+  if (!mhd) return ProdDef{{{c1, 3 + c2, 1}, {c2, 3 + c1, -1}, {0, 0, 0}, {0, 0, 0}}};
+  if (fo < 3)  // u x w + j x b
+    return ProdDef{{{c1, 3 + c2, 1}, {c2, 3 + c1, -1}, {9 + c1, 6 + c2, 1}, {9 + c2, 6 + c1, -1}}};
+  return ProdDef{{{c1, 6 + c2, 1}, {c2, 6 + c1, -1}, {0, 0, 0}, {0, 0, 0}}};  // u x b
+}
+__host__ __device__ constexpr int xprod_fin(bool mhd, bool els) { return els ? (mhd ? 6 : 3) : mhd ? 12 : 6; }
+__host__ __device__ constexpr int xprod_fout(bool mhd, bool els) { return els ? (mhd ? 8 : 5) : mhd ? 6 : 3; }
+// complex transforms (workgroup slots) of the packed pass for RB grid rows
+__host__ __device__ constexpr int xpk_ninv(bool mhd, bool els, int rb) { return (xprod_fin(mhd, els) * rb + 1) / 2; }
+__host__ __device__ constexpr int xpk_nfwd(bool mhd, bool els, int rb) { return (xprod_fout(mhd, els) * rb + 1) / 2; }
+__host__ __device__ constexpr int xpk_slots(bool mhd, bool els, int rb) {
+  return xpk_ninv(mhd, els, rb) > xpk_nfwd(mhd, els, rb) ? xpk_ninv(mhd, els, rb) : xpk_nfwd(mhd, els, rb);
+}
+
+// EX: the Stockham exchanges use per-exchange layouts (LayEx, immediate
+// offsets) and rows are kept in natural order; otherwise every exchange and
+// row uses RLay.
+template <typename T, int N, int TQ, int RB, class RL, bool MHD, bool ELS, class RLay, bool EX>
+__global__ __launch_bounds__(xpk_slots(MHD, ELS, RB) * TQ) void k_x_prod_pk(XArgs<T> a) {
+  static_assert(RB % 2 == 0, "a transform pairs one field on two grid rows");
+  constexpr int FIN = xprod_fin(MHD, ELS), FOUT = xprod_fout(MHD, ELS);
+  constexpr int NI = xpk_ninv(MHD, ELS, RB), NO = xpk_nfwd(MHD, ELS, RB), W = xpk_slots(MHD, ELS, RB);
+  constexpr int NT = W * TQ;
+  using EI = Stockham<T, N, TQ, INV, RL>;
+  using EF = Stockham<T, N, TQ, FWD, RL>;
+  constexpr int LP = EX ? EI::EX_SLOTS : RLay::slots(N);
+  // element n of a row kept between the phases
+  auto roff = [](int n) { return EX ? n : RLay::off(n, 1); };
+  __shared__ C2<T> smem[W * LP + N];
+  C2<T>* tws = smem + W * LP;  // the transforms' twiddles, staged (TwStaged layout)
+  const int tid = threadIdx.x, q = tid % TQ;
+  // the transform index is uniform over a wave when a transform spans whole
+  // waves: keep it in a scalar register (row pointers and product terms
+  // then cost scalar, not vector, instructions)
+  const int c = TQ % 64 == 0 ? __builtin_amdgcn_readfirstlane(tid / TQ) : tid / TQ;
+  // grid rows of the workgroup: row0 + rb, rb < RB, in boxes of a.rows rows
+  // (one division per workgroup; a.rows >= RB)
+  const unsigned rows = (unsigned)a.rows, nrows = (unsigned)(a.rows * a.nb);
+  const unsigned row0 = (unsigned)xcd_remap(blockIdx.x, gridDim.x) * RB;
+  const unsigned box0 = row0 / rows, loc0 = row0 - box0 * rows;
+  auto row_of = [&](int rb, unsigned& box, unsigned& loc) {
+    box = box0;
+    loc = loc0 + rb;
+    if (loc >= rows) {
+      loc -= rows;
+      ++box;
+    }
+    return row0 + rb < nrows;
+  };
+  fill_staged<T, N>(tws, a.tw, 1, tid, NT, RL{});
+  __syncthreads();
+  const TwStaged<T> tw{tws};
+  C2<T>* buf = smem + c * LP;
+  // row pointer of input real row r (field r / RB, grid row r % RB), or null
+  auto in_row = [&](int r) -> const C2<T>* {
+    unsigned box, loc;
+    if (r >= FIN * RB || !row_of(r % RB, box, loc)) return nullptr;
+    return a.in + (long)box * a.in_bs + (long)(r / RB) * a.in_fs + (long)loc * a.in_pitch;
+  };
+  auto fft = [&](auto E, C2<T>(&v)[decltype(E)::SLOTS], auto ld, bool act) {
+    using EE = decltype(E);
+    if constexpr (EX)
+      EE::run_ex(v, buf, q, tw, ld, act);
+    else
+      EE::template run_tw<RLay>(v, buf, 1, q, tw, ld, act);
+  };
+  // ---- inverse: Z = X + i Y from the stored half spectra, in the first stage
+  {
+    const C2<T>* sx = in_row(2 * c);
+    const C2<T>* sy = in_row(2 * c + 1);
+    const bool act = c < NI;
+    C2<T> v[EI::SLOTS];
+    fft(EI{}, v,
+        [&](int, int k) -> C2<T> {
+          const bool up = k > N / 2;
+          const int kk = up ? N - k : k;           // stored index
+          const bool real_bin = kk == 0 || 2 * kk == N;
+          const bool live = kk <= a.kmax;
+          C2<T> x = sx && live ? sx[kk] : zero2<T>();
+          C2<T> y = sy && live ? sy[kk] : zero2<T>();
+          const T xi = real_bin ? T(0) : (up ? -x.y : x.y);
+          const T yi = real_bin ? T(0) : (up ? -y.y : y.y);
+          return C2<T>{x.x - yi, xi + y.x};
+        },
+        act);
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int s = 0; s < EI::LAST_NB * EI::RL_; ++s)
+        if (EI::last_valid(q, s)) buf[roff(EI::last_index(q, s))] = v[s];
+    }
+  }
+  __syncthreads();
+  // ---- forward: products of the physical rows, two per transform.  With RB
+  // even, transform c carries product field fo on grid rows rb and rb + 1
+  // (rb = 2c mod RB), and input field f on those two rows sits in one slot as
+  // (x, y): each term of the pair is one component-wise product of two slots.
+  const bool fact = c < NO;
+  {
+    const int fo = (2 * c) / RB, rb2 = ((2 * c) % RB) / 2;
+    C2<T> v[EF::SLOTS];
+    fft(EF{}, v,
+        [&](int, int n) -> C2<T> {
+          C2<T> acc = zero2<T>();
+          if (2 * c >= FOUT * RB) return acc;
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const PTerm pt = prod_def(MHD, ELS, fo).t[t];
+            if (pt.s != 0) {
+              const C2<T> x = smem[(pt.a * (RB / 2) + rb2) * LP + roff(n)];
+              const C2<T> y = smem[(pt.b * (RB / 2) + rb2) * LP + roff(n)];
+              acc = C2<T>{acc.x + T(pt.s) * x.x * y.x, acc.y + T(pt.s) * x.y * y.y};
+            }
+          }
+          return acc;
+        },
+        fact);
+    __syncthreads();
+    if (fact) {
+#pragma unroll
+      for (int s = 0; s < EF::LAST_NB * EF::RL_; ++s)
+        if (EF::last_valid(q, s)) buf[roff(EF::last_index(q, s))] = v[s];
+    }
+  }
+  __syncthreads();
+  if (!fact) return;
+  // ---- split the two spectra and store kx = 0 .. min(N/2, kmax)
+  const int kend = a.kmax < N / 2 ? a.kmax : N / 2;
+  C2<T>* dst[2] = {nullptr, nullptr};
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int p = 2 * c + h;
+    unsigned box, loc;
+    if (p < FOUT * RB && row_of(p % RB, box, loc))
+      dst[h] = a.out + (long)box * a.out_bs + (long)(p / RB) * a.out_fs + (long)loc * a.out_pitch;
+  }
+  for (int k = q; k <= kend; k += TQ) {
+    const C2<T> zk = buf[roff(k)];
+    const C2<T> zm = conj(buf[roff(k == 0 ? 0 : N - k)]);
+    const C2<T> P = T(0.5) * (zk + zm);
+    const C2<T> Q = T(0.5) * mul_mi(zk - zm);
+    if (a.nt) {
+      if (dst[0]) store_nt(dst[0] + k, P);
+      if (dst[1]) store_nt(dst[1] + k, Q);
+    } else {
+      if (dst[0]) dst[0][k] = P;
+      if (dst[1]) dst[1][k] = Q;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Shell spectra, deterministic.  Kernel 1: one workgroup per kz plane; the
 // thread owning shell s visits, for every ky of the plane, the contiguous kx
 // run of modes with round(|k|) = s and accumulates Q quantities with

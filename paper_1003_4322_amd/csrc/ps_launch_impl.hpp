@@ -233,9 +233,44 @@ hipError_t x_r2c_n(XArgs<T> a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// packed form: full-length complex transforms, two real rows each
+template <typename T, int N, int I>
+hipError_t x_prod_pk_v(bool mhd, bool els, XArgs<T> a, hipStream_t s) {
+  constexpr XV v = XPROD_V[I];
+  using LC = Sched<N, v.sched == 1>;
+  using X = XPkCfg<T, N, LC::TQ>;
+  constexpr int LIM = v.big ? 81920 : 65536;
+  using RLay = std::conditional_t<v.swz, LaySwz32, LayPad8>;
+  constexpr int LP = v.ex ? Stockham<T, N, LC::TQ, FWD, typename LC::RL>::EX_SLOTS : RLay::slots(N);
+  auto go = [&](auto mhd_c, auto els_c) -> hipError_t {
+    constexpr bool M_ = decltype(mhd_c)::value, E_ = decltype(els_c)::value;
+    constexpr int FI = xprod_fin(M_, E_), FO = xprod_fout(M_, E_);
+    // short transforms: enough rows per workgroup for about 256 threads
+    constexpr int want0 = M_ ? v.rb_mhd : v.rb_ns;
+    constexpr int wfill = 256 / (X::w(FI, FO, 1) * LC::TQ) > want0 ? 256 / (X::w(FI, FO, 1) * LC::TQ) : want0;
+    constexpr int RB = X::rb(FI, FO, wfill, LP, LIM);
+    if constexpr (!X::fits(FI, FO, RB, LP, 163840)) {
+      return hipErrorInvalidValue;
+    } else {
+      if (a.rows < RB) return hipErrorInvalidValue;  // the kernel assumes a box holds RB rows
+      const long grid = (a.rows * a.nb + RB - 1) / RB;
+      k_x_prod_pk<T, N, LC::TQ, RB, typename LC::RL, M_, E_, RLay, v.ex>
+          <<<dim3((unsigned)grid), dim3(xpk_slots(M_, E_, RB) * LC::TQ), 0, s>>>(a);
+      return hipGetLastError();
+    }
+  };
+  using t_ = std::true_type;
+  using f_ = std::false_type;
+  if (mhd && els) return go(t_{}, t_{});
+  if (mhd) return go(t_{}, f_{});
+  if (els) return go(f_{}, t_{});
+  return go(f_{}, f_{});
+}
+
 template <typename T, int N, int I>
 hipError_t x_prod_v(bool mhd, bool els, XArgs<T> a, hipStream_t s) {
   constexpr XV v = XPROD_V[I];
+  if constexpr (v.pk) return x_prod_pk_v<T, N, I>(mhd, els, a, s);
   using LC = std::conditional_t<v.sched == 2, LenWide<N / 2>, Sched<N / 2, v.sched == 1>>;
   using X = XCfg<T, N / 2, LC::TQ>;
   constexpr int LIM = v.big ? 81920 : 65536;  // LDS bytes per workgroup

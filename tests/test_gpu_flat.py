@@ -152,3 +152,45 @@ def test_fft768_sampled_and_roundtrip(B, ref, dt):
     err = float(((back / N ** 3 - u).norm() / u.norm()).item())
     assert err < (2e-6 if dt == "f32" else 1e-13), err
     p.close()
+
+
+# sampled modes of a 512^3 box: on and near the 2/3 sphere (|k| <= 170), low
+# modes, negative ky/kz, one outside the sphere
+SAMPLE512 = [(170, 0, 0), (0, 170, 0), (0, 0, 342), (100, 100, 60), (1, 511, 1), (120, 400, 20),
+             (160, 30, 500), (3, 5, 7), (40, 470, 400), (128, 256, 0)]
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+def test_xprod_variants_512_flat(B, ref, dt):
+    """Every product-pass variant (including the packed forms, whose 512-point
+    transforms span whole waves) at 512^3 on a flat MHD input, both forms,
+    pruned: against the oracle's triad sums at sampled modes and, over the
+    whole field, against the default variant (itself checked the same way)."""
+    N = 512
+    say("x_prod variants 512 flat: input and triad sums", dt)
+    x = flat(N, 91, 2, dt)
+    kx = np.array([s[0] for s in SAMPLE512]); ky = np.array([s[1] for s in SAMPLE512])
+    kz = np.array([s[2] for s in SAMPLE512])
+    want = ref.nonlinear_at(x, MHD, kx, ky, kz)           # [mode][field]
+    scale = np.abs(want).max(axis=1)
+    live = scale > 0
+    xd = to_dev(x, dt)
+    del x
+    p = B.Plan(N, 6, dt)
+    p.set_variant("prune", 1)
+    bad = []
+    for form in (0, 1):
+        p.set_variant("form", form)
+        p.set_variant("x_prod", 0)
+        base = p.nonlinear_mhd(xd).clone()
+        for v in range(p.variant_count("x_prod")):
+            p.set_variant("x_prod", v)
+            got_d = p.nonlinear_mhd(xd)
+            got = host(got_d[:, kz, ky, kx]).T
+            err = (np.abs(got - want).max(axis=1)[live] / scale[live]).max()
+            e0 = rel_l2_w_dev(got_d, base)
+            say(dt, "form", form, "x_prod", v, f"worst mode {err:.2e}, vs variant 0 {e0:.2e}")
+            if not (err < TOL_SHELL[dt] and e0 < TOL_NL[dt] and np.abs(got[~live]).max() == 0.0):
+                bad.append((form, v, err, e0))
+    p.close()
+    assert not bad, bad
