@@ -151,6 +151,7 @@ struct ZV {
   int minb;     // workgroups per CU the register allocator must leave room for (1: no request)
   bool alt;     // radix-16 schedule
   bool direct;  // z_curl: gather inputs per output field instead of holding them in registers
+  bool wide = false;  // wide schedule (LenWide: a last radix of 4 over twice the threads)
 };
 struct XV {
   int rb_ns, rb_mhd;  // rows per workgroup (reduced while the LDS tile would not fit)
@@ -163,7 +164,9 @@ struct XV {
 constexpr ZV ZCURL_V[] = {{1, 1, 1, false, false}, {1, 2, 1, false, false}, {1, 2, 2, false, false},
                           {1, 2, 1, true, false},  {1, 1, 1, false, true}};
 constexpr ZV ZEPI_V[] = {{0, 1, 1, false}, {1, 1, 1, false}, {1, 1, 2, false}, {1, 1, 1, true},
-                         {2, 1, 1, false}, {1, 2, 1, false}, {1, 2, 2, false}, {2, 2, 1, false}};
+                         {2, 1, 1, false}, {1, 2, 1, false}, {1, 2, 2, false}, {2, 2, 1, false},
+                         {0, 1, 1, false, false, true}, {1, 1, 1, false, false, true},
+                         {1, 1, 2, false, false, true}, {2, 1, 1, false, false, true}};
 constexpr ZV STR_V[] = {{0, 1, 1, false}, {1, 1, 1, false}, {0, 1, 1, true}, {1, 1, 1, true}};
 constexpr XV XPROD_V[] = {{2, 1, 0, false}, {4, 2, 0, false}, {4, 2, 1, false}, {2, 1, 1, false},
                           {2, 1, 0, true},  {4, 2, 0, true},  {1, 1, 2, true},  {1, 1, 2, false},

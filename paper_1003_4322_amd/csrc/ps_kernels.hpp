@@ -435,33 +435,25 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_z_epi(ZEpiArgs<T> a) {
 #pragma unroll
       for (int s = 0; s < NO; ++s) r[f][s] = zero2<T>();
     if constexpr (SPLIT == 1) {
-      // the loop over i stays rolled (a_i gathers in acc and moves to its
-      // place after each row) so that the eight transforms' loads are not
-      // stretched across each other
+      // one rolled loop over the eight products, so that a single transform's
+      // loads and temporaries are live at a time: a_i += k_j T_ij and
+      // c_j += k_i T_ij through selects on the loop's (i, j)
 #pragma unroll 1
-      for (int i3 = 0; i3 < 3; ++i3) {
-        C2<T> acc[NO];
-#pragma unroll
-        for (int s = 0; s < NO; ++s) acc[s] = zero2<T>();
-#pragma unroll
-        for (int j3 = 0; j3 < 3; ++j3) {
-          if (j3 == 2 && i3 == 2) break;  // T_22 is zero (uniform over the workgroup)
-          C2<T> v[E::SLOTS];
-          E::template run_tw<typename CT::Lay>(v, smem + c, TX, q, tw, ld_of(3 * i3 + j3));
-#pragma unroll
-          for (int s = 0; s < NO; ++s) {
-            const T kzd0 = a.sz * (T)dwav(E::last_index(q, s), L);
-            const T kj = j3 == 0 ? kxd0 : j3 == 1 ? kyd0 : kzd0;
-            const T ki = i3 == 0 ? kxd0 : i3 == 1 ? kyd0 : kzd0;
-            acc[s] = acc[s] + kj * v[s];
-            r[3 + j3][s] = r[3 + j3][s] + ki * v[s];
-          }
-        }
+      for (int f = 0; f < 8; ++f) {  // (2, 2) is zero
+        const int i3 = f / 3, j3 = f % 3;
+        C2<T> v[E::SLOTS];
+        E::template run_tw<typename CT::Lay>(v, smem + c, TX, q, tw, ld_of(f));
 #pragma unroll
         for (int s = 0; s < NO; ++s) {
-          r[0][s] = i3 == 0 ? acc[s] : r[0][s];
-          r[1][s] = i3 == 1 ? acc[s] : r[1][s];
-          r[2][s] = i3 == 2 ? acc[s] : r[2][s];
+          const T kzd0 = a.sz * (T)dwav(E::last_index(q, s), L);
+          const T kj = j3 == 0 ? kxd0 : j3 == 1 ? kyd0 : kzd0;
+          const T ki = i3 == 0 ? kxd0 : i3 == 1 ? kyd0 : kzd0;
+          r[0][s] = r[0][s] + (i3 == 0 ? kj : T(0)) * v[s];
+          r[1][s] = r[1][s] + (i3 == 1 ? kj : T(0)) * v[s];
+          r[2][s] = r[2][s] + (i3 == 2 ? kj : T(0)) * v[s];
+          r[3][s] = r[3][s] + (j3 == 0 ? ki : T(0)) * v[s];
+          r[4][s] = r[4][s] + (j3 == 1 ? ki : T(0)) * v[s];
+          r[5][s] = r[5][s] + (j3 == 2 ? ki : T(0)) * v[s];
         }
       }
     } else {

@@ -69,10 +69,14 @@ constexpr int zcurl_tx_of() {
   constexpr ZV v = ZCURL_V[I];
   return StridedTX<T, N, Sched<N, v.alt>::TQ, v.sh>::value;
 }
+// schedule of a z-pass variant: radix-16 (alt), wide (a last radix of 4
+// over twice the threads), or the default
+template <int N, int I>
+using ZepiSched = std::conditional_t<ZEPI_V[I].wide, LenWide<N>, Sched<N, ZEPI_V[I].alt>>;
+
 template <typename T, int N, int I>
 constexpr int zepi_tx_of() {
-  constexpr ZV v = ZEPI_V[I];
-  return StridedTX<T, N, Sched<N, v.alt>::TQ, v.sh>::value;
+  return StridedTX<T, N, ZepiSched<N, I>::TQ, ZEPI_V[I].sh>::value;
 }
 
 // grid of a z pass: every tile, or only those in the disk list
@@ -155,7 +159,7 @@ int z_curl_tx(int N, int var) {
 template <typename T, int N, int I, bool MHD, bool ELS = false>
 hipError_t z_epi_v(ZEpiArgs<T> a, const DiskTiles* dt, hipStream_t s) {
   constexpr ZV v = ZEPI_V[I];
-  using LC = Sched<N, v.alt>;
+  using LC = ZepiSched<N, I>;
   constexpr int TX = StridedTX<T, N, LC::TQ, v.sh>::value;
   constexpr int SPLIT = ELS && MHD && v.split >= 2 ? 2 : 1;
   if (a.g.nz != N) return hipErrorInvalidValue;
