@@ -427,6 +427,19 @@ def cpu_baseline(w, sample_N: int = 0, single_N: int = 128):
     return res
 
 
+def diagnostics(plan, state, nf):
+    """FP64 global quantities of the state (deterministic compensated sums):
+    MHD kinetic and magnetic energy and cross-helicity, or NS energy,
+    enstrophy and max |k . u|."""
+    if nf == 6:
+        _, t = plan.mhd_spectrum(state)
+        t = t.cpu().tolist()
+        return {"E_u": t[0], "E_b": t[1], "H_c": t[2]}
+    _, t = plan.energy_spectrum(state)
+    t = t.cpu().tolist()
+    return {"E": t[0], "Z": t[1], "maxdiv": t[2]}
+
+
 def run_primary(args, w, model, nf, N, dev):
     """The headline workload: FP32 timed region (+ FP64 side by side)."""
     import torch
@@ -439,11 +452,14 @@ def run_primary(args, w, model, nf, N, dev):
     plan32.set_variant("prune", PRUNE)
     plan32.set_variant("form", FORM)
     log("fp32 plan ready, workspace GB", plan32.workspace_bytes() / 1e9)
+    diag = {"initial": diagnostics(plan32, s32, nf)}
     tuned32 = None if args.no_tune else plan32.autotune(s32, model, 3)
     log("fp32 variants", tuned32)
     ms, stats, ms_graph = run_timed(plan32, s32, model, w, args.steps, args.warmup)
     passes32 = pass_table(stats)
     log(f"fp32: {ms:.3f} ms/step (graph replay {ms_graph:.3f})")
+    diag[f"after_{args.warmup + 2 * args.steps}_steps"] = diagnostics(plan32, s32, nf)
+    log("fp32 diagnostics", diag)
 
     dom = max(stats, key=lambda k: stats[k]["total_ms"])
     d = passes32[dom]
@@ -501,7 +517,7 @@ def run_primary(args, w, model, nf, N, dev):
                 "tolerance_per_step": 2e-6}
         log(f"fp32 vs fp64: one step {l2_1:.3e}, increment {inc:.3e}, run {l2_run:.3e}")
 
-    return ms, ms_graph, tuned32, passes32, roofline, fp64
+    return ms, ms_graph, tuned32, passes32, roofline, fp64, diag
 
 
 def main():
@@ -549,7 +565,7 @@ def main():
     N = w["N"]
     log(f"workload {args.workload}: N={N} fields={nf} steps={args.steps} warmup={args.warmup}")
 
-    ms, ms_graph, tuned32, passes32, roofline, fp64 = run_primary(args, w, model, nf, N, dev)
+    ms, ms_graph, tuned32, passes32, roofline, fp64, diag = run_primary(args, w, model, nf, N, dev)
     torch.cuda.empty_cache()
 
     extras = None
@@ -589,6 +605,7 @@ def main():
         "device_copy": copy_ref,
         "roofline": roofline,
         "fp64": fp64,
+        "diagnostics": diag,
         "extras": extras,
         "cpu_baseline": cpu,
         "src_hash": src_hash(),

@@ -421,8 +421,13 @@ struct Seq {
     if (!strcmp(kind, "z_curl")) return pass_zcurl(state, mhd);
     if (!strcmp(kind, "y")) return ypass(work(), b.P, wk_bs(), nphys(mhd), ps::INV, p->prune ? 1 : 0);
     if (!strcmp(kind, "x_prod")) return pass_xprod(mhd);
-    // as in the step's first stage (mode 1: pruned like the step, z* <- state)
-    if (!strcmp(kind, "z_epi")) return pass_zepi(mhd, 1, zstar(), state, nullptr, T(0), T(0), T(0));
+    // as in the step's two stages: mode 1 (z* <- state) and mode 2, which
+    // reads two state-sized buffers and updates one in place: here z*
+    // (updated) and the caller's state (only read)
+    if (!strcmp(kind, "z_epi")) {
+      ps_status st = pass_zepi(mhd, 1, zstar(), state, nullptr, T(0), T(0), T(0));
+      return st ? st : pass_zepi(mhd, 2, nullptr, zstar(), state, T(0), T(0), T(0));
+    }
     return fail(PS_ERR_ARG, std::string("no tuning launch for kind ") + kind);
   }
 
