@@ -244,9 +244,11 @@ ps_status ps_mhd_spectrum(ps_plan p, const void *zhat, double *spec_dev, double 
  * P(u div u) and by the aliases of the products); nothing checks the
  * precondition.  Kind "pipe" v: the inverse y pass, the product pass and
  * the forward y pass of each right-hand side run as 2^v slabs of z-planes
- * spread over helper streams (each plane's chain is independent of the
- * others'), so that one slab's memory-bound y passes overlap another's
- * compute-bound product pass; 0 = one slab on the plan's stream (default;
+ * (each plane's chain is independent of the others'): for v = 1..3 spread
+ * over helper streams, so that one slab's memory-bound y passes overlap
+ * another's compute-bound product pass; for v = 4..6 one after another on
+ * the plan's stream, so that each slab's chain finds its data in the
+ * last-level cache; 0 = one slab on the plan's stream (default;
  * ps_plan_autotune leaves this kind as set).  Setting a variant drops a
  * cached graph. */
 ps_status ps_plan_set_variant(ps_plan p, const char *kind, int variant);

@@ -144,8 +144,9 @@ namespace {
 size_t csize(const ps_plan_s* p) { return p->dtype == PS_F32 ? 8 : 16; }
 
 const char* const KINDS[] = {"y", "z", "z_curl", "z_epi", "x_prod", "batch", "prune", "form", "pipe"};
-// "pipe" variant v: the y / x / y passes run as 2^v z-slabs over the helper streams
-constexpr int NPIPE = 4;
+// "pipe" variant v: the y / x / y passes run as 2^v z-slabs, over the helper
+// streams for v = 1..3, one after another on the plan's stream for v = 4..6
+constexpr int NPIPE = 7;
 
 int var_of(const ps_plan_s* p, const char* kind) {
   auto it = p->var.find(kind);
@@ -391,9 +392,18 @@ struct Seq {
   ps_status rhs(const C* src, bool mhd, int mode, C* out, const C* st0, const C* st1, T h, T nua, T nub) {
     ps_status st = pass_zcurl(src, mhd);
     if (st) return st;
-    const int slabs = std::min(1 << var_of(p, "pipe"), b.nz);
+    const int pv = var_of(p, "pipe");
+    const int slabs = std::min(1 << pv, b.nz);
     if (slabs <= 1) {
       if ((st = yxy(mhd, 0, b.nz))) return st;
+    } else if (pv >= 4) {
+      // slabs in order on the plan's stream: each slab's chain (inverse y,
+      // products, forward y) works on data the previous pass of the chain
+      // has just left in the last-level cache
+      for (int i = 0; i < slabs; ++i) {
+        const int z0 = (int)((long)i * b.nz / slabs), z1 = (int)((long)(i + 1) * b.nz / slabs);
+        if ((st = yxy(mhd, z0, z1 - z0))) return st;
+      }
     } else {
       // fork the slabs over the helper streams (their memory-bound y passes
       // overlap other slabs' compute-bound product pass), then join
