@@ -256,7 +256,10 @@ int ps_plan_get_variant(ps_plan p, const char *kind);
 int ps_plan_variant_count(ps_plan p, const char *kind);
 
 /* Autotuner: times every variant of the RK2 passes (z_curl, y, x_prod, z_epi)
- * reps times on the caller's state for model m and keeps the fastest.  Reads
+ * over reps launches on the caller's state for model m, times the variants
+ * within 10 % of the fastest again in three interleaved rounds (each keeping
+ * its best time, so that clock drift over the sequence does not rank them)
+ * and keeps the fastest.  Reads
  * state, writes only the workspace; synchronises the plan's stream.  Plan
  * time, like FFT planning, is not part of a step (Sec. 4 leaves planning out
  * of its timings).  When the environment variable PS_TUNE_CACHE names a
@@ -282,7 +285,8 @@ ps_status ps_plan_timing_reset(ps_plan p);
 int ps_plan_timing_count(ps_plan p);
 /* Statistics of kind idx: name (static storage), total milliseconds, launch
  * count and algorithmic bytes moved per launch (reads + writes of the
- * values the pass must touch). */
+ * values the pass must touch), averaged over the kind's launches (the two
+ * RK stages' epilogues move different amounts). */
 ps_status ps_plan_timing_get(ps_plan p, int idx, const char **name, double *total_ms,
                              long *launches, double *bytes_per_launch);
 

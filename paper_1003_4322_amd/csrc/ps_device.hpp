@@ -344,6 +344,21 @@ __device__ __forceinline__ void fill_staged(C2<T>* dst, const C2<T>* tw, int twm
   }
 }
 
+// Exchange through LDS among the lanes of one wave.  A wave's LDS operations
+// complete in the order it issues them, so no s_barrier is needed; the
+// wavefront-scope fences and the wave barrier only keep the compiler from
+// moving LDS accesses across this point.  Every lane of the wave must reach it.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// WAVE (the run_* template argument): every transform is done by lanes of a
+// single wave (the group of TQ threads lies in one wave) in an LDS buffer of
+// its own, so the exchanges after the first need only wave_lds_sync.  The
+// first stage's pre-write barrier stays a workgroup barrier, because a first
+// stage may gather from other transforms' buffers (a product of fields).
 template <typename T, int L, int TQ, int DIR, class RL>
 struct Stockham {
   static constexpr int R1 = RadixInfo<RL>::first;
@@ -388,7 +403,7 @@ struct Stockham {
 
   // act = false: the thread only takes part in the barriers (its group has no
   // transform to do); v is left undefined
-  template <int NS, int R, bool FIRST, bool LAST, class Lay, class TW, class Ld>
+  template <int NS, int R, bool FIRST, bool LAST, class Lay, bool WAVE, class TW, class Ld>
   __device__ __forceinline__ static void stage(C2<T> (&v)[SLOTS], C2<T>* lds, int ls, int q, const TW& tw,
                                                Ld& ld, bool act) {
     constexpr int NB = cdiv(L / R, TQ);
@@ -427,7 +442,11 @@ struct Stockham {
     }
     if constexpr (!LAST) {
       constexpr bool SPLIT_W = Lay::SPLIT == 2 || (Lay::SPLIT == 1 && (NS % 8 == 0 || (NS == 1 && R % 8 == 0)));
-      __syncthreads();  // all reads of the previous LDS contents are done
+      // all reads of the previous LDS contents are done
+      if constexpr (WAVE && !FIRST)
+        wave_lds_sync();
+      else
+        __syncthreads();
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
         const int j = q + TQ * b;
@@ -441,21 +460,25 @@ struct Stockham {
           }
         }
       }
-      __syncthreads();  // writes visible before the next stage gathers
+      // writes visible before the next stage gathers
+      if constexpr (WAVE)
+        wave_lds_sync();
+      else
+        __syncthreads();
     }
   }
 
-  template <int NS, class Lay, class TW, class Ld, int R, int... Rest>
+  template <int NS, class Lay, bool WAVE, class TW, class Ld, int R, int... Rest>
   __device__ __forceinline__ static void chain(C2<T> (&v)[SLOTS], C2<T>* lds, int ls, int q, const TW& tw,
                                                Ld& ld, bool act, Radices<R, Rest...>) {
-    stage<NS, R, NS == 1, sizeof...(Rest) == 0, Lay>(v, lds, ls, q, tw, ld, act);
-    if constexpr (sizeof...(Rest) > 0) chain<NS * R, Lay>(v, lds, ls, q, tw, ld, act, Radices<Rest...>{});
+    stage<NS, R, NS == 1, sizeof...(Rest) == 0, Lay, WAVE>(v, lds, ls, q, tw, ld, act);
+    if constexpr (sizeof...(Rest) > 0) chain<NS * R, Lay, WAVE>(v, lds, ls, q, tw, ld, act, Radices<Rest...>{});
   }
 
   // ---- the same with a layout of its own per exchange (LayEx): stage
   // (NS, R) gathers through the layout of the exchange before it (LR) and
   // writes through LayEx<NS, R>.  One transform per buffer, unit stride.
-  template <int NS, int R, bool FIRST, bool LAST, class LR, class TW, class Ld>
+  template <int NS, int R, bool FIRST, bool LAST, class LR, bool WAVE, class TW, class Ld>
   __device__ __forceinline__ static void stage_ex(C2<T> (&v)[SLOTS], C2<T>* lds, int q, const TW& tw, Ld& ld,
                                                   bool act) {
     using LW = LayEx<NS, R>;
@@ -492,7 +515,11 @@ struct Stockham {
       }
     }
     if constexpr (!LAST) {
-      __syncthreads();  // all reads of the previous LDS contents are done
+      // all reads of the previous LDS contents are done
+      if constexpr (WAVE && !FIRST)
+        wave_lds_sync();
+      else
+        __syncthreads();
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
         const int j = q + TQ * b;
@@ -503,19 +530,25 @@ struct Stockham {
           for (int m = 0; m < R; ++m) lds[LW::write_splits ? ba + m * NS : LW::off(base + m * NS)] = v[b * R + m];
         }
       }
-      __syncthreads();  // writes visible before the next stage gathers
+      // writes visible before the next stage gathers
+      if constexpr (WAVE)
+        wave_lds_sync();
+      else
+        __syncthreads();
     }
   }
-  template <int NS, class LR, class TW, class Ld, int R, int... Rest>
+  template <int NS, class LR, bool WAVE, class TW, class Ld, int R, int... Rest>
   __device__ __forceinline__ static void chain_ex(C2<T> (&v)[SLOTS], C2<T>* lds, int q, const TW& tw, Ld& ld,
                                                   bool act, Radices<R, Rest...>) {
-    stage_ex<NS, R, NS == 1, sizeof...(Rest) == 0, LR>(v, lds, q, tw, ld, act);
-    if constexpr (sizeof...(Rest) > 0) chain_ex<NS * R, LayEx<NS, R>>(v, lds, q, tw, ld, act, Radices<Rest...>{});
+    stage_ex<NS, R, NS == 1, sizeof...(Rest) == 0, LR, WAVE>(v, lds, q, tw, ld, act);
+    if constexpr (sizeof...(Rest) > 0)
+      chain_ex<NS * R, LayEx<NS, R>, WAVE>(v, lds, q, tw, ld, act, Radices<Rest...>{});
   }
-  template <class TW, class Ld>
+  template <bool WAVE = false, class TW, class Ld>
   __device__ __forceinline__ static void run_ex(C2<T> (&v)[SLOTS], C2<T>* lds, int q, const TW& tw, Ld ld,
                                                 bool act = true) {
-    chain_ex<1, LayEx<1, 1>>(v, lds, q, tw, ld, act, RL{});
+    static_assert(!WAVE || (TQ <= 64 && 64 % TQ == 0), "WAVE needs each transform inside one wave");
+    chain_ex<1, LayEx<1, 1>, WAVE>(v, lds, q, tw, ld, act, RL{});
   }
   // LDS slots of one transform's buffer under run_ex (the exchanges, and the
   // natural-order copy callers keep after the last stage)
@@ -541,13 +574,14 @@ struct Stockham {
   template <class Lay = LayStride, class Ld>
   __device__ __forceinline__ static void run(C2<T> (&v)[SLOTS], C2<T>* lds, int ls, int q,
                                              const C2<T>* __restrict__ tw, int twmul, Ld ld) {
-    chain<1, Lay>(v, lds, ls, q, TwTable<T>{tw, twmul}, ld, true, RL{});
+    chain<1, Lay, false>(v, lds, ls, q, TwTable<T>{tw, twmul}, ld, true, RL{});
   }
   // any twiddle source (TwTable, TwStaged); act as in stage()
-  template <class Lay, class TW, class Ld>
+  template <class Lay, bool WAVE = false, class TW, class Ld>
   __device__ __forceinline__ static void run_tw(C2<T> (&v)[SLOTS], C2<T>* lds, int ls, int q, const TW& tw,
                                                 Ld ld, bool act = true) {
-    chain<1, Lay>(v, lds, ls, q, tw, ld, act, RL{});
+    static_assert(!WAVE || (TQ <= 64 && 64 % TQ == 0), "WAVE needs each transform inside one wave");
+    chain<1, Lay, WAVE>(v, lds, ls, q, tw, ld, act, RL{});
   }
 };
 

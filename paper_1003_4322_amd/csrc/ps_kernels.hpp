@@ -736,6 +736,8 @@ __global__ __launch_bounds__(xprod_slots(MHD, ELS) * RB * TQ) void k_x_prod(XArg
   // factors in the bank-friendly staged order, or (when that would not fit in
   // LDSLIM bytes) the plain table of length N = 2M, which serves both
   constexpr bool STAGED = (G * LP + 2 * M) * (int)sizeof(C2<T>) <= LDSLIM;
+  // a group of TQ <= 64 threads lies in one wave: wave-level exchanges
+  constexpr bool XW = TQ <= 64 && 64 % TQ == 0;
   __shared__ C2<T> smem[G * LP + 2 * M];
   C2<T>* twl = smem + G * LP;
   const int tid = threadIdx.x, g = tid / TQ, q = tid % TQ;
@@ -764,11 +766,11 @@ __global__ __launch_bounds__(xprod_slots(MHD, ELS) * RB * TQ) void k_x_prod(XArg
   {
     C2<T> v[EI::SLOTS];
     if constexpr (ELS)
-      EI::template run_tw<RLay>(
+      EI::template run_tw<RLay, XW>(
           v, buf, 1, q, twf,
           [&](int, int k) { return rok ? c2r_pre_g(src, k, M, a.kmax, twl) : zero2<T>(); }, in_act);
     else
-      EI::template run_tw<RLay>(v, buf, 1, q, twf, [&](int, int k) { return c2r_pre<T, RLay>(buf, k, M, twl); },
+      EI::template run_tw<RLay, XW>(v, buf, 1, q, twf, [&](int, int k) { return c2r_pre<T, RLay>(buf, k, M, twl); },
                                    in_act);
     __syncthreads();
     if (in_act) {
@@ -822,7 +824,7 @@ __global__ __launch_bounds__(xprod_slots(MHD, ELS) * RB * TQ) void k_x_prod(XArg
       const C2<T>* ra2 = smem + (2 * RB + rb) * LP;
       const C2<T>* rm2 = smem + ((MHD ? 5 : 2) * RB + rb) * LP;
       const bool diag = MHD ? f % 4 == 0 : f < 2;
-      EF::template run_tw<RLay>(
+      EF::template run_tw<RLay, XW>(
           v, buf, 1, q, twf,
           [&](int, int n) {
             const C2<T> x = ra[RLay::off(n, 1)], y = rm[RLay::off(n, 1)];
@@ -835,7 +837,7 @@ __global__ __launch_bounds__(xprod_slots(MHD, ELS) * RB * TQ) void k_x_prod(XArg
           },
           active);
     } else {
-      EF::template run_tw<RLay>(v, buf, 1, q, twf, [&](int, int n) { return buf[RLay::off(n, 1)]; }, active);
+      EF::template run_tw<RLay, XW>(v, buf, 1, q, twf, [&](int, int n) { return buf[RLay::off(n, 1)]; }, active);
     }
     __syncthreads();
     if (active) {
@@ -924,6 +926,8 @@ __global__ __launch_bounds__(xpk_slots(MHD, ELS, RB) * TQ) void k_x_prod_pk(XArg
   using EI = Stockham<T, N, TQ, INV, RL>;
   using EF = Stockham<T, N, TQ, FWD, RL>;
   constexpr int LP = EX ? EI::EX_SLOTS : RLay::slots(N);
+  // a transform's TQ <= 64 threads lie in one wave: wave-level exchanges
+  constexpr bool XW = TQ <= 64 && 64 % TQ == 0;
   // element n of a row kept between the phases
   auto roff = [](int n) { return EX ? n : RLay::off(n, 1); };
   __shared__ C2<T> smem[W * LP + N];
@@ -960,9 +964,9 @@ __global__ __launch_bounds__(xpk_slots(MHD, ELS, RB) * TQ) void k_x_prod_pk(XArg
   auto fft = [&](auto E, C2<T>(&v)[decltype(E)::SLOTS], auto ld, bool act) {
     using EE = decltype(E);
     if constexpr (EX)
-      EE::run_ex(v, buf, q, tw, ld, act);
+      EE::template run_ex<XW>(v, buf, q, tw, ld, act);
     else
-      EE::template run_tw<RLay>(v, buf, 1, q, tw, ld, act);
+      EE::template run_tw<RLay, XW>(v, buf, 1, q, tw, ld, act);
   };
   // ---- inverse: Z = X + i Y from the stored half spectra, in the first stage
   {
