@@ -365,7 +365,24 @@ def host_info():
                 info[k + "_GB"] = round(float(v.split()[0]) * 1024 / 1e9, 1)
     except OSError:
         pass
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        keep = ("CPU(s)", "Thread(s) per core", "Core(s) per socket", "Socket(s)", "NUMA node(s)",
+                "CPU max MHz", "L3 cache")
+        info["lscpu"] = {k.strip(): v.strip() for k, v in (l.split(":", 1) for l in out.splitlines() if ":" in l)
+                         if k.strip() in keep}
+    except (OSError, ValueError, subprocess.SubprocessError):
+        pass
     return info
+
+
+def model_step_bytes(N: int, nf: int, real_bytes: int = 8) -> float:
+    """Bytes of one RK2 step in the fused-pipeline byte model (93 half-spectrum
+    fields for NS, 186 for MHD, unpruned), the yardstick the oracle's rate is
+    quoted on."""
+    sc = N * N * (N // 2 + 1) * 2.0 * real_bytes
+    return (186 if nf == 6 else 93) * sc
 
 
 def oracle_step_bytes(N: int, nf: int) -> float:
@@ -420,9 +437,11 @@ def cpu_baseline(w, sample_N: int = 0, single_N: int = 128):
                      ("" if sample_N == N else f"; the {N}^3 step does not fit this host's memory, "
                                                f"so the value is the {sample_N}^3 rate, not scaled"),
            "measured": {"N": sample_N, "threads": cores, "s_per_step": round(t_all, 3),
-                        "steps_per_s": round(1.0 / t_all, 5)},
+                        "steps_per_s": round(1.0 / t_all, 5),
+                        "GB_per_s_byte_model": round(model_step_bytes(sample_N, nf) / t_all / 1e9, 3)},
            "single_thread": {"N": single_N, "threads": 1, "s_per_step": round(t_one, 3),
-                             "steps_per_s": round(1.0 / t_one, 5)},
+                             "steps_per_s": round(1.0 / t_one, 5),
+                             "GB_per_s_byte_model": round(model_step_bytes(single_N, nf) / t_one / 1e9, 3)},
            "host": host}
     return res
 

@@ -69,11 +69,29 @@ __global__ __launch_bounds__(1024) void k_spec_final(const double* part, const d
   for (int s0 = 0; s0 < nshell; s0 += blockDim.x) {
     const int s = s0 + threadIdx.x;
     if (s < nshell) {
+      // planes in order; the loads of U planes are issued before their adds
+      constexpr int U = 8;
+      NSum e[Q];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) e[q] = NSum{0, 0};
+      int p = 0;
+      for (; p + U <= nplanes; p += U) {
+        double v[U][Q];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+          for (int q = 0; q < Q; ++q) v[u][q] = part[((long)(p + u) * nshell + s) * Q + q];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+          for (int q = 0; q < Q; ++q) nadd(e[q], v[u][q]);
+      }
+      for (; p < nplanes; ++p)
+#pragma unroll
+        for (int q = 0; q < Q; ++q) nadd(e[q], part[((long)p * nshell + s) * Q + q]);
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
-        NSum e{0, 0};
-        for (int p = 0; p < nplanes; ++p) nadd(e, part[((long)p * nshell + s) * Q + q]);
-        const double v = e.s + e.c;
+        const double v = e[q].s + e[q].c;
         sh[q][threadIdx.x] = v;
         if (Q == 3)
           spec[q * nshell + s] = v;
@@ -104,10 +122,12 @@ __global__ __launch_bounds__(1024) void k_spec_final(const double* part, const d
 
 template <typename T>
 hipError_t launch_spectrum(SpecArgs<T> a, bool mhd, double* spec, double* totals, hipStream_t s) {
+  // at most one 64-shell window per wave, at most SPEC_NF fields
+  if (a.nshell > 64 * SPEC_WAVES || (!mhd && a.nf > SPEC_NF)) return hipErrorInvalidValue;
   if (mhd)
-    k_spec_planes<T, true><<<dim3(a.nz), dim3(256), 0, s>>>(a);
+    k_spec_planes<T, true><<<dim3(a.nz), dim3(SPEC_WAVES * 64), 0, s>>>(a);
   else
-    k_spec_planes<T, false><<<dim3(a.nz), dim3(256), 0, s>>>(a);
+    k_spec_planes<T, false><<<dim3(a.nz), dim3(SPEC_WAVES * 64), 0, s>>>(a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (mhd)

@@ -1054,18 +1054,28 @@ __global__ __launch_bounds__(xpk_slots(MHD, ELS, RB) * TQ) void k_x_prod_pk(XArg
 }
 
 // ---------------------------------------------------------------------------
-// Shell spectra, deterministic.  Kernel 1: one workgroup per kz plane; the
-// thread owning shell s visits, for every ky of the plane, the contiguous kx
-// run of modes with round(|k|) = s and accumulates Q quantities with
-// Neumaier compensation in a fixed order.  Kernel 2 sums the per-plane
-// partials over planes in order.  No atomics, so results are bitwise
-// reproducible.
+// Shell spectra, deterministic.  Kernel 1: one workgroup per kz plane.
+// The shells are cut into windows of 64 (window w: shells 64 w .. 64 w + 63,
+// lane l of a wave owning shell 64 w + l), and each window gets R =
+// SPEC_WAVES / (number of windows) waves, wave r of a window visiting the
+// rows ky = r, r + R, ... in order.  The modes of a row whose shells fall in
+// the window form one contiguous kx range (the shell of (kx, ky, kz) does not
+// decrease with kx); the wave reads it in chunks of 64 consecutive kx, one
+// mode per lane (the next chunk's loads issued before the current chunk is
+// summed), sums each shell's run within the chunk by a segmented scan across
+// the lanes, and hands each run's sum to the shell's lane, which adds it to Q
+// Neumaier-compensated sums.  The R partial sums of a shell are then added
+// in the order r = 0 .. R - 1.  Every shell's terms are thus added in one
+// fixed order.  Kernel 2 sums the per-plane partials over planes in order.
+// No atomics, so results are bitwise reproducible.
 //   energy (Q = 2): E(s) = 1/2 sum w |f|^2 and Z(s) = 1/2 sum w |k|^2 |f|^2
 //                   over nf fields, plus max |k_d . f| per plane;
 //   MHD    (Q = 3): with u = (z+ + z-)/2, b = (z+ - z-)/2 (fields 0-2, 3-5):
 //                   Eu(s) = 1/2 sum w |u|^2, Eb(s) = 1/2 sum w |b|^2,
 //                   Hc(s) = 1/2 sum w Re(u . conj b).
 // ---------------------------------------------------------------------------
+constexpr int SPEC_WAVES = 16;  // waves per workgroup; nshell <= 64 SPEC_WAVES
+constexpr int SPEC_NF = 6;      // fields a spectrum reads at most
 struct NSum {
   double s, c;
 };
@@ -1095,76 +1105,159 @@ struct SpecArgs {
   double sx, sy, sz;  // box factors 2 pi / L (enstrophy and divergence; shells stay on the index)
 };
 
+// shell of |k|^2 = k2: the smallest s with 4 k2 < (2 s + 1)^2
+__device__ __forceinline__ int shell_of_k2(long k2) { return (int)((isqrt_floor(4 * k2) + 1) / 2); }
+
 template <typename T, bool MHD>
-__global__ __launch_bounds__(256) void k_spec_planes(SpecArgs<T> a) {
+__global__ __launch_bounds__(SPEC_WAVES * 64) void k_spec_planes(SpecArgs<T> a) {
   constexpr int Q = MHD ? 3 : 2;
   const int kz = blockIdx.x, NX = a.nx, NY = a.ny, H = NX / 2 + 1;
+  const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
+  const int nwin = (a.nshell + 63) / 64, R = SPEC_WAVES / nwin;  // nwin <= SPEC_WAVES (host check)
+  const int win = wv % nwin, grp = wv / nwin;
+  const bool active = grp < R;
+  const int s0 = 64 * win, own = s0 + lane;  // this lane's shell
   const long izw = wav(kz, a.nz);
   const double kzd = a.sz * dwav(kz, a.nz);
   const double qz2 = a.sz * a.sz * (double)(izw * izw);
-  __shared__ double red[256];
-  double mx = 0;
-  for (int s = threadIdx.x; s < a.nshell; s += blockDim.x) {
-    NSum acc[Q];
+  const int nf = MHD ? 6 : a.nf;
+  __shared__ double seg[SPEC_WAVES][64][Q];
+  __shared__ double red[SPEC_WAVES * 64];
+  double (*sg)[Q] = seg[wv];
 #pragma unroll
-    for (int qq = 0; qq < Q; ++qq) acc[qq] = NSum{0, 0};
-    const long lo2 = (long)(2 * s - 1) * (2 * s - 1);  // shell s: lo2 <= 4|k|^2 < hi2
-    const long hi2 = (long)(2 * s + 1) * (2 * s + 1);
-    for (int ky = 0; ky < NY; ++ky) {
+  for (int qq = 0; qq < Q; ++qq) sg[lane][qq] = 0.0;
+  wave_lds_sync();
+  NSum acc[Q];
+#pragma unroll
+  for (int qq = 0; qq < Q; ++qq) acc[qq] = NSum{0, 0};
+  double mx = 0;
+  // shells s0 .. s1 of the window: 4|k|^2 in [lo2, hi2)
+  const int s1 = s0 + 63 < a.nshell - 1 ? s0 + 63 : a.nshell - 1;
+  const long lo2 = (long)(2 * s0 - 1) * (2 * s0 - 1);
+  const long hi2 = (long)(2 * s1 + 1) * (2 * s1 + 1);
+  // the wave's chunks in order: row ky (kx range ..kx1, ky^2 + kz^2 = A),
+  // first kx base; uniform over the wave
+  int ky = grp - R;
+  long base = 0, kx1 = -1, A = 0;
+  auto advance = [&]() -> bool {
+    base += 64;
+    while (base > kx1) {
+      ky += R;
+      if (ky >= NY) return false;
       const long iyw = wav(ky, NY);
-      const long A4 = 4 * (iyw * iyw + izw * izw);
+      A = iyw * iyw + izw * izw;
+      const long A4 = 4 * A;
+      kx1 = -1;
       if (A4 >= hi2) continue;
       long kx0 = 0;
-      if (s > 0 && lo2 - A4 > 0) {  // smallest kx with 4 kx^2 >= lo2 - A4
+      if (s0 > 0 && lo2 - A4 > 0) {  // smallest kx with 4 kx^2 >= lo2 - A4
         const long B = lo2 - A4;
         long t = isqrt_floor(B);
-        if (t * t < B) ++t;  // ceil sqrt
+        if (t * t < B) ++t;
         kx0 = (t + 1) / 2;
       }
-      long kx1 = isqrt_floor(hi2 - A4 - 1) / 2;  // largest kx with 4 kx^2 < hi2 - A4
+      kx1 = isqrt_floor(hi2 - A4 - 1) / 2;  // largest kx with 4 kx^2 < hi2 - A4
       if (kx1 > H - 1) kx1 = H - 1;
-      const C2<T>* row = a.f + (long)kz * NY * a.pitch + (long)ky * a.pitch;
-      const double kyd = a.sy * dwav(ky, NY);
-      const double qyz2 = a.sy * a.sy * (double)(iyw * iyw) + qz2;
-      for (long kx = kx0; kx <= kx1; ++kx) {
-        const double w = (kx == 0 || 2 * kx == NX) ? 0.5 : 1.0;  // (1/2) * weight
-        if constexpr (MHD) {
-          double eu = 0, eb = 0, hc = 0;
+      base = kx0;
+    }
+    return true;
+  };
+  auto load = [&](C2<T>(&x)[SPEC_NF]) {
+    const long kx = base + lane;
+    const C2<T>* row = a.f + (long)kz * NY * a.pitch + (long)ky * a.pitch + kx;
 #pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            const C2<T> zp = row[c * a.fs + kx], zm = row[(3 + c) * a.fs + kx];
-            const double ux = 0.5 * ((double)zp.x + (double)zm.x), uy = 0.5 * ((double)zp.y + (double)zm.y);
-            const double bx = 0.5 * ((double)zp.x - (double)zm.x), by = 0.5 * ((double)zp.y - (double)zm.y);
-            eu += ux * ux + uy * uy;
-            eb += bx * bx + by * by;
-            hc += ux * bx + uy * by;
-          }
-          nadd(acc[0], w * eu);
-          nadd(acc[1], w * eb);
-          nadd(acc[2], w * hc);
-        } else {
-          double e = 0;
-          for (int ff = 0; ff < a.nf; ++ff) {
-            const C2<T> v = row[ff * a.fs + kx];
-            e += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
-          }
-          const double q2 = a.sx * a.sx * (double)(kx * kx) + qyz2;  // physical |k|^2
-          nadd(acc[0], w * e);
-          nadd(acc[1], w * q2 * e);
-          const double kxd = a.sx * dwavx((int)kx, NX);
-          for (int ff = 0; ff + 2 < a.nf; ff += 3) {
-            const C2<T> v0 = row[ff * a.fs + kx], v1 = row[(ff + 1) * a.fs + kx], v2 = row[(ff + 2) * a.fs + kx];
-            const double dx = kxd * v0.x + kyd * v1.x + kzd * v2.x;
-            const double dy = kxd * v0.y + kyd * v1.y + kzd * v2.y;
+    for (int ff = 0; ff < SPEC_NF; ++ff) x[ff] = kx <= kx1 && ff < nf ? row[ff * a.fs] : zero2<T>();
+  };
+  bool have = active && advance();
+  C2<T> cur[SPEC_NF];
+  if (have) load(cur);
+  while (have) {
+    const int cky = ky;
+    const long ckx = base + lane, ckx1 = kx1, cA = A;
+    have = advance();
+    C2<T> nxt[SPEC_NF];
+    if (have) load(nxt);  // in flight while this chunk is summed
+    const bool live = ckx <= ckx1;
+    const int sh = live ? shell_of_k2(ckx * ckx + cA) : s1 + 1;  // past the window: its own segment
+    double v[Q];
+#pragma unroll
+    for (int qq = 0; qq < Q; ++qq) v[qq] = 0.0;
+    if (live) {
+      const double w = (ckx == 0 || 2 * ckx == NX) ? 0.5 : 1.0;  // (1/2) * weight
+      if constexpr (MHD) {
+        double eu = 0, eb = 0, hc = 0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const C2<T> zp = cur[c], zm = cur[3 + c];
+          const double ux = 0.5 * ((double)zp.x + (double)zm.x), uy = 0.5 * ((double)zp.y + (double)zm.y);
+          const double bx = 0.5 * ((double)zp.x - (double)zm.x), by = 0.5 * ((double)zp.y - (double)zm.y);
+          eu += ux * ux + uy * uy;
+          eb += bx * bx + by * by;
+          hc += ux * bx + uy * by;
+        }
+        v[0] = w * eu;
+        v[1] = w * eb;
+        v[2] = w * hc;
+      } else {
+        double e = 0;
+#pragma unroll
+        for (int ff = 0; ff < SPEC_NF; ++ff)
+          e += (double)cur[ff].x * (double)cur[ff].x + (double)cur[ff].y * (double)cur[ff].y;
+        const long iyw = wav(cky, NY);
+        const double q2 = a.sx * a.sx * (double)(ckx * ckx) + a.sy * a.sy * (double)(iyw * iyw) + qz2;
+        v[0] = w * e;
+        v[1] = w * q2 * e;
+        const double kxd = a.sx * dwavx((int)ckx, NX), kyd = a.sy * dwav(cky, NY);
+#pragma unroll
+        for (int ff = 0; ff + 2 < SPEC_NF; ff += 3) {
+          if (ff + 2 < nf) {
+            const double dx = kxd * cur[ff].x + kyd * cur[ff + 1].x + kzd * cur[ff + 2].x;
+            const double dy = kxd * cur[ff].y + kyd * cur[ff + 1].y + kzd * cur[ff + 2].y;
             const double d = sqrt(dx * dx + dy * dy);
             mx = d > mx ? d : mx;
           }
         }
       }
     }
-    double* p = a.part + ((long)kz * a.nshell + s) * Q;
+    // inclusive segmented scan over the lanes (segments: equal shells,
+    // contiguous because sh does not decrease with the lane)
 #pragma unroll
-    for (int qq = 0; qq < Q; ++qq) p[qq] = acc[qq].s + acc[qq].c;
+    for (int d = 1; d < 64; d *= 2) {
+      const int shd = __shfl_up(sh, d, 64);
+#pragma unroll
+      for (int qq = 0; qq < Q; ++qq) {
+        const double vd = __shfl_up(v[qq], d, 64);
+        if (lane >= d && shd == sh) v[qq] += vd;
+      }
+    }
+    const int shn = __shfl_down(sh, 1, 64);
+    if (live && (lane == 63 || shn != sh)) {  // last lane of its run
+#pragma unroll
+      for (int qq = 0; qq < Q; ++qq) sg[sh - s0][qq] = v[qq];
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int qq = 0; qq < Q; ++qq) {
+      nadd(acc[qq], sg[lane][qq]);  // + 0 where this chunk has no run of the shell
+      sg[lane][qq] = 0.0;
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int ff = 0; ff < SPEC_NF; ++ff) cur[ff] = nxt[ff];
+  }
+  // the R partials of each shell, in row-group order
+  __syncthreads();
+#pragma unroll
+  for (int qq = 0; qq < Q; ++qq) sg[lane][qq] = acc[qq].s + acc[qq].c;
+  __syncthreads();
+  if (active && grp == 0 && own < a.nshell) {
+    double* p = a.part + ((long)kz * a.nshell + own) * Q;
+#pragma unroll
+    for (int qq = 0; qq < Q; ++qq) {
+      NSum t{0, 0};
+      for (int r = 0; r < R; ++r) nadd(t, seg[win + r * nwin][lane][qq]);
+      p[qq] = t.s + t.c;
+    }
   }
   if constexpr (!MHD) {
     red[threadIdx.x] = mx;

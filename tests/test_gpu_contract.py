@@ -145,6 +145,41 @@ def test_mhd_spectrum(B, ref, N, dt):
     assert abs(host(et)[0] - 2 * (tot[0] + tot[1])) <= 1e-12 * host(et)[0]
 
 
+def test_spectra_bitwise_reproducible(B):
+    """Fixed-order sums: the same state gives the same bits, call after call."""
+    say("spectra reproducible")
+    N = 96
+    z = synth.random_mhd(N, 41, 42, 6.0)
+    p = B.Plan(N, 6, "f64")
+    zd = to_dev(z, "f64")
+    a = [t.clone() for t in p.mhd_spectrum(zd)]
+    b = p.mhd_spectrum(zd)
+    assert all(torch.equal(x, y) for x, y in zip(a, b))
+    a = [t.clone() for t in p.energy_spectrum(zd)]
+    b = p.energy_spectrum(zd)
+    assert all(torch.equal(x, y) for x, y in zip(a, b))
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_mhd_spectrum_384(B, ref, dt):
+    """333 shells: more than one round of shells per workgroup."""
+    say("mhd spectrum 384", dt)
+    N = 384
+    rng = np.random.default_rng(777)
+    s = (6, N, N, N // 2 + 1)
+    z = rounded(rng.standard_normal(s) + 1j * rng.standard_normal(s), dt)
+    p = B.Plan(N, 6, dt)
+    spec, tot = p.mhd_spectrum(to_dev(z, dt))
+    ws, wt = ref.mhd_spectrum(z)
+    del z
+    spec, tot = host(spec), host(tot)
+    scale = ws[0] + ws[1]
+    assert ws.shape[1] > 256
+    assert (np.abs(spec - ws) <= 1e-13 * scale[None, :] + 1e-300).all()
+    assert np.abs(tot - wt).max() <= 1e-13 * (wt[0] + wt[1])
+    p.close()
+
+
 def test_mhd_spectrum_ensemble(B, ref):
     say("mhd spectrum ensemble")
     sizes = [16, 16, 24]
