@@ -152,6 +152,7 @@ struct ZV {
   bool alt;     // radix-16 schedule
   bool direct;  // z_curl: gather inputs per output field instead of holding them in registers
   bool wide = false;  // wide schedule (LenWide: a last radix of 4 over twice the threads)
+  bool tws = false;   // strided passes: twiddles staged in LDS beside the tile
 };
 struct XV {
   int rb_ns, rb_mhd;  // rows per workgroup (reduced while the LDS tile would not fit)
@@ -167,7 +168,8 @@ constexpr ZV ZEPI_V[] = {{0, 1, 1, false}, {1, 1, 1, false}, {1, 1, 2, false}, {
                          {2, 1, 1, false}, {1, 2, 1, false}, {1, 2, 2, false}, {2, 2, 1, false},
                          {0, 1, 1, false, false, true}, {1, 1, 1, false, false, true},
                          {1, 1, 2, false, false, true}, {2, 1, 1, false, false, true}};
-constexpr ZV STR_V[] = {{0, 1, 1, false}, {1, 1, 1, false}, {0, 1, 1, true}, {1, 1, 1, true}};
+constexpr ZV STR_V[] = {{0, 1, 1, false}, {1, 1, 1, false}, {0, 1, 1, true}, {1, 1, 1, true},
+                        {0, 1, 1, true, false, false, true}, {0, 1, 1, false, false, false, true}};
 constexpr XV XPROD_V[] = {{2, 1, 0, false}, {4, 2, 0, false}, {4, 2, 1, false}, {2, 1, 1, false},
                           {2, 1, 0, true},  {4, 2, 0, true},  {1, 1, 2, true},  {1, 1, 2, false},
                           {8, 4, 0, true, true}, {8, 4, 0, false, true}, {4, 2, 2, true, true},

@@ -83,11 +83,13 @@ struct StridedArgs {
   int nt;  // inverse passes: streaming stores (set when the output far exceeds the caches)
 };
 
-template <typename T, int L, int TQ, int TX, int DIR, class RL, int MINW = 1>
+// TWS: the transform's twiddles staged in LDS beside the tile (TwStaged)
+// instead of read from the table in global memory at every stage.
+template <typename T, int L, int TQ, int TX, int DIR, class RL, int MINW = 1, bool TWS = false>
 __global__ __launch_bounds__(TX* TQ, MINW) void k_strided(StridedArgs<T> a) {
   using E = Stockham<T, L, TQ, DIR, RL>;
   using CT = ColTile<T, L, TX, 0>;
-  __shared__ C2<T> smem[CT::ROWS * TX];
+  __shared__ C2<T> smem[CT::ROWS * TX + (TWS ? L : 0)];
   const int tid = threadIdx.x, c = tid % TX, q = tid / TX;
   int blk = xcd_remap(blockIdx.x, gridDim.x);
   const int tile = blk % a.ntile;
@@ -102,9 +104,16 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_strided(StridedArgs<T> a) {
   const C2<T>* in = a.in + box * a.in_bs + f * a.in_fs + line * a.in_ls + col;
   C2<T>* out = a.out + box * a.out_bs + f * a.out_fs + line * a.out_ls + col;
   C2<T> v[E::SLOTS];
-  E::template run<typename CT::Lay>(v, smem + c, TX, q, a.tw, 1, [&](int, int idx) {
-    return ok && (a.prune != 1 || in_disk(idx)) ? in[idx * a.in_es] : zero2<T>();
-  });
+  auto ld = [&](int, int idx) { return ok && (a.prune != 1 || in_disk(idx)) ? in[idx * a.in_es] : zero2<T>(); };
+  if constexpr (TWS) {
+    // read only from the second stage on: the first stage's barrier before
+    // its LDS writes orders the fill before every read
+    static_assert(E::NSTAGE > 1, "a single-stage transform has no twiddles to stage");
+    fill_staged<T, L>(smem + CT::ROWS * TX, a.tw, 1, tid, TX * TQ, RL{});
+    E::template run_tw<typename CT::Lay>(v, smem + c, TX, q, TwStaged<T>{smem + CT::ROWS * TX}, ld);
+  } else {
+    E::template run<typename CT::Lay>(v, smem + c, TX, q, a.tw, 1, ld);
+  }
   if constexpr (E::NSTAGE == 1) __syncthreads();  // in place: all reads before any write
 #pragma unroll
   for (int s = 0; s < E::LAST_NB * E::RL_; ++s) {

@@ -35,10 +35,14 @@ hipError_t strided_v(int dir, StridedArgs<T> a, hipStream_t s) {
     while (a.ntile > 0 && !a.g.disk((a.ntile - 1) * TX, 0)) --a.ntile;
   const long grid = (long)a.ntile * a.nlines * a.nf * a.nb;
   if (grid <= 0) return hipSuccess;
+  // staged twiddles only where the transform has more than one stage
+  constexpr bool TWS = v.tws && RadixInfo<typename LC::RL>::count > 1;
   if (dir == FWD)
-    k_strided<T, N, LC::TQ, TX, FWD, typename LC::RL, waves_per_simd(v.minb, TX * LC::TQ)><<<dim3((unsigned)grid), dim3(TX * LC::TQ), 0, s>>>(a);
+    k_strided<T, N, LC::TQ, TX, FWD, typename LC::RL, waves_per_simd(v.minb, TX * LC::TQ), TWS>
+        <<<dim3((unsigned)grid), dim3(TX * LC::TQ), 0, s>>>(a);
   else
-    k_strided<T, N, LC::TQ, TX, INV, typename LC::RL, waves_per_simd(v.minb, TX * LC::TQ)><<<dim3((unsigned)grid), dim3(TX * LC::TQ), 0, s>>>(a);
+    k_strided<T, N, LC::TQ, TX, INV, typename LC::RL, waves_per_simd(v.minb, TX * LC::TQ), TWS>
+        <<<dim3((unsigned)grid), dim3(TX * LC::TQ), 0, s>>>(a);
   return hipGetLastError();
 }
 
