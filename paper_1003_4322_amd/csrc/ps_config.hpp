@@ -163,7 +163,8 @@ struct XV {
   bool ex = false;    // packed form: per-exchange LDS layouts (LayEx) and rows in natural order
 };
 constexpr ZV ZCURL_V[] = {{1, 1, 1, false, false}, {1, 2, 1, false, false}, {1, 2, 2, false, false},
-                          {1, 2, 1, true, false},  {1, 1, 1, false, true}};
+                          {1, 2, 1, true, false},  {1, 1, 1, false, true},  {0, 2, 1, true, false},
+                          {0, 1, 1, true, false}};
 constexpr ZV ZEPI_V[] = {{0, 1, 1, false}, {1, 1, 1, false}, {1, 1, 2, false}, {1, 1, 1, true},
                          {2, 1, 1, false}, {1, 2, 1, false}, {1, 2, 2, false}, {2, 2, 1, false},
                          {0, 1, 1, false, false, true}, {1, 1, 1, false, false, true},

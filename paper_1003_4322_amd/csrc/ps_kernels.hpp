@@ -53,10 +53,11 @@ struct ColTile {
   static constexpr int ROWS = PAD ? ROWS_PAD : L;
   using Lay = std::conditional_t<PAD, LayColPad8, LayStride>;
   // a table of L twiddles fits beside the tile without lowering the number
-  // of workgroups that fit in a CU's 160 KB of LDS
+  // of workgroups that fit in a CU's 160 KB of LDS (a workgroup may hold up
+  // to 80 KB of it here, two per CU)
   static constexpr int BYTES = ROWS * TX * (int)sizeof(C2<T>);
   static constexpr bool TW_FITS =
-      BYTES + L * (int)sizeof(C2<T>) <= 65536 &&
+      BYTES + L * (int)sizeof(C2<T>) <= 81920 &&
       163840 / (BYTES + L * (int)sizeof(C2<T>)) == 163840 / BYTES;
 };
 
