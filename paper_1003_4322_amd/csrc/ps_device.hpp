@@ -324,24 +324,22 @@ struct TwStaged {
     return t[(NS - 1) + (m - 1) * NS + k];
   }
 };
+// entry idx of the TwStaged layout, found stage by stage with the span NS a
+// compile-time constant (the divisions by NS are shifts or constant divisions)
+template <typename T, int L, int NS, int R, int... Rest>
+__device__ __forceinline__ void fill_staged_at(C2<T>* dst, const C2<T>* tw, int twmul, int idx) {
+  if (idx < NS * R - 1) {
+    const int r = idx - (NS - 1), m = 1 + r / NS, k = r % NS;
+    dst[idx] = tw[(m * k * (L / (NS * R))) * twmul];
+  } else if constexpr (sizeof...(Rest) > 0) {
+    fill_staged_at<T, L, NS * R, Rest...>(dst, tw, twmul, idx);
+  }
+}
 // fill dst[0, L - 1) with the TwStaged layout of schedule RL from a plain table
 template <typename T, int L, int... Rs>
 __device__ __forceinline__ void fill_staged(C2<T>* dst, const C2<T>* tw, int twmul, int tid, int nt,
                                             Radices<Rs...>) {
-  constexpr int rs[] = {Rs...};
-  for (int idx = tid; idx < L - 1; idx += nt) {
-    int ns = 1;
-#pragma unroll
-    for (int st = 0; st < (int)sizeof...(Rs); ++st) {
-      const int R = rs[st];
-      if (idx < ns * R - 1) {
-        const int r = idx - (ns - 1), m = 1 + r / ns, k = r % ns;
-        dst[idx] = tw[(m * k * (L / (ns * R))) * twmul];
-        break;
-      }
-      ns *= R;
-    }
-  }
+  for (int idx = tid; idx < L - 1; idx += nt) fill_staged_at<T, L, 1, Rs...>(dst, tw, twmul, idx);
 }
 
 // Exchange through LDS among the lanes of one wave.  A wave's LDS operations
