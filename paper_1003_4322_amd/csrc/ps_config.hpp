@@ -161,6 +161,8 @@ struct XV {
   bool big = false;   // up to 80 KB of LDS per workgroup (two per CU) instead of 64 KB
   bool pk = false;    // packed form (k_x_prod_pk): two real rows per complex transform of length N
   bool ex = false;    // packed form: per-exchange LDS layouts (LayEx) and rows in natural order
+  bool pr = false;    // packed form on dealiased input (kx <= (N - 1) / 3): the slots of
+                      // zeros and of unread outputs skipped (falls back when kmax is larger)
 };
 constexpr ZV ZCURL_V[] = {{1, 1, 1, false, false}, {1, 2, 1, false, false}, {1, 2, 2, false, false},
                           {1, 2, 1, true, false},  {1, 1, 1, false, true},  {0, 2, 1, true, false},
@@ -178,7 +180,10 @@ constexpr XV XPROD_V[] = {{2, 1, 0, false}, {4, 2, 0, false}, {4, 2, 1, false}, 
                           {2, 2, 0, false, false, true, true}, {4, 4, 0, false, true, true, true},
                           {2, 2, 0, true, false, true}, {4, 4, 0, true, true, true},
                           {2, 2, 1, false, false, true, true}, {4, 4, 1, false, true, true, true},
-                          {8, 8, 0, false, true, true, true}};
+                          {8, 8, 0, false, true, true, true},
+                          // packed, dealiased input
+                          {2, 2, 0, false, false, true, true, true}, {8, 8, 0, false, true, true, true, true},
+                          {2, 2, 0, true, false, true, false, true}};
 constexpr int NZCURL = sizeof(ZCURL_V) / sizeof(ZV);
 // waves per SIMD that minb workgroups of `threads` threads occupy (4 SIMDs per CU)
 constexpr int waves_per_simd(int minb, int threads) {

@@ -195,6 +195,98 @@ struct Dft<16, DIR, T> {
 template <int R, int DIR, typename T>
 __device__ __forceinline__ void dft(C2<T>* a) { Dft<R, DIR, T>::run(a); }
 
+// The same DFTs with the inputs whose bit is set in ZM known to be zero at
+// compile time: the additions with them are left out (the compiler may not
+// drop x + 0 itself, which differs from x for x = -0).  Radix 4 and 8; other
+// radices fall back to the full DFT.
+template <typename T>
+__device__ __forceinline__ C2<T> neg2(C2<T> a) { return C2<T>{-a.x, -a.y}; }
+template <int R, int DIR, unsigned ZM, typename T>
+struct DftZ {
+  __device__ __forceinline__ static void run(C2<T>* a) { Dft<R, DIR, T>::run(a); }
+};
+template <int DIR, unsigned ZM, typename T>
+struct DftZ<4, DIR, ZM, T> {
+  __device__ __forceinline__ static void run(C2<T>* a) {
+    constexpr bool z0 = ZM & 1u, z1 = ZM & 2u, z2 = ZM & 4u, z3 = ZM & 8u;
+    C2<T> t0, t1, t2, t3;
+    if constexpr (z0 && z2) {
+      t0 = zero2<T>(), t1 = zero2<T>();
+    } else if constexpr (z2) {
+      t0 = a[0], t1 = a[0];
+    } else if constexpr (z0) {
+      t0 = a[2], t1 = neg2(a[2]);
+    } else {
+      t0 = a[0] + a[2], t1 = a[0] - a[2];
+    }
+    if constexpr (z1 && z3) {
+      t2 = zero2<T>(), t3 = zero2<T>();
+    } else if constexpr (z3) {
+      t2 = a[1], t3 = rot4<DIR>(a[1]);
+    } else if constexpr (z1) {
+      t2 = a[3], t3 = rot4<DIR>(neg2(a[3]));
+    } else {
+      t2 = a[1] + a[3], t3 = rot4<DIR>(a[1] - a[3]);
+    }
+    a[0] = t0 + t2;
+    a[2] = t0 - t2;
+    a[1] = t1 + t3;
+    a[3] = t1 - t3;
+  }
+};
+template <int DIR, unsigned ZM, typename T>
+struct DftZ<8, DIR, ZM, T> {
+  __device__ __forceinline__ static void run(C2<T>* a) {
+    // even inputs 0, 2, 4, 6 and odd inputs 1, 3, 5, 7 of the 2 x 4 split
+    constexpr unsigned ze = (ZM & 1u) | ((ZM >> 1) & 2u) | ((ZM >> 2) & 4u) | ((ZM >> 3) & 8u);
+    constexpr unsigned zo = ((ZM >> 1) & 1u) | ((ZM >> 2) & 2u) | ((ZM >> 3) & 4u) | ((ZM >> 4) & 8u);
+    const T h = T(0.70710678118654752440084436210484904);
+    C2<T> e[4] = {a[0], a[2], a[4], a[6]};
+    C2<T> o[4] = {a[1], a[3], a[5], a[7]};
+    DftZ<4, DIR, ze, T>::run(e);
+    DftZ<4, DIR, zo, T>::run(o);
+    {
+      C2<T> v = o[1];
+      o[1] = DIR == FWD ? C2<T>{h * (v.x + v.y), h * (v.y - v.x)} : C2<T>{h * (v.x - v.y), h * (v.y + v.x)};
+      o[2] = rot4<DIR>(o[2]);
+      v = o[3];
+      o[3] = DIR == FWD ? C2<T>{h * (v.y - v.x), -h * (v.x + v.y)} : C2<T>{-h * (v.x + v.y), h * (v.x - v.y)};
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      a[k] = e[k] + o[k];
+      a[k + 4] = e[k] - o[k];
+    }
+  }
+};
+
+// A first-stage loader whose slots with a bit set in ZM are zero at compile
+// time (the loader of the slot is not called); the Stockham engine then uses
+// DftZ for the first stage when each thread does one butterfly there.
+template <unsigned ZM, class F>
+struct LdZ {
+  F f;
+  __device__ __forceinline__ auto operator()(int slot, int idx) const {
+    using V = decltype(f(slot, idx));
+    if constexpr (ZM == 0)
+      return f(slot, idx);
+    else
+      return slot < 32 && ((ZM >> slot) & 1u) ? V{} : f(slot, idx);
+  }
+};
+template <unsigned ZM, class F>
+__device__ __forceinline__ LdZ<ZM, F> ld_zero(F f) {
+  return LdZ<ZM, F>{f};
+}
+template <class L>
+struct LdZeroMask {
+  static constexpr unsigned value = 0;
+};
+template <unsigned ZM, class F>
+struct LdZeroMask<LdZ<ZM, F>> {
+  static constexpr unsigned value = ZM;
+};
+
 // ---------------------------------------------------------------------------
 // Radix schedules
 // ---------------------------------------------------------------------------
@@ -435,7 +527,11 @@ struct Stockham {
 #pragma unroll
           for (int m = 1; m < R; ++m) a[m] = tw_apply<DIR>(a[m], tw.template get<L, NS, R>(m, k));
         }
-        dft<R, DIR>(a);
+        // slots the loader makes zero (one butterfly per thread: slot = m)
+        if constexpr (FIRST && NB == 1 && LdZeroMask<Ld>::value != 0)
+          DftZ<R, DIR, LdZeroMask<Ld>::value, T>::run(a);
+        else
+          dft<R, DIR>(a);
       }
     }
     if constexpr (!LAST) {
@@ -509,7 +605,11 @@ struct Stockham {
 #pragma unroll
           for (int m = 1; m < R; ++m) a[m] = tw_apply<DIR>(a[m], tw.template get<L, NS, R>(m, k));
         }
-        dft<R, DIR>(a);
+        // slots the loader makes zero (one butterfly per thread: slot = m)
+        if constexpr (FIRST && NB == 1 && LdZeroMask<Ld>::value != 0)
+          DftZ<R, DIR, LdZeroMask<Ld>::value, T>::run(a);
+        else
+          dft<R, DIR>(a);
       }
     }
     if constexpr (!LAST) {

@@ -924,10 +924,27 @@ __host__ __device__ constexpr int xpk_slots(bool mhd, bool els, int rb) {
   return xpk_ninv(mhd, els, rb) > xpk_nfwd(mhd, els, rb) ? xpk_ninv(mhd, els, rb) : xpk_nfwd(mhd, els, rb);
 }
 
+// Slots of the first inverse stage (radix R1, one butterfly per thread: slot
+// m covers k = m N / R1 .. + N / R1 - 1) and of the last forward stage (radix
+// RL, output m the same range) that lie entirely between KM and N - KM: with
+// kx <= KM on input (the 2/3 rule) the former are zero, and the latter are
+// never read by the split into real spectra.
+template <int N, int R, int TQ, int KM>
+__host__ __device__ constexpr unsigned xpk_mid_slots() {
+  unsigned z = 0;
+  if (N / R != TQ) return 0;  // more than one butterfly per thread
+  for (int m = 0; m < R; ++m) {
+    const int lo = m * (N / R), hi = lo + N / R - 1;
+    if (lo > KM && N - hi > KM) z |= 1u << m;
+  }
+  return z;
+}
+
 // EX: the Stockham exchanges use per-exchange layouts (LayEx, immediate
 // offsets) and rows are kept in natural order; otherwise every exchange and
-// row uses RLay.
-template <typename T, int N, int TQ, int RB, class RL, bool MHD, bool ELS, class RLay, bool EX>
+// row uses RLay.  PR: the input holds kx <= (N - 1) / 3 only (the launcher
+// checks a.kmax), so the slots xpk_mid_slots names are skipped.
+template <typename T, int N, int TQ, int RB, class RL, bool MHD, bool ELS, class RLay, bool EX, bool PR = false>
 __global__ __launch_bounds__(xpk_slots(MHD, ELS, RB) * TQ) void k_x_prod_pk(XArgs<T> a) {
   static_assert(RB % 2 == 0, "a transform pairs one field on two grid rows");
   constexpr int FIN = xprod_fin(MHD, ELS), FOUT = xprod_fout(MHD, ELS);
@@ -935,6 +952,8 @@ __global__ __launch_bounds__(xpk_slots(MHD, ELS, RB) * TQ) void k_x_prod_pk(XArg
   constexpr int NT = W * TQ;
   using EI = Stockham<T, N, TQ, INV, RL>;
   using EF = Stockham<T, N, TQ, FWD, RL>;
+  constexpr unsigned ZIN = PR ? xpk_mid_slots<N, EI::R1, TQ, (N - 1) / 3>() : 0u;
+  constexpr unsigned ZOUT = PR ? xpk_mid_slots<N, EF::RL_, TQ, (N - 1) / 3>() : 0u;
   constexpr int LP = EX ? EI::EX_SLOTS : RLay::slots(N);
   // a transform's TQ <= 64 threads lie in one wave: wave-level exchanges
   constexpr bool XW = TQ <= 64 && 64 % TQ == 0;
@@ -985,7 +1004,7 @@ __global__ __launch_bounds__(xpk_slots(MHD, ELS, RB) * TQ) void k_x_prod_pk(XArg
     const bool act = c < NI;
     C2<T> v[EI::SLOTS];
     fft(EI{}, v,
-        [&](int, int k) -> C2<T> {
+        ld_zero<ZIN>([&](int, int k) -> C2<T> {
           const bool up = k > N / 2;
           const int kk = up ? N - k : k;           // stored index
           const bool real_bin = kk == 0 || 2 * kk == N;
@@ -995,7 +1014,7 @@ __global__ __launch_bounds__(xpk_slots(MHD, ELS, RB) * TQ) void k_x_prod_pk(XArg
           const T xi = real_bin ? T(0) : (up ? -x.y : x.y);
           const T yi = real_bin ? T(0) : (up ? -y.y : y.y);
           return C2<T>{x.x - yi, xi + y.x};
-        },
+        }),
         act);
     __syncthreads();
     if (act) {
@@ -1033,7 +1052,7 @@ __global__ __launch_bounds__(xpk_slots(MHD, ELS, RB) * TQ) void k_x_prod_pk(XArg
     if (fact) {
 #pragma unroll
       for (int s = 0; s < EF::LAST_NB * EF::RL_; ++s)
-        if (EF::last_valid(q, s)) buf[roff(EF::last_index(q, s))] = v[s];
+        if (!((ZOUT >> s) & 1u) && EF::last_valid(q, s)) buf[roff(EF::last_index(q, s))] = v[s];
     }
   }
   __syncthreads();

@@ -262,8 +262,16 @@ hipError_t x_prod_pk_v(bool mhd, bool els, XArgs<T> a, hipStream_t s) {
     } else {
       if (a.rows < RB) return hipErrorInvalidValue;  // the kernel assumes a box holds RB rows
       const long grid = (a.rows * a.nb + RB - 1) / RB;
-      k_x_prod_pk<T, N, LC::TQ, RB, typename LC::RL, M_, E_, RLay, v.ex>
-          <<<dim3((unsigned)grid), dim3(xpk_slots(M_, E_, RB) * LC::TQ), 0, s>>>(a);
+      // dealiased input (kx <= (N - 1) / 3): the pruned form skips the slots
+      // that hold only zeros or outputs nobody reads
+      bool pruned = false;
+      if constexpr (v.pr) pruned = a.kmax <= (N - 1) / 3;
+      if (pruned)
+        k_x_prod_pk<T, N, LC::TQ, RB, typename LC::RL, M_, E_, RLay, v.ex, v.pr>
+            <<<dim3((unsigned)grid), dim3(xpk_slots(M_, E_, RB) * LC::TQ), 0, s>>>(a);
+      else
+        k_x_prod_pk<T, N, LC::TQ, RB, typename LC::RL, M_, E_, RLay, v.ex, false>
+            <<<dim3((unsigned)grid), dim3(xpk_slots(M_, E_, RB) * LC::TQ), 0, s>>>(a);
       return hipGetLastError();
     }
   };
