@@ -101,28 +101,32 @@ def rel_l2_w(a, b):
 
 
 def run_timed(plan, state, model, w, steps, warmup):
-    """Warmup (graph replay), then the timed region with per-kernel events.
-    Returns (ms_per_step, per-kernel stats, ms_per_step_graph)."""
+    """Warmup, then the timed region: `steps` RK2 steps as the library runs
+    them by default (one HIP graph replay per step), bracketed by
+    synchronisations.  Then `steps` more with a HIP event pair around every
+    kernel on the plan's stream (graphs off while timing) for the per-kernel
+    table; the events cost a few microseconds per launch, so that region is
+    reported beside the timed one, not as it.
+    Returns (ms_per_step, per-kernel stats, ms_per_step of the event region)."""
     import torch
 
     plan.set_timing(False)
     plan.rk2_step(state, model, w["nu"], w["eta"], w["dt"], warmup)
     torch.cuda.synchronize()
-    # graph-replay rate (informational; the reported value is the timed region below)
     t0 = time.perf_counter()
     plan.rk2_step(state, model, w["nu"], w["eta"], w["dt"], steps)
     torch.cuda.synchronize()
-    ms_graph = (time.perf_counter() - t0) * 1e3 / max(steps, 1)
+    ms = (time.perf_counter() - t0) * 1e3 / max(steps, 1)
     plan.set_timing(True)
     plan.timing_reset()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     plan.rk2_step(state, model, w["nu"], w["eta"], w["dt"], steps)
     torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / max(steps, 1)
+    ms_events = (time.perf_counter() - t0) * 1e3 / max(steps, 1)
     stats = plan.timings()
     plan.set_timing(False)
-    return ms, stats, ms_graph
+    return ms, stats, ms_events
 
 
 def pass_table(stats):
@@ -474,9 +478,9 @@ def run_primary(args, w, model, nf, N, dev):
     diag = {"initial": diagnostics(plan32, s32, nf)}
     tuned32 = None if args.no_tune else plan32.autotune(s32, model, 3)
     log("fp32 variants", tuned32)
-    ms, stats, ms_graph = run_timed(plan32, s32, model, w, args.steps, args.warmup)
+    ms, stats, ms_events = run_timed(plan32, s32, model, w, args.steps, args.warmup)
     passes32 = pass_table(stats)
-    log(f"fp32: {ms:.3f} ms/step (graph replay {ms_graph:.3f})")
+    log(f"fp32: {ms:.3f} ms/step (with per-kernel events {ms_events:.3f})")
     diag[f"after_{args.warmup + 2 * args.steps}_steps"] = diagnostics(plan32, s32, nf)
     log("fp32 diagnostics", diag)
 
@@ -509,8 +513,8 @@ def run_primary(args, w, model, nf, N, dev):
         plan64.set_variant("form", form_for(w["model"], "f64"))
         tuned64 = None if args.no_tune else plan64.autotune(s64, model, 3)
         log("fp64 variants", tuned64)
-        ms64, stats64, ms64_graph = run_timed(plan64, s64, model, w, args.steps, args.warmup)
-        log(f"fp64: {ms64:.3f} ms/step (graph replay {ms64_graph:.3f})")
+        ms64, stats64, ms64_events = run_timed(plan64, s64, model, w, args.steps, args.warmup)
+        log(f"fp64: {ms64:.3f} ms/step (with per-kernel events {ms64_events:.3f})")
         # same number of steps from the same initial state in both precisions
         l2_run = rel_l2_w(s32, s64)
         # one step from the identical initial state
@@ -528,7 +532,7 @@ def run_primary(args, w, model, nf, N, dev):
         l2_1 = rel_l2_w(a, b)
         inc = rel_l2_w(a.to(torch.complex128) - s64_0, b - s64_0)
         fp64 = {"steps_per_s": round(1e3 / ms64, 3), "ms_per_step": round(ms64, 3),
-                "ms_per_step_graph": round(ms64_graph, 3), "passes": pass_table(stats64),
+                "ms_per_step_events": round(ms64_events, 3), "passes": pass_table(stats64),
                 "variants": tuned64,
                 "l2_f32_vs_f64_one_step": l2_1,
                 "l2_f32_vs_f64_increment_one_step": inc,
@@ -536,7 +540,7 @@ def run_primary(args, w, model, nf, N, dev):
                 "tolerance_per_step": 2e-6}
         log(f"fp32 vs fp64: one step {l2_1:.3e}, increment {inc:.3e}, run {l2_run:.3e}")
 
-    return ms, ms_graph, tuned32, passes32, roofline, fp64, diag
+    return ms, ms_events, tuned32, passes32, roofline, fp64, diag
 
 
 def main():
@@ -584,7 +588,7 @@ def main():
     N = w["N"]
     log(f"workload {args.workload}: N={N} fields={nf} steps={args.steps} warmup={args.warmup}")
 
-    ms, ms_graph, tuned32, passes32, roofline, fp64, diag = run_primary(args, w, model, nf, N, dev)
+    ms, ms_events, tuned32, passes32, roofline, fp64, diag = run_primary(args, w, model, nf, N, dev)
     torch.cuda.empty_cache()
 
     extras = None
@@ -618,7 +622,7 @@ def main():
                    "N": N, "fields": nf, "workload_key": args.workload,
                    "prune": PRUNE,
                    "form": "divergence" if FORM == 1 else "rotational"},
-        "ms_per_step_graph": round(ms_graph, 4),
+        "ms_per_step_events": round(ms_events, 4),
         "variants": tuned32,
         "passes": passes32,
         "device_copy": copy_ref,

@@ -146,7 +146,7 @@ size_t csize(const ps_plan_s* p) { return p->dtype == PS_F32 ? 8 : 16; }
 const char* const KINDS[] = {"y", "z", "z_curl", "z_epi", "x_prod", "batch", "prune", "form", "pipe"};
 // "pipe" variant v: the y / x / y passes run as 2^v z-slabs, over the helper
 // streams for v = 1..3, one after another on the plan's stream for v = 4..6
-constexpr int NPIPE = 7;
+constexpr int NPIPE = 7, PIPE_SERIAL = 4;
 
 int var_of(const ps_plan_s* p, const char* kind) {
   auto it = p->var.find(kind);
@@ -396,7 +396,7 @@ struct Seq {
     const int slabs = std::min(1 << pv, b.nz);
     if (slabs <= 1) {
       if ((st = yxy(mhd, 0, b.nz))) return st;
-    } else if (pv >= 4) {
+    } else if (pv >= PIPE_SERIAL) {
       // slabs in order on the plan's stream: each slab's chain (inverse y,
       // products, forward y) works on data the previous pass of the chain
       // has just left in the last-level cache
@@ -438,6 +438,8 @@ struct Seq {
       ps_status st = pass_zepi(mhd, 1, zstar(), state, nullptr, T(0), T(0), T(0));
       return st ? st : pass_zepi(mhd, 2, nullptr, zstar(), state, T(0), T(0), T(0));
     }
+    // a whole right-hand side in the first stage's mode (writes z* only)
+    if (!strcmp(kind, "step")) return rhs(state, mhd, 1, zstar(), state, nullptr, T(0), T(0), T(0));
     return fail(PS_ERR_ARG, std::string("no tuning launch for kind ") + kind);
   }
 
@@ -646,14 +648,16 @@ std::string tune_key(ps_plan p, bool mhd) {
     snprintf(buf, sizeof buf, "|%dx%dx%d*%d", c.nx, c.ny, c.nz, c.nb);
     k += buf;
   }
-  for (const char* kind : {"form", "prune", "batch", "pipe"}) {
+  for (const char* kind : {"form", "prune", "batch"}) {
     snprintf(buf, sizeof buf, "|%s=%d", kind, var_of(p, kind));
     k += buf;
   }
   return k;
 }
 
-const char* const TUNED[] = {"z_curl", "y", "x_prod", "z_epi"};
+// kinds the autotuner chooses (per pass, then the slab pipeline per right-hand side)
+const char* const TUNED[] = {"z_curl", "y", "x_prod", "z_epi", "pipe"};
+constexpr int NTUNED = sizeof(TUNED) / sizeof(TUNED[0]);
 
 bool tune_cache_lookup(ps_plan p, const std::string& key) {
   const char* path = getenv("PS_TUNE_CACHE");
@@ -692,7 +696,7 @@ void tune_cache_store(ps_plan p, const std::string& key) {
   const char* path = getenv("PS_TUNE_CACHE");
   if (!path || !*path) return;
   std::string line = key + "\t";
-  for (int i = 0; i < 4; ++i) {
+  for (int i = 0; i < NTUNED; ++i) {
     char buf[64];
     snprintf(buf, sizeof buf, "%s%s=%d", i ? "," : "", TUNED[i], var_of(p, TUNED[i]));
     line += buf;
@@ -1302,14 +1306,18 @@ ps_status ps_plan_autotune(ps_plan p, const void* state, ps_model m, int reps) {
       if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return fail(PS_ERR_HIP, "hipEventCreate failed");
       ps_status out = PS_OK;
-      // (the slab pipeline is left as set: its effect here is within 2 %, and
-      // its concurrent launches would blur the per-pass timings)
-      // reps launches of variant v between two events; ms = their time
+      // the passes are timed one at a time with the slab pipeline off (its
+      // concurrent launches would blur the per-pass timings); the pipeline
+      // setting is chosen afterwards on whole right-hand sides
+      p->var["pipe"] = 0;
+      // reps launches of variant v of `kind` (kind "pipe": right-hand sides)
+      // between two events; ms = their time
       auto time_v = [&](const char* kind, int v, float& ms) -> ps_status {
         p->var[kind] = v;
+        const char* launch = strcmp(kind, "pipe") ? kind : "step";
         ps_status o = PS_OK;
         hipEventRecord(e0, p->stream);
-        for (int r = 0; r < reps && o == PS_OK; ++r, ++timed) o = q.tune_launch(kind, st, mhd);
+        for (int r = 0; r < reps && o == PS_OK; ++r, ++timed) o = q.tune_launch(launch, st, mhd);
         hipEventRecord(e1, p->stream);
         hipError_t e = hipEventSynchronize(e1);
         ms = 0;
@@ -1317,8 +1325,8 @@ ps_status ps_plan_autotune(ps_plan p, const void* state, ps_model m, int reps) {
         if (e != hipSuccess && o == PS_OK) o = hip_fail(e, "autotune timing");
         return o;
       };
-      for (const char* kind : {"z_curl", "y", "x_prod", "z_epi"}) {
-        const int n = ps::variant_count(kind, axis_len(b, kind), mhd);
+      for (const char* kind : TUNED) {
+        const int n = strcmp(kind, "pipe") ? ps::variant_count(kind, axis_len(b, kind), mhd) : NPIPE;
         if (n <= 1) continue;
         // every variant once (after a warm-up launch), then the ones within
         // 10 % of the fastest again in FINAL interleaved rounds, each keeping
@@ -1327,8 +1335,12 @@ ps_status ps_plan_autotune(ps_plan p, const void* state, ps_model m, int reps) {
         constexpr int FINAL = 3;
         std::vector<float> best_ms(n, 1e30f);
         for (int v = 0; v < n && out == PS_OK; ++v) {
+          // pipeline settings whose slabs run concurrently on helper streams
+          // are not considered: per-kernel timings of overlapping launches
+          // would mean nothing
+          if (!strcmp(kind, "pipe") && v >= 1 && v < PIPE_SERIAL) continue;
           p->var[kind] = v;
-          if ((out = q.tune_launch(kind, st, mhd))) break;  // warm-up
+          if ((out = q.tune_launch(strcmp(kind, "pipe") ? kind : "step", st, mhd))) break;  // warm-up
           out = time_v(kind, v, best_ms[v]);
         }
         const float first = *std::min_element(best_ms.begin(), best_ms.end());

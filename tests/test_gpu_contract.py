@@ -112,7 +112,7 @@ def test_autotune_cache(B, tmp_path, monkeypatch):
     v1 = p1.autotune(u, B.PS_NS, 1)
     assert p1.autotune_timed() > 0
     lines = path.read_text().splitlines()
-    assert len(lines) == 3 and "\t" in lines[-1]
+    assert len(lines) == 3 and "\t" in lines[-1] and "pipe=" in lines[-1]
     p2 = B.Plan(N, 3, "f32")
     p2.set_variant("prune", 1)
     assert p2.autotune_timed() == -1
