@@ -144,9 +144,11 @@ def pass_table(stats):
     return out
 
 
-def load_traffic(kernel_kind, workload, dtype):
+def load_traffic(kernel_kind, workload, dtype, variants=None):
     """HBM traffic per launch from committed rocprofv3 counter runs, only if
-    the kernel sources are unchanged since the counters were taken."""
+    the kernel sources are unchanged since the counters were taken and the
+    counters were taken in the same slab-pipeline setting (a launch covers
+    the whole box or one slab)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -157,6 +159,8 @@ def load_traffic(kernel_kind, workload, dtype):
     key = f"{workload}/{dtype}/{kernel_kind}"
     r = rec.get(key)
     if not r or r.get("src_hash") != src_hash():
+        return None
+    if r.get("pipe") != (variants or {}).get("pipe"):
         return None
     return r.get("bytes_per_launch")
 
@@ -486,7 +490,7 @@ def run_primary(args, w, model, nf, N, dev):
 
     dom = max(stats, key=lambda k: stats[k]["total_ms"])
     d = passes32[dom]
-    traffic = load_traffic(dom, args.workload, "f32")
+    traffic = load_traffic(dom, args.workload, "f32", tuned32)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": d["GB/s"], "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(d["GB/s"] / HBM_PEAK_GBS, 4),
                 "traffic": traffic}
