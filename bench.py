@@ -500,7 +500,10 @@ def run_primary(args, w, model, nf, N, dev):
         # each, over N^2 rows; FP32 without packed instructions peaks at
         # 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz = 78.6 TFLOP/s
         nt = (8 if FORM == 1 else 9) if nf == 3 else (14 if FORM == 1 else 18)
-        flops = nt * N * N * 2.5 * N * math.log2(N)
+        # a launch covers one z-slab of the box under the slab pipeline
+        pipe = (tuned32 or {}).get("pipe", 0)
+        slabs = min(2 ** pipe, N) if pipe else 1
+        flops = nt * N * N * 2.5 * N * math.log2(N) / slabs
         tf = flops / (d["avg_ms"] * 1e-3) / 1e12
         roofline["alu_view"] = {"bound": "alu", "achieved": round(tf, 2), "peak": ALU_PEAK_TFS,
                                 "unit": "TFLOP/s", "frac": round(tf / ALU_PEAK_TFS, 4),
