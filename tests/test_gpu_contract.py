@@ -100,6 +100,28 @@ def test_monitor_leaves_a_normal_step_alone(B, graphs):
     p1.set_monitor(0, 0.0)  # off
 
 
+def test_pipe_settings_bitwise_equal(B):
+    """Every slab-pipeline setting (concurrent and serial slabs, and more
+    slabs than planes) computes the same step bit for bit: each plane's chain
+    of passes is the same arithmetic whichever slab it falls in."""
+    say("pipe settings bitwise")
+    N = 192
+    z = to_dev(synth.flat_solenoidal(N, 31, groups=2), "f32")
+    p = B.Plan(N, 6, "f32")
+    p.set_variant("prune", 1)
+    p.set_variant("form", 1)
+    ref = None
+    for v in range(p.variant_count("pipe")):
+        p.set_variant("pipe", v)
+        s = z.clone()
+        p.rk2_step(s, B.PS_MHD, 1e-3, 5e-4, 1e-3, 2)
+        if ref is None:
+            ref = s
+        else:
+            assert torch.equal(s, ref), v
+    p.close()
+
+
 def test_autotune_cache(B, tmp_path, monkeypatch):
     say("autotune cache")
     path = tmp_path / "tune.txt"
