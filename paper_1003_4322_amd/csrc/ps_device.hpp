@@ -357,15 +357,17 @@ struct LayColPad8 {
 
 // Per-exchange layout: the buffer a stage of span NS and radix R writes (and
 // the next stage reads) keeps element i at i + P floor(i / B), P = NS and
-// B = max(NS R, 32) while NS < 32, plain otherwise.  Over any 32 consecutive
-// threads the stage's writes (base (j / NS) NS R + j % NS, plus m NS) and the
-// next stage's reads (j + m L / R') fall in distinct 8-byte bank pairs, and
-// every access of a thread is its base plus a constant: offc(c) when
-// c % B == 0 (reads at stride L / R'), m NS when B % (NS R) == 0 (writes).
-template <int NS, int R>
+// B = max(NS R, W) while NS < W, plain otherwise, where W = 256 bytes (the
+// 64 four-byte LDS banks) over the element size: 32 complex floats, 16
+// complex doubles.  Over any W consecutive threads the stage's writes (base
+// (j / NS) NS R + j % NS, plus m NS) and the next stage's reads
+// (j + m L / R') fall in distinct groups of banks, and every access of a
+// thread is its base plus a constant: offc(c) when c % B == 0 (reads at
+// stride L / R'), m NS when B % (NS R) == 0 (writes).
+template <int NS, int R, int W = 32>
 struct LayEx {
-  static constexpr int P = NS < 32 ? NS : 0;
-  static constexpr int B = NS * R > 32 ? NS * R : 32;
+  static constexpr int P = NS < W ? NS : 0;
+  static constexpr int B = NS * R > W ? NS * R : W;
   __host__ __device__ static constexpr int off(int i) { return P ? i + P * (i / B) : i; }
   __host__ __device__ static constexpr int offc(int c) { return P ? c + P * (c / B) : c; }
   static constexpr bool read_splits(int c) { return P == 0 || c % B == 0; }
@@ -471,6 +473,8 @@ struct Stockham {
     }();
   };
   static constexpr int SLOTS = MaxSlots<RL>::value;
+  // lanes whose accesses one LDS cycle (64 four-byte banks) serves
+  static constexpr int EXW = 256 / (int)sizeof(C2<T>);
   static constexpr int FIRST_SLOTS = cdiv(L / R1, TQ) * R1;
   static constexpr int LAST_NB = cdiv(L / RL_, TQ);
 
@@ -575,7 +579,7 @@ struct Stockham {
   template <int NS, int R, bool FIRST, bool LAST, class LR, bool WAVE, class TW, class Ld>
   __device__ __forceinline__ static void stage_ex(C2<T> (&v)[SLOTS], C2<T>* lds, int q, const TW& tw, Ld& ld,
                                                   bool act) {
-    using LW = LayEx<NS, R>;
+    using LW = LayEx<NS, R, EXW>;
     constexpr int NB = cdiv(L / R, TQ);
     constexpr bool EXACT = (L / R) % TQ == 0;
     if (act) {
@@ -640,13 +644,13 @@ struct Stockham {
                                                   bool act, Radices<R, Rest...>) {
     stage_ex<NS, R, NS == 1, sizeof...(Rest) == 0, LR, WAVE>(v, lds, q, tw, ld, act);
     if constexpr (sizeof...(Rest) > 0)
-      chain_ex<NS * R, LayEx<NS, R>, WAVE>(v, lds, q, tw, ld, act, Radices<Rest...>{});
+      chain_ex<NS * R, LayEx<NS, R, EXW>, WAVE>(v, lds, q, tw, ld, act, Radices<Rest...>{});
   }
   template <bool WAVE = false, class TW, class Ld>
   __device__ __forceinline__ static void run_ex(C2<T> (&v)[SLOTS], C2<T>* lds, int q, const TW& tw, Ld ld,
                                                 bool act = true) {
     static_assert(!WAVE || (TQ <= 64 && 64 % TQ == 0), "WAVE needs each transform inside one wave");
-    chain_ex<1, LayEx<1, 1>, WAVE>(v, lds, q, tw, ld, act, RL{});
+    chain_ex<1, LayEx<1, 1, EXW>, WAVE>(v, lds, q, tw, ld, act, RL{});
   }
   // LDS slots of one transform's buffer under run_ex (the exchanges, and the
   // natural-order copy callers keep after the last stage)
@@ -658,7 +662,7 @@ struct Stockham {
       int rs[] = {Rs...};
       int m = L, ns = 1;
       for (int r : rs) {
-        const int p = ns < 32 ? ns : 0, b = ns * r > 32 ? ns * r : 32;
+        const int p = ns < EXW ? ns : 0, b = ns * r > EXW ? ns * r : EXW;
         const int sl = (p ? (L - 1) + p * ((L - 1) / b) : L - 1) + 1;
         m = sl > m ? sl : m;
         ns *= r;
