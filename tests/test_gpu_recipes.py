@@ -61,6 +61,28 @@ def test_recipe_256_one_step(B, ref, model, dt):
         assert e < TOL_STEP[dt], (bench_config, e)
 
 
+def test_recipe_256_ten_steps_fp32_vs_fp64(B):
+    """The benchmark's launch configuration (autotuned, slab pipeline
+    included) over ten steps of the MHD recipe at 256^3: FP32 against FP64
+    from the same FP32-representable state, within the per-step bar summed
+    over the steps (10 x 2e-6)."""
+    N, steps = 256, 10
+    x = rounded(synth.random_mhd(N, 3, 4, 3.0), "f32")
+    out = {}
+    for dt in ("f64", "f32"):
+        p = B.Plan(N, 6, dt)
+        s = to_dev(x, dt)
+        p.set_variant("prune", 1)
+        p.set_variant("form", 1)
+        say("ten steps", dt, p.autotune(s, B.PS_MHD, 2))
+        p.rk2_step(s, B.PS_MHD, 5e-4, 5e-4, 1e-3, steps)
+        out[dt] = s
+        p.close()
+    e = rel_l2_w_dev(out["f32"], out["f64"])
+    say(f"f32 vs f64 after {steps} steps: {e:.3e}")
+    assert e < steps * TOL_STEP["f32"], e
+
+
 def mem_available() -> float:
     with open("/proc/meminfo") as f:
         for line in f:
