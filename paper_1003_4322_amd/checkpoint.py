@@ -1,0 +1,146 @@
+"""Checkpoint and resume of a run's spectral state.
+
+The paper's code writes its fields with parallel MPI I/O and writes nothing
+in benchmark mode (Sec. 4); here a run saves the spectral state (the half
+spectra ps_rk2_step advances, layout [box][f][kz][ky][kx <= nx/2]) with a JSON
+header of what is needed to continue it, and resumes from it bit for bit.
+
+File layout (one file, little-endian):
+    b"PSCKPT1\\n"                   magic
+    8-byte unsigned length L
+    L bytes of UTF-8 JSON           header (see save)
+    the state's bytes               complex64 or complex128, C order
+
+The header also records the plan's kernel variants: the variants differ in
+their order of rounding, so a resumed run reproduces the uninterrupted one
+bit for bit only on the same variants (apply_variants sets them on a new
+plan).  The header records the shape, the element type, the payload's size
+and its SHA-256; load checks all of them and raises ValueError on any mismatch, so a
+truncated or altered file is refused rather than resumed.  Nothing in a
+checkpoint is executed: the header is JSON and the payload raw numbers.
+Writes go to a temporary file in the same folder, then replace the target,
+so a crash mid-write leaves any earlier checkpoint intact.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+import struct
+from typing import Any, Dict, Optional, Sequence, Tuple, Union
+
+import numpy as np
+import torch
+
+MAGIC = b"PSCKPT1\n"
+_DTYPES = {torch.complex64: "complex64", torch.complex128: "complex128"}
+
+
+def save(path: str, state: torch.Tensor, *, sizes: Union[int, Sequence[int]], nfields: int, t: float,
+         step: int, nu: float, eta: float, dt: float, seed: Optional[Any] = None,
+         variants: Optional[Dict[str, int]] = None, extra: Optional[Dict[str, Any]] = None) -> Dict[str, Any]:
+    """Write `state` (a complex tensor on any device) and its header to `path`.
+
+    sizes: the plan's box size N (an int), a list of sizes (an ensemble) or a
+    grid (nx, ny, nz); t, step: the simulation time and step count reached;
+    nu, eta, dt: the step's parameters; seed: whatever made the initial state;
+    variants: the plan's kernel variants (Plan.variants()); extra: further
+    JSON-serialisable fields.  Returns the header written."""
+    if state.dtype not in _DTYPES:
+        raise ValueError(f"state must be complex64 or complex128, not {state.dtype}")
+    host = state.detach().contiguous().to("cpu")
+    payload = host.numpy().tobytes(order="C")
+    header = {
+        "format": "pseudospectral-state",
+        "version": 1,
+        "sizes": list(sizes) if isinstance(sizes, (list, tuple)) else int(sizes),
+        "nfields": int(nfields),
+        "dtype": _DTYPES[state.dtype],
+        "shape": list(host.shape),
+        "t": float(t),
+        "step": int(step),
+        "nu": float(nu),
+        "eta": float(eta),
+        "dt": float(dt),
+        "seed": seed,
+        "variants": {str(k): int(v) for k, v in (variants or {}).items()},
+        "payload_bytes": len(payload),
+        "sha256": hashlib.sha256(payload).hexdigest(),
+    }
+    if extra:
+        header["extra"] = extra
+    text = json.dumps(header, sort_keys=True).encode("utf-8")
+    folder = os.path.dirname(os.path.abspath(path))
+    tmp = os.path.join(folder, f".{os.path.basename(path)}.tmp{os.getpid()}")
+    with open(tmp, "wb") as f:
+        f.write(MAGIC)
+        f.write(struct.pack("<Q", len(text)))
+        f.write(text)
+        f.write(payload)
+        f.flush()
+        os.fsync(f.fileno())
+    os.replace(tmp, path)
+    return header
+
+
+def read_header(path: str) -> Dict[str, Any]:
+    """The header of a checkpoint, without reading its payload."""
+    with open(path, "rb") as f:
+        return _header(f)
+
+
+def _header(f) -> Dict[str, Any]:
+    if f.read(len(MAGIC)) != MAGIC:
+        raise ValueError("not a checkpoint of this format (bad magic)")
+    raw = f.read(8)
+    if len(raw) != 8:
+        raise ValueError("checkpoint truncated in its header")
+    (n,) = struct.unpack("<Q", raw)
+    if n > 1 << 20:
+        raise ValueError("checkpoint header implausibly long")
+    text = f.read(n)
+    if len(text) != n:
+        raise ValueError("checkpoint truncated in its header")
+    header = json.loads(text.decode("utf-8"))
+    if header.get("format") != "pseudospectral-state" or header.get("version") != 1:
+        raise ValueError("unknown checkpoint format or version")
+    return header
+
+
+def load(path: str, device: Union[str, torch.device, None] = None) -> Tuple[torch.Tensor, Dict[str, Any]]:
+    """Read a checkpoint: (state on `device` (CPU if None), header).  Raises
+    ValueError if the file is truncated, altered or of another format."""
+    with open(path, "rb") as f:
+        header = _header(f)
+        payload = f.read()
+    if len(payload) != header["payload_bytes"]:
+        raise ValueError(f"checkpoint payload has {len(payload)} bytes, header says {header['payload_bytes']}")
+    if hashlib.sha256(payload).hexdigest() != header["sha256"]:
+        raise ValueError("checkpoint payload does not match its SHA-256")
+    dtype = {"complex64": np.complex64, "complex128": np.complex128}.get(header["dtype"])
+    if dtype is None:
+        raise ValueError(f"unknown element type {header['dtype']!r}")
+    shape = tuple(int(s) for s in header["shape"])
+    if int(np.prod(shape)) * np.dtype(dtype).itemsize != len(payload):
+        raise ValueError("checkpoint shape does not match its payload")
+    arr = np.frombuffer(payload, dtype=dtype).reshape(shape).copy()
+    state = torch.from_numpy(arr)
+    if device is not None:
+        state = state.to(device)
+    return state, header
+
+
+def apply_variants(plan, header: Dict[str, Any]) -> Dict[str, int]:
+    """Set the kernel variants a checkpoint recorded on `plan`; returns them.
+    Raises ValueError if the plan's element type, field count or state size
+    differs from the checkpoint's."""
+    if _DTYPES[plan.complex_dtype] != header["dtype"] or plan.nfields != header["nfields"]:
+        raise ValueError(f"plan ({_DTYPES[plan.complex_dtype]}, {plan.nfields} fields) does not match "
+                         f"the checkpoint ({header['dtype']}, {header['nfields']} fields)")
+    if plan.n_complex() != int(np.prod(header["shape"])):
+        raise ValueError(f"plan holds {plan.n_complex()} spectral values, checkpoint "
+                         f"{int(np.prod(header['shape']))}")
+    v = header.get("variants") or {}
+    for kind, value in v.items():
+        plan.set_variant(kind, int(value))
+    return dict(v)

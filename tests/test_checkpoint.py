@@ -1,0 +1,111 @@
+"""Checkpoint files on the host: round trip of state and header, and refusal
+of truncated, altered and foreign files (the GPU resume test is in
+test_gpu_checkpoint.py)."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1003_4322_amd import checkpoint as ck
+
+
+def _state(dtype, shape=(6, 8, 8, 5), seed=0):
+    g = torch.Generator().manual_seed(seed)
+    re = torch.randn(shape, generator=g, dtype=torch.float64)
+    im = torch.randn(shape, generator=g, dtype=torch.float64)
+    return torch.complex(re, im).to(dtype)
+
+
+META = dict(sizes=8, nfields=6, t=0.005, step=5, nu=5e-4, eta=5e-4, dt=1e-3, seed=[3, 4])
+
+
+@pytest.mark.parametrize("dtype", [torch.complex64, torch.complex128])
+def test_round_trip_bitwise(tmp_path, dtype):
+    s = _state(dtype)
+    s[0, 0, 0, 0] = complex(float("nan"), -0.0)  # any bit pattern survives
+    path = str(tmp_path / "a.ckpt")
+    h = ck.save(path, s, variants={"x_prod": 11, "pipe": 4}, extra={"note": "x"}, **META)
+    got, h2 = ck.load(path)
+    assert got.dtype == dtype and got.shape == s.shape
+    assert got.numpy().tobytes() == s.numpy().tobytes()
+    assert h2 == h == ck.read_header(path)
+    for k, v in META.items():
+        assert h2[k] == v, k
+    assert h2["variants"] == {"x_prod": 11, "pipe": 4} and h2["extra"] == {"note": "x"}
+    assert not [f for f in os.listdir(tmp_path) if ".tmp" in f]  # no temporary left
+
+
+def test_overwrite_is_atomic_replace(tmp_path):
+    path = str(tmp_path / "a.ckpt")
+    ck.save(path, _state(torch.complex64, seed=1), **META)
+    s2 = _state(torch.complex64, seed=2)
+    ck.save(path, s2, **{**META, "step": 6})
+    got, h = ck.load(path)
+    assert torch.equal(got, s2) and h["step"] == 6
+
+
+def test_rejects_real_state(tmp_path):
+    with pytest.raises(ValueError):
+        ck.save(str(tmp_path / "r.ckpt"), torch.zeros(4), **META)
+
+
+def _corrupt(path, fn):
+    with open(path, "rb") as f:
+        b = bytearray(f.read())
+    with open(path, "wb") as f:
+        f.write(fn(b))
+
+
+@pytest.mark.parametrize("how", ["truncate_payload", "flip_payload_byte", "bad_magic", "truncate_header",
+                                 "foreign_format", "wrong_shape"])
+def test_refuses_damaged_files(tmp_path, how):
+    path = str(tmp_path / "a.ckpt")
+    ck.save(path, _state(torch.complex128), **META)
+    hlen = int.from_bytes(open(path, "rb").read()[8:16], "little")
+    start = 16 + hlen
+
+    def edit_header(b, **upd):
+        h = json.loads(bytes(b[16:start]))
+        h.update(upd)
+        t = json.dumps(h).encode()
+        return b[:8] + len(t).to_bytes(8, "little") + t + b[start:]
+
+    fns = {
+        "truncate_payload": lambda b: b[:-16],
+        "flip_payload_byte": lambda b: b[:start + 100] + bytes([b[start + 100] ^ 1]) + b[start + 101:],
+        "bad_magic": lambda b: b"NOTCKPT\n" + b[8:],
+        "truncate_header": lambda b: b[:20],
+        "foreign_format": lambda b: edit_header(b, format="something-else"),
+        "wrong_shape": lambda b: edit_header(b, shape=[6, 8, 8, 4]),
+    }
+    _corrupt(path, fns[how])
+    with pytest.raises(ValueError):
+        ck.load(path)
+
+
+class _FakePlan:
+    """The attributes apply_variants reads and the call it makes."""
+
+    def __init__(self, cdtype, nfields, n):
+        self.complex_dtype, self.nfields, self._n, self.set = cdtype, nfields, n, {}
+
+    def n_complex(self):
+        return self._n
+
+    def set_variant(self, k, v):
+        self.set[k] = v
+
+
+def test_apply_variants_checks_plan(tmp_path):
+    path = str(tmp_path / "a.ckpt")
+    s = _state(torch.complex64)
+    ck.save(path, s, variants={"x_prod": 18, "prune": 1, "form": 1}, **META)
+    h = ck.read_header(path)
+    p = _FakePlan(torch.complex64, 6, s.numel())
+    assert ck.apply_variants(p, h) == {"x_prod": 18, "prune": 1, "form": 1} == p.set
+    for bad in (_FakePlan(torch.complex128, 6, s.numel()), _FakePlan(torch.complex64, 3, s.numel()),
+                _FakePlan(torch.complex64, 6, s.numel() // 2)):
+        with pytest.raises(ValueError):
+            ck.apply_variants(bad, h)
