@@ -248,9 +248,14 @@ ps_status ps_mhd_spectrum(ps_plan p, const void *zhat, double *spec_dev, double 
  * over helper streams, so that one slab's memory-bound y passes overlap
  * another's compute-bound product pass; for v = 4..6 one after another on
  * the plan's stream, so that each slab's chain finds its data in the
- * last-level cache; 0 = one slab on the plan's stream (default;
- * ps_plan_autotune chooses among 0 and 4..6, the settings whose launches
- * do not overlap).  Setting a variant drops a cached graph. */
+ * last-level cache; for v = 7..9, 2^(v-3) slabs (16, 32, 64) as two chains,
+ * even and odd slabs, on two helper streams, so that the two slabs in flight
+ * still fit the last-level cache while each fills the other's launch gaps;
+ * 0 = one slab on the plan's stream (default; ps_plan_autotune chooses among
+ * 0 and 4..6, the settings whose launches do not overlap: a caller who wants
+ * the fastest step over per-kernel timings sets 7..9 by hand).  Every setting
+ * computes the same step bit for bit.  Setting a variant drops a cached
+ * graph. */
 ps_status ps_plan_set_variant(ps_plan p, const char *kind, int variant);
 int ps_plan_get_variant(ps_plan p, const char *kind);
 int ps_plan_variant_count(ps_plan p, const char *kind);

@@ -144,9 +144,21 @@ namespace {
 size_t csize(const ps_plan_s* p) { return p->dtype == PS_F32 ? 8 : 16; }
 
 const char* const KINDS[] = {"y", "z", "z_curl", "z_epi", "x_prod", "batch", "prune", "form", "pipe"};
-// "pipe" variant v: the y / x / y passes run as 2^v z-slabs, over the helper
-// streams for v = 1..3, one after another on the plan's stream for v = 4..6
-constexpr int NPIPE = 7, PIPE_SERIAL = 4;
+// "pipe" variant v: the y / x / y passes run as z-slabs: 2^v slabs over the
+// three helper streams for v = 1..3, 2^v slabs one after another on the plan's
+// stream for v = 4..6, and 2^(v-3) slabs as two chains (even and odd slabs) on
+// two helper streams for v = 7..9
+constexpr int NPIPE = 10, PIPE_SERIAL = 4, PIPE_TWO = 7;
+struct PipeShape {
+  int slabs;    // z-slabs (before capping at the box's planes)
+  int streams;  // 0: in order on the plan's stream; else helper streams
+};
+PipeShape pipe_shape(int v) {
+  if (v <= 0) return {1, 0};
+  if (v < PIPE_SERIAL) return {1 << v, 3};
+  if (v < PIPE_TWO) return {1 << v, 0};
+  return {1 << (v - 3), 2};
+}
 
 int var_of(const ps_plan_s* p, const char* kind) {
   auto it = p->var.find(kind);
@@ -392,11 +404,11 @@ struct Seq {
   ps_status rhs(const C* src, bool mhd, int mode, C* out, const C* st0, const C* st1, T h, T nua, T nub) {
     ps_status st = pass_zcurl(src, mhd);
     if (st) return st;
-    const int pv = var_of(p, "pipe");
-    const int slabs = std::min(1 << pv, b.nz);
+    const PipeShape ps = pipe_shape(var_of(p, "pipe"));
+    const int slabs = std::min(ps.slabs, b.nz);
     if (slabs <= 1) {
       if ((st = yxy(mhd, 0, b.nz))) return st;
-    } else if (pv >= PIPE_SERIAL) {
+    } else if (ps.streams == 0) {
       // slabs in order on the plan's stream: each slab's chain (inverse y,
       // products, forward y) works on data the previous pass of the chain
       // has just left in the last-level cache
@@ -406,8 +418,10 @@ struct Seq {
       }
     } else {
       // fork the slabs over the helper streams (their memory-bound y passes
-      // overlap other slabs' compute-bound product pass), then join
-      const int k = std::min(slabs, ps_plan_s::NAUX);
+      // overlap other slabs' compute-bound product pass), then join; with two
+      // chains of small slabs, the two slabs in flight together can still
+      // stay in the last-level cache
+      const int k = std::min({slabs, ps.streams, ps_plan_s::NAUX});
       hipError_t e = hipEventRecord(p->ev_fork, s);
       for (int i = 0; i < k && e == hipSuccess; ++i) e = hipStreamWaitEvent(p->aux[i], p->ev_fork, 0);
       if (e != hipSuccess) return hip_fail(e, "slab fork");
@@ -1338,7 +1352,7 @@ ps_status ps_plan_autotune(ps_plan p, const void* state, ps_model m, int reps) {
           // pipeline settings whose slabs run concurrently on helper streams
           // are not considered: per-kernel timings of overlapping launches
           // would mean nothing
-          if (!strcmp(kind, "pipe") && v >= 1 && v < PIPE_SERIAL) continue;
+          if (!strcmp(kind, "pipe") && pipe_shape(v).streams != 0) continue;
           p->var[kind] = v;
           if ((out = q.tune_launch(strcmp(kind, "pipe") ? kind : "step", st, mhd))) break;  // warm-up
           out = time_v(kind, v, best_ms[v]);

@@ -54,3 +54,10 @@ def test_traffic_guards(tmp_path, monkeypatch):
 def test_host_info_fields():
     info = bench.host_info()
     assert info["nproc"] >= 1 and "MemTotal_GB" in info
+
+
+def test_pipe_slabs():
+    # in order or over three helper streams: 2^pipe; two chains: 2^(pipe - 3);
+    # never more slabs than planes
+    assert [bench.pipe_slabs(v, 512) for v in range(10)] == [1, 2, 4, 8, 16, 32, 64, 16, 32, 64]
+    assert bench.pipe_slabs(6, 24) == 24 and bench.pipe_slabs(9, 24) == 24

@@ -326,12 +326,13 @@ def test_box_abc_closed_form(B, dt):
 
 # ---------------------------------------------------------------- slab pipeline
 @pytest.mark.parametrize("graphs", [True, False])
-@pytest.mark.parametrize("pipe", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("pipe", [1, 2, 3, 4, 5, 6, 7, 8, 9])
 def test_rk2_pipe(B, ref, pipe, graphs):
-    """The y / x / y passes split into 2^pipe z-slabs, over helper streams
-    (1..3) or in order on the plan's stream (4..6; at N = 24, 2^5 and 2^6
-    exceed the planes: one plane per slab), captured into the step's graph or
-    launched directly, give the same step."""
+    """The y / x / y passes split into z-slabs: 2^pipe over three helper
+    streams (1..3) or in order on the plan's stream (4..6), or 2^(pipe-3) as
+    two chains on two helper streams (7..9); at N = 24, 32 and 64 slabs
+    exceed the planes (one plane per slab).  Captured into the step's graph
+    or launched directly, every setting gives the same step."""
     say("rk2 pipe", pipe, graphs)
     for model, N, nf in ((NS, 32, 3), (MHD, 24, 6)):
         z0 = synth.random_ns(N, 7, 2.0) if model == NS else synth.random_mhd(N, 8, 9, 2.0)
