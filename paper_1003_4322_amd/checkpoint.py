@@ -36,24 +36,32 @@ MAGIC = b"PSCKPT1\n"
 _DTYPES = {torch.complex64: "complex64", torch.complex128: "complex128"}
 
 
-def save(path: str, state: torch.Tensor, *, sizes: Union[int, Sequence[int]], nfields: int, t: float,
-         step: int, nu: float, eta: float, dt: float, seed: Optional[Any] = None,
-         variants: Optional[Dict[str, int]] = None, extra: Optional[Dict[str, Any]] = None) -> Dict[str, Any]:
+def save(path: str, state: torch.Tensor, *, nfields: int, t: float, step: int, nu: float, eta: float,
+         dt: float, sizes: Union[int, Sequence[int], None] = None, grid: Optional[Sequence[int]] = None,
+         seed: Optional[Any] = None, variants: Optional[Dict[str, int]] = None,
+         extra: Optional[Dict[str, Any]] = None) -> Dict[str, Any]:
     """Write `state` (a complex tensor on any device) and its header to `path`.
 
-    sizes: the plan's box size N (an int), a list of sizes (an ensemble) or a
-    grid (nx, ny, nz); t, step: the simulation time and step count reached;
+    Exactly one of sizes (the plan's box size N, or a list of sizes for an
+    ensemble) and grid (nx, ny, nz) names the plan's boxes.
+    t, step: the simulation time and step count reached;
     nu, eta, dt: the step's parameters; seed: whatever made the initial state;
     variants: the plan's kernel variants (Plan.variants()); extra: further
     JSON-serialisable fields.  Returns the header written."""
     if state.dtype not in _DTYPES:
         raise ValueError(f"state must be complex64 or complex128, not {state.dtype}")
+    if (sizes is None) == (grid is None):
+        raise ValueError("give exactly one of sizes and grid")
+    if grid is not None and len(grid) != 3:
+        raise ValueError("grid must be (nx, ny, nz)")
     host = state.detach().contiguous().to("cpu")
     payload = host.numpy().tobytes(order="C")
     header = {
         "format": "pseudospectral-state",
         "version": 1,
-        "sizes": list(sizes) if isinstance(sizes, (list, tuple)) else int(sizes),
+        "sizes": None if sizes is None else [int(n) for n in sizes] if isinstance(sizes, (list, tuple))
+        else int(sizes),
+        "grid": None if grid is None else [int(n) for n in grid],
         "nfields": int(nfields),
         "dtype": _DTYPES[state.dtype],
         "shape": list(host.shape),
@@ -128,6 +136,14 @@ def load(path: str, device: Union[str, torch.device, None] = None) -> Tuple[torc
     if device is not None:
         state = state.to(device)
     return state, header
+
+
+def plan_args(header: Dict[str, Any]) -> Dict[str, Any]:
+    """Keyword arguments of binding.Plan that recreate the checkpoint's boxes,
+    fields and element type."""
+    dtype = {"complex64": "f32", "complex128": "f64"}[header["dtype"]]
+    boxes = {"grid": tuple(header["grid"])} if header.get("grid") else {"N": header["sizes"]}
+    return {**boxes, "nfields": header["nfields"], "dtype": dtype}
 
 
 def apply_variants(plan, header: Dict[str, Any]) -> Dict[str, int]:

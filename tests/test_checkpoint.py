@@ -98,6 +98,23 @@ class _FakePlan:
         self.set[k] = v
 
 
+def test_boxes_in_header(tmp_path):
+    path = str(tmp_path / "a.ckpt")
+    s = _state(torch.complex128)
+    meta = {k: v for k, v in META.items() if k != "sizes"}
+    ck.save(path, s, sizes=[16, 16, 24], **meta)
+    h = ck.read_header(path)
+    assert h["sizes"] == [16, 16, 24] and h["grid"] is None
+    assert ck.plan_args(h) == {"N": [16, 16, 24], "nfields": 6, "dtype": "f64"}
+    ck.save(path, s.to(torch.complex64), grid=(32, 48, 64), **meta)
+    h = ck.read_header(path)
+    assert h["grid"] == [32, 48, 64] and h["sizes"] is None
+    assert ck.plan_args(h) == {"grid": (32, 48, 64), "nfields": 6, "dtype": "f32"}
+    for bad in ({}, {"sizes": 8, "grid": (8, 8, 8)}, {"grid": (8, 8)}):
+        with pytest.raises(ValueError):
+            ck.save(path, s, **bad, **meta)
+
+
 def test_apply_variants_checks_plan(tmp_path):
     path = str(tmp_path / "a.ckpt")
     s = _state(torch.complex64)
