@@ -55,7 +55,7 @@ def save(path: str, state: torch.Tensor, *, nfields: int, t: float, step: int, n
     if grid is not None and len(grid) != 3:
         raise ValueError("grid must be (nx, ny, nz)")
     host = state.detach().contiguous().to("cpu")
-    payload = host.numpy().tobytes(order="C")
+    payload = memoryview(np.ascontiguousarray(host.numpy())).cast("B")  # no copy
     header = {
         "format": "pseudospectral-state",
         "version": 1,
@@ -72,7 +72,7 @@ def save(path: str, state: torch.Tensor, *, nfields: int, t: float, step: int, n
         "dt": float(dt),
         "seed": seed,
         "variants": {str(k): int(v) for k, v in (variants or {}).items()},
-        "payload_bytes": len(payload),
+        "payload_bytes": payload.nbytes,
         "sha256": hashlib.sha256(payload).hexdigest(),
     }
     if extra:
@@ -120,18 +120,25 @@ def load(path: str, device: Union[str, torch.device, None] = None) -> Tuple[torc
     ValueError if the file is truncated, altered or of another format."""
     with open(path, "rb") as f:
         header = _header(f)
-        payload = f.read()
-    if len(payload) != header["payload_bytes"]:
-        raise ValueError(f"checkpoint payload has {len(payload)} bytes, header says {header['payload_bytes']}")
-    if hashlib.sha256(payload).hexdigest() != header["sha256"]:
+        dtype = {"complex64": np.complex64, "complex128": np.complex128}.get(header["dtype"])
+        if dtype is None:
+            raise ValueError(f"unknown element type {header['dtype']!r}")
+        shape = tuple(int(s) for s in header["shape"])
+        nbytes = int(np.prod(shape)) * np.dtype(dtype).itemsize
+        if nbytes != header["payload_bytes"]:
+            raise ValueError("checkpoint shape does not match its payload size")
+        arr = np.empty(shape, dtype=dtype)  # the payload is read straight into it
+        view = memoryview(arr).cast("B")
+        got = 0
+        while got < nbytes:  # a single read may return less (about 2 GB per system call)
+            n = f.readinto(view[got:])
+            if not n:
+                break
+            got += n
+        if got != nbytes or f.read(1):
+            raise ValueError(f"checkpoint payload is not the {nbytes} bytes its header says")
+    if hashlib.sha256(view).hexdigest() != header["sha256"]:
         raise ValueError("checkpoint payload does not match its SHA-256")
-    dtype = {"complex64": np.complex64, "complex128": np.complex128}.get(header["dtype"])
-    if dtype is None:
-        raise ValueError(f"unknown element type {header['dtype']!r}")
-    shape = tuple(int(s) for s in header["shape"])
-    if int(np.prod(shape)) * np.dtype(dtype).itemsize != len(payload):
-        raise ValueError("checkpoint shape does not match its payload")
-    arr = np.frombuffer(payload, dtype=dtype).reshape(shape).copy()
     state = torch.from_numpy(arr)
     if device is not None:
         state = state.to(device)

@@ -59,7 +59,7 @@ def _corrupt(path, fn):
 
 
 @pytest.mark.parametrize("how", ["truncate_payload", "flip_payload_byte", "bad_magic", "truncate_header",
-                                 "foreign_format", "wrong_shape"])
+                                 "foreign_format", "wrong_shape", "trailing_bytes"])
 def test_refuses_damaged_files(tmp_path, how):
     path = str(tmp_path / "a.ckpt")
     ck.save(path, _state(torch.complex128), **META)
@@ -79,6 +79,7 @@ def test_refuses_damaged_files(tmp_path, how):
         "truncate_header": lambda b: b[:20],
         "foreign_format": lambda b: edit_header(b, format="something-else"),
         "wrong_shape": lambda b: edit_header(b, shape=[6, 8, 8, 4]),
+        "trailing_bytes": lambda b: b + b"\0",
     }
     _corrupt(path, fns[how])
     with pytest.raises(ValueError):
