@@ -155,6 +155,7 @@ struct ZCurlArgs {
   const int* tiles;
   int ntl;
   T sx, sy, sz;  // box factors 2 pi / L: physical wavenumber = s * index
+  int nt;        // streaming stores of the output (set when it far exceeds the caches)
 };
 
 // tile, ky and box of a z-pass workgroup
@@ -245,7 +246,13 @@ __global__ __launch_bounds__(TX* TQ, MINW) void k_z_curl(ZCurlArgs<T> a) {
     if constexpr (E::NSTAGE == 1) __syncthreads();
 #pragma unroll
     for (int s = 0; s < E::LAST_NB * E::RL_; ++s)
-      if (ok && E::last_valid(q, s)) out[fout * a.out_fs + E::last_index(q, s) * out_es] = v[s];
+      if (ok && E::last_valid(q, s)) {
+        C2<T>* o = out + fout * a.out_fs + E::last_index(q, s) * out_es;
+        if (a.nt)
+          store_nt(o, v[s]);
+        else
+          *o = v[s];
+      }
   };
 
   if constexpr (ELS) {
