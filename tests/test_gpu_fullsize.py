@@ -160,3 +160,30 @@ def test_ensemble_full_config(B, ref):
         got = h[p.cplx_off[i]:p.cplx_off[i] + f.size].reshape(f.shape)
         want = ref.rk2_step(f, NS, 5e-3, 0.0, 2e-3, 1)
         assert rel_l2_w(got, want) < 2e-6, (i, rel_l2_w(got, want))
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+def test_mhd512_slab_settings_bitwise(B, dt):
+    """At the benchmark's size, the tuned in-order slabs (16) and the two
+    overlapping chains of 32 and 64 slabs give the same two steps bit for bit
+    (each plane's chain is the same arithmetic whichever slab or stream runs
+    it)."""
+    cdt = torch.complex64 if dt == "f32" else torch.complex128
+    s0 = sparse_to_dev(synth.mhd_sparse(512, 3, 4, 3.0), cdt)
+    p = B.Plan(512, 6, dt)
+    p.set_variant("prune", 1)
+    p.set_variant("form", 1)
+    ref = None
+    for pipe in (4, 8, 9):
+        say("mhd512 slab settings", dt, "pipe", pipe)
+        p.set_variant("pipe", pipe)
+        s = s0.clone()
+        p.rk2_step(s, B.PS_MHD, 5e-4, 5e-4, 1e-3, 2)
+        torch.cuda.synchronize()
+        if ref is None:
+            ref = s
+        else:
+            iv = torch.int32 if dt == "f32" else torch.int64
+            assert torch.equal(torch.view_as_real(s).view(iv), torch.view_as_real(ref).view(iv)), pipe
+            del s
+    p.close()
