@@ -122,6 +122,41 @@ def test_pipe_settings_bitwise_equal(B):
     p.close()
 
 
+@pytest.mark.parametrize("kind", ["ensemble", "grid"])
+def test_pipe_settings_bitwise_other_plans(B, kind):
+    """Every slab-pipeline setting on an ensemble of uneven boxes (NS) and on
+    an nx x ny x nz grid (MHD) computes the same two steps bit for bit as one
+    slab (slab counts are capped at each box's planes)."""
+    say("pipe settings bitwise", kind)
+    if kind == "ensemble":
+        sizes = [16, 24, 32, 16]
+        p = B.Plan(sizes, 3, "f64")
+        z = torch.zeros(p.n_complex(), dtype=torch.complex128, device=DEV)
+        for b, n in enumerate(sizes):
+            f = synth.random_ns(n, 600 + b, synth.ensemble_k0(600 + b))
+            z[p.cplx_off[b]:p.cplx_off[b] + f.size] = torch.from_numpy(np.ascontiguousarray(f).ravel()).to(DEV)
+        model, nu, eta, dt = B.PS_NS, 1e-3, 0.0, 2e-3
+    else:
+        n = (32, 48, 64)
+        p = B.Plan(nfields=6, dtype="f32", grid=n)
+        u, b_ = synth.random_grid(*n, 41, 2.0), synth.random_grid(*n, 42, 2.0)
+        z = to_dev(np.concatenate([u + b_, u - b_]), "f32")
+        model, nu, eta, dt = B.PS_MHD, 1e-3, 5e-4, 1e-3
+    p.set_variant("prune", 1)
+    ref = None
+    for v in range(p.variant_count("pipe")):
+        p.set_variant("pipe", v)
+        s = z.clone()
+        p.rk2_step(s, model, nu, eta, dt, 2)
+        r = torch.view_as_real(s)
+        bits = r.view(torch.int64 if r.dtype == torch.float64 else torch.int32)
+        if ref is None:
+            ref = bits.clone()
+        else:
+            assert torch.equal(bits, ref), (kind, v)
+    p.close()
+
+
 def test_autotune_cache(B, tmp_path, monkeypatch):
     say("autotune cache")
     path = tmp_path / "tune.txt"
