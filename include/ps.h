@@ -252,10 +252,12 @@ ps_status ps_mhd_spectrum(ps_plan p, const void *zhat, double *spec_dev, double 
  * even and odd slabs, on two helper streams, so that the two slabs in flight
  * still fit the last-level cache while each fills the other's launch gaps;
  * 0 = one slab on the plan's stream (default; ps_plan_autotune chooses among
- * 0 and 4..6, the settings whose launches do not overlap: a caller who wants
- * the fastest step over per-kernel timings sets 7..9 by hand).  Every setting
- * computes the same step bit for bit.  Setting a variant drops a cached
- * graph. */
+ * 0 and 4..6, the settings whose launches do not overlap, unless "overlap"
+ * is 1).  Every setting computes the same step bit for bit.  Kind "overlap"
+ * (0 default, 1): whether ps_plan_autotune may also choose the two-chain
+ * settings 7..9, for a caller who wants the fastest step over per-kernel
+ * timings (a launch's duration is no longer its own when two overlap); it
+ * changes no arithmetic.  Setting a variant drops a cached graph. */
 ps_status ps_plan_set_variant(ps_plan p, const char *kind, int variant);
 int ps_plan_get_variant(ps_plan p, const char *kind);
 int ps_plan_variant_count(ps_plan p, const char *kind);
@@ -264,16 +266,16 @@ int ps_plan_variant_count(ps_plan p, const char *kind);
  * over reps launches on the caller's state for model m, times the variants
  * within 10 % of the fastest again in three interleaved rounds (each keeping
  * its best time, so that clock drift over the sequence does not rank them)
- * and keeps the fastest; then chooses the "pipe" setting (0 or 4..6) the
- * same way on whole right-hand sides (evaluated in the first RK stage's
- * mode).  Reads
+ * and keeps the fastest; then chooses the "pipe" setting (0 or 4..6, and
+ * 7..9 when "overlap" is 1) the same way on whole right-hand sides
+ * (evaluated in the first RK stage's mode).  Reads
  * state, writes only the workspace; synchronises the plan's stream.  Plan
  * time, like FFT planning, is not part of a step (Sec. 4 leaves planning out
  * of its timings).  When the environment variable PS_TUNE_CACHE names a
  * file, the tuned variants are kept there under a key of everything the
  * timings depend on (device architecture, HIP runtime version, this
  * library's build hash, model, dtype, fields, every size class, and the
- * "form", "prune" and "batch" variants); a later call with the same
+ * "form", "prune", "batch" and "overlap" variants); a later call with the same
  * key takes them from the file and times nothing.  A file that cannot be
  * read or written only costs the timing runs. */
 ps_status ps_plan_autotune(ps_plan p, const void *state, ps_model m, int reps);

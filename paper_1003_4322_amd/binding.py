@@ -336,7 +336,7 @@ class Plan:
         _check(lib().ps_plan_set_box(self.handle, float(Lx), float(Ly), float(Lz)), "set_box")
 
     # -- variants and autotuning ---------------------------------------------------
-    KINDS = ("y", "z", "z_curl", "z_epi", "x_prod", "batch", "prune", "form", "pipe")
+    KINDS = ("y", "z", "z_curl", "z_epi", "x_prod", "batch", "prune", "form", "pipe", "overlap")
 
     def set_variant(self, kind: str, v: int):
         _check(lib().ps_plan_set_variant(self.handle, kind.encode(), int(v)), "set_variant")

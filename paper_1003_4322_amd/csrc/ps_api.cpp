@@ -143,7 +143,7 @@ namespace {
 
 size_t csize(const ps_plan_s* p) { return p->dtype == PS_F32 ? 8 : 16; }
 
-const char* const KINDS[] = {"y", "z", "z_curl", "z_epi", "x_prod", "batch", "prune", "form", "pipe"};
+const char* const KINDS[] = {"y", "z", "z_curl", "z_epi", "x_prod", "batch", "prune", "form", "pipe", "overlap"};
 // "pipe" variant v: the y / x / y passes run as z-slabs: 2^v slabs over the
 // three helper streams for v = 1..3, 2^v slabs one after another on the plan's
 // stream for v = 4..6, and 2^(v-3) slabs as two chains (even and odd slabs) on
@@ -666,7 +666,7 @@ std::string tune_key(ps_plan p, bool mhd) {
     snprintf(buf, sizeof buf, "|%dx%dx%d*%d", c.nx, c.ny, c.nz, c.nb);
     k += buf;
   }
-  for (const char* kind : {"form", "prune", "batch"}) {
+  for (const char* kind : {"form", "prune", "batch", "overlap"}) {
     snprintf(buf, sizeof buf, "|%s=%d", kind, var_of(p, kind));
     k += buf;
   }
@@ -1282,7 +1282,7 @@ int ps_plan_get_variant(ps_plan p, const char* kind) {
 int ps_plan_variant_count(ps_plan p, const char* kind) {
   if (!p || !kind) return PS_ERR_ARG;
   if (!strcmp(kind, "batch") || !strcmp(kind, "prune")) return 2;
-  if (!strcmp(kind, "form")) return 2;
+  if (!strcmp(kind, "form") || !strcmp(kind, "overlap")) return 2;
   if (!strcmp(kind, "pipe")) return NPIPE;
   int n = 1;
   for (auto& c : p->classes) n = std::max(n, ps::variant_count(kind, axis_len(c, kind), p->nfields == 6));
@@ -1354,9 +1354,12 @@ ps_status ps_plan_autotune(ps_plan p, const void* state, ps_model m, int reps) {
         std::vector<float> best_ms(n, 1e30f);
         for (int v = 0; v < n && out == PS_OK; ++v) {
           // pipeline settings whose slabs run concurrently on helper streams
-          // are not considered: per-kernel timings of overlapping launches
-          // would mean nothing
-          if (!strcmp(kind, "pipe") && pipe_shape(v).streams != 0) continue;
+          // are not considered (per-kernel timings of overlapping launches
+          // would mean nothing), except the two-chain settings when the
+          // caller has asked for them ("overlap" 1)
+          if (!strcmp(kind, "pipe") && pipe_shape(v).streams != 0 &&
+              !(var_of(p, "overlap") == 1 && v >= PIPE_TWO))
+            continue;
           p->var[kind] = v;
           if ((out = q.tune_launch(strcmp(kind, "pipe") ? kind : "step", st, mhd))) break;  // warm-up
           out = time_v(kind, v, best_ms[v]);

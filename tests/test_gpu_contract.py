@@ -182,6 +182,43 @@ def test_autotune_cache(B, tmp_path, monkeypatch):
     assert len(path.read_text().splitlines()) == 4
 
 
+def test_autotune_overlap(B, tmp_path, monkeypatch):
+    """With "overlap" 1 the autotuner may also choose the two-chain slab
+    settings; whatever it chooses computes the one-slab step bit for bit, and
+    the tuning cache keeps overlap-tuned and in-order-tuned entries apart."""
+    say("autotune overlap")
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("PS_TUNE_CACHE", str(path))
+    N = 256
+    z = to_dev(synth.random_mhd(N, 3, 4, 3.0), "f32")
+
+    def plan(overlap):
+        p = B.Plan(N, 6, "f32")
+        p.set_variant("prune", 1)
+        p.set_variant("form", 1)
+        p.set_variant("overlap", overlap)
+        return p
+
+    p1 = plan(1)
+    v1 = p1.autotune(z, B.PS_MHD, 1)
+    assert p1.autotune_timed() > 0 and v1["overlap"] == 1
+    assert v1["pipe"] in (0, 4, 5, 6, 7, 8, 9), v1
+    s = z.clone()
+    p1.rk2_step(s, B.PS_MHD, 5e-4, 5e-4, 1e-3, 2)
+    p1.set_variant("pipe", 0)
+    s0 = z.clone()
+    p1.rk2_step(s0, B.PS_MHD, 5e-4, 5e-4, 1e-3, 2)
+    assert torch.equal(torch.view_as_real(s).view(torch.int32), torch.view_as_real(s0).view(torch.int32))
+    p2 = plan(0)                          # another key: timed again, in-order settings only
+    v2 = p2.autotune(z, B.PS_MHD, 1)
+    assert p2.autotune_timed() > 0 and v2["pipe"] in (0, 4, 5, 6), v2
+    p3 = plan(1)                          # the overlap entry again: from the file
+    assert p3.autotune(z, B.PS_MHD, 1) == v1 and p3.autotune_timed() == 0
+    assert len(path.read_text().splitlines()) == 2
+    for p in (p1, p2, p3):
+        p.close()
+
+
 @pytest.mark.parametrize("dt", ["f64", "f32"])
 @pytest.mark.parametrize("N", [16, 32])
 def test_mhd_spectrum(B, ref, N, dt):
